@@ -1,0 +1,152 @@
+"""Pins for the oracle's solver (Algorithm 1), load vector and L2 error.
+
+* Algorithm 1 with the Jacobi preconditioner against scipy's preconditioned
+  CG (a library routine computing the same recurrence) and a direct solve,
+* a numpy toy of Algorithm 5 (merged PCG, Sec. 4.2) reproduces Algorithm 1:
+  same iteration count, same x, both exit parities,
+* sum of the load vector = integral of f (partition of unity),
+* O(h^{k+1}) L2 convergence to u = prod sin(pi x_j) on the Cartesian mesh
+  and on the boundary-preserving sine-product map.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+
+def _problem(O, ncells=(4, 3, 5), k=2, kind=1, seed=0):
+    rng = np.random.default_rng(seed)
+    coeff = np.exp(rng.normal(size=int(np.prod(ncells))))
+    m = O.Mesh(ncells, k, map_kind=kind, amp=0.05, coeff=coeff)
+    A = O.assemble(m)
+    b = rng.normal(size=A.n)
+    b[m.constrained_mask()] = 0.0
+    return m, A, b
+
+
+def test_pcg_matches_scipy_cg(oracle_mod):
+    O = oracle_mod
+    m, A, b = _problem(O)
+    d = A.diagonal()
+    tol = 1e-10
+    x, its, hist, rc = O.pcg(A, d, b, tol=tol, maxit=2000)
+    assert rc == 0
+    S = A.to_scipy()
+    M = spla.LinearOperator(S.shape, matvec=lambda r: r / d)
+    count = [0]
+
+    def cb(_):
+        count[0] += 1
+    xs, info = spla.cg(S, b, rtol=tol, atol=0.0, M=M, maxiter=2000, callback=cb)
+    assert info == 0
+    assert abs(count[0] - its) <= 1
+    assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
+    xd = spla.spsolve(S.tocsc(), b)
+    assert np.linalg.norm(x - xd) <= 1e-7 * np.linalg.norm(xd)
+    # history: starts at ||b||, ends below tol*||b||, the one before not
+    nb = np.linalg.norm(b)
+    assert hist[0] == pytest.approx(nb, rel=1e-14)
+    assert hist[-1] < tol * nb <= hist[-2]
+    assert np.linalg.norm(b - A.matvec(x)) <= 2 * tol * nb
+
+
+def test_pcg_edge_cases(oracle_mod):
+    O = oracle_mod
+    m, A, b = _problem(O, ncells=(2, 2, 2))
+    d = A.diagonal()
+    x, its, hist, rc = O.pcg(A, d, np.zeros(A.n), tol=1e-10)
+    assert rc == 0 and its == 0 and np.all(x == 0)
+    x, its, hist, rc = O.pcg(A, d, b, tol=1e-10, maxit=1)
+    assert rc == -4 and its == 1
+    # a warm start at the solution needs no iteration
+    xs = spla.spsolve(A.to_scipy().tocsc(), b)
+    x, its, hist, rc = O.pcg(A, d, b, x0=xs, tol=1e-8)
+    assert rc == 0 and its == 0
+    # non-SPD (negated operator) breaks down in the first iteration
+    from oracle.oracle import CSR
+    An = CSR(A.rowptr, A.col, -A.val)
+    x, its, hist, rc = O.pcg(An, np.abs(d), b, tol=1e-10)
+    assert rc == -5
+
+
+def merged_pcg_toy(A, d, b, tol, maxit):
+    """Algorithm 5 in numpy, with the reading x_1 = x_0 (x updated every
+    other iteration and reconstructed at exit)."""
+    x = np.zeros_like(b)
+    r = b - A @ x
+    p = np.zeros_like(b)
+    v = np.zeros_like(b)
+    alpha, beta = 0.0, 0.0
+    alpha_prev, beta_prev = 0.0, 0.0
+    eps = tol * np.linalg.norm(b)
+    if np.linalg.norm(r) < eps:
+        return x, 0
+    for k in range(1, maxit + 1):
+        if k > 1 and k % 2 == 1:
+            x = x + alpha * p + (alpha_prev / beta_prev) * (p - r / d)
+        r = r - alpha * v
+        p = r / d + beta * p
+        v = A @ p
+        g, a, bb, c = r @ r, p @ v, r @ v, v @ v
+        dd, e, f = r @ (r / d), r @ (v / d), v @ (v / d)
+        alpha_new = dd / a
+        if np.sqrt(max(g - 2 * alpha_new * bb + alpha_new ** 2 * c, 0.0)) < eps:
+            if k % 2 == 1:
+                x = x + alpha_new * p
+            else:
+                x = x + alpha_new * p + (alpha / beta) * (p - r / d)
+            return x, k
+        beta_new = (dd - 2 * alpha_new * e + alpha_new ** 2 * f) / dd
+        alpha_prev, beta_prev = alpha, beta
+        alpha, beta = alpha_new, beta_new
+    return x, maxit
+
+
+@pytest.mark.parametrize("seed,tol", [(0, 1e-6), (1, 1e-9), (2, 1e-12), (3, 1e-4)])
+def test_algorithm5_toy_reproduces_algorithm1(oracle_mod, seed, tol):
+    O = oracle_mod
+    m, A, b = _problem(O, ncells=(3, 3, 2), k=2, seed=seed)
+    d = A.diagonal()
+    x1, its1, _, rc = O.pcg(A, d, b, tol=tol)
+    S = A.to_scipy()
+    x5, its5 = merged_pcg_toy(S, d, b, tol, 1000)
+    assert rc == 0 and abs(its5 - its1) <= 1
+    assert np.linalg.norm(x5 - x1) <= 1e-10 * np.linalg.norm(x1)
+
+
+def test_algorithm5_toy_both_parities(oracle_mod):
+    O = oracle_mod
+    m, A, b = _problem(O, ncells=(3, 3, 2), k=2, seed=7)
+    d = A.diagonal()
+    S = A.to_scipy()
+    parities = set()
+    for tol in np.logspace(-2, -10, 9):
+        x1, its1, _, _ = O.pcg(A, d, b, tol=tol)
+        x5, its5 = merged_pcg_toy(S, d, b, tol, 1000)
+        if its1 == its5:
+            parities.add(its1 % 2)
+            assert np.linalg.norm(x5 - x1) <= 1e-10 * np.linalg.norm(x1)
+    assert parities == {0, 1}
+
+
+@pytest.mark.parametrize("kind", [0, 2])
+def test_rhs_integral(oracle_mod, kind):
+    O = oracle_mod
+    m = O.Mesh(4, 2, map_kind=kind, amp=0.05, bc=O.BC_NONE)
+    b = O.rhs(m, O.F_SINE)
+    assert b.sum() == pytest.approx(24.0 / np.pi, rel=2e-5)
+
+
+@pytest.mark.parametrize("kind", [0, 2])
+@pytest.mark.parametrize("k,Ns", [(1, (4, 8)), (2, (4, 8)), (3, (3, 6)), (4, (4, 8))])
+def test_l2_convergence_rate(oracle_mod, kind, k, Ns):
+    O = oracle_mod
+    errs = []
+    for N in Ns:
+        m = O.Mesh(N, k, map_kind=kind, amp=0.05)
+        A = O.assemble(m)
+        b = O.rhs(m, O.F_SINE)
+        x, its, _, rc = O.pcg(A, A.diagonal(), b, tol=1e-13, maxit=5000)
+        assert rc == 0
+        errs.append(O.l2_error(m, x))
+    rate = np.log2(errs[0] / errs[1]) / np.log2(Ns[1] / Ns[0])
+    assert abs(rate - (k + 1)) < 0.35, (errs, rate)
