@@ -1,0 +1,176 @@
+/*
+ * mfcg.h -- C-ABI of the MI355X (gfx950) fused matrix-free conjugate
+ * gradient library.
+ *
+ * The library solves A u = b for the Q_k continuous finite-element
+ * discretisation of the scalar Poisson problem -div(a grad u) = f on a
+ * structured hexahedral mesh of [0,1]^3 deformed by an analytic map
+ * (Kronbichler, Sashko, Munch, arXiv 2205.08909, Sec. 2, Eq. 1-5, in its
+ * scalar form).  The operator is never assembled: every product with A is
+ * the sum of cell integrals of Eq. 4/5 evaluated by sum factorisation.
+ * The solver is the merged Jacobi-preconditioned CG of Algorithm 5 (Sec. 4.2)
+ * whose vector updates ("pre") and seven inner products ("post") are
+ * interleaved with the cell loop of the operator (Sec. 5), so that each
+ * vector entry crosses HBM about once per iteration.
+ *
+ * Conventions shared by all entry points
+ *  - Every function returns an int: MFCG_OK (0) or a negative MFCG_E* code.
+ *    No C++ exception crosses this boundary.  mfcg_last_error() returns a
+ *    human-readable description of the last failure on a handle.
+ *  - Vectors are device pointers (caller owned, 8-byte aligned, on the
+ *    handle's device) in lexicographic node order:
+ *        i = gx + (nx*k + 1) * (gy + (ny*k + 1) * gz),
+ *    gx in [0, nx*k], ...  The node count is (nx k+1)(ny k+1)(nz k+1) and
+ *    includes the Dirichlet nodes (Sec. 5.3 keeps constrained unknowns in
+ *    the linear system).
+ *  - Cell-wise input is host memory, cell index c = cx + nx*(cy + ny*cz).
+ *  - hip_stream is a hipStream_t passed as void* (NULL: the null stream).
+ *    Calls are stream ordered; calls that return results on the host
+ *    synchronise the stream before returning.
+ *  - A handle owns all its device buffers; it is not thread safe: use one
+ *    handle per host thread/stream.
+ *  - Argument errors (MFCG_EINVAL) are detected before any HIP call.
+ */
+#ifndef MFCG_H
+#define MFCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MFCG_OK = 0,
+    MFCG_EINVAL = -1,      /* invalid argument (detected on the host, before any HIP call) */
+    MFCG_ENOMEM = -2,      /* device allocation failed */
+    MFCG_EHIP = -3,        /* a HIP runtime call failed */
+    MFCG_ENOTCONV = -4,    /* maxit reached: x holds the last iterate */
+    MFCG_EBREAKDOWN = -5,  /* p^T A p <= 0 or a non-finite scalar: operator not SPD or NaN input */
+    MFCG_ESTAGNATION = -6  /* iterative refinement stopped reducing the residual */
+};
+
+enum {
+    MFCG_MAP_AFFINE = 0,        /* x = X (Cartesian unit cube) */
+    MFCG_MAP_SINE_SHEAR = 1,    /* x_i = X_i + A sin(2 pi X_{i+1}) sin(2 pi X_{i+2}) (indices mod 3) */
+    MFCG_MAP_SINE_PRODUCT = 2   /* x_i = X_i + A prod_j sin(2 pi X_j) (keeps the unit cube) */
+};
+
+enum {
+    MFCG_BC_DIRICHLET0 = 0,     /* boundary nodes are identity rows/columns of A */
+    MFCG_BC_NONE = 1            /* no constraint (pure Neumann operator; singular) */
+};
+
+enum {
+    MFCG_RHS_SINE = 0,          /* f = 3 pi^2 prod_j sin(pi x_j) */
+    MFCG_RHS_BUMPS = 1          /* f = sum_m A_m exp(-|x - c_m|^2 / (2 s_m^2)) */
+};
+
+typedef struct mfcg_ctx *mfcg_handle;
+
+/* Mesh: cells per direction on [0,1]^3, the map applied to it, the
+ * boundary treatment. */
+typedef struct {
+    int32_t cells[3];
+    int32_t map_kind;        /* MFCG_MAP_* */
+    double map_amplitude;    /* A of the map; ignored for MFCG_MAP_AFFINE */
+    int32_t bc;              /* MFCG_BC_* */
+} mfcg_mesh;
+
+/* Options.  Zero-initialised fields select the defaults. */
+typedef struct {
+    int32_t n_q_1d;          /* Gauss points per direction; 0: k+1 (only k+1 is supported) */
+    int32_t tile[3];         /* cells per tile in x, y, z; 0: per-degree default */
+    int32_t check_every;     /* iterations between host polls of the convergence flag; 0: 16 */
+    int32_t fp32;            /* 1: also build the FP32 operator copy needed by mfcg_solve_ir */
+} mfcg_options;
+
+/* Builds the operator (Sec. 2, Eq. 3-5): tiles and DoF enumeration of the
+ * fused loop (Sec. 5.3), the stored per-quadrature-point tensor
+ * G_q = a_e w_q det(J_q) J_q^{-1} J_q^{-T} (the "final tensor load"
+ * variant of Sec. 2.2), and the Jacobi diagonal (Sec. 3).
+ *   degree      polynomial degree k, 1..8
+ *   cell_coeff  host, nx*ny*nz positive finite values a_e; NULL: a = 1
+ *   opt         NULL: defaults
+ * Errors: EINVAL (null mesh/out, cells < 1, degree out of range, bad map or
+ * bc, non-positive coefficient, unsupported n_q_1d, tile < 0), ENOMEM, EHIP.
+ * On error *out is NULL. */
+int mfcg_setup(const mfcg_mesh *mesh, int32_t degree, const double *cell_coeff,
+               const mfcg_options *opt, void *hip_stream, mfcg_handle *out);
+
+/* Number of nodes (vector length), Dirichlet nodes included. */
+int mfcg_n_dofs(mfcg_handle h, int64_t *n);
+
+/* dst = A src (Eq. 4): the matrix-free operator, identity rows on Dirichlet
+ * nodes.  dst and src are distinct device vectors of length n_dofs. */
+int mfcg_vmult(mfcg_handle h, double *dst, const double *src, void *hip_stream);
+
+/* diag = diag(A) (the point-Jacobi preconditioner, Sec. 3); 1 on Dirichlet
+ * nodes.  Device vector of length n_dofs. */
+int mfcg_diagonal(mfcg_handle h, double *diag, void *hip_stream);
+
+/* Load vector b_i = sum_e sum_q f(x_q) phi_i(x_q) w_q det J_q on free nodes,
+ * 0 on Dirichlet nodes, Gauss quadrature with k+1 points per direction.
+ *   kind    MFCG_RHS_*
+ *   params  host; MFCG_RHS_BUMPS: [nb, (A, cx, cy, cz, s) x nb], nb <= 64;
+ *           ignored for MFCG_RHS_SINE. */
+int mfcg_assemble_rhs(mfcg_handle h, int32_t kind, const double *params, double *b, void *hip_stream);
+
+/* Jacobi-preconditioned CG, Algorithm 5 with the vector updates and inner
+ * products fused into the operator's cell loop (Sec. 4.2, Sec. 5).
+ *   b, x           device vectors; x holds x_0 on entry and the solution on
+ *                  return (also on ENOTCONV: the last iterate)
+ *   tol            stop when the residual norm ||r_j||_2 < tol * ||b||_2
+ *                  (Sec. 3.1 terminates on the unpreconditioned residual);
+ *                  tol = 0 runs exactly maxit iterations
+ *   maxit          >= 1
+ *   iters          host out: iterations performed (matrix-vector products)
+ *   res_hist       host, maxit+1 doubles or NULL: res_hist[0] = ||r_0||,
+ *                  res_hist[j] = the residual norm after iteration j as
+ *                  predicted by Eq. 8 (the algorithm's own stopping value)
+ *   true_rel_res   host or NULL: ||b - A x||_2 / ||b||_2 recomputed after
+ *                  the solve (costs one operator application)
+ * ||b|| = 0 returns x = 0, *iters = 0, MFCG_OK.
+ * Errors: EINVAL (null pointers, tol < 0 or not finite, maxit < 1),
+ * ENOTCONV, EBREAKDOWN, EHIP.  Synchronises hip_stream. */
+int mfcg_solve(mfcg_handle h, const double *b, double *x, double tol, int32_t maxit,
+               int32_t *iters, double *res_hist, double *true_rel_res, void *hip_stream);
+
+/* Stepping interface used for throughput measurement: mfcg_cg_begin
+ * initialises the solver state from (b, x0) exactly as mfcg_solve does;
+ * mfcg_cg_iterate enqueues n fused iterations (no host synchronisation;
+ * iterations after convergence are no-ops); mfcg_cg_end reconstructs the
+ * final x (Algorithm 5's delayed x update) into x and returns the
+ * iteration count and status.  Timing: when mfcg_set_timing(h, 1) is on,
+ * every launch of the fused cell kernel and of the shared-node kernel is
+ * bracketed by HIP events on hip_stream; mfcg_get_timing returns the summed
+ * milliseconds and launch counts since the last reset. */
+int mfcg_cg_begin(mfcg_handle h, const double *b, const double *x0, double tol, int32_t maxit,
+                  void *hip_stream);
+int mfcg_cg_iterate(mfcg_handle h, int32_t n, void *hip_stream);
+int mfcg_cg_end(mfcg_handle h, double *x, int32_t *iters, double *res_hist, void *hip_stream);
+int mfcg_set_timing(mfcg_handle h, int32_t enable);
+int mfcg_get_timing(mfcg_handle h, double *fused_ms, int64_t *fused_launches, double *shared_ms,
+                    int64_t *shared_launches);
+
+/* Layout facts of the handle (host out, any may be NULL): tile sizes in
+ * cells, node counts of the classes of the enumeration (tile-interior,
+ * shared between tiles, Dirichlet), tile count, bytes of the stored
+ * geometry tensor. */
+int mfcg_layout_info(mfcg_handle h, int32_t *tile, int64_t *n_interior, int64_t *n_shared,
+                     int64_t *n_dirichlet, int64_t *n_tiles, int64_t *geometry_bytes);
+
+/* Host-only: the lexicographic -> internal permutation the library would
+ * use for this mesh, degree and tile (tile entries 0: defaults), written to
+ * perm[n_dofs] (host), and the class counts.  No HIP call. */
+int mfcg_layout_permutation(const mfcg_mesh *mesh, int32_t degree, const int32_t *tile, int64_t *perm,
+                            int64_t *n_interior, int64_t *n_shared, int64_t *n_dirichlet);
+
+int mfcg_destroy(mfcg_handle h);
+const char *mfcg_error_string(int code);
+const char *mfcg_last_error(mfcg_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,628 @@
+/*
+ * capi.hip -- the C-ABI of include/mfcg.h: handle set-up, operator
+ * application, the solve driver and the stepping/timing interface.
+ *
+ * The solve keeps all scalars of Algorithm 5 in device memory; the host
+ * only enqueues launches (fused tile kernel + shared-node kernel per
+ * iteration) and polls one status word every `check_every` iterations.
+ */
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mfcg.h"
+#include "kernels.h"
+#include "setup_host.h"
+
+using namespace mfcg;
+
+struct EventPair {
+    hipEvent_t a, b;
+};
+
+struct mfcg_ctx {
+    int device = 0;
+    mfcg_mesh mesh{};
+    int K = 0;
+    int check_every = 16;
+    HostLayout hl;
+    LayoutView lv{};
+    Tables<double> tab{};
+    Tables<float> tab32{};
+    /* device buffers */
+    int64_t *d_ent_base = nullptr;
+    EntityRef *d_tile_ent = nullptr;
+    TileDesc *d_tiles = nullptr;
+    double *d_coeff = nullptr;
+    double *G = nullptr, *dinv = nullptr, *diag_lex = nullptr;
+    double *r = nullptr, *p = nullptr, *v = nullptr, *x = nullptr;
+    double *vin = nullptr, *vout = nullptr;
+    double *part = nullptr, *dots = nullptr, *sums = nullptr;
+    double *hist = nullptr;
+    int hist_cap = 0;
+    CGState *st = nullptr;
+    int nshared_blocks = 1;
+    int nsum_blocks = 1;
+    /* solve bookkeeping */
+    int maxit = 0;
+    int launched = 0;
+    double bnorm = 0.0;
+    bool zero_rhs = false;
+    /* timing */
+    bool timing = false;
+    std::vector<EventPair> ev_fused, ev_shared, ev_pool;
+    std::string err;
+};
+
+static thread_local std::string g_last_error;
+
+static int fail(mfcg_ctx *h, int code, const std::string &msg)
+{
+    if (h)
+        h->err = msg;
+    else
+        g_last_error = msg;
+    return code;
+}
+
+#define HIPCHK(h, call)                                                                               \
+    do {                                                                                              \
+        hipError_t e_ = (call);                                                                       \
+        if (e_ != hipSuccess)                                                                         \
+            return fail((h), e_ == hipErrorOutOfMemory ? MFCG_ENOMEM : MFCG_EHIP,                     \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                            \
+    } while (0)
+
+template <typename T>
+static hipError_t dalloc(T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc((void **)p, sizeof(T) * count);
+}
+
+static void release(mfcg_ctx *h)
+{
+    void *bufs[] = {h->d_ent_base, h->d_tile_ent, h->d_tiles, h->d_coeff, h->G,    h->dinv, h->diag_lex,
+                    h->r,          h->p,          h->v,       h->x,       h->vin,  h->vout, h->part,
+                    h->dots,       h->sums,       h->hist,    h->st};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    for (auto &e : h->ev_pool) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    for (auto &e : h->ev_fused) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    for (auto &e : h->ev_shared) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+}
+
+static int validate_mesh(const mfcg_mesh *mesh, int32_t degree, const int32_t *tile, std::string &msg)
+{
+    if (!mesh) {
+        msg = "mesh is NULL";
+        return MFCG_EINVAL;
+    }
+    if (degree < 1 || degree > 8) {
+        msg = "degree must be in 1..8";
+        return MFCG_EINVAL;
+    }
+    for (int d = 0; d < 3; ++d)
+        if (mesh->cells[d] < 1 || mesh->cells[d] > (1 << 20)) {
+            msg = "cells must be >= 1";
+            return MFCG_EINVAL;
+        }
+    if (mesh->map_kind < 0 || mesh->map_kind > 2) {
+        msg = "unknown map_kind";
+        return MFCG_EINVAL;
+    }
+    if (!std::isfinite(mesh->map_amplitude)) {
+        msg = "map amplitude not finite";
+        return MFCG_EINVAL;
+    }
+    if (mesh->bc != MFCG_BC_DIRICHLET0 && mesh->bc != MFCG_BC_NONE) {
+        msg = "unknown bc";
+        return MFCG_EINVAL;
+    }
+    int tx, ty;
+    tile_limits(degree, &tx, &ty);
+    if (tile) {
+        for (int d = 0; d < 3; ++d)
+            if (tile[d] < 0) {
+                msg = "tile sizes must be >= 0";
+                return MFCG_EINVAL;
+            }
+        if (tile[0] > tx || tile[1] > ty) {
+            msg = "tile x/y extent exceeds the compiled maximum for this degree";
+            return MFCG_EINVAL;
+        }
+    }
+    int64_t lat = 1;
+    for (int d = 0; d < 3; ++d) lat *= (int64_t)mesh->cells[d] * degree + 1;
+    if (lat > ((int64_t)1 << 40)) {
+        msg = "mesh too large";
+        return MFCG_EINVAL;
+    }
+    return MFCG_OK;
+}
+
+/* vmult on internal vectors: dst = A src */
+static int vmult_internal(mfcg_ctx *h, const double *src, double *dst, hipStream_t s)
+{
+    IterArgs<double> a{};
+    a.L = h->lv;
+    a.tab = h->tab;
+    a.G = h->G;
+    a.dinv = h->dinv;
+    a.src = src;
+    a.dst = dst;
+    a.part = h->part;
+    a.dots = h->dots;
+    a.st = h->st;
+    a.hist = h->hist;
+    a.nshared_blocks = h->nshared_blocks;
+    HIPCHK(h, launch_fused<double>(h->K, MODE_VMULT, a, s));
+    HIPCHK(h, launch_shared<double>(MODE_VMULT, a, s));
+    return MFCG_OK;
+}
+
+static int host_sumsq(mfcg_ctx *h, const double *a, const double *c, int64_t n, double *out, hipStream_t s)
+{
+    HIPCHK(h, launch_sumsq(n, a, c, h->sums, h->nsum_blocks, s));
+    std::vector<double> tmp(h->nsum_blocks);
+    HIPCHK(h, hipMemcpyAsync(tmp.data(), h->sums, sizeof(double) * h->nsum_blocks, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    double t = 0.0;
+    for (double v : tmp) t += v;
+    *out = t;
+    return MFCG_OK;
+}
+
+extern "C" {
+
+const char *mfcg_error_string(int code)
+{
+    switch (code) {
+    case MFCG_OK: return "ok";
+    case MFCG_EINVAL: return "invalid argument";
+    case MFCG_ENOMEM: return "out of device memory";
+    case MFCG_EHIP: return "HIP runtime error";
+    case MFCG_ENOTCONV: return "not converged within maxit";
+    case MFCG_EBREAKDOWN: return "CG breakdown (p^T A p <= 0 or non-finite)";
+    case MFCG_ESTAGNATION: return "iterative refinement stagnated";
+    default: return "unknown error";
+    }
+}
+
+const char *mfcg_last_error(mfcg_handle h)
+{
+    return h ? h->err.c_str() : g_last_error.c_str();
+}
+
+int mfcg_layout_permutation(const mfcg_mesh *mesh, int32_t degree, const int32_t *tile, int64_t *perm,
+                            int64_t *n_interior, int64_t *n_shared, int64_t *n_dirichlet)
+{
+    std::string msg;
+    int rc = validate_mesh(mesh, degree, tile, msg);
+    if (rc) return fail(nullptr, rc, msg);
+    HostLayout L;
+    int nc[3] = {mesh->cells[0], mesh->cells[1], mesh->cells[2]};
+    int t[3] = {tile ? tile[0] : 0, tile ? tile[1] : 0, tile ? tile[2] : 0};
+    build_layout(nc, degree, t, mesh->bc, L);
+    if (perm) host_permutation(L, perm);
+    if (n_interior) *n_interior = L.nI;
+    if (n_shared) *n_shared = L.nF + L.nE + L.nV;
+    if (n_dirichlet) *n_dirichlet = L.nC;
+    return MFCG_OK;
+}
+
+int mfcg_setup(const mfcg_mesh *mesh, int32_t degree, const double *cell_coeff, const mfcg_options *opt,
+               void *hip_stream, mfcg_handle *out)
+{
+    if (!out) return fail(nullptr, MFCG_EINVAL, "out is NULL");
+    *out = nullptr;
+    std::string msg;
+    const int32_t *tile = opt ? opt->tile : nullptr;
+    int rc = validate_mesh(mesh, degree, tile, msg);
+    if (rc) return fail(nullptr, rc, msg);
+    if (opt && opt->n_q_1d != 0 && opt->n_q_1d != degree + 1)
+        return fail(nullptr, MFCG_EINVAL, "only n_q_1d = k+1 is supported");
+    if (opt && opt->check_every < 0) return fail(nullptr, MFCG_EINVAL, "check_every must be >= 0");
+    const int64_t ncell = (int64_t)mesh->cells[0] * mesh->cells[1] * mesh->cells[2];
+    if (cell_coeff) {
+        for (int64_t c = 0; c < ncell; ++c)
+            if (!(cell_coeff[c] > 0.0) || !std::isfinite(cell_coeff[c]))
+                return fail(nullptr, MFCG_EINVAL, "cell coefficients must be positive and finite");
+    }
+
+    mfcg_ctx *h = new (std::nothrow) mfcg_ctx();
+    if (!h) return fail(nullptr, MFCG_ENOMEM, "host allocation failed");
+    h->mesh = *mesh;
+    h->K = degree;
+    if (opt && opt->check_every > 0) h->check_every = opt->check_every;
+    hipStream_t s = (hipStream_t)hip_stream;
+
+    auto bail = [&](int code) {
+        g_last_error = h->err;
+        release(h);
+        delete h;
+        return code;
+    };
+#define SCHK(call)                                                                               \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess) {                                                                  \
+            h->err = std::string(#call) + ": " + hipGetErrorString(e_);                          \
+            return bail(e_ == hipErrorOutOfMemory ? MFCG_ENOMEM : MFCG_EHIP);                    \
+        }                                                                                        \
+    } while (0)
+
+    SCHK(hipGetDevice(&h->device));
+    int nc[3] = {mesh->cells[0], mesh->cells[1], mesh->cells[2]};
+    int t[3] = {tile ? tile[0] : 0, tile ? tile[1] : 0, tile ? tile[2] : 0};
+    build_layout(nc, degree, t, mesh->bc, h->hl);
+    build_tables(degree, h->tab);
+    tables_to_float(h->tab, h->tab32);
+    HostLayout &L = h->hl;
+
+    SCHK(dalloc(&h->d_ent_base, L.ent_base.size()));
+    SCHK(dalloc(&h->d_tile_ent, L.tile_ent.size()));
+    SCHK(dalloc(&h->d_tiles, L.tiles.size()));
+    SCHK(hipMemcpyAsync(h->d_ent_base, L.ent_base.data(), sizeof(int64_t) * L.ent_base.size(),
+                        hipMemcpyHostToDevice, s));
+    SCHK(hipMemcpyAsync(h->d_tile_ent, L.tile_ent.data(), sizeof(EntityRef) * L.tile_ent.size(),
+                        hipMemcpyHostToDevice, s));
+    SCHK(hipMemcpyAsync(h->d_tiles, L.tiles.data(), sizeof(TileDesc) * L.tiles.size(), hipMemcpyHostToDevice, s));
+    if (cell_coeff) {
+        SCHK(dalloc(&h->d_coeff, ncell));
+        SCHK(hipMemcpyAsync(h->d_coeff, cell_coeff, sizeof(double) * ncell, hipMemcpyHostToDevice, s));
+    }
+
+    LayoutView &lv = h->lv;
+    for (int d = 0; d < 3; ++d) lv.d[d] = L.d[d];
+    lv.n = L.n;
+    lv.nI = L.nI;
+    lv.nF = L.nF;
+    lv.nE = L.nE;
+    lv.nV = L.nV;
+    lv.nC = L.nC;
+    lv.offF = L.offF;
+    lv.offE = L.offE;
+    lv.offV = L.offV;
+    lv.offC = L.offC;
+    lv.partF = L.partF;
+    lv.partE = L.partE;
+    lv.partV = L.partV;
+    lv.ntiles = L.ntiles;
+    lv.ent_base = h->d_ent_base;
+    lv.tile_ent = h->d_tile_ent;
+    lv.tiles = h->d_tiles;
+
+    const int64_t nS = L.n - L.offF;
+    h->nshared_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (nS + 4 * 256 - 1) / (4 * 256)));
+    h->nsum_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (L.n + 1023) / 1024));
+
+    SCHK(dalloc(&h->G, L.g_elems));
+    SCHK(dalloc(&h->dinv, L.n));
+    SCHK(dalloc(&h->diag_lex, L.n));
+    SCHK(dalloc(&h->r, L.n));
+    SCHK(dalloc(&h->p, L.n));
+    SCHK(dalloc(&h->v, L.n));
+    SCHK(dalloc(&h->x, L.n));
+    SCHK(dalloc(&h->vin, L.n));
+    SCHK(dalloc(&h->vout, L.n));
+    SCHK(dalloc(&h->part, L.npart));
+    SCHK(dalloc(&h->dots, 8 * (L.ntiles + h->nshared_blocks)));
+    SCHK(dalloc(&h->sums, h->nsum_blocks));
+    SCHK(dalloc(&h->st, 1));
+    h->hist_cap = 1024;
+    SCHK(dalloc(&h->hist, h->hist_cap + 1));
+    /* slots of shared nodes that no tile owns (domain boundary without
+     * Dirichlet condition) must read as zero */
+    SCHK(hipMemsetAsync(h->part, 0, sizeof(double) * std::max<int64_t>(1, L.npart), s));
+    SCHK(hipMemsetAsync(h->st, 0, sizeof(CGState), s));
+
+    GeomArgs g{};
+    g.L = lv;
+    g.tab = h->tab;
+    g.K = degree;
+    g.map_kind = mesh->map_kind;
+    g.amp = mesh->map_kind == MFCG_MAP_AFFINE ? 0.0 : mesh->map_amplitude;
+    g.bc = mesh->bc;
+    g.coeff = h->d_coeff;
+    SCHK(launch_geometry(g, h->G, s));
+    SCHK(launch_diagonal(g, h->G, h->diag_lex, h->dinv, s));
+    SCHK(hipStreamSynchronize(s));
+#undef SCHK
+    *out = h;
+    return MFCG_OK;
+}
+
+int mfcg_destroy(mfcg_handle h)
+{
+    if (!h) return MFCG_OK;
+    (void)hipDeviceSynchronize();
+    release(h);
+    delete h;
+    return MFCG_OK;
+}
+
+int mfcg_n_dofs(mfcg_handle h, int64_t *n)
+{
+    if (!h || !n) return fail(h, MFCG_EINVAL, "null argument");
+    *n = h->hl.n;
+    return MFCG_OK;
+}
+
+int mfcg_layout_info(mfcg_handle h, int32_t *tile, int64_t *n_interior, int64_t *n_shared, int64_t *n_dirichlet,
+                     int64_t *n_tiles, int64_t *geometry_bytes)
+{
+    if (!h) return fail(h, MFCG_EINVAL, "null handle");
+    if (tile)
+        for (int d = 0; d < 3; ++d) tile[d] = h->hl.d[d].T;
+    if (n_interior) *n_interior = h->hl.nI;
+    if (n_shared) *n_shared = h->hl.nF + h->hl.nE + h->hl.nV;
+    if (n_dirichlet) *n_dirichlet = h->hl.nC;
+    if (n_tiles) *n_tiles = h->hl.ntiles;
+    if (geometry_bytes) *geometry_bytes = h->hl.g_elems * (int64_t)sizeof(double);
+    return MFCG_OK;
+}
+
+int mfcg_vmult(mfcg_handle h, double *dst, const double *src, void *hip_stream)
+{
+    if (!h || !dst || !src) return fail(h, MFCG_EINVAL, "null argument");
+    if (dst == src) return fail(h, MFCG_EINVAL, "dst and src must differ");
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIPCHK(h, launch_lex_to_int<double>(h->lv, src, h->vin, s));
+    int rc = vmult_internal(h, h->vin, h->vout, s);
+    if (rc) return rc;
+    HIPCHK(h, launch_int_to_lex<double>(h->lv, h->vout, dst, s));
+    return MFCG_OK;
+}
+
+int mfcg_diagonal(mfcg_handle h, double *diag, void *hip_stream)
+{
+    if (!h || !diag) return fail(h, MFCG_EINVAL, "null argument");
+    HIPCHK(h, hipMemcpyAsync(diag, h->diag_lex, sizeof(double) * h->hl.n, hipMemcpyDeviceToDevice,
+                             (hipStream_t)hip_stream));
+    return MFCG_OK;
+}
+
+int mfcg_assemble_rhs(mfcg_handle h, int32_t kind, const double *params, double *b, void *hip_stream)
+{
+    if (!h || !b) return fail(h, MFCG_EINVAL, "null argument");
+    if (kind != MFCG_RHS_SINE && kind != MFCG_RHS_BUMPS) return fail(h, MFCG_EINVAL, "unknown rhs kind");
+    int np = 0;
+    if (kind == MFCG_RHS_BUMPS) {
+        if (!params) return fail(h, MFCG_EINVAL, "bump parameters missing");
+        const int nb = (int)params[0];
+        if (!(params[0] >= 0) || nb > 16 || (double)nb != params[0]) return fail(h, MFCG_EINVAL, "bad bump count");
+        np = 1 + 5 * nb;
+    }
+    GeomArgs g{};
+    g.L = h->lv;
+    g.tab = h->tab;
+    g.K = h->K;
+    g.map_kind = h->mesh.map_kind;
+    g.amp = h->mesh.map_kind == MFCG_MAP_AFFINE ? 0.0 : h->mesh.map_amplitude;
+    g.bc = h->mesh.bc;
+    g.coeff = h->d_coeff;
+    HIPCHK(h, launch_rhs(g, kind, params, np, b, (hipStream_t)hip_stream));
+    return MFCG_OK;
+}
+
+int mfcg_set_timing(mfcg_handle h, int32_t enable)
+{
+    if (!h) return fail(h, MFCG_EINVAL, "null handle");
+    h->timing = enable != 0;
+    for (auto &e : h->ev_fused) h->ev_pool.push_back(e);
+    for (auto &e : h->ev_shared) h->ev_pool.push_back(e);
+    h->ev_fused.clear();
+    h->ev_shared.clear();
+    return MFCG_OK;
+}
+
+static int get_events(mfcg_ctx *h, EventPair &e)
+{
+    if (!h->ev_pool.empty()) {
+        e = h->ev_pool.back();
+        h->ev_pool.pop_back();
+        return MFCG_OK;
+    }
+    HIPCHK(h, hipEventCreate(&e.a));
+    HIPCHK(h, hipEventCreate(&e.b));
+    return MFCG_OK;
+}
+
+int mfcg_get_timing(mfcg_handle h, double *fused_ms, int64_t *fused_launches, double *shared_ms,
+                    int64_t *shared_launches)
+{
+    if (!h) return fail(h, MFCG_EINVAL, "null handle");
+    double tf = 0.0, ts = 0.0;
+    for (auto &e : h->ev_fused) {
+        HIPCHK(h, hipEventSynchronize(e.b));
+        float ms = 0.0f;
+        HIPCHK(h, hipEventElapsedTime(&ms, e.a, e.b));
+        tf += ms;
+    }
+    for (auto &e : h->ev_shared) {
+        HIPCHK(h, hipEventSynchronize(e.b));
+        float ms = 0.0f;
+        HIPCHK(h, hipEventElapsedTime(&ms, e.a, e.b));
+        ts += ms;
+    }
+    if (fused_ms) *fused_ms = tf;
+    if (shared_ms) *shared_ms = ts;
+    if (fused_launches) *fused_launches = (int64_t)h->ev_fused.size();
+    if (shared_launches) *shared_launches = (int64_t)h->ev_shared.size();
+    return MFCG_OK;
+}
+
+int mfcg_cg_begin(mfcg_handle h, const double *b, const double *x0, double tol, int32_t maxit, void *hip_stream)
+{
+    if (!h || !b) return fail(h, MFCG_EINVAL, "null argument");
+    if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(h, MFCG_EINVAL, "tol must be finite and >= 0");
+    if (maxit < 1) return fail(h, MFCG_EINVAL, "maxit must be >= 1");
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (maxit > h->hist_cap) {
+        HIPCHK(h, hipStreamSynchronize(s));
+        HIPCHK(h, hipFree(h->hist));
+        h->hist = nullptr;
+        HIPCHK(h, dalloc(&h->hist, (size_t)maxit + 1));
+        h->hist_cap = maxit;
+    }
+    const int64_t n = h->hl.n;
+    /* r = b (internal order); x = x0 or 0 */
+    HIPCHK(h, launch_lex_to_int<double>(h->lv, b, h->r, s));
+    double bb = 0.0;
+    int rc = host_sumsq(h, h->r, nullptr, n, &bb, s);
+    if (rc) return rc;
+    h->bnorm = std::sqrt(bb);
+    h->zero_rhs = (bb == 0.0);
+    const bool use_x0 = x0 != nullptr && !h->zero_rhs;
+    if (use_x0) {
+        HIPCHK(h, launch_lex_to_int<double>(h->lv, x0, h->x, s));
+        rc = vmult_internal(h, h->x, h->v, s);
+        if (rc) return rc;
+    } else {
+        HIPCHK(h, hipMemsetAsync(h->x, 0, sizeof(double) * n, s));
+    }
+    HIPCHK(h, launch_init_cg(n, h->r, h->p, h->v, use_x0 ? 1 : 0, s));
+    double rr = 0.0;
+    rc = host_sumsq(h, h->r, nullptr, n, &rr, s);
+    if (rc) return rc;
+    CGState st{};
+    st.eps = tol * h->bnorm;
+    st.bnorm = h->bnorm;
+    st.r0norm = std::sqrt(rr);
+    st.maxit = maxit;
+    st.flag = (h->zero_rhs || st.r0norm < st.eps) ? FLAG_CONV : FLAG_RUN;
+    HIPCHK(h, hipMemcpyAsync(h->st, &st, sizeof(CGState), hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(h->hist, &st.r0norm, sizeof(double), hipMemcpyHostToDevice, s));
+    h->maxit = maxit;
+    h->launched = 0;
+    return MFCG_OK;
+}
+
+int mfcg_cg_iterate(mfcg_handle h, int32_t n_it, void *hip_stream)
+{
+    if (!h || n_it < 0) return fail(h, MFCG_EINVAL, "bad argument");
+    if (h->launched + n_it > h->maxit) return fail(h, MFCG_EINVAL, "iterations beyond maxit");
+    hipStream_t s = (hipStream_t)hip_stream;
+    IterArgs<double> a{};
+    a.L = h->lv;
+    a.tab = h->tab;
+    a.G = h->G;
+    a.dinv = h->dinv;
+    a.r = h->r;
+    a.p = h->p;
+    a.v = h->v;
+    a.x = h->x;
+    a.part = h->part;
+    a.dots = h->dots;
+    a.st = h->st;
+    a.hist = h->hist;
+    a.nshared_blocks = h->nshared_blocks;
+    for (int it = 0; it < n_it; ++it) {
+        EventPair e1{}, e2{};
+        if (h->timing) {
+            int rc = get_events(h, e1);
+            if (rc) return rc;
+            rc = get_events(h, e2);
+            if (rc) return rc;
+            HIPCHK(h, hipEventRecord(e1.a, s));
+        }
+        HIPCHK(h, launch_fused<double>(h->K, MODE_CG, a, s));
+        if (h->timing) {
+            HIPCHK(h, hipEventRecord(e1.b, s));
+            HIPCHK(h, hipEventRecord(e2.a, s));
+        }
+        HIPCHK(h, launch_shared<double>(MODE_CG, a, s));
+        if (h->timing) {
+            HIPCHK(h, hipEventRecord(e2.b, s));
+            h->ev_fused.push_back(e1);
+            h->ev_shared.push_back(e2);
+        }
+    }
+    h->launched += n_it;
+    return MFCG_OK;
+}
+
+static int read_state(mfcg_ctx *h, CGState &st, hipStream_t s)
+{
+    HIPCHK(h, hipMemcpyAsync(&st, h->st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    return MFCG_OK;
+}
+
+int mfcg_cg_end(mfcg_handle h, double *x, int32_t *iters, double *res_hist, void *hip_stream)
+{
+    if (!h || !x) return fail(h, MFCG_EINVAL, "null argument");
+    hipStream_t s = (hipStream_t)hip_stream;
+    CGState st{};
+    int rc = read_state(h, st, s);
+    if (rc) return rc;
+    if (h->zero_rhs) {
+        HIPCHK(h, hipMemsetAsync(x, 0, sizeof(double) * h->hl.n, s));
+        if (iters) *iters = 0;
+        if (res_hist) res_hist[0] = 0.0;
+        HIPCHK(h, hipStreamSynchronize(s));
+        return MFCG_OK;
+    }
+    HIPCHK(h, launch_reconstruct<double>(h->hl.n, h->x, h->p, h->r, h->dinv, h->st, s));
+    HIPCHK(h, launch_int_to_lex<double>(h->lv, h->x, x, s));
+    if (res_hist) HIPCHK(h, hipMemcpyAsync(res_hist, h->hist, sizeof(double) * (st.k + 1), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    if (iters) *iters = st.k;
+    if (st.flag == FLAG_CONV) return MFCG_OK;
+    if (st.flag == FLAG_BREAK) return fail(h, MFCG_EBREAKDOWN, "breakdown: p^T A p <= 0 or non-finite scalar");
+    return fail(h, MFCG_ENOTCONV, "maxit reached");
+}
+
+int mfcg_solve(mfcg_handle h, const double *b, double *x, double tol, int32_t maxit, int32_t *iters,
+               double *res_hist, double *true_rel_res, void *hip_stream)
+{
+    if (!h || !b || !x || !iters) return fail(h, MFCG_EINVAL, "null argument");
+    hipStream_t s = (hipStream_t)hip_stream;
+    int rc = mfcg_cg_begin(h, b, x, tol, maxit, hip_stream);
+    if (rc) return rc;
+    CGState st{};
+    rc = read_state(h, st, s);
+    if (rc) return rc;
+    while (st.flag == FLAG_RUN && h->launched < maxit) {
+        const int chunk = std::min(h->check_every, maxit - h->launched);
+        rc = mfcg_cg_iterate(h, chunk, hip_stream);
+        if (rc) return rc;
+        rc = read_state(h, st, s);
+        if (rc) return rc;
+    }
+    const int status = mfcg_cg_end(h, x, iters, res_hist, hip_stream);
+    if (status != MFCG_OK && status != MFCG_ENOTCONV && status != MFCG_EBREAKDOWN) return status;
+    if (true_rel_res) {
+        if (h->zero_rhs) {
+            *true_rel_res = 0.0;
+        } else {
+            HIPCHK(h, launch_lex_to_int<double>(h->lv, x, h->vin, s));
+            rc = vmult_internal(h, h->vin, h->vout, s);
+            if (rc) return rc;
+            HIPCHK(h, launch_int_to_lex<double>(h->lv, h->vout, h->vin, s));
+            double rr = 0.0;
+            rc = host_sumsq(h, b, h->vin, h->hl.n, &rr, s);
+            if (rc) return rc;
+            *true_rel_res = std::sqrt(rr) / h->bnorm;
+        }
+    }
+    return status;
+}
+
+}  // extern "C"

@@ -1,0 +1,65 @@
+/* kernels.h -- launch wrappers of the gfx950 kernels (host callable). */
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mfcg_internal.h"
+
+namespace mfcg {
+
+enum Mode : int { MODE_CG = 0, MODE_VMULT = 1 };
+
+/* Arguments of the fused tile kernel and the shared-node kernel. */
+template <typename T>
+struct IterArgs {
+    LayoutView L;
+    Tables<T> tab;
+    const T *G;     /* geometry tensor, tile-blocked */
+    const T *dinv;  /* inverse diagonal, internal order (1 on Dirichlet nodes) */
+    T *r, *p, *v, *x;
+    const T *src;   /* MODE_VMULT input */
+    T *dst;         /* MODE_VMULT output */
+    T *part;        /* shared-node partial sums */
+    T *dots;        /* per-block partial inner products, 8 per block */
+    CGState *st;
+    double *hist;
+    int32_t nshared_blocks;
+};
+
+/* Maximum tile extent in x and y (cells) compiled for degree K. */
+void tile_limits(int K, int *tx, int *ty);
+int fused_block_size(int K);
+
+template <typename T>
+hipError_t launch_fused(int K, int mode, const IterArgs<T> &a, hipStream_t s);
+template <typename T>
+hipError_t launch_shared(int mode, const IterArgs<T> &a, hipStream_t s);
+
+/* Setup kernels (FP64). */
+struct GeomArgs {
+    LayoutView L;
+    Tables<double> tab;
+    int32_t K, map_kind;
+    double amp;
+    int32_t bc;
+    const double *coeff; /* per cell, device */
+};
+hipError_t launch_geometry(const GeomArgs &g, double *G, hipStream_t s);
+hipError_t launch_diagonal(const GeomArgs &g, const double *G, double *diag_lex, double *dinv_int, hipStream_t s);
+hipError_t launch_rhs(const GeomArgs &g, int kind, const double *params, int nparams, double *b_lex, hipStream_t s);
+
+/* Vector utilities. */
+template <typename T>
+hipError_t launch_lex_to_int(const LayoutView &L, const double *in_lex, T *out_int, hipStream_t s);
+template <typename T>
+hipError_t launch_int_to_lex(const LayoutView &L, const T *in_int, double *out_lex, hipStream_t s);
+/* r = r - v (use_v), p = 0, v = 0 */
+hipError_t launch_init_cg(int64_t n, double *r, double *p, double *v, int use_v, hipStream_t s);
+template <typename T>
+hipError_t launch_reconstruct(int64_t n, T *x, const T *p, const T *r, const T *dinv, const CGState *st,
+                              hipStream_t s);
+/* part[0..nb) = block sums of (a_i - c_i)^2 (c may be NULL); the caller adds them in order */
+hipError_t launch_sumsq(int64_t n, const double *a, const double *c, double *part, int nb, hipStream_t s);
+hipError_t launch_convert(int64_t n, const double *in, float *out, hipStream_t s);
+
+}  // namespace mfcg

@@ -1,0 +1,788 @@
+/*
+ * kernels_cg.hip -- the per-iteration kernels of the fused Jacobi-PCG
+ * (Algorithm 5 of Kronbichler, Sashko, Munch, with the vector updates and
+ * inner products embedded in the cell loop of the matrix-free operator,
+ * Sec. 5), written for gfx950 (wave64, 160 KB LDS per CU).
+ *
+ * One iteration k is two launches:
+ *
+ *  fused_tile_kernel   one workgroup per tile of TX x TY x TZ cells,
+ *                      streaming the tile's cell layers along z:
+ *     pre   (Alg. 5 "pre" region) on the node planes a layer touches first:
+ *           r_k = r_{k-1} - alpha_{k-1} v_{k-1},
+ *           p_k = D^{-1} r_k + beta_{k-1} p_{k-1},
+ *           x_k = x_{k-2} + alpha_{k-1} p_{k-1}
+ *                 + alpha_{k-2}/beta_{k-2} (p_{k-1} - D^{-1} r_{k-1})  (odd k > 1),
+ *           written back for tile-interior nodes; recomputed (not written)
+ *           for nodes shared with other tiles; p_k staged in an LDS window
+ *           of k+1 node planes.
+ *     cell  Eq. 5 by sum factorisation: gather from the window, 1D
+ *           interpolations to the Gauss points and collocation derivatives
+ *           (Sec. 2, sum factorisation), G_q = a w det J J^{-1} J^{-T}
+ *           applied per quadrature point, transposed contractions.  Each
+ *           thread owns one 1D line of a cell per pass; lines of other
+ *           directions are exchanged through LDS.
+ *     sum   v = sum of the cell contributions (Eq. 4), in a fixed order.
+ *     post  (Alg. 5 "post" region) after the last contribution to a node
+ *           (Sec. 5.1): the seven partial sums gamma, a, b, c, d, e, f for
+ *           tile-interior nodes, v written once; nodes shared with other
+ *           tiles get this tile's partial sum in `part`.
+ *
+ *  shared_node_kernel  grid-stride over shared and Dirichlet nodes: adds the
+ *                      partial sums in a fixed slot order, applies pre and
+ *                      post there, and the last block to arrive (atomic
+ *                      ticket) reduces all per-block sums in a fixed order
+ *                      and computes alpha_k, beta_k and the convergence test
+ *                      on the device (single-pass finish).
+ *
+ * Every reduction and every summation of partial contributions runs in a
+ * fixed order, so a solve is bitwise reproducible.
+ */
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace mfcg {
+
+/* ------------------------------------------------------------------ */
+/* Per-degree configuration (compile time)                             */
+/* ------------------------------------------------------------------ */
+
+template <int K>
+struct Cfg;
+template <> struct Cfg<1> { static constexpr int TX = 8, TY = 8, WG = 256; };
+template <> struct Cfg<2> { static constexpr int TX = 8, TY = 8, WG = 576; };
+template <> struct Cfg<3> { static constexpr int TX = 5, TY = 5, WG = 448; };
+template <> struct Cfg<4> { static constexpr int TX = 4, TY = 4, WG = 448; };
+template <> struct Cfg<5> { static constexpr int TX = 3, TY = 3, WG = 384; };
+template <> struct Cfg<6> { static constexpr int TX = 2, TY = 2, WG = 256; };
+template <> struct Cfg<7> { static constexpr int TX = 2, TY = 2, WG = 256; };
+template <> struct Cfg<8> { static constexpr int TX = 2, TY = 2, WG = 384; };
+
+void tile_limits(int K, int *tx, int *ty)
+{
+    static const int t[9] = {0, 8, 8, 5, 4, 3, 2, 2, 2};
+    *tx = *ty = (K >= 1 && K <= 8) ? t[K] : 0;
+}
+
+int fused_block_size(int K)
+{
+    static const int w[9] = {0, 256, 576, 448, 448, 384, 256, 256, 384};
+    return (K >= 1 && K <= 8) ? w[K] : 0;
+}
+
+constexpr int SHARED_WG = 256;
+
+/* ------------------------------------------------------------------ */
+/* Helpers                                                             */
+/* ------------------------------------------------------------------ */
+
+/* Workgroups are dispatched round-robin over the 8 XCDs (separate L2s).
+ * Map consecutive blocks of one XCD to consecutive tiles so that tiles
+ * sharing faces mostly run under the same L2. */
+__device__ inline int64_t xcd_remap(int64_t b, int64_t nb)
+{
+    const int64_t X = 8;
+    const int64_t q = nb / X, r = nb % X;
+    const int64_t x = b % X, i = b / X;
+    return x * q + (x < r ? x : r) + i;
+}
+
+/* The "pre" update of one entry, shared by both kernels so that the value
+ * a tile recomputes for a shared node is bitwise the value the shared-node
+ * kernel stores. */
+template <typename T>
+__device__ __forceinline__ void pre_update(T r, T v, T p, T dinv, T alpha, T beta, T &rn, T &pn)
+{
+    rn = fma(-alpha, v, r);
+    pn = fma(dinv, rn, beta * p);
+}
+
+template <typename T>
+__device__ __forceinline__ T x_update(T x, T r, T p, T dinv, T alpha, T ratio)
+{
+    return fma(ratio, fma(-dinv, r, p), fma(alpha, p, x));
+}
+
+/* Deterministic reduction of NV values over a block into out[0..NV). */
+template <typename T, int NV, int WG>
+__device__ __forceinline__ void block_reduce(T (&acc)[NV], T *red, T *out)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+        T s = acc[c];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        if (lane == 0) red[wave * NV + c] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        T s = 0;
+        for (int w = 0; w < WG / 64; ++w) s += red[w * NV + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Fused tile kernel                                                   */
+/* ------------------------------------------------------------------ */
+
+template <int K, typename T, int MODE>
+__global__ __launch_bounds__(Cfg<K>::WG) void fused_tile_kernel(const IterArgs<T> a)
+{
+    constexpr int n = K + 1, n2 = n * n, n3 = n * n * n;
+    constexpr int WG = Cfg<K>::WG;
+    constexpr int NLC = Cfg<K>::TX * Cfg<K>::TY;
+    constexpr int R = (NLC * n2 + WG - 1) / WG;
+    constexpr int PNM = (Cfg<K>::TX * K + 1) * (Cfg<K>::TY * K + 1);
+    constexpr int NS = (K * PNM + WG - 1) / WG;
+    constexpr int NC = (PNM + WG - 1) / WG;
+
+    __shared__ T win[(K + 1) * PNM];
+    __shared__ T TA[NLC * n3];
+    __shared__ T TB[NLC * n3];
+    __shared__ T cv[2 * PNM];
+    __shared__ T cr[PNM];
+    __shared__ T cd[PNM];
+    __shared__ T red[8 * (WG / 64)];
+    __shared__ EntityRef ent[27];
+
+    const int tid = threadIdx.x;
+    if (MODE == MODE_CG && a.st->flag != FLAG_RUN) return;
+
+    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
+    const TileDesc td = a.L.tiles[tile];
+    if (tid < 27) ent[tid] = a.L.tile_ent[tile * 27 + tid];
+
+    T alpha = 0, beta = 0, ratio = 0;
+    bool xupd = false;
+    if (MODE == MODE_CG) {
+        alpha = (T)a.st->alpha;
+        beta = (T)a.st->beta;
+        ratio = (T)a.st->ratio;
+        const int kk = a.st->k + 1;
+        xupd = (kk > 1) && (kk & 1);
+    }
+
+    const int TXa = td.nc[0], TYa = td.nc[1], TZa = td.nc[2];
+    const int EX = TXa * K, EY = TYa * K, EZ = TZa * K;
+    const int PW = EX + 1;
+    const int PN = (EX + 1) * (EY + 1);
+    const int nlines = TXa * TYa * n2;
+    const int64_t glayer = 6LL * TXa * TYa * n3;
+    const int gq = TXa * TYa * n2; /* stride of the y-index in a layer's component block */
+    __syncthreads();
+
+    T acc[7];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) acc[c] = 0;
+    T rs[NS], ds[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) rs[s] = ds[s] = 0;
+
+    /* global index, kind and partial slot of the tile-local node (ax, by, zz) */
+    auto locate = [&](int ax, int by, int zz, int64_t &idx, int &kind, int64_t &pidx) {
+        const int dx = ax == 0 ? 0 : (ax == EX ? 2 : 1);
+        const int dy = by == 0 ? 0 : (by == EY ? 2 : 1);
+        const int dz = zz == 0 ? 0 : (zz == EZ ? 2 : 1);
+        const int lx = dx == 1 ? ax - 1 : 0, sx = dx == 1 ? EX - 1 : 1;
+        const int ly = dy == 1 ? by - 1 : 0, sy = dy == 1 ? EY - 1 : 1;
+        const int lz = dz == 1 ? zz - 1 : 0;
+        const EntityRef &e = ent[dx + 3 * dy + 9 * dz];
+        const int64_t loc = lx + (int64_t)sx * (ly + (int64_t)sy * lz);
+        idx = e.vbase + loc;
+        kind = e.kind;
+        pidx = e.pbase + loc;
+    };
+
+    /* pre on one node: returns p_k (0 on Dirichlet nodes), r_k and D^{-1} */
+    auto pre_node = [&](int ax, int by, int zz, T &pn, T &rn, T &dv) {
+        int64_t idx, pidx;
+        int kind;
+        locate(ax, by, zz, idx, kind, pidx);
+        pn = 0;
+        rn = 0;
+        dv = 0;
+        if (kind == KIND_C) return;
+        if (MODE == MODE_VMULT) {
+            pn = a.src[idx];
+            return;
+        }
+        const T r0 = a.r[idx], v0 = a.v[idx], p0 = a.p[idx];
+        dv = a.dinv[idx];
+        pre_update(r0, v0, p0, dv, alpha, beta, rn, pn);
+        if (kind == KIND_I) {
+            a.r[idx] = rn;
+            a.p[idx] = pn;
+            if (xupd) a.x[idx] = x_update(a.x[idx], r0, p0, dv, alpha, ratio);
+        }
+    };
+
+    /* v of the layer node (ax, by, zl) summed over the layer's cells */
+    auto sum_cells = [&](int ax, int by, int zl) -> T {
+        const int cxa = ax / K, cya = by / K;
+        const bool bx = (ax % K) == 0, byy = (by % K) == 0;
+        T s = 0;
+#pragma unroll 1
+        for (int oy = 1; oy >= 0; --oy) {
+            const int cy = cya - oy;
+            if (oy == 1 && !byy) continue;
+            if (cy < 0 || cy >= TYa) continue;
+#pragma unroll 1
+            for (int ox = 1; ox >= 0; --ox) {
+                const int cx = cxa - ox;
+                if (ox == 1 && !bx) continue;
+                if (cx < 0 || cx >= TXa) continue;
+                s += TB[(cx + TXa * cy) * n3 + (ax - cx * K) + n * (by - cy * K) + n2 * zl];
+            }
+        }
+        return s;
+    };
+
+    auto post_node = [&](int ax, int by, int zz, int slot, T v, T rn, T dv) {
+        int64_t idx, pidx;
+        int kind;
+        locate(ax, by, zz, idx, kind, pidx);
+        if (kind == KIND_S) {
+            a.part[pidx] = v;
+        } else if (kind == KIND_I) {
+            if (MODE == MODE_VMULT) {
+                a.dst[idx] = v;
+            } else {
+                const T pn = win[slot * PNM + ax + PW * by];
+                const T zr = dv * rn, zv = dv * v;
+                acc[0] += rn * rn;
+                acc[1] += pn * v;
+                acc[2] += rn * v;
+                acc[3] += v * v;
+                acc[4] += rn * zr;
+                acc[5] += rn * zv;
+                acc[6] += v * zv;
+                a.v[idx] = v;
+            }
+        }
+    };
+
+    /* bottom plane of the tile: pre with the plane mapping, r and D^{-1}
+     * kept in the carry arrays */
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const int node = tid + WG * c;
+        if (node < PN) {
+            T pn, rn, dv;
+            pre_node(node % PW, node / PW, 0, pn, rn, dv);
+            win[node] = pn;
+            cr[node] = rn;
+            cd[node] = dv;
+        }
+    }
+
+#pragma unroll 1
+    for (int L = 0; L < TZa; ++L) {
+        const int s0 = (L * K) % (K + 1);
+        /* ---- pre on the planes first touched by this layer ---- */
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int f = tid + WG * s;
+            if (f < K * PN) {
+                const int zl = 1 + f / PN, node = f % PN;
+                int slot = s0 + zl;
+                if (slot > K) slot -= K + 1;
+                T pn, rn, dv;
+                pre_node(node % PW, node / PW, L * K + zl, pn, rn, dv);
+                win[slot * PNM + node] = pn;
+                rs[s] = rn;
+                ds[s] = dv;
+            }
+        }
+        __syncthreads();
+
+        const T *Gl = a.G + td.gbase + (int64_t)L * glayer;
+        T gy[R][n], wy[R][n], wz[R][n];
+
+        /* F1 [z-lines]: gather p from the window, interpolate along z */
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            const int l = tid + WG * rr;
+            if (l < nlines) {
+                const int c = l / n2, rem = l % n2, i = rem % n, j = rem / n;
+                const int cx = c % TXa, cy = c / TXa;
+                const int nodexy = cx * K + i + PW * (cy * K + j);
+                T u[n];
+#pragma unroll
+                for (int z = 0; z < n; ++z) {
+                    int slot = s0 + z;
+                    if (slot > K) slot -= K + 1;
+                    u[z] = win[slot * PNM + nodexy];
+                }
+#pragma unroll
+                for (int q = 0; q < n; ++q) {
+                    T t = 0;
+#pragma unroll
+                    for (int z = 0; z < n; ++z) t = fma(a.tab.S[q * n + z], u[z], t);
+                    TA[c * n3 + rem + n2 * q] = t;
+                }
+            }
+        }
+        __syncthreads();
+        /* F2 [x-lines]: interpolate along x */
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            const int l = tid + WG * rr;
+            if (l < nlines) {
+                const int c = l / n2, rem = l % n2;
+                const int base = c * n3 + n * rem;
+                T u[n];
+#pragma unroll
+                for (int i = 0; i < n; ++i) u[i] = TA[base + i];
+#pragma unroll
+                for (int q = 0; q < n; ++q) {
+                    T t = 0;
+#pragma unroll
+                    for (int i = 0; i < n; ++i) t = fma(a.tab.S[q * n + i], u[i], t);
+                    TB[base + q] = t;
+                }
+            }
+        }
+        __syncthreads();
+        /* F3 [y-lines]: interpolate along y -> values at the Gauss points,
+         * y derivative kept in registers */
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            const int l = tid + WG * rr;
+            if (l < nlines) {
+                const int c = l / n2, rem = l % n2, i = rem % n, z = rem / n;
+                const int base = c * n3 + i + n2 * z;
+                T u[n], uq[n];
+#pragma unroll
+                for (int j = 0; j < n; ++j) u[j] = TB[base + n * j];
+#pragma unroll
+                for (int q = 0; q < n; ++q) {
+                    T t = 0;
+#pragma unroll
+                    for (int j = 0; j < n; ++j) t = fma(a.tab.S[q * n + j], u[j], t);
+                    uq[q] = t;
+                    TA[base + n * q] = t;
+                }
+#pragma unroll
+                for (int q = 0; q < n; ++q) {
+                    T t = 0;
+#pragma unroll
+                    for (int m = 0; m < n; ++m) t = fma(a.tab.D[q * n + m], uq[m], t);
+                    gy[rr][q] = t;
+                }
+            }
+        }
+        __syncthreads();
+        /* F4 [x-lines]: x derivative */
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            const int l = tid + WG * rr;
+            if (l < nlines) {
+                const int c = l / n2, rem = l % n2;
+                const int base = c * n3 + n * rem;
+                T u[n];
+#pragma unroll
+                for (int i = 0; i < n; ++i) u[i] = TA[base + i];
+#pragma unroll
+                for (int q = 0; q < n; ++q) {
+                    T t = 0;
+#pragma unroll
+                    for (int m = 0; m < n; ++m) t = fma(a.tab.D[q * n + m], u[m], t);
+                    TB[base + q] = t;
+                }
+            }
+        }
+        __syncthreads();
+        /* F5 [z-lines]: z derivative, in place */
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            const int l = tid + WG * rr;
+            if (l < nlines) {
+                const int c = l / n2, rem = l % n2;
+                const int base = c * n3 + rem;
+                T u[n];
+#pragma unroll
+                for (int z = 0; z < n; ++z) u[z] = TA[base + n2 * z];
+#pragma unroll
+                for (int q = 0; q < n; ++q) {
+                    T t = 0;
+#pragma unroll
+                    for (int m = 0; m < n; ++m) t = fma(a.tab.D[q * n + m], u[m], t);
+                    TA[base + n2 * q] = t;
+                }
+            }
+        }
+        __syncthreads();
+        /* G [y-lines]: flux = G_q grad u at each Gauss point; y part of the
+         * transposed derivative in registers */
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            const int l = tid + WG * rr;
+            if (l < nlines) {
+                const int c = l / n2, rem = l % n2, i = rem % n, z = rem / n;
+                const int base = c * n3 + i + n2 * z;
+                T fy[n];
+#pragma unroll
+                for (int j = 0; j < n; ++j) {
+                    const T *g = Gl + j * gq + l;
+                    const T g00 = g[0], g11 = g[(int64_t)n3 * TXa * TYa], g22 = g[2LL * n3 * TXa * TYa];
+                    const T g01 = g[3LL * n3 * TXa * TYa], g02 = g[4LL * n3 * TXa * TYa],
+                            g12 = g[5LL * n3 * TXa * TYa];
+                    const T ux = TB[base + n * j], uy = gy[rr][j], uz = TA[base + n * j];
+                    const T fx = g00 * ux + g01 * uy + g02 * uz;
+                    fy[j] = g01 * ux + g11 * uy + g12 * uz;
+                    const T fz = g02 * ux + g12 * uy + g22 * uz;
+                    TB[base + n * j] = fx;
+                    TA[base + n * j] = fz;
+                }
+#pragma unroll
+                for (int m = 0; m < n; ++m) {
+                    T t = 0;
+#pragma unroll
+                    for (int q = 0; q < n; ++q) t = fma(a.tab.D[q * n + m], fy[q], t);
+                    wy[rr][m] = t;
+                }
+            }
+        }
+        __syncthreads();
+        /* B2 [x-lines]: transposed x derivative, in place; B3 [z-lines]:
+         * transposed z derivative into registers */
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            const int l = tid + WG * rr;
+            if (l < nlines) {
+                const int c = l / n2, rem = l % n2;
+                {
+                    const int base = c * n3 + n * rem;
+                    T f[n];
+#pragma unroll
+                    for (int q = 0; q < n; ++q) f[q] = TB[base + q];
+#pragma unroll
+                    for (int m = 0; m < n; ++m) {
+                        T t = 0;
+#pragma unroll
+                        for (int q = 0; q < n; ++q) t = fma(a.tab.D[q * n + m], f[q], t);
+                        TB[base + m] = t;
+                    }
+                }
+                {
+                    const int base = c * n3 + rem;
+                    T f[n];
+#pragma unroll
+                    for (int q = 0; q < n; ++q) f[q] = TA[base + n2 * q];
+#pragma unroll
+                    for (int m = 0; m < n; ++m) {
+                        T t = 0;
+#pragma unroll
+                        for (int q = 0; q < n; ++q) t = fma(a.tab.D[q * n + m], f[q], t);
+                        wz[rr][m] = t;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        /* B4 [y-lines]: add the y part */
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            const int l = tid + WG * rr;
+            if (l < nlines) {
+                const int c = l / n2, rem = l % n2, i = rem % n, z = rem / n;
+                const int base = c * n3 + i + n2 * z;
+#pragma unroll
+                for (int j = 0; j < n; ++j) TB[base + n * j] += wy[rr][j];
+            }
+        }
+        __syncthreads();
+        /* B5 [z-lines]: add the z part, transposed interpolation along z */
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            const int l = tid + WG * rr;
+            if (l < nlines) {
+                const int c = l / n2, rem = l % n2;
+                const int base = c * n3 + rem;
+                T w[n];
+#pragma unroll
+                for (int q = 0; q < n; ++q) w[q] = TB[base + n2 * q] + wz[rr][q];
+#pragma unroll
+                for (int z = 0; z < n; ++z) {
+                    T t = 0;
+#pragma unroll
+                    for (int q = 0; q < n; ++q) t = fma(a.tab.S[q * n + z], w[q], t);
+                    TB[base + n2 * z] = t;
+                }
+            }
+        }
+        __syncthreads();
+        /* B6 [x-lines]: transposed interpolation along x */
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            const int l = tid + WG * rr;
+            if (l < nlines) {
+                const int c = l / n2, rem = l % n2;
+                const int base = c * n3 + n * rem;
+                T w[n];
+#pragma unroll
+                for (int q = 0; q < n; ++q) w[q] = TB[base + q];
+#pragma unroll
+                for (int i = 0; i < n; ++i) {
+                    T t = 0;
+#pragma unroll
+                    for (int q = 0; q < n; ++q) t = fma(a.tab.S[q * n + i], w[q], t);
+                    TB[base + i] = t;
+                }
+            }
+        }
+        __syncthreads();
+        /* B7 [y-lines]: transposed interpolation along y -> cell vectors */
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            const int l = tid + WG * rr;
+            if (l < nlines) {
+                const int c = l / n2, rem = l % n2, i = rem % n, z = rem / n;
+                const int base = c * n3 + i + n2 * z;
+                T w[n];
+#pragma unroll
+                for (int q = 0; q < n; ++q) w[q] = TB[base + n * q];
+#pragma unroll
+                for (int j = 0; j < n; ++j) {
+                    T t = 0;
+#pragma unroll
+                    for (int q = 0; q < n; ++q) t = fma(a.tab.S[q * n + j], w[q], t);
+                    TB[base + n * j] = t;
+                }
+            }
+        }
+        __syncthreads();
+
+        /* ---- sum over cells and post ---- */
+        /* plane z = 0 of the layer: plane mapping, r and D^{-1} from the carry */
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int node = tid + WG * c;
+            if (node < PN) {
+                const int ax = node % PW, by = node / PW;
+                T v = sum_cells(ax, by, 0);
+                if (L > 0) v = cv[(L & 1) * PNM + node] + v;
+                post_node(ax, by, L * K, s0, v, cr[node], cd[node]);
+            }
+        }
+        /* planes z = 1..K: same mapping as the pre of this layer */
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int f = tid + WG * s;
+            if (f < K * PN) {
+                const int zl = 1 + f / PN, node = f % PN;
+                const int ax = node % PW, by = node / PW;
+                const T v = sum_cells(ax, by, zl);
+                if (zl == K && L + 1 < TZa) {
+                    cv[((L + 1) & 1) * PNM + node] = v;
+                } else {
+                    int slot = s0 + zl;
+                    if (slot > K) slot -= K + 1;
+                    post_node(ax, by, L * K + zl, slot, v, rs[s], ds[s]);
+                }
+            }
+        }
+        __syncthreads();
+        /* r and D^{-1} of the shared top plane move to the carry */
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int f = tid + WG * s;
+            if (f < K * PN && f / PN == K - 1) {
+                const int node = f % PN;
+                cr[node] = rs[s];
+                cd[node] = ds[s];
+            }
+        }
+        /* the next layer's pre only writes window slots of planes that are
+         * no longer read; the carry arrays are read after its barrier */
+    }
+
+    if (MODE == MODE_CG) {
+        __syncthreads();
+        block_reduce<T, 7, WG>(acc, red, a.dots + tile * 8);
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Shared-node kernel with the single-pass finish                      */
+/* ------------------------------------------------------------------ */
+
+template <typename T>
+__device__ void finish_iteration(const IterArgs<T> &a, int64_t nparts, T *red)
+{
+    /* fixed-order sums of the 7 inner products over all per-block partials */
+    T acc[7];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) acc[c] = 0;
+    for (int64_t b = threadIdx.x; b < nparts; b += SHARED_WG) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) acc[c] += a.dots[b * 8 + c];
+    }
+    __shared__ T tot[8];
+    block_reduce<T, 7, SHARED_WG>(acc, red, tot);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        CGState *st = a.st;
+        const T gam = tot[0], pa = tot[1], rb = tot[2], vc = tot[3], dd = tot[4], ee = tot[5], ff = tot[6];
+        const int k = st->k + 1;
+        const T prev_ratio = st->beta != 0.0 ? (T)(st->alpha / st->beta) : (T)0;
+        const bool bad = !(pa > 0) || !isfinite(pa) || !isfinite(gam) || !isfinite(dd) || !isfinite(vc);
+        if (bad) {
+            st->flag = FLAG_BREAK;
+            st->xa = 0.0;
+            st->xratio = (double)prev_ratio;
+            st->k = k;
+            return;
+        }
+        const T alpha = dd / pa;
+        T rho2 = gam - 2 * alpha * rb + alpha * alpha * vc;
+        const T rho = sqrt(rho2 > 0 ? rho2 : (T)0);
+        a.hist[k] = (double)rho;
+        st->xa = (double)alpha;
+        st->xratio = (double)prev_ratio;
+        if ((double)rho < st->eps) {
+            st->flag = FLAG_CONV;
+        } else {
+            const T beta = (dd - 2 * alpha * ee + alpha * alpha * ff) / dd;
+            if (!(beta != 0) || !isfinite(beta)) {
+                st->flag = (beta == 0) ? FLAG_CONV : FLAG_BREAK;
+            } else {
+                st->ratio = (double)prev_ratio;
+                st->alpha = (double)alpha;
+                st->beta = (double)beta;
+            }
+        }
+        st->k = k;
+    }
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(SHARED_WG) void shared_node_kernel(const IterArgs<T> a)
+{
+    __shared__ T red[8 * (SHARED_WG / 64)];
+    __shared__ int last;
+    if (MODE == MODE_CG && a.st->flag != FLAG_RUN) return;
+    const LayoutView &L = a.L;
+
+    T alpha = 0, beta = 0, ratio = 0;
+    bool xupd = false;
+    if (MODE == MODE_CG) {
+        alpha = (T)a.st->alpha;
+        beta = (T)a.st->beta;
+        ratio = (T)a.st->ratio;
+        const int kk = a.st->k + 1;
+        xupd = (kk > 1) && (kk & 1);
+    }
+    T acc[7];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) acc[c] = 0;
+
+    const int64_t stride = (int64_t)gridDim.x * SHARED_WG;
+    for (int64_t i = L.offF + (int64_t)blockIdx.x * SHARED_WG + threadIdx.x; i < L.n; i += stride) {
+        T v = 0;
+        bool cons = false;
+        if (i < L.offE) {
+            const int64_t j = i - L.offF;
+            v = a.part[L.partF + j] + a.part[L.partF + L.nF + j];
+        } else if (i < L.offV) {
+            const int64_t j = i - L.offE;
+            const T *q = a.part + L.partE + j;
+            v = ((q[0] + q[L.nE]) + q[2 * L.nE]) + q[3 * L.nE];
+        } else if (i < L.offC) {
+            const int64_t j = i - L.offV;
+            const T *q = a.part + L.partV + j;
+            v = q[0];
+#pragma unroll
+            for (int s = 1; s < 8; ++s) v += q[s * L.nV];
+        } else {
+            cons = true;
+        }
+        if (MODE == MODE_VMULT) {
+            a.dst[i] = cons ? a.src[i] : v;
+            continue;
+        }
+        const T r0 = a.r[i], v0 = a.v[i], p0 = a.p[i], dv = a.dinv[i];
+        T rn, pn;
+        pre_update(r0, v0, p0, dv, alpha, beta, rn, pn);
+        if (xupd) a.x[i] = x_update(a.x[i], r0, p0, dv, alpha, ratio);
+        if (cons) v = pn; /* identity rows */
+        a.r[i] = rn;
+        a.p[i] = pn;
+        a.v[i] = v;
+        const T zr = dv * rn, zv = dv * v;
+        acc[0] += rn * rn;
+        acc[1] += pn * v;
+        acc[2] += rn * v;
+        acc[3] += v * v;
+        acc[4] += rn * zr;
+        acc[5] += rn * zv;
+        acc[6] += v * zv;
+    }
+    if (MODE == MODE_VMULT) return;
+
+    block_reduce<T, 7, SHARED_WG>(acc, red, a.dots + (L.ntiles + blockIdx.x) * 8);
+    /* make this block's partials visible, then take a ticket */
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned prev = atomicAdd(&a.st->ticket, 1u);
+        last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    finish_iteration<T>(a, L.ntiles + gridDim.x, red);
+    if (threadIdx.x == 0) a.st->ticket = 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Launch wrappers                                                     */
+/* ------------------------------------------------------------------ */
+
+template <int K, typename T>
+static hipError_t launch_fused_k(int mode, const IterArgs<T> &a, hipStream_t s)
+{
+    dim3 grid((unsigned)a.L.ntiles), block(Cfg<K>::WG);
+    if (mode == MODE_CG)
+        hipLaunchKernelGGL((fused_tile_kernel<K, T, MODE_CG>), grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL((fused_tile_kernel<K, T, MODE_VMULT>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fused(int K, int mode, const IterArgs<T> &a, hipStream_t s)
+{
+    switch (K) {
+    case 1: return launch_fused_k<1, T>(mode, a, s);
+    case 2: return launch_fused_k<2, T>(mode, a, s);
+    case 3: return launch_fused_k<3, T>(mode, a, s);
+    case 4: return launch_fused_k<4, T>(mode, a, s);
+    case 5: return launch_fused_k<5, T>(mode, a, s);
+    case 6: return launch_fused_k<6, T>(mode, a, s);
+    case 7: return launch_fused_k<7, T>(mode, a, s);
+    case 8: return launch_fused_k<8, T>(mode, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_shared(int mode, const IterArgs<T> &a, hipStream_t s)
+{
+    dim3 grid((unsigned)a.nshared_blocks), block(SHARED_WG);
+    if (mode == MODE_CG)
+        hipLaunchKernelGGL((shared_node_kernel<T, MODE_CG>), grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL((shared_node_kernel<T, MODE_VMULT>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+template hipError_t launch_fused<double>(int, int, const IterArgs<double> &, hipStream_t);
+template hipError_t launch_fused<float>(int, int, const IterArgs<float> &, hipStream_t);
+template hipError_t launch_shared<double>(int, const IterArgs<double> &, hipStream_t);
+template hipError_t launch_shared<float>(int, const IterArgs<float> &, hipStream_t);
+
+}  // namespace mfcg

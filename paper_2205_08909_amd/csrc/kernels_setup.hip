@@ -1,0 +1,456 @@
+/*
+ * kernels_setup.hip -- once-per-handle and once-per-solve kernels:
+ *   geometry tensor G_q = a_e w_q det(J_q) J_q^{-1} J_q^{-T} per quadrature
+ *   point (the "final tensor load" data of Sec. 2.2, Eq. 5), the Jacobi
+ *   diagonal (Sec. 3), the load vector, the lexicographic <-> internal
+ *   permutations, the solver initialisation (Algorithm 5, first line) and
+ *   the delayed x reconstruction at exit (Algorithm 5, exit branch).
+ * Node-centric kernels gather over the cells around a node in a fixed
+ * order, so no atomics are used and results are reproducible.
+ */
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace mfcg {
+
+constexpr int SETUP_WG = 256;
+
+/* ------------------------------------------------------------------ */
+/* Geometry                                                            */
+/* ------------------------------------------------------------------ */
+
+/* Global map x = F(X) of [0,1]^3 and its Jacobian DF. */
+__device__ inline void map_eval(int kind, double A, const double X[3], double x[3], double DF[3][3])
+{
+    const double twopi = 6.283185307179586476925286766559;
+    double s[3], c[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) sincos(twopi * X[d], &s[d], &c[d]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        x[i] = X[i];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) DF[i][j] = i == j ? 1.0 : 0.0;
+    }
+    if (kind == 1) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int p = (i + 1) % 3, q = (i + 2) % 3;
+            x[i] += A * s[p] * s[q];
+            DF[i][p] += A * twopi * c[p] * s[q];
+            DF[i][q] += A * twopi * s[p] * c[q];
+        }
+    } else if (kind == 2) {
+        const double pr = s[0] * s[1] * s[2];
+        const double g[3] = {twopi * c[0] * s[1] * s[2], twopi * s[0] * c[1] * s[2], twopi * s[0] * s[1] * c[2]};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            x[i] += A * pr;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) DF[i][j] += A * g[j];
+        }
+    }
+}
+
+/* Reference point xi of cell c -> mapped point x, J = dx/dxi, det J. */
+__device__ inline double cell_jacobian(const GeomArgs &g, const int c[3], const double xi[3], double x[3],
+                                       double J[3][3])
+{
+    double X[3], DF[3][3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) X[d] = (c[d] + xi[d]) / g.L.d[d].ncells;
+    map_eval(g.map_kind, g.amp, X, x, DF);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) J[i][j] = DF[i][j] / g.L.d[j].ncells;
+    return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
+/* Offset of component 0 of G at (cell, q) in the tile-blocked layout read
+ * by the fused kernel, and the component stride. */
+__device__ inline int64_t g_offset(const LayoutView &L, int K, const int c[3], int qx, int qy, int qz,
+                                   int64_t &cstride)
+{
+    const int n = K + 1, n2 = n * n, n3 = n2 * n;
+    int t[3], cl[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        t[d] = c[d] / L.d[d].T;
+    }
+    const int64_t tid = t[0] + (int64_t)L.d[0].ntiles * (t[1] + (int64_t)L.d[1].ntiles * t[2]);
+    const TileDesc td = L.tiles[tid];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) cl[d] = c[d] - td.c0[d];
+    const int nlc = td.nc[0] * td.nc[1];
+    const int line = (cl[0] + td.nc[0] * cl[1]) * n2 + qx + n * qz;
+    cstride = (int64_t)nlc * n3;
+    return td.gbase + (int64_t)cl[2] * 6 * nlc * n3 + (int64_t)qy * nlc * n2 + line;
+}
+
+__global__ __launch_bounds__(SETUP_WG) void geometry_kernel(const GeomArgs g, double *G)
+{
+    const int K = g.K, n = K + 1, n3 = n * n * n;
+    const int64_t ncell = (int64_t)g.L.d[0].ncells * g.L.d[1].ncells * g.L.d[2].ncells;
+    const int64_t t = (int64_t)blockIdx.x * SETUP_WG + threadIdx.x;
+    if (t >= ncell * n3) return;
+    const int64_t cell = t / n3;
+    const int q = (int)(t % n3), qx = q % n, qy = (q / n) % n, qz = q / (n * n);
+    const int c[3] = {(int)(cell % g.L.d[0].ncells), (int)((cell / g.L.d[0].ncells) % g.L.d[1].ncells),
+                      (int)(cell / ((int64_t)g.L.d[0].ncells * g.L.d[1].ncells))};
+    const double xi[3] = {g.tab.xq[qx], g.tab.xq[qy], g.tab.xq[qz]};
+    double x[3], J[3][3];
+    const double det = cell_jacobian(g, c, xi, x, J);
+    double Ji[3][3];
+    const double id = 1.0 / det;
+    Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) * id;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+    Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) * id;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+    Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) * id;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+    const double ae = g.coeff ? g.coeff[cell] : 1.0;
+    const double w = ae * g.tab.wq[qx] * g.tab.wq[qy] * g.tab.wq[qz] * det;
+    auto m = [&](int p, int r) { return w * (Ji[p][0] * Ji[r][0] + Ji[p][1] * Ji[r][1] + Ji[p][2] * Ji[r][2]); };
+    int64_t cs;
+    const int64_t o = g_offset(g.L, K, c, qx, qy, qz, cs);
+    G[o] = m(0, 0);
+    G[o + cs] = m(1, 1);
+    G[o + 2 * cs] = m(2, 2);
+    G[o + 3 * cs] = m(0, 1);
+    G[o + 4 * cs] = m(0, 2);
+    G[o + 5 * cs] = m(1, 2);
+}
+
+hipError_t launch_geometry(const GeomArgs &g, double *G, hipStream_t s)
+{
+    const int n = g.K + 1;
+    const int64_t tot = (int64_t)g.L.d[0].ncells * g.L.d[1].ncells * g.L.d[2].ncells * n * n * n;
+    const int64_t nb = (tot + SETUP_WG - 1) / SETUP_WG;
+    hipLaunchKernelGGL(geometry_kernel, dim3((unsigned)nb), dim3(SETUP_WG), 0, s, g, G);
+    return hipGetLastError();
+}
+
+/* ------------------------------------------------------------------ */
+/* Node helpers                                                        */
+/* ------------------------------------------------------------------ */
+
+__device__ inline void dim_locate(const Dim1 &d, int64_t g, int64_t &e, int64_t &l, int64_t &len)
+{
+    const int64_t Ek = (int64_t)d.T * d.K;
+    const int64_t last = (int64_t)d.ncells * d.K;
+    if (g == last) {
+        e = 2 * (int64_t)d.ntiles;
+        l = 0;
+        len = 1;
+        return;
+    }
+    const int64_t j = g / Ek, r = g - j * Ek;
+    if (r == 0) {
+        e = 2 * j;
+        l = 0;
+        len = 1;
+    } else {
+        e = 2 * j + 1;
+        l = r - 1;
+        const int64_t rem = d.ncells - j * d.T;
+        len = (rem < d.T ? rem : d.T) * d.K - 1;
+    }
+}
+
+__device__ inline int64_t internal_index(const LayoutView &L, const int64_t g[3])
+{
+    int64_t e[3], l[3], len[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) dim_locate(L.d[d], g[d], e[d], l[d], len[d]);
+    const int64_t ne0 = 2 * (int64_t)L.d[0].ntiles + 1, ne1 = 2 * (int64_t)L.d[1].ntiles + 1;
+    return L.ent_base[e[0] + ne0 * (e[1] + ne1 * e[2])] + l[0] + len[0] * (l[1] + len[1] * l[2]);
+}
+
+__device__ inline void lex_coords(const LayoutView &L, int64_t t, int64_t g[3])
+{
+    const int64_t l0 = (int64_t)L.d[0].ncells * L.d[0].K + 1, l1 = (int64_t)L.d[1].ncells * L.d[1].K + 1;
+    g[0] = t % l0;
+    g[1] = (t / l0) % l1;
+    g[2] = t / (l0 * l1);
+}
+
+__device__ inline bool on_boundary(const LayoutView &L, const int64_t g[3])
+{
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        if (g[d] == 0 || g[d] == (int64_t)L.d[d].ncells * L.d[d].K) return true;
+    return false;
+}
+
+/* cells containing lattice coordinate gd in one direction */
+__device__ inline void cell_range(const Dim1 &d, int64_t gd, int &lo, int &hi)
+{
+    if (gd % d.K == 0) {
+        lo = (int)(gd / d.K) - 1;
+        hi = (int)(gd / d.K);
+    } else {
+        lo = hi = (int)(gd / d.K);
+    }
+    if (lo < 0) lo = 0;
+    if (hi > d.ncells - 1) hi = d.ncells - 1;
+}
+
+/* ------------------------------------------------------------------ */
+/* Diagonal (Sec. 3: point Jacobi)                                     */
+/* ------------------------------------------------------------------ */
+
+__global__ __launch_bounds__(SETUP_WG) void diagonal_kernel(const GeomArgs g, const double *G, double *diag_lex,
+                                                            double *dinv_int)
+{
+    const LayoutView &L = g.L;
+    const int K = g.K, n = K + 1;
+    const int64_t t = (int64_t)blockIdx.x * SETUP_WG + threadIdx.x;
+    if (t >= L.n) return;
+    int64_t gc[3];
+    lex_coords(L, t, gc);
+    double dsum = 0.0;
+    if (g.bc == 0 && on_boundary(L, gc)) {
+        dsum = 1.0;
+    } else {
+        int lo[3], hi[3];
+        for (int d = 0; d < 3; ++d) cell_range(L.d[d], gc[d], lo[d], hi[d]);
+        for (int cz = lo[2]; cz <= hi[2]; ++cz)
+            for (int cy = lo[1]; cy <= hi[1]; ++cy)
+                for (int cx = lo[0]; cx <= hi[0]; ++cx) {
+                    const int c[3] = {cx, cy, cz};
+                    const int ix = (int)(gc[0] - (int64_t)cx * K), iy = (int)(gc[1] - (int64_t)cy * K),
+                              iz = (int)(gc[2] - (int64_t)cz * K);
+                    for (int qz = 0; qz < n; ++qz)
+                        for (int qy = 0; qy < n; ++qy)
+                            for (int qx = 0; qx < n; ++qx) {
+                                const double gx = g.tab.Sd[qx * n + ix] * g.tab.S[qy * n + iy] * g.tab.S[qz * n + iz];
+                                const double gy = g.tab.S[qx * n + ix] * g.tab.Sd[qy * n + iy] * g.tab.S[qz * n + iz];
+                                const double gz = g.tab.S[qx * n + ix] * g.tab.S[qy * n + iy] * g.tab.Sd[qz * n + iz];
+                                int64_t cs;
+                                const int64_t o = g_offset(L, K, c, qx, qy, qz, cs);
+                                const double g00 = G[o], g11 = G[o + cs], g22 = G[o + 2 * cs], g01 = G[o + 3 * cs],
+                                             g02 = G[o + 4 * cs], g12 = G[o + 5 * cs];
+                                dsum += g00 * gx * gx + g11 * gy * gy + g22 * gz * gz +
+                                        2.0 * (g01 * gx * gy + g02 * gx * gz + g12 * gy * gz);
+                            }
+                }
+    }
+    if (diag_lex) diag_lex[t] = dsum;
+    if (dinv_int) dinv_int[internal_index(L, gc)] = 1.0 / dsum;
+}
+
+hipError_t launch_diagonal(const GeomArgs &g, const double *G, double *diag_lex, double *dinv_int, hipStream_t s)
+{
+    const int64_t nb = (g.L.n + SETUP_WG - 1) / SETUP_WG;
+    hipLaunchKernelGGL(diagonal_kernel, dim3((unsigned)nb), dim3(SETUP_WG), 0, s, g, G, diag_lex, dinv_int);
+    return hipGetLastError();
+}
+
+/* ------------------------------------------------------------------ */
+/* Load vector                                                         */
+/* ------------------------------------------------------------------ */
+
+struct RhsParams {
+    int32_t kind, nbumps;
+    double p[5 * 16];
+};
+
+__device__ inline double forcing(const RhsParams &f, const double x[3])
+{
+    const double pi = 3.141592653589793238462643383279;
+    if (f.kind == 0) return 3.0 * pi * pi * sin(pi * x[0]) * sin(pi * x[1]) * sin(pi * x[2]);
+    double s = 0.0;
+    for (int b = 0; b < f.nbumps; ++b) {
+        const double *q = f.p + 5 * b;
+        const double dx = x[0] - q[1], dy = x[1] - q[2], dz = x[2] - q[3];
+        s += q[0] * exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * q[4] * q[4]));
+    }
+    return s;
+}
+
+__global__ __launch_bounds__(SETUP_WG) void rhs_kernel(const GeomArgs g, const RhsParams f, double *b)
+{
+    const LayoutView &L = g.L;
+    const int K = g.K, n = K + 1;
+    const int64_t t = (int64_t)blockIdx.x * SETUP_WG + threadIdx.x;
+    if (t >= L.n) return;
+    int64_t gc[3];
+    lex_coords(L, t, gc);
+    double acc = 0.0;
+    if (!(g.bc == 0 && on_boundary(L, gc))) {
+        int lo[3], hi[3];
+        for (int d = 0; d < 3; ++d) cell_range(L.d[d], gc[d], lo[d], hi[d]);
+        for (int cz = lo[2]; cz <= hi[2]; ++cz)
+            for (int cy = lo[1]; cy <= hi[1]; ++cy)
+                for (int cx = lo[0]; cx <= hi[0]; ++cx) {
+                    const int c[3] = {cx, cy, cz};
+                    const int ix = (int)(gc[0] - (int64_t)cx * K), iy = (int)(gc[1] - (int64_t)cy * K),
+                              iz = (int)(gc[2] - (int64_t)cz * K);
+                    for (int qz = 0; qz < n; ++qz)
+                        for (int qy = 0; qy < n; ++qy)
+                            for (int qx = 0; qx < n; ++qx) {
+                                const double xi[3] = {g.tab.xq[qx], g.tab.xq[qy], g.tab.xq[qz]};
+                                double x[3], J[3][3];
+                                const double det = cell_jacobian(g, c, xi, x, J);
+                                const double phi = g.tab.S[qx * n + ix] * g.tab.S[qy * n + iy] * g.tab.S[qz * n + iz];
+                                acc += forcing(f, x) * phi * g.tab.wq[qx] * g.tab.wq[qy] * g.tab.wq[qz] * det;
+                            }
+                }
+    }
+    b[t] = acc;
+}
+
+hipError_t launch_rhs(const GeomArgs &g, int kind, const double *params, int nparams, double *b_lex, hipStream_t s)
+{
+    RhsParams f;
+    f.kind = kind;
+    f.nbumps = 0;
+    if (kind == 1) {
+        f.nbumps = (int)params[0];
+        if (f.nbumps < 0 || f.nbumps > 16 || nparams < 1 + 5 * f.nbumps) return hipErrorInvalidValue;
+        for (int i = 0; i < 5 * f.nbumps; ++i) f.p[i] = params[1 + i];
+    }
+    const int64_t nb = (g.L.n + SETUP_WG - 1) / SETUP_WG;
+    hipLaunchKernelGGL(rhs_kernel, dim3((unsigned)nb), dim3(SETUP_WG), 0, s, g, f, b_lex);
+    return hipGetLastError();
+}
+
+/* ------------------------------------------------------------------ */
+/* Permutations and vector kernels                                     */
+/* ------------------------------------------------------------------ */
+
+template <typename T>
+__global__ __launch_bounds__(SETUP_WG) void lex_to_int_kernel(const LayoutView L, const double *in, T *out)
+{
+    const int64_t t = (int64_t)blockIdx.x * SETUP_WG + threadIdx.x;
+    if (t >= L.n) return;
+    int64_t g[3];
+    lex_coords(L, t, g);
+    out[internal_index(L, g)] = (T)in[t];
+}
+
+template <typename T>
+__global__ __launch_bounds__(SETUP_WG) void int_to_lex_kernel(const LayoutView L, const T *in, double *out)
+{
+    const int64_t t = (int64_t)blockIdx.x * SETUP_WG + threadIdx.x;
+    if (t >= L.n) return;
+    int64_t g[3];
+    lex_coords(L, t, g);
+    out[t] = (double)in[internal_index(L, g)];
+}
+
+template <typename T>
+hipError_t launch_lex_to_int(const LayoutView &L, const double *in_lex, T *out_int, hipStream_t s)
+{
+    const int64_t nb = (L.n + SETUP_WG - 1) / SETUP_WG;
+    hipLaunchKernelGGL((lex_to_int_kernel<T>), dim3((unsigned)nb), dim3(SETUP_WG), 0, s, L, in_lex, out_int);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_int_to_lex(const LayoutView &L, const T *in_int, double *out_lex, hipStream_t s)
+{
+    const int64_t nb = (L.n + SETUP_WG - 1) / SETUP_WG;
+    hipLaunchKernelGGL((int_to_lex_kernel<T>), dim3((unsigned)nb), dim3(SETUP_WG), 0, s, L, in_int, out_lex);
+    return hipGetLastError();
+}
+
+template hipError_t launch_lex_to_int<double>(const LayoutView &, const double *, double *, hipStream_t);
+template hipError_t launch_lex_to_int<float>(const LayoutView &, const double *, float *, hipStream_t);
+template hipError_t launch_int_to_lex<double>(const LayoutView &, const double *, double *, hipStream_t);
+template hipError_t launch_int_to_lex<float>(const LayoutView &, const float *, double *, hipStream_t);
+
+/* r = r - v (when use_v), p = 0, v = 0: Algorithm 5, first line. */
+__global__ __launch_bounds__(SETUP_WG) void init_cg_kernel(int64_t n, double *r, double *p, double *v, int use_v)
+{
+    const int64_t i = (int64_t)blockIdx.x * SETUP_WG + threadIdx.x;
+    if (i >= n) return;
+    if (use_v) r[i] = r[i] - v[i];
+    p[i] = 0.0;
+    v[i] = 0.0;
+}
+
+hipError_t launch_init_cg(int64_t n, double *r, double *p, double *v, int use_v, hipStream_t s)
+{
+    const int64_t nb = (n + SETUP_WG - 1) / SETUP_WG;
+    hipLaunchKernelGGL(init_cg_kernel, dim3((unsigned)nb), dim3(SETUP_WG), 0, s, n, r, p, v, use_v);
+    return hipGetLastError();
+}
+
+/* part[b] = sum over block b's grid-stride range of (a_i - c_i)^2 (c may be
+ * NULL); partial sums in a fixed order, finished on the host. */
+__global__ __launch_bounds__(SETUP_WG) void sumsq_kernel(int64_t n, const double *a, const double *c, double *part)
+{
+    __shared__ double red[SETUP_WG / 64];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * SETUP_WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * SETUP_WG) {
+        const double d = c ? a[i] - c[i] : a[i];
+        s += d * d;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < SETUP_WG / 64; ++w) t += red[w];
+        part[blockIdx.x] = t;
+    }
+}
+
+hipError_t launch_sumsq(int64_t n, const double *b, const double *ax, double *part, int nb, hipStream_t s)
+{
+    hipLaunchKernelGGL(sumsq_kernel, dim3((unsigned)nb), dim3(SETUP_WG), 0, s, n, b, ax, part);
+    return hipGetLastError();
+}
+
+/* Algorithm 5 exit: x_{k+1} = x_k + alpha_k p_k (k odd) or
+ * x_{k-1} + alpha_k p_k + alpha_{k-1}/beta_{k-1} (p_k - D^{-1} r_k) (k even);
+ * x_k on breakdown (xa = 0). */
+template <typename T>
+__global__ __launch_bounds__(SETUP_WG) void reconstruct_kernel(int64_t n, T *x, const T *p, const T *r,
+                                                               const T *dinv, const CGState *st)
+{
+    const int64_t i = (int64_t)blockIdx.x * SETUP_WG + threadIdx.x;
+    if (i >= n) return;
+    const int k = st->k;
+    if (k == 0) return;
+    const T xa = (T)st->xa, xr = (T)st->xratio;
+    T xi = fma(xa, p[i], x[i]);
+    if ((k & 1) == 0) xi = fma(xr, fma(-dinv[i], r[i], p[i]), xi);
+    x[i] = xi;
+}
+
+template <typename T>
+hipError_t launch_reconstruct(int64_t n, T *x, const T *p, const T *r, const T *dinv, const CGState *st,
+                              hipStream_t s)
+{
+    const int64_t nb = (n + SETUP_WG - 1) / SETUP_WG;
+    hipLaunchKernelGGL((reconstruct_kernel<T>), dim3((unsigned)nb), dim3(SETUP_WG), 0, s, n, x, p, r, dinv, st);
+    return hipGetLastError();
+}
+template hipError_t launch_reconstruct<double>(int64_t, double *, const double *, const double *, const double *,
+                                               const CGState *, hipStream_t);
+template hipError_t launch_reconstruct<float>(int64_t, float *, const float *, const float *, const float *,
+                                              const CGState *, hipStream_t);
+
+__global__ __launch_bounds__(SETUP_WG) void convert_kernel(int64_t n, const double *in, float *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * SETUP_WG + threadIdx.x;
+    if (i < n) out[i] = (float)in[i];
+}
+
+hipError_t launch_convert(int64_t n, const double *in, float *out, hipStream_t s)
+{
+    const int64_t nb = (n + SETUP_WG - 1) / SETUP_WG;
+    hipLaunchKernelGGL(convert_kernel, dim3((unsigned)nb), dim3(SETUP_WG), 0, s, n, in, out);
+    return hipGetLastError();
+}
+
+}  // namespace mfcg

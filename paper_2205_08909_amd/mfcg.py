@@ -1,0 +1,243 @@
+"""Thin ctypes binding of libmfcg.so (include/mfcg.h).
+
+Argument marshalling only: every step of the solver runs in the library's
+HIP kernels.  Device vectors are torch CUDA (HIP) tensors of dtype float64;
+streams are torch streams.  Loading fails loudly when the library is not
+built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmfcg.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOTCONV, EBREAKDOWN, ESTAGNATION = 0, -1, -2, -3, -4, -5, -6
+MAP_AFFINE, MAP_SINE_SHEAR, MAP_SINE_PRODUCT = 0, 1, 2
+BC_DIRICHLET0, BC_NONE = 0, 1
+RHS_SINE, RHS_BUMPS = 0, 1
+
+EXPORTED = [
+    "mfcg_setup", "mfcg_n_dofs", "mfcg_vmult", "mfcg_diagonal", "mfcg_assemble_rhs", "mfcg_solve",
+    "mfcg_cg_begin", "mfcg_cg_iterate", "mfcg_cg_end", "mfcg_set_timing", "mfcg_get_timing",
+    "mfcg_layout_info", "mfcg_layout_permutation", "mfcg_destroy", "mfcg_error_string", "mfcg_last_error",
+]
+
+
+class MfcgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mfcg error {code}: {msg}")
+        self.code = code
+
+
+class Mesh(ctypes.Structure):
+    _fields_ = [("cells", ctypes.c_int32 * 3), ("map_kind", ctypes.c_int32), ("map_amplitude", ctypes.c_double),
+                ("bc", ctypes.c_int32)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("n_q_1d", ctypes.c_int32), ("tile", ctypes.c_int32 * 3), ("check_every", ctypes.c_int32),
+                ("fp32", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2205_08909_amd.build` "
+                               "(or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.mfcg_setup.argtypes = [ctypes.POINTER(Mesh), I32, P, ctypes.POINTER(Options), P, ctypes.POINTER(P)]
+        L.mfcg_n_dofs.argtypes = [P, ctypes.POINTER(I64)]
+        L.mfcg_vmult.argtypes = [P, P, P, P]
+        L.mfcg_diagonal.argtypes = [P, P, P]
+        L.mfcg_assemble_rhs.argtypes = [P, I32, P, P, P]
+        L.mfcg_solve.argtypes = [P, P, P, D, I32, ctypes.POINTER(I32), P, P, P]
+        L.mfcg_cg_begin.argtypes = [P, P, P, D, I32, P]
+        L.mfcg_cg_iterate.argtypes = [P, I32, P]
+        L.mfcg_cg_end.argtypes = [P, P, ctypes.POINTER(I32), P, P]
+        L.mfcg_set_timing.argtypes = [P, I32]
+        L.mfcg_get_timing.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(I64), ctypes.POINTER(D),
+                                      ctypes.POINTER(I64)]
+        L.mfcg_layout_info.argtypes = [P, P, P, P, P, P, P]
+        L.mfcg_layout_permutation.argtypes = [ctypes.POINTER(Mesh), I32, P, P, P, P, P]
+        L.mfcg_destroy.argtypes = [P]
+        L.mfcg_error_string.argtypes = [ctypes.c_int]
+        L.mfcg_error_string.restype = ctypes.c_char_p
+        L.mfcg_last_error.argtypes = [P]
+        L.mfcg_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(code, handle=None):
+    if code != OK:
+        msg = lib().mfcg_last_error(handle).decode()
+        raise MfcgError(code, msg)
+    return code
+
+
+def make_mesh(cells, map_kind=MAP_AFFINE, amplitude=0.0, bc=BC_DIRICHLET0):
+    if np.isscalar(cells):
+        cells = (cells, cells, cells)
+    m = Mesh()
+    for d in range(3):
+        m.cells[d] = int(cells[d])
+    m.map_kind = int(map_kind)
+    m.map_amplitude = float(amplitude)
+    m.bc = int(bc)
+    return m
+
+
+def make_options(tile=None, check_every=0, fp32=0):
+    o = Options()
+    o.n_q_1d = 0
+    for d in range(3):
+        o.tile[d] = 0 if tile is None else int(tile[d])
+    o.check_every = int(check_every)
+    o.fp32 = int(fp32)
+    return o
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_vec(t, n, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+            and t.numel() == n):
+        raise ValueError(f"{name} must be a contiguous float64 device tensor of length {n}")
+    return t
+
+
+def layout_permutation(cells, degree, tile=None, map_kind=MAP_AFFINE, bc=BC_DIRICHLET0):
+    """Host-only: lexicographic -> internal permutation and class counts."""
+    m = make_mesh(cells, map_kind, 0.0, bc)
+    n = 1
+    for c in (cells if not np.isscalar(cells) else (cells,) * 3):
+        n *= int(c) * degree + 1
+    perm = np.zeros(n, dtype=np.int64)
+    t = (ctypes.c_int32 * 3)(*(tile or (0, 0, 0)))
+    nI, nS, nC = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().mfcg_layout_permutation(ctypes.byref(m), int(degree), ctypes.cast(t, ctypes.c_void_p),
+                                         perm.ctypes.data_as(ctypes.c_void_p), ctypes.byref(nI), ctypes.byref(nS),
+                                         ctypes.byref(nC)))
+    return perm, nI.value, nS.value, nC.value
+
+
+class Problem:
+    """mfcg_setup on a mesh + degree + per-cell coefficient."""
+
+    def __init__(self, cells, degree, coeff=None, map_kind=MAP_AFFINE, amplitude=0.0, bc=BC_DIRICHLET0, tile=None,
+                 check_every=0, stream=None):
+        self.mesh = make_mesh(cells, map_kind, amplitude, bc)
+        self.degree = int(degree)
+        self.opt = make_options(tile, check_every)
+        self.h = ctypes.c_void_p()
+        self._coeff = None
+        if coeff is not None:
+            self._coeff = np.ascontiguousarray(coeff, dtype=np.float64).ravel()
+        cptr = self._coeff.ctypes.data_as(ctypes.c_void_p) if self._coeff is not None else None
+        _check(lib().mfcg_setup(ctypes.byref(self.mesh), self.degree, cptr, ctypes.byref(self.opt),
+                                _stream(stream), ctypes.byref(self.h)))
+        n = ctypes.c_int64()
+        _check(lib().mfcg_n_dofs(self.h, ctypes.byref(n)), self.h)
+        self.n = n.value
+
+    def close(self):
+        if self.h:
+            lib().mfcg_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def empty(self):
+        import torch
+        return torch.empty(self.n, dtype=torch.float64, device="cuda")
+
+    def vmult(self, dst, src, stream=None):
+        _dev_vec(dst, self.n, "dst")
+        _dev_vec(src, self.n, "src")
+        _check(lib().mfcg_vmult(self.h, _ptr(dst), _ptr(src), _stream(stream)), self.h)
+        return dst
+
+    def diagonal(self, out=None, stream=None):
+        out = self.empty() if out is None else _dev_vec(out, self.n, "out")
+        _check(lib().mfcg_diagonal(self.h, _ptr(out), _stream(stream)), self.h)
+        return out
+
+    def rhs(self, kind=RHS_SINE, params=None, out=None, stream=None):
+        out = self.empty() if out is None else _dev_vec(out, self.n, "out")
+        p = None
+        if params is not None:
+            self._params = np.ascontiguousarray(params, dtype=np.float64)
+            p = self._params.ctypes.data_as(ctypes.c_void_p)
+        _check(lib().mfcg_assemble_rhs(self.h, int(kind), p, _ptr(out), _stream(stream)), self.h)
+        return out
+
+    def solve(self, b, x, tol=1e-10, maxit=10000, want_hist=True, want_true_res=False, stream=None, raise_on=True):
+        """Returns (code, iters, hist, true_rel_res); x is overwritten."""
+        _dev_vec(b, self.n, "b")
+        _dev_vec(x, self.n, "x")
+        its = ctypes.c_int32()
+        hist = np.zeros(maxit + 1) if want_hist else None
+        tr = ctypes.c_double(float("nan"))
+        code = lib().mfcg_solve(self.h, _ptr(b), _ptr(x), float(tol), int(maxit), ctypes.byref(its),
+                                hist.ctypes.data_as(ctypes.c_void_p) if want_hist else None,
+                                ctypes.byref(tr) if want_true_res else None, _stream(stream))
+        if raise_on and code not in (OK, ENOTCONV):
+            _check(code, self.h)
+        h = hist[: its.value + 1].copy() if want_hist else None
+        return code, its.value, h, tr.value
+
+    # stepping interface (throughput measurement)
+    def cg_begin(self, b, x0=None, tol=0.0, maxit=100, stream=None):
+        _dev_vec(b, self.n, "b")
+        if x0 is not None:
+            _dev_vec(x0, self.n, "x0")
+        _check(lib().mfcg_cg_begin(self.h, _ptr(b), _ptr(x0), float(tol), int(maxit), _stream(stream)), self.h)
+
+    def cg_iterate(self, n, stream=None):
+        _check(lib().mfcg_cg_iterate(self.h, int(n), _stream(stream)), self.h)
+
+    def cg_end(self, x, want_hist=False, maxit=None, stream=None):
+        _dev_vec(x, self.n, "x")
+        its = ctypes.c_int32()
+        hist = np.zeros((maxit or 100000) + 1) if want_hist else None
+        code = lib().mfcg_cg_end(self.h, _ptr(x), ctypes.byref(its),
+                                 hist.ctypes.data_as(ctypes.c_void_p) if want_hist else None, _stream(stream))
+        return code, its.value, (hist[: its.value + 1] if want_hist else None)
+
+    def set_timing(self, on=True):
+        _check(lib().mfcg_set_timing(self.h, 1 if on else 0), self.h)
+
+    def get_timing(self):
+        fm, sm = ctypes.c_double(), ctypes.c_double()
+        fl, sl = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().mfcg_get_timing(self.h, ctypes.byref(fm), ctypes.byref(fl), ctypes.byref(sm),
+                                     ctypes.byref(sl)), self.h)
+        return {"fused_ms": fm.value, "fused_launches": fl.value, "shared_ms": sm.value, "shared_launches": sl.value}
+
+    def layout_info(self):
+        t = (ctypes.c_int32 * 3)()
+        vals = [ctypes.c_int64() for _ in range(5)]
+        _check(lib().mfcg_layout_info(self.h, ctypes.cast(t, ctypes.c_void_p), *[ctypes.byref(v) for v in vals]),
+               self.h)
+        return {"tile": tuple(t), "n_interior": vals[0].value, "n_shared": vals[1].value,
+                "n_dirichlet": vals[2].value, "n_tiles": vals[3].value, "geometry_bytes": vals[4].value}

@@ -1,0 +1,127 @@
+"""Host-side checks of the C-ABI library: it loads, exports every function
+that include/mfcg.h declares, rejects invalid arguments before any HIP call,
+and its enumeration of unknowns (tile interiors, shared nodes, Dirichlet
+nodes; the GPU form of the paper's Sec. 5.3 numbering) is a bijection with
+the class sizes given by closed forms."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2205_08909_amd import mfcg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "mfcg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mfcg_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = mfcg.lib()
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(mfcg.EXPORTED)
+
+
+def test_error_strings():
+    L = mfcg.lib()
+    for code in range(-6, 1):
+        assert L.mfcg_error_string(code)
+
+
+@pytest.mark.parametrize("cells,degree,bc,msg", [
+    ((0, 4, 4), 2, 0, "cells"),
+    ((4, 4, 4), 0, 0, "degree"),
+    ((4, 4, 4), 9, 0, "degree"),
+    ((4, 4, 4), 2, 7, "bc"),
+])
+def test_setup_rejects_invalid_arguments(cells, degree, bc, msg):
+    L = mfcg.lib()
+    m = mfcg.make_mesh(cells, 0, 0.0, bc)
+    h = ctypes.c_void_p()
+    rc = L.mfcg_setup(ctypes.byref(m), degree, None, None, None, ctypes.byref(h))
+    assert rc == mfcg.EINVAL and not h.value
+    assert msg in L.mfcg_last_error(None).decode()
+
+
+def test_setup_rejects_bad_coefficient_and_tile():
+    L = mfcg.lib()
+    m = mfcg.make_mesh((2, 2, 2))
+    h = ctypes.c_void_p()
+    c = np.ones(8)
+    c[3] = -1.0
+    assert L.mfcg_setup(ctypes.byref(m), 2, c.ctypes.data_as(ctypes.c_void_p), None, None, ctypes.byref(h)) == mfcg.EINVAL
+    c[3] = np.nan
+    assert L.mfcg_setup(ctypes.byref(m), 2, c.ctypes.data_as(ctypes.c_void_p), None, None, ctypes.byref(h)) == mfcg.EINVAL
+    o = mfcg.make_options(tile=(99, 1, 1))
+    assert L.mfcg_setup(ctypes.byref(m), 2, None, ctypes.byref(o), None, ctypes.byref(h)) == mfcg.EINVAL
+    o = mfcg.make_options()
+    o.n_q_1d = 5
+    assert L.mfcg_setup(ctypes.byref(m), 2, None, ctypes.byref(o), None, ctypes.byref(h)) == mfcg.EINVAL
+    assert L.mfcg_setup(ctypes.byref(m), 2, None, None, None, None) == mfcg.EINVAL
+
+
+def test_null_handle_calls():
+    L = mfcg.lib()
+    n = ctypes.c_int64()
+    assert L.mfcg_n_dofs(None, ctypes.byref(n)) == mfcg.EINVAL
+    assert L.mfcg_vmult(None, None, None, None) == mfcg.EINVAL
+    assert L.mfcg_solve(None, None, None, 1e-10, 10, None, None, None, None) == mfcg.EINVAL
+    assert L.mfcg_destroy(None) == mfcg.OK
+
+
+def _closed_form_counts(cells, k, tile, bc):
+    n = np.prod([c * k + 1 for c in cells])
+    nI = 1
+    per_dim = []
+    for c, t in zip(cells, tile):
+        t = min(t, c)
+        sizes = [min(t, c - j) for j in range(0, c, t)]
+        per_dim.append(sum(s * k - 1 for s in sizes))
+    nI = int(np.prod(per_dim))
+    nC = int(n - np.prod([c * k - 1 for c in cells])) if bc == 0 else 0
+    return int(n), nI, int(n - nI - nC), nC
+
+
+@pytest.mark.parametrize("cells,k,tile,bc", [
+    ((8, 8, 8), 2, (0, 0, 0), 0),
+    ((5, 7, 9), 3, (2, 3, 4), 0),
+    ((4, 4, 4), 4, (0, 0, 0), 1),
+    ((3, 2, 5), 1, (2, 2, 2), 0),
+    ((6, 5, 4), 8, (2, 2, 3), 0),
+    ((1, 1, 1), 4, (0, 0, 0), 0),
+    ((2, 3, 1), 5, (1, 2, 1), 1),
+])
+def test_enumeration_bijection_and_counts(cells, k, tile, bc):
+    perm, nI, nS, nC = mfcg.layout_permutation(cells, k, tile=tile, bc=bc)
+    n, cI, cS, cC = _closed_form_counts(cells, k, [t if t else 10 ** 9 for t in tile] if any(tile) else
+                                        [mfcg_default_tile(k)[d] for d in range(3)], bc)
+    assert (nI, nS, nC) == (cI, cS, cC)
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    # Dirichlet nodes occupy the tail of the internal order; interior nodes the head
+    L = [c * k + 1 for c in cells]
+    gz, gy, gx = np.meshgrid(*[np.arange(v) for v in L[::-1]], indexing="ij")
+    bnd = ((gx == 0) | (gx == L[0] - 1) | (gy == 0) | (gy == L[1] - 1) | (gz == 0) | (gz == L[2] - 1)).ravel()
+    if bc == 0:
+        assert np.all(perm[bnd] >= n - nC) and np.all(perm[~bnd] < n - nC)
+
+
+def mfcg_default_tile(k):
+    txy = {1: 8, 2: 8, 3: 5, 4: 4, 5: 3, 6: 2, 7: 2, 8: 2}[k]
+    return (txy, txy, 16)
+
+
+def test_tile_interior_blocks_are_contiguous():
+    cells, k, tile = (4, 4, 4), 2, (2, 2, 2)
+    perm, nI, nS, nC = mfcg.layout_permutation(cells, k, tile=tile)
+    L = cells[0] * k + 1
+    # tile (0,0,0) interior: lattice coords 1..3 in each direction -> internal 0..26, lexicographic
+    idx = [perm[x + L * (y + L * z)] for z in range(1, 4) for y in range(1, 4) for x in range(1, 4)]
+    assert idx == list(range(27))

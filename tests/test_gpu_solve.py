@@ -1,0 +1,135 @@
+"""GPU solve parity: the fused Algorithm 5 against the oracle's Algorithm 1.
+
+In exact arithmetic both produce the same iterates (Sec. 4.2: Eq. 6-8 only
+regroup the inner products), so the iteration counts agree (up to one
+iteration when the residual lands at the threshold), the residual
+histories agree to rounding, and the converged solutions agree to 1e-10
+relative (the benchmark spec's solution tolerance).  Also checked: the exit
+reconstruction of x for both parities of the last iteration (maxit exits),
+warm starts, a zero right-hand side, reproducibility.
+"""
+import numpy as np
+import pytest
+
+from paper_2205_08909_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _problem(oracle_mod, cells, k, kind, amp, coeff_seed=None, tile=None, bc=0):
+    from paper_2205_08909_amd import mfcg
+    coeff = inputs.grf_coefficient(cells, 0.1, 1.0, seed=coeff_seed) if coeff_seed is not None else None
+    m = oracle_mod.Mesh(cells, k, map_kind=kind, amp=amp, bc=bc, coeff=coeff)
+    A = oracle_mod.assemble(m)
+    P = mfcg.Problem(cells, k, coeff=coeff, map_kind=kind, amplitude=amp, bc=bc, tile=tile)
+    return m, A, P
+
+
+def _compare(torch, oracle_mod, A, P, b, x0=None, tol=1e-10, maxit=5000):
+    d = A.diagonal()
+    xo, its_o, hist_o, rc_o = oracle_mod.pcg(A, d, b, x0=x0, tol=tol, maxit=maxit)
+    bt = torch.from_numpy(b).cuda()
+    xt = torch.from_numpy(x0 if x0 is not None else np.zeros_like(b)).cuda()
+    code, its, hist, tr = P.solve(bt, xt, tol=tol, maxit=maxit, want_true_res=True)
+    return xo, its_o, hist_o, rc_o, xt.cpu().numpy(), its, hist, tr, code
+
+
+@pytest.mark.parametrize("cells,k,kind,coeff_seed,tile", [
+    ((8, 8, 8), 2, 0, None, None),           # the plain Q2 workload, f from the manufactured solution
+    ((16, 16, 16), 4, 1, 3, None),           # curved Q4, random coefficient
+    ((6, 7, 5), 3, 1, 4, (2, 3, 2)),         # ragged tiles
+    ((4, 4, 4), 8, 1, 5, (1, 2, 3)),
+])
+def test_solve_matches_oracle(cells, k, kind, coeff_seed, tile, oracle_mod, torch_cuda):
+    torch = torch_cuda
+    m, A, P = _problem(oracle_mod, cells, k, kind, 0.05, coeff_seed, tile)
+    b = oracle_mod.rhs(m, oracle_mod.F_SINE)
+    xo, its_o, hist_o, rc_o, x, its, hist, tr, code = _compare(torch, oracle_mod, A, P, b)
+    assert rc_o == 0 and code == 0
+    assert abs(its - its_o) <= 1
+    assert np.linalg.norm(x - xo) <= 1e-10 * np.linalg.norm(xo)
+    nb = np.linalg.norm(b)
+    j = min(its, its_o)
+    assert np.abs(hist[:j + 1] - hist_o[:j + 1]).max() <= 1e-12 * nb
+    assert hist[its] < 1e-10 * nb
+    assert tr <= 2e-10
+    # the oracle's own residual of the GPU solution
+    assert np.linalg.norm(b - A.matvec(x)) <= 2e-10 * nb
+    P.close()
+
+
+def test_random_rhs_warm_start_and_reproducible(oracle_mod, torch_cuda):
+    torch = torch_cuda
+    cells, k = (6, 6, 6), 4
+    m, A, P = _problem(oracle_mod, cells, k, 1, 0.05, coeff_seed=8)
+    b = inputs.random_rhs(cells, k, seed=9)
+    x0 = 0.1 * inputs.random_vector(A.n, seed=10)
+    x0[m.constrained_mask()] = 0.0
+    xo, its_o, _, _, x, its, _, tr, code = _compare(torch, oracle_mod, A, P, b, x0=x0)
+    assert code == 0 and abs(its - its_o) <= 1
+    assert np.linalg.norm(x - xo) <= 1e-10 * np.linalg.norm(xo)
+    # bitwise reproducible
+    xt = torch.from_numpy(x0).cuda()
+    bt = torch.from_numpy(b).cuda()
+    P.solve(bt, xt, tol=1e-10, maxit=5000)
+    assert np.array_equal(xt.cpu().numpy(), x)
+    P.close()
+
+
+@pytest.mark.parametrize("maxit", [1, 2, 3, 4, 7])
+def test_maxit_exit_both_parities(maxit, oracle_mod, torch_cuda):
+    """x after exactly maxit iterations (not converged) equals Algorithm 1's
+    x_maxit: the delayed x update is reconstructed for odd and even exits."""
+    torch = torch_cuda
+    from paper_2205_08909_amd import mfcg
+    cells, k = (5, 4, 6), 3
+    m, A, P = _problem(oracle_mod, cells, k, 1, 0.05, coeff_seed=2, tile=(2, 2, 3))
+    b = inputs.random_rhs(cells, k, seed=1)
+    xo, its_o, hist_o, rc_o = oracle_mod.pcg(A, A.diagonal(), b, tol=1e-14, maxit=maxit)
+    assert rc_o == -4 and its_o == maxit
+    bt = torch.from_numpy(b).cuda()
+    xt = torch.zeros_like(bt)
+    code, its, hist, _ = P.solve(bt, xt, tol=1e-14, maxit=maxit)
+    assert code == mfcg.ENOTCONV and its == maxit
+    x = xt.cpu().numpy()
+    assert np.linalg.norm(x - xo) <= 1e-12 * np.linalg.norm(xo)
+    assert np.abs(hist - hist_o).max() <= 1e-12 * np.linalg.norm(b)
+    P.close()
+
+
+def test_zero_rhs_and_exact_warm_start(oracle_mod, torch_cuda):
+    torch = torch_cuda
+    cells, k = (4, 4, 4), 2
+    m, A, P = _problem(oracle_mod, cells, k, 1, 0.05)
+    z = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    x = torch.ones_like(z)
+    code, its, hist, tr = P.solve(z, x, tol=1e-10, maxit=10, want_true_res=True)
+    assert code == 0 and its == 0 and torch.count_nonzero(x).item() == 0 and tr == 0.0
+    # warm start at the (oracle) solution: converged before the first iteration
+    import scipy.sparse.linalg as spla
+    b = oracle_mod.rhs(m)
+    xs = spla.spsolve(A.to_scipy().tocsc(), b)
+    xt = torch.from_numpy(xs).cuda()
+    code, its, hist, _ = P.solve(torch.from_numpy(b).cuda(), xt, tol=1e-8, maxit=10)
+    assert code == 0 and its == 0
+    P.close()
+
+
+def test_breakdown_on_nan(oracle_mod, torch_cuda):
+    torch = torch_cuda
+    from paper_2205_08909_amd import mfcg
+    cells, k = (3, 3, 3), 2
+    P = mfcg.Problem(cells, k)
+    b = torch.from_numpy(inputs.random_rhs(cells, k, seed=3)).cuda()
+    b[P.n // 2] = float("nan")
+    x = torch.zeros_like(b)
+    code, its, hist, _ = P.solve(b, x, tol=1e-10, maxit=20, raise_on=False)
+    assert code in (mfcg.EBREAKDOWN,)
+    P.close()
