@@ -1,0 +1,214 @@
+"""Benchmark: fused Jacobi-PCG iterations (Algorithm 5 with the vector
+updates and inner products embedded in the matrix-free cell loop) on one
+MI355X.
+
+Workload (default): scalar Poisson, Q4 elements on 64^3 cells of the unit
+cube deformed by x_i + 0.05 sin(2 pi x_{i+1}) sin(2 pi x_{i+2}),
+257^3 = 16,974,593 DoFs (Dirichlet nodes included), Gauss 5^3 quadrature,
+the geometry tensor G_q stored per quadrature point, a = 1, f from the
+manufactured solution prod sin(pi x_j), FP64.  One step = one CG
+iteration (the fused tile kernel + the shared-node kernel).
+
+Prints one JSON line (the driver's contract).  With --gpus > 1 it exits:
+this build runs on one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DoFs×CG iters/s + HBM roofline %, Q4 ~17M DoFs FP64; time-to-1e-10 vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def counter_traffic(kernel_prefix):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE runs scaled by a copy-kernel
+    calibration), or None if absent or taken on other sources."""
+    path = os.path.join(ROOT, "profiles", "fused_cg_q4_n64_counters.md")
+    if not os.path.exists(path):
+        return None
+    try:
+        for line in open(path):
+            if line.startswith("traffic_json:"):
+                d = json.loads(line.split(":", 1)[1])
+                if d.get("kernel", "").startswith(kernel_prefix) and d.get("source_hash") == source_hash():
+                    return d["bytes_per_launch"]
+    except Exception:
+        return None
+    return None
+
+
+def source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2205_08909_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(seconds_budget=20.0):
+    """The oracle (CSR assembly + Algorithm 1) timed on the host cores on a
+    bounded sample of the same workload: Q4, 24^3 cells of the same curved
+    mesh (912,673 DoFs), a fixed number of PCG iterations."""
+    import numpy as np
+    from oracle import oracle
+    cells, k = 24, 4
+    m = oracle.Mesh(cells, k, map_kind=oracle.MAP_SINE_SHEAR, amp=0.05)
+    A = oracle.assemble(m)
+    b = oracle.rhs(m, oracle.F_SINE)
+    d = A.diagonal()
+    # calibrate the iteration count to the budget
+    t = time.perf_counter()
+    oracle.pcg(A, d, b, tol=0.0, maxit=5)
+    per_it = (time.perf_counter() - t) / 5
+    its = int(max(10, min(400, seconds_budget / max(per_it, 1e-6))))
+    t = time.perf_counter()
+    _, done, _, _ = oracle.pcg(A, d, b, tol=0.0, maxit=its)
+    dt = time.perf_counter() - t
+    return {"value": round(A.n * done / dt / 1e9, 4), "unit": "GDoF*iter/s", "cores": oracle.max_threads(),
+            "kind": "oracle",
+            "sample": f"Algorithm 1 on the assembled CSR matrix, Q4 {cells}^3 cells of the same curved mesh "
+                      f"({A.n} DoFs, {int(A.rowptr[-1])} nonzeros), {done} iterations in {dt:.1f} s; "
+                      "assembly excluded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cells", type=int, default=64)
+    ap.add_argument("--degree", type=int, default=4)
+    ap.add_argument("--tile", type=int, nargs=3, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (the multi-GPU sharding is described in DESIGN.md); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2205_08909_amd import mfcg
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    torch.cuda.set_device(0)
+    N, k, K, W = args.cells, args.degree, args.steps, args.warmup
+    t0 = time.perf_counter()
+    P = mfcg.Problem(N, k, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05, tile=args.tile)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    info = P.layout_info()
+    n = P.n
+    b = P.rhs(mfcg.RHS_SINE)
+    x = torch.zeros_like(b)
+    print(f"[bench] setup {setup_s:.2f} s, n={n}, tiles={info['n_tiles']} tile={info['tile']}", file=sys.stderr,
+          flush=True)
+
+    # ---- timed region: K fused iterations, inputs resident in HBM ----
+    P.cg_begin(b, None, tol=0.0, maxit=W + K)
+    P.cg_iterate(W)
+    torch.cuda.synchronize()
+    P.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.cg_iterate(K)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tm = P.get_timing()
+    P.set_timing(False)
+    code, its, _ = P.cg_end(x)
+    assert its == W + K, (code, its)
+    ms_per_step = wall * 1e3 / K
+    value = n * K / wall / 1e9
+    print(f"[bench] {K} iterations in {wall * 1e3:.2f} ms: {ms_per_step:.4f} ms/it, {value:.3f} GDoF*it/s; "
+          f"fused {tm['fused_ms'] / K:.4f} ms, shared {tm['shared_ms'] / K:.4f} ms", file=sys.stderr, flush=True)
+
+    # ---- algorithmic bytes (paper's ideal transfer, Table 1 with a scalar diagonal) ----
+    nq = (k + 1) ** 3
+    ncell = N ** 3
+    g_bytes = 8 * 6 * nq * ncell
+    nI, nS, nC = info["n_interior"], info["n_shared"], info["n_dirichlet"]
+    it_bytes = 8 * 8 * n + g_bytes                      # 4.5 reads + 3.5 writes per vector entry, plus G
+    fused_bytes = g_bytes + 64 * nI + 32 * nS + 8 * nS  # G, interior nodes once, shared nodes read once + handed over once
+    fused_avg_ms = tm["fused_ms"] / max(1, tm["fused_launches"])
+    achieved = fused_bytes / (fused_avg_ms * 1e-3) / 1e9
+    traffic = counter_traffic("fused_tile_kernel")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
+
+    # ---- copy bandwidth of a plain device copy (context for the roofline) ----
+    nb = 256 * 1024 * 1024  # 2 GiB per buffer
+    a_ = torch.empty(nb, dtype=torch.float64, device="cuda")
+    c_ = torch.empty_like(a_)
+    a_.fill_(1.0)
+    c_.copy_(a_)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        c_.copy_(a_)
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * 8 * nb / (time.perf_counter() - t0) / 1e9
+    del a_, c_
+
+    # ---- time to 1e-10 with the plain fused FP64 solver ----
+    solve = None
+    if not args.no_solve:
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        code, its_s, hist, tr = P.solve(b, x, tol=1e-10, maxit=20000, want_hist=False, want_true_res=False)
+        torch.cuda.synchronize()
+        t_sol = time.perf_counter() - t0
+        xs = x.clone()
+        _, _, _, tr = P.solve(b, xs, tol=1e-10, maxit=1, want_hist=False, want_true_res=True)
+        solve = {"iters": its_s, "seconds": round(t_sol, 4), "status": int(code),
+                 "true_rel_res": float(f"{tr:.3e}")}
+        print(f"[bench] solve to 1e-10: {its_s} iterations, {t_sol:.3f} s, true rel res {tr:.2e}", file=sys.stderr,
+              flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline()
+        print(f"[bench] cpu baseline {cpu}", file=sys.stderr, flush=True)
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "GDoF*iter/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"Q{k} scalar Poisson CG step, {N}^3 cells curved (sine shear 0.05), "
+                               f"{n} DoFs, Gauss {k + 1}^3, stored G_q, FP64",
+                   "cells": N, "degree": k, "n_dofs": n, "tile": list(info["tile"]), "n_tiles": info["n_tiles"],
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "iteration_roofline": {"bytes_per_dof": round(it_bytes / n, 2),
+                               "achieved_GBs": round(it_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+                               "frac": round(it_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "kernel_ms": {"fused": round(fused_avg_ms, 5), "shared": round(tm["shared_ms"] / max(1, tm["shared_launches"]), 5)},
+        "copy_GBs": round(copy_gbs, 1),
+        "time_to_1e-10": solve,
+        "setup_s": round(setup_s, 3),
+    }
+    print(json.dumps(line), flush=True)
+    P.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -32,6 +32,23 @@ def _problem(oracle_mod, cells, k, kind, amp, coeff_seed=None, tile=None, bc=0):
     return m, A, P
 
 
+def oracle_noise_floor(oracle_mod, A, b, tol, maxit=5000):
+    """Relative deviation of the oracle's residual history from itself
+    when the same system is solved in another node order (P A P^T, P b):
+    only the summation order of every product and sum changes."""
+    from oracle.oracle import CSR
+    rng = np.random.default_rng(0)
+    perm = rng.permutation(A.n)
+    S = A.to_scipy()[perm][:, perm].tocsr()
+    S.sort_indices()
+    Ap = CSR(S.indptr.astype(np.int64), S.indices.astype(np.int32), S.data.copy())
+    d = A.diagonal()
+    _, its1, h1, _ = oracle_mod.pcg(A, d, b, tol=tol, maxit=maxit)
+    _, its2, h2, _ = oracle_mod.pcg(Ap, d[perm], b[perm], tol=tol, maxit=maxit)
+    j = min(its1, its2)
+    return np.max(np.abs(h1[:j + 1] - h2[:j + 1]) / h1[:j + 1])
+
+
 def _compare(torch, oracle_mod, A, P, b, x0=None, tol=1e-10, maxit=5000):
     d = A.diagonal()
     xo, its_o, hist_o, rc_o = oracle_mod.pcg(A, d, b, x0=x0, tol=tol, maxit=maxit)
@@ -57,7 +74,13 @@ def test_solve_matches_oracle(cells, k, kind, coeff_seed, tile, oracle_mod, torc
     assert np.linalg.norm(x - xo) <= 1e-10 * np.linalg.norm(xo)
     nb = np.linalg.norm(b)
     j = min(its, its_o)
-    assert np.abs(hist[:j + 1] - hist_o[:j + 1]).max() <= 1e-12 * nb
+    # early iterations agree to rounding; later ones within 10x the
+    # oracle's own order-of-summation noise floor
+    e = min(j, 5)
+    assert np.abs(hist[:e + 1] - hist_o[:e + 1]).max() <= 1e-12 * max(nb, hist_o[:e + 1].max())
+    floor = oracle_noise_floor(oracle_mod, A, b, 1e-10)
+    dev = np.max(np.abs(hist[:j + 1] - hist_o[:j + 1]) / hist_o[:j + 1])
+    assert dev <= 10 * floor + 1e-12, (dev, floor)
     assert hist[its] < 1e-10 * nb
     assert tr <= 2e-10
     # the oracle's own residual of the GPU solution
