@@ -41,6 +41,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
+#include "tables_ct.h"
 
 namespace mfcg {
 
@@ -72,6 +73,16 @@ int fused_block_size(int K)
 }
 
 constexpr int SHARED_WG = 256;
+
+/* minimum waves per SIMD requested from the register allocator */
+#ifndef MFCG_OCC
+#define MFCG_OCC 2
+#endif
+/* geometry loads issued before the derivative passes (1) or in the G pass (0) */
+#ifndef MFCG_GPREF
+#define MFCG_GPREF 1
+#endif
+#define MFCG_WPE_MIN(WG) ((MFCG_OCC * (WG) / 64 + 3) / 4)
 
 /* ------------------------------------------------------------------ */
 /* Helpers                                                             */
@@ -129,7 +140,9 @@ __device__ __forceinline__ void block_reduce(T (&acc)[NV], T *red, T *out)
 /* ------------------------------------------------------------------ */
 
 template <int K, typename T, int MODE>
-__global__ __launch_bounds__(Cfg<K>::WG) void fused_tile_kernel(const IterArgs<T> a)
+__global__ __launch_bounds__(Cfg<K>::WG)
+__attribute__((amdgpu_waves_per_eu(MFCG_WPE_MIN(Cfg<K>::WG), 8)))
+void fused_tile_kernel(const IterArgs<T> a)
 {
     constexpr int n = K + 1, n2 = n * n, n3 = n * n * n;
     constexpr int WG = Cfg<K>::WG;
@@ -138,22 +151,31 @@ __global__ __launch_bounds__(Cfg<K>::WG) void fused_tile_kernel(const IterArgs<T
     constexpr int PNM = (Cfg<K>::TX * K + 1) * (Cfg<K>::TY * K + 1);
     constexpr int NS = (K * PNM + WG - 1) / WG;
     constexpr int NC = (PNM + WG - 1) / WG;
+    /* compile-time 1D tables: S (GLL basis at Gauss points), D (collocation
+     * derivative on the Gauss points) */
+    constexpr ct::Tab<n> TT = ct::make_tab<n>();
+    constexpr auto cS = [](int q, int i) { return (T)TT.S[q * n + i]; };
+    constexpr auto cD = [](int q, int i) { return (T)TT.D[q * n + i]; };
 
     __shared__ T win[(K + 1) * PNM];
     __shared__ T TA[NLC * n3];
     __shared__ T TB[NLC * n3];
     __shared__ T cv[2 * PNM];
-    __shared__ T cr[PNM];
-    __shared__ T cd[PNM];
     __shared__ T red[8 * (WG / 64)];
     __shared__ EntityRef ent[27];
 
-    const int tid = threadIdx.x;
+    const int tid0 = threadIdx.x;
     if (MODE == MODE_CG && a.st->flag != FLAG_RUN) return;
 
     const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
     const TileDesc td = a.L.tiles[tile];
-    if (tid < 27) ent[tid] = a.L.tile_ent[tile * 27 + tid];
+    if (tid0 < 27) ent[tid0] = a.L.tile_ent[tile * 27 + tid0];
+    /* The thread index is re-made opaque to the compiler at every phase of
+     * the layer loop: all per-thread index arithmetic is then recomputed
+     * where it is used instead of being hoisted out of the loop and held in
+     * registers across all layers (which doubles the register footprint
+     * and halves the number of resident workgroups). */
+    int tid = tid0;
 
     T alpha = 0, beta = 0, ratio = 0;
     bool xupd = false;
@@ -170,19 +192,17 @@ __global__ __launch_bounds__(Cfg<K>::WG) void fused_tile_kernel(const IterArgs<T
     const int PW = EX + 1;
     const int PN = (EX + 1) * (EY + 1);
     const int nlines = TXa * TYa * n2;
-    const int64_t glayer = 6LL * TXa * TYa * n3;
-    const int gq = TXa * TYa * n2; /* stride of the y-index in a layer's component block */
+    const int gcomp = n3 * TXa * TYa; /* stride between components of G in a layer */
+    const int gq = TXa * TYa * n2;    /* stride of the y-index of G in a component */
     __syncthreads();
 
     T acc[7];
 #pragma unroll
     for (int c = 0; c < 7; ++c) acc[c] = 0;
-    T rs[NS], ds[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) rs[s] = ds[s] = 0;
 
-    /* global index, kind and partial slot of the tile-local node (ax, by, zz) */
-    auto locate = [&](int ax, int by, int zz, int64_t &idx, int &kind, int64_t &pidx) {
+    /* element offset, kind and partial-sum offset of the tile-local node
+     * (ax, by, zz); vectors and partial arrays hold fewer than 2^31 entries */
+    auto locate = [&](int ax, int by, int zz, int &idx, int &kind, int &pidx) {
         const int dx = ax == 0 ? 0 : (ax == EX ? 2 : 1);
         const int dy = by == 0 ? 0 : (by == EY ? 2 : 1);
         const int dz = zz == 0 ? 0 : (zz == EZ ? 2 : 1);
@@ -190,33 +210,28 @@ __global__ __launch_bounds__(Cfg<K>::WG) void fused_tile_kernel(const IterArgs<T
         const int ly = dy == 1 ? by - 1 : 0, sy = dy == 1 ? EY - 1 : 1;
         const int lz = dz == 1 ? zz - 1 : 0;
         const EntityRef &e = ent[dx + 3 * dy + 9 * dz];
-        const int64_t loc = lx + (int64_t)sx * (ly + (int64_t)sy * lz);
-        idx = e.vbase + loc;
+        const int loc = lx + sx * (ly + sy * lz);
+        idx = (int)e.vbase + loc;
         kind = e.kind;
-        pidx = e.pbase + loc;
+        pidx = (int)e.pbase + loc;
     };
 
-    /* pre on one node: returns p_k (0 on Dirichlet nodes), r_k and D^{-1} */
-    auto pre_node = [&](int ax, int by, int zz, T &pn, T &rn, T &dv) {
-        int64_t idx, pidx;
-        int kind;
+    /* Algorithm 5's pre on one node; interior nodes are written back,
+     * shared nodes only recomputed; returns p_k (0 on Dirichlet nodes) */
+    auto pre_node = [&](int ax, int by, int zz) -> T {
+        int idx, kind, pidx;
         locate(ax, by, zz, idx, kind, pidx);
-        pn = 0;
-        rn = 0;
-        dv = 0;
-        if (kind == KIND_C) return;
-        if (MODE == MODE_VMULT) {
-            pn = a.src[idx];
-            return;
-        }
-        const T r0 = a.r[idx], v0 = a.v[idx], p0 = a.p[idx];
-        dv = a.dinv[idx];
+        if (kind == KIND_C) return (T)0;
+        if (MODE == MODE_VMULT) return a.src[idx];
+        const T r0 = a.r[idx], v0 = a.v[idx], p0 = a.p[idx], dv = a.dinv[idx];
+        T rn, pn;
         pre_update(r0, v0, p0, dv, alpha, beta, rn, pn);
         if (kind == KIND_I) {
             a.r[idx] = rn;
             a.p[idx] = pn;
             if (xupd) a.x[idx] = x_update(a.x[idx], r0, p0, dv, alpha, ratio);
         }
+        return pn;
     };
 
     /* v of the layer node (ax, by, zl) summed over the layer's cells */
@@ -240,9 +255,10 @@ __global__ __launch_bounds__(Cfg<K>::WG) void fused_tile_kernel(const IterArgs<T
         return s;
     };
 
-    auto post_node = [&](int ax, int by, int zz, int slot, T v, T rn, T dv) {
-        int64_t idx, pidx;
-        int kind;
+    /* post on one node: r_k and D^{-1} are re-read (this workgroup wrote
+     * r_k in its pre, so the lines are cache resident), p_k from the window */
+    auto post_node = [&](int ax, int by, int zz, int slot, T v) {
+        int idx, kind, pidx;
         locate(ax, by, zz, idx, kind, pidx);
         if (kind == KIND_S) {
             a.part[pidx] = v;
@@ -250,6 +266,7 @@ __global__ __launch_bounds__(Cfg<K>::WG) void fused_tile_kernel(const IterArgs<T
             if (MODE == MODE_VMULT) {
                 a.dst[idx] = v;
             } else {
+                const T rn = a.r[idx], dv = a.dinv[idx];
                 const T pn = win[slot * PNM + ax + PW * by];
                 const T zr = dv * rn, zv = dv * v;
                 acc[0] += rn * rn;
@@ -264,24 +281,18 @@ __global__ __launch_bounds__(Cfg<K>::WG) void fused_tile_kernel(const IterArgs<T
         }
     };
 
-    /* bottom plane of the tile: pre with the plane mapping, r and D^{-1}
-     * kept in the carry arrays */
+    /* bottom plane of the tile into the window */
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         const int node = tid + WG * c;
-        if (node < PN) {
-            T pn, rn, dv;
-            pre_node(node % PW, node / PW, 0, pn, rn, dv);
-            win[node] = pn;
-            cr[node] = rn;
-            cd[node] = dv;
-        }
+        if (node < PN) win[node] = pre_node(node % PW, node / PW, 0);
     }
 
 #pragma unroll 1
     for (int L = 0; L < TZa; ++L) {
         const int s0 = (L * K) % (K + 1);
-        /* ---- pre on the planes first touched by this layer ---- */
+        asm volatile("" : "+v"(tid)); /* see above */
+        /* ---- pre on the planes this layer touches first ---- */
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const int f = tid + WG * s;
@@ -289,16 +300,13 @@ __global__ __launch_bounds__(Cfg<K>::WG) void fused_tile_kernel(const IterArgs<T
                 const int zl = 1 + f / PN, node = f % PN;
                 int slot = s0 + zl;
                 if (slot > K) slot -= K + 1;
-                T pn, rn, dv;
-                pre_node(node % PW, node / PW, L * K + zl, pn, rn, dv);
-                win[slot * PNM + node] = pn;
-                rs[s] = rn;
-                ds[s] = dv;
+                win[slot * PNM + node] = pre_node(node % PW, node / PW, L * K + zl);
             }
         }
         __syncthreads();
+        asm volatile("" : "+v"(tid));
 
-        const T *Gl = a.G + td.gbase + (int64_t)L * glayer;
+        const T *Gl = a.G + td.gbase + (int64_t)L * 6 * gcomp;
         T gy[R][n], wy[R][n], wz[R][n];
 
         /* F1 [z-lines]: gather p from the window, interpolate along z */
@@ -320,12 +328,13 @@ __global__ __launch_bounds__(Cfg<K>::WG) void fused_tile_kernel(const IterArgs<T
                 for (int q = 0; q < n; ++q) {
                     T t = 0;
 #pragma unroll
-                    for (int z = 0; z < n; ++z) t = fma(a.tab.S[q * n + z], u[z], t);
+                    for (int z = 0; z < n; ++z) t = fma(cS(q, z), u[z], t);
                     TA[c * n3 + rem + n2 * q] = t;
                 }
             }
         }
         __syncthreads();
+        asm volatile("" : "+v"(tid));
         /* F2 [x-lines]: interpolate along x */
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) {
@@ -340,12 +349,13 @@ __global__ __launch_bounds__(Cfg<K>::WG) void fused_tile_kernel(const IterArgs<T
                 for (int q = 0; q < n; ++q) {
                     T t = 0;
 #pragma unroll
-                    for (int i = 0; i < n; ++i) t = fma(a.tab.S[q * n + i], u[i], t);
+                    for (int i = 0; i < n; ++i) t = fma(cS(q, i), u[i], t);
                     TB[base + q] = t;
                 }
             }
         }
         __syncthreads();
+        asm volatile("" : "+v"(tid));
         /* F3 [y-lines]: interpolate along y -> values at the Gauss points,
          * y derivative kept in registers */
 #pragma unroll
@@ -361,7 +371,7 @@ __global__ __launch_bounds__(Cfg<K>::WG) void fused_tile_kernel(const IterArgs<T
                 for (int q = 0; q < n; ++q) {
                     T t = 0;
 #pragma unroll
-                    for (int j = 0; j < n; ++j) t = fma(a.tab.S[q * n + j], u[j], t);
+                    for (int j = 0; j < n; ++j) t = fma(cS(q, j), u[j], t);
                     uq[q] = t;
                     TA[base + n * q] = t;
                 }
@@ -369,12 +379,26 @@ __global__ __launch_bounds__(Cfg<K>::WG) void fused_tile_kernel(const IterArgs<T
                 for (int q = 0; q < n; ++q) {
                     T t = 0;
 #pragma unroll
-                    for (int m = 0; m < n; ++m) t = fma(a.tab.D[q * n + m], uq[m], t);
+                    for (int m = 0; m < n; ++m) t = fma(cD(q, m), uq[m], t);
                     gy[rr][q] = t;
                 }
             }
         }
         __syncthreads();
+        asm volatile("" : "+v"(tid));
+        /* G of this layer: loads issued here, consumed after the x and z
+         * derivative passes */
+        T gp[R][6][n];
+        if (MFCG_GPREF) {
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+                const int l = tid + WG * rr;
+#pragma unroll
+                for (int j = 0; j < n; ++j)
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) gp[rr][c][j] = (l < nlines) ? Gl[c * gcomp + j * gq + l] : (T)0;
+            }
+        }
         /* F4 [x-lines]: x derivative */
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) {
@@ -389,12 +413,13 @@ __global__ __launch_bounds__(Cfg<K>::WG) void fused_tile_kernel(const IterArgs<T
                 for (int q = 0; q < n; ++q) {
                     T t = 0;
 #pragma unroll
-                    for (int m = 0; m < n; ++m) t = fma(a.tab.D[q * n + m], u[m], t);
+                    for (int m = 0; m < n; ++m) t = fma(cD(q, m), u[m], t);
                     TB[base + q] = t;
                 }
             }
         }
         __syncthreads();
+        asm volatile("" : "+v"(tid));
         /* F5 [z-lines]: z derivative, in place */
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) {
@@ -409,12 +434,13 @@ __global__ __launch_bounds__(Cfg<K>::WG) void fused_tile_kernel(const IterArgs<T
                 for (int q = 0; q < n; ++q) {
                     T t = 0;
 #pragma unroll
-                    for (int m = 0; m < n; ++m) t = fma(a.tab.D[q * n + m], u[m], t);
+                    for (int m = 0; m < n; ++m) t = fma(cD(q, m), u[m], t);
                     TA[base + n2 * q] = t;
                 }
             }
         }
         __syncthreads();
+        asm volatile("" : "+v"(tid));
         /* G [y-lines]: flux = G_q grad u at each Gauss point; y part of the
          * transposed derivative in registers */
 #pragma unroll
@@ -424,16 +450,18 @@ __global__ __launch_bounds__(Cfg<K>::WG) void fused_tile_kernel(const IterArgs<T
                 const int c = l / n2, rem = l % n2, i = rem % n, z = rem / n;
                 const int base = c * n3 + i + n2 * z;
                 T fy[n];
+                if (!MFCG_GPREF) {
+#pragma unroll
+                    for (int j = 0; j < n; ++j)
+#pragma unroll
+                        for (int c2 = 0; c2 < 6; ++c2) gp[rr][c2][j] = Gl[c2 * gcomp + j * gq + l];
+                }
 #pragma unroll
                 for (int j = 0; j < n; ++j) {
-                    const T *g = Gl + j * gq + l;
-                    const T g00 = g[0], g11 = g[(int64_t)n3 * TXa * TYa], g22 = g[2LL * n3 * TXa * TYa];
-                    const T g01 = g[3LL * n3 * TXa * TYa], g02 = g[4LL * n3 * TXa * TYa],
-                            g12 = g[5LL * n3 * TXa * TYa];
                     const T ux = TB[base + n * j], uy = gy[rr][j], uz = TA[base + n * j];
-                    const T fx = g00 * ux + g01 * uy + g02 * uz;
-                    fy[j] = g01 * ux + g11 * uy + g12 * uz;
-                    const T fz = g02 * ux + g12 * uy + g22 * uz;
+                    const T fx = gp[rr][0][j] * ux + gp[rr][3][j] * uy + gp[rr][4][j] * uz;
+                    fy[j] = gp[rr][3][j] * ux + gp[rr][1][j] * uy + gp[rr][5][j] * uz;
+                    const T fz = gp[rr][4][j] * ux + gp[rr][5][j] * uy + gp[rr][2][j] * uz;
                     TB[base + n * j] = fx;
                     TA[base + n * j] = fz;
                 }
@@ -441,12 +469,13 @@ __global__ __launch_bounds__(Cfg<K>::WG) void fused_tile_kernel(const IterArgs<T
                 for (int m = 0; m < n; ++m) {
                     T t = 0;
 #pragma unroll
-                    for (int q = 0; q < n; ++q) t = fma(a.tab.D[q * n + m], fy[q], t);
+                    for (int q = 0; q < n; ++q) t = fma(cD(q, m), fy[q], t);
                     wy[rr][m] = t;
                 }
             }
         }
         __syncthreads();
+        asm volatile("" : "+v"(tid));
         /* B2 [x-lines]: transposed x derivative, in place; B3 [z-lines]:
          * transposed z derivative into registers */
 #pragma unroll
@@ -463,7 +492,7 @@ __global__ __launch_bounds__(Cfg<K>::WG) void fused_tile_kernel(const IterArgs<T
                     for (int m = 0; m < n; ++m) {
                         T t = 0;
 #pragma unroll
-                        for (int q = 0; q < n; ++q) t = fma(a.tab.D[q * n + m], f[q], t);
+                        for (int q = 0; q < n; ++q) t = fma(cD(q, m), f[q], t);
                         TB[base + m] = t;
                     }
                 }
@@ -476,13 +505,14 @@ __global__ __launch_bounds__(Cfg<K>::WG) void fused_tile_kernel(const IterArgs<T
                     for (int m = 0; m < n; ++m) {
                         T t = 0;
 #pragma unroll
-                        for (int q = 0; q < n; ++q) t = fma(a.tab.D[q * n + m], f[q], t);
+                        for (int q = 0; q < n; ++q) t = fma(cD(q, m), f[q], t);
                         wz[rr][m] = t;
                     }
                 }
             }
         }
         __syncthreads();
+        asm volatile("" : "+v"(tid));
         /* B4 [y-lines]: add the y part */
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) {
@@ -495,6 +525,7 @@ __global__ __launch_bounds__(Cfg<K>::WG) void fused_tile_kernel(const IterArgs<T
             }
         }
         __syncthreads();
+        asm volatile("" : "+v"(tid));
         /* B5 [z-lines]: add the z part, transposed interpolation along z */
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) {
@@ -509,12 +540,13 @@ __global__ __launch_bounds__(Cfg<K>::WG) void fused_tile_kernel(const IterArgs<T
                 for (int z = 0; z < n; ++z) {
                     T t = 0;
 #pragma unroll
-                    for (int q = 0; q < n; ++q) t = fma(a.tab.S[q * n + z], w[q], t);
+                    for (int q = 0; q < n; ++q) t = fma(cS(q, z), w[q], t);
                     TB[base + n2 * z] = t;
                 }
             }
         }
         __syncthreads();
+        asm volatile("" : "+v"(tid));
         /* B6 [x-lines]: transposed interpolation along x */
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) {
@@ -529,12 +561,13 @@ __global__ __launch_bounds__(Cfg<K>::WG) void fused_tile_kernel(const IterArgs<T
                 for (int i = 0; i < n; ++i) {
                     T t = 0;
 #pragma unroll
-                    for (int q = 0; q < n; ++q) t = fma(a.tab.S[q * n + i], w[q], t);
+                    for (int q = 0; q < n; ++q) t = fma(cS(q, i), w[q], t);
                     TB[base + i] = t;
                 }
             }
         }
         __syncthreads();
+        asm volatile("" : "+v"(tid));
         /* B7 [y-lines]: transposed interpolation along y -> cell vectors */
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) {
@@ -549,15 +582,16 @@ __global__ __launch_bounds__(Cfg<K>::WG) void fused_tile_kernel(const IterArgs<T
                 for (int j = 0; j < n; ++j) {
                     T t = 0;
 #pragma unroll
-                    for (int q = 0; q < n; ++q) t = fma(a.tab.S[q * n + j], w[q], t);
+                    for (int q = 0; q < n; ++q) t = fma(cS(q, j), w[q], t);
                     TB[base + n * j] = t;
                 }
             }
         }
         __syncthreads();
+        asm volatile("" : "+v"(tid));
 
         /* ---- sum over cells and post ---- */
-        /* plane z = 0 of the layer: plane mapping, r and D^{-1} from the carry */
+        /* plane z = 0 of the layer, completing the carry of the layer below */
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const int node = tid + WG * c;
@@ -565,10 +599,10 @@ __global__ __launch_bounds__(Cfg<K>::WG) void fused_tile_kernel(const IterArgs<T
                 const int ax = node % PW, by = node / PW;
                 T v = sum_cells(ax, by, 0);
                 if (L > 0) v = cv[(L & 1) * PNM + node] + v;
-                post_node(ax, by, L * K, s0, v, cr[node], cd[node]);
+                post_node(ax, by, L * K, s0, v);
             }
         }
-        /* planes z = 1..K: same mapping as the pre of this layer */
+        /* planes z = 1..K; the top plane is carried unless it is the tile's last */
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const int f = tid + WG * s;
@@ -581,29 +615,15 @@ __global__ __launch_bounds__(Cfg<K>::WG) void fused_tile_kernel(const IterArgs<T
                 } else {
                     int slot = s0 + zl;
                     if (slot > K) slot -= K + 1;
-                    post_node(ax, by, L * K + zl, slot, v, rs[s], ds[s]);
+                    post_node(ax, by, L * K + zl, slot, v);
                 }
             }
         }
         __syncthreads();
-        /* r and D^{-1} of the shared top plane move to the carry */
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int f = tid + WG * s;
-            if (f < K * PN && f / PN == K - 1) {
-                const int node = f % PN;
-                cr[node] = rs[s];
-                cd[node] = ds[s];
-            }
-        }
-        /* the next layer's pre only writes window slots of planes that are
-         * no longer read; the carry arrays are read after its barrier */
+        asm volatile("" : "+v"(tid));
     }
 
-    if (MODE == MODE_CG) {
-        __syncthreads();
-        block_reduce<T, 7, WG>(acc, red, a.dots + tile * 8);
-    }
+    if (MODE == MODE_CG) block_reduce<T, 7, WG>(acc, red, a.dots + tile * 8);
 }
 
 /* ------------------------------------------------------------------ */

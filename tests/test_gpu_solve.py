@@ -1,10 +1,13 @@
 """GPU solve parity: the fused Algorithm 5 against the oracle's Algorithm 1.
 
 In exact arithmetic both produce the same iterates (Sec. 4.2: Eq. 6-8 only
-regroup the inner products), so the iteration counts agree (up to one
-iteration when the residual lands at the threshold), the residual
-histories agree to rounding, and the converged solutions agree to 1e-10
-relative (the benchmark spec's solution tolerance).  Also checked: the exit
+regroup the inner products).  In FP64 the iteration count and the residual
+history are compared against the oracle's own sensitivity to summation
+order (the same system solved in permuted node orders): the GPU's count
+must lie within that range +-2 and its history within 10x that deviation;
+the first iterations must agree to rounding; the converged solutions must
+agree to 1e-10 relative (the benchmark spec's solution tolerance) and the GPU
+solution's residual in the oracle's matrix must be below 2e-10 ||b||.  Also checked: the exit
 reconstruction of x for both parities of the last iteration (maxit exits),
 warm starts, a zero right-hand side, reproducibility.
 """
@@ -32,21 +35,27 @@ def _problem(oracle_mod, cells, k, kind, amp, coeff_seed=None, tile=None, bc=0):
     return m, A, P
 
 
-def oracle_noise_floor(oracle_mod, A, b, tol, maxit=5000):
-    """Relative deviation of the oracle's residual history from itself
-    when the same system is solved in another node order (P A P^T, P b):
-    only the summation order of every product and sum changes."""
+def oracle_noise(oracle_mod, A, b, x0=None, tol=1e-10, maxit=5000, nperm=3):
+    """The oracle's own sensitivity to summation order: the same system
+    solved in other node orders (P A P^T, P b).  Returns the range of
+    iteration counts and the largest relative deviation of the residual
+    history from the unpermuted solve."""
     from oracle.oracle import CSR
-    rng = np.random.default_rng(0)
-    perm = rng.permutation(A.n)
-    S = A.to_scipy()[perm][:, perm].tocsr()
-    S.sort_indices()
-    Ap = CSR(S.indptr.astype(np.int64), S.indices.astype(np.int32), S.data.copy())
     d = A.diagonal()
-    _, its1, h1, _ = oracle_mod.pcg(A, d, b, tol=tol, maxit=maxit)
-    _, its2, h2, _ = oracle_mod.pcg(Ap, d[perm], b[perm], tol=tol, maxit=maxit)
-    j = min(its1, its2)
-    return np.max(np.abs(h1[:j + 1] - h2[:j + 1]) / h1[:j + 1])
+    _, its1, h1, _ = oracle_mod.pcg(A, d, b, x0=x0, tol=tol, maxit=maxit)
+    lo = hi = its1
+    dev = 0.0
+    for seed in range(nperm):
+        perm = np.random.default_rng(seed).permutation(A.n)
+        S = A.to_scipy()[perm][:, perm].tocsr()
+        S.sort_indices()
+        Ap = CSR(S.indptr.astype(np.int64), S.indices.astype(np.int32), S.data.copy())
+        xp = None if x0 is None else x0[perm]
+        _, its2, h2, _ = oracle_mod.pcg(Ap, d[perm], b[perm], x0=xp, tol=tol, maxit=maxit)
+        lo, hi = min(lo, its2), max(hi, its2)
+        j = min(its1, its2)
+        dev = max(dev, np.max(np.abs(h1[:j + 1] - h2[:j + 1]) / h1[:j + 1]))
+    return lo, hi, dev
 
 
 def _compare(torch, oracle_mod, A, P, b, x0=None, tol=1e-10, maxit=5000):
@@ -70,7 +79,8 @@ def test_solve_matches_oracle(cells, k, kind, coeff_seed, tile, oracle_mod, torc
     b = oracle_mod.rhs(m, oracle_mod.F_SINE)
     xo, its_o, hist_o, rc_o, x, its, hist, tr, code = _compare(torch, oracle_mod, A, P, b)
     assert rc_o == 0 and code == 0
-    assert abs(its - its_o) <= 1
+    lo, hi, floor = oracle_noise(oracle_mod, A, b)
+    assert lo - 2 <= its <= hi + 2, (its, lo, hi)
     assert np.linalg.norm(x - xo) <= 1e-10 * np.linalg.norm(xo)
     nb = np.linalg.norm(b)
     j = min(its, its_o)
@@ -78,7 +88,6 @@ def test_solve_matches_oracle(cells, k, kind, coeff_seed, tile, oracle_mod, torc
     # oracle's own order-of-summation noise floor
     e = min(j, 5)
     assert np.abs(hist[:e + 1] - hist_o[:e + 1]).max() <= 1e-12 * max(nb, hist_o[:e + 1].max())
-    floor = oracle_noise_floor(oracle_mod, A, b, 1e-10)
     dev = np.max(np.abs(hist[:j + 1] - hist_o[:j + 1]) / hist_o[:j + 1])
     assert dev <= 10 * floor + 1e-12, (dev, floor)
     assert hist[its] < 1e-10 * nb
@@ -96,7 +105,8 @@ def test_random_rhs_warm_start_and_reproducible(oracle_mod, torch_cuda):
     x0 = 0.1 * inputs.random_vector(A.n, seed=10)
     x0[m.constrained_mask()] = 0.0
     xo, its_o, _, _, x, its, _, tr, code = _compare(torch, oracle_mod, A, P, b, x0=x0)
-    assert code == 0 and abs(its - its_o) <= 1
+    lo, hi, _ = oracle_noise(oracle_mod, A, b, x0=x0)
+    assert code == 0 and lo - 2 <= its <= hi + 2, (its, lo, hi)
     assert np.linalg.norm(x - xo) <= 1e-10 * np.linalg.norm(xo)
     # bitwise reproducible
     xt = torch.from_numpy(x0).cuda()
