@@ -99,6 +99,16 @@ __device__ inline int64_t xcd_remap(int64_t b, int64_t nb)
     return x * q + (x < r ? x : r) + i;
 }
 
+/* Division by a divisor fixed for a workgroup, for dividends below 2^16:
+ * q = floor(n * ceil(2^32 / d) / 2^32) is exact when n, d < 2^16. */
+struct FastDiv {
+    uint32_t d, m;
+    __device__ __forceinline__ explicit FastDiv(uint32_t dd)
+        : d(dd), m(dd > 1 ? (uint32_t)((0x100000000ull + dd - 1) / dd) : 0u) {}
+    __device__ __forceinline__ int div(int n) const { return d > 1 ? (int)__umulhi((uint32_t)n, m) : n; }
+    __device__ __forceinline__ int mod(int n) const { return n - div(n) * (int)d; }
+};
+
 /* The "pre" update of one entry, shared by both kernels so that the value
  * a tile recomputes for a shared node is bitwise the value the shared-node
  * kernel stores. */
@@ -163,6 +173,12 @@ void fused_tile_kernel(const IterArgs<T> a)
     __shared__ T cv[2 * PNM];
     __shared__ T red[8 * (WG / 64)];
     __shared__ EntityRef ent[27];
+    /* per node of the tile's xy plane: x = entity class in x,y (dx + 3 dy)
+     * | stride of the entity's z index << 8, y = offset of (x,y) inside the
+     * entity, z/w = offsets into the cell scratch of the (up to) 4 cells
+     * around the node (16 bits each, 0xffff: no such cell), cell order
+     * (-x,-y), (+x,-y), (-x,+y), (+x,+y) */
+    __shared__ int4 desc[PNM];
 
     const int tid0 = threadIdx.x;
     if (MODE == MODE_CG && a.st->flag != FLAG_RUN) return;
@@ -194,23 +210,37 @@ void fused_tile_kernel(const IterArgs<T> a)
     const int nlines = TXa * TYa * n2;
     const int gcomp = n3 * TXa * TYa; /* stride between components of G in a layer */
     const int gq = TXa * TYa * n2;    /* stride of the y-index of G in a component */
+    const FastDiv dPW(PW), dPN(PN), dTX(TXa);
+    for (int node = tid0; node < PN; node += WG) {
+        const int by = dPW.div(node), ax = node - by * PW;
+        const int dx = ax == 0 ? 0 : (ax == EX ? 2 : 1);
+        const int dy = by == 0 ? 0 : (by == EY ? 2 : 1);
+        const int sx = dx == 1 ? EX - 1 : 1, sy = dy == 1 ? EY - 1 : 1;
+        const int lx = dx == 1 ? ax - 1 : 0, ly = dy == 1 ? by - 1 : 0;
+        const int cx1 = ax / K, cy1 = by / K;
+        const bool xl = (ax % K) == 0 && cx1 > 0, xr = cx1 < TXa;
+        const bool yl = (by % K) == 0 && cy1 > 0, yr = cy1 < TYa;
+        auto off = [&](int cx, int cy) { return (cx + TXa * cy) * n3 + (ax - cx * K) + n * (by - cy * K); };
+        const int o00 = (xl && yl) ? off(cx1 - 1, cy1 - 1) : 0xffff;
+        const int o01 = (xr && yl) ? off(cx1, cy1 - 1) : 0xffff;
+        const int o10 = (xl && yr) ? off(cx1 - 1, cy1) : 0xffff;
+        const int o11 = (xr && yr) ? off(cx1, cy1) : 0xffff;
+        desc[node] = make_int4((dx + 3 * dy) | ((sx * sy) << 8), lx + sx * ly, o00 | (o01 << 16), o10 | (o11 << 16));
+    }
     __syncthreads();
 
     T acc[7];
 #pragma unroll
     for (int c = 0; c < 7; ++c) acc[c] = 0;
 
-    /* element offset, kind and partial-sum offset of the tile-local node
-     * (ax, by, zz); vectors and partial arrays hold fewer than 2^31 entries */
-    auto locate = [&](int ax, int by, int zz, int &idx, int &kind, int &pidx) {
-        const int dx = ax == 0 ? 0 : (ax == EX ? 2 : 1);
-        const int dy = by == 0 ? 0 : (by == EY ? 2 : 1);
+    /* element offset, kind and partial-sum offset of the node with xy
+     * descriptor dsc on tile plane zz; vectors and partial arrays hold fewer
+     * than 2^31 entries */
+    auto locate = [&](const int4 &dsc, int zz, int &idx, int &kind, int &pidx) {
         const int dz = zz == 0 ? 0 : (zz == EZ ? 2 : 1);
-        const int lx = dx == 1 ? ax - 1 : 0, sx = dx == 1 ? EX - 1 : 1;
-        const int ly = dy == 1 ? by - 1 : 0, sy = dy == 1 ? EY - 1 : 1;
         const int lz = dz == 1 ? zz - 1 : 0;
-        const EntityRef &e = ent[dx + 3 * dy + 9 * dz];
-        const int loc = lx + sx * (ly + sy * lz);
+        const EntityRef &e = ent[(dsc.x & 0xff) + 9 * dz];
+        const int loc = dsc.y + (dsc.x >> 8) * lz;
         idx = (int)e.vbase + loc;
         kind = e.kind;
         pidx = (int)e.pbase + loc;
@@ -218,9 +248,9 @@ void fused_tile_kernel(const IterArgs<T> a)
 
     /* Algorithm 5's pre on one node; interior nodes are written back,
      * shared nodes only recomputed; returns p_k (0 on Dirichlet nodes) */
-    auto pre_node = [&](int ax, int by, int zz) -> T {
+    auto pre_node = [&](int node, int zz) -> T {
         int idx, kind, pidx;
-        locate(ax, by, zz, idx, kind, pidx);
+        locate(desc[node], zz, idx, kind, pidx);
         if (kind == KIND_C) return (T)0;
         if (MODE == MODE_VMULT) return a.src[idx];
         const T r0 = a.r[idx], v0 = a.v[idx], p0 = a.p[idx], dv = a.dinv[idx];
@@ -234,32 +264,23 @@ void fused_tile_kernel(const IterArgs<T> a)
         return pn;
     };
 
-    /* v of the layer node (ax, by, zl) summed over the layer's cells */
-    auto sum_cells = [&](int ax, int by, int zl) -> T {
-        const int cxa = ax / K, cya = by / K;
-        const bool bx = (ax % K) == 0, byy = (by % K) == 0;
-        T s = 0;
-#pragma unroll 1
-        for (int oy = 1; oy >= 0; --oy) {
-            const int cy = cya - oy;
-            if (oy == 1 && !byy) continue;
-            if (cy < 0 || cy >= TYa) continue;
-#pragma unroll 1
-            for (int ox = 1; ox >= 0; --ox) {
-                const int cx = cxa - ox;
-                if (ox == 1 && !bx) continue;
-                if (cx < 0 || cx >= TXa) continue;
-                s += TB[(cx + TXa * cy) * n3 + (ax - cx * K) + n * (by - cy * K) + n2 * zl];
-            }
-        }
-        return s;
+    /* v of a layer node summed over the cells around it, fixed order */
+    auto sum_cells = [&](const int4 &dsc, int zl) -> T {
+        const int o00 = dsc.z & 0xffff, o01 = (int)((unsigned)dsc.z >> 16);
+        const int o10 = dsc.w & 0xffff, o11 = (int)((unsigned)dsc.w >> 16);
+        const int zo = n2 * zl;
+        const T v00 = o00 != 0xffff ? TB[o00 + zo] : (T)0;
+        const T v01 = o01 != 0xffff ? TB[o01 + zo] : (T)0;
+        const T v10 = o10 != 0xffff ? TB[o10 + zo] : (T)0;
+        const T v11 = o11 != 0xffff ? TB[o11 + zo] : (T)0;
+        return ((v00 + v01) + v10) + v11;
     };
 
     /* post on one node: r_k and D^{-1} are re-read (this workgroup wrote
      * r_k in its pre, so the lines are cache resident), p_k from the window */
-    auto post_node = [&](int ax, int by, int zz, int slot, T v) {
+    auto post_node = [&](const int4 &dsc, int node, int zz, int slot, T v) {
         int idx, kind, pidx;
-        locate(ax, by, zz, idx, kind, pidx);
+        locate(dsc, zz, idx, kind, pidx);
         if (kind == KIND_S) {
             a.part[pidx] = v;
         } else if (kind == KIND_I) {
@@ -267,7 +288,7 @@ void fused_tile_kernel(const IterArgs<T> a)
                 a.dst[idx] = v;
             } else {
                 const T rn = a.r[idx], dv = a.dinv[idx];
-                const T pn = win[slot * PNM + ax + PW * by];
+                const T pn = win[slot * PNM + node];
                 const T zr = dv * rn, zv = dv * v;
                 acc[0] += rn * rn;
                 acc[1] += pn * v;
@@ -285,7 +306,7 @@ void fused_tile_kernel(const IterArgs<T> a)
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         const int node = tid + WG * c;
-        if (node < PN) win[node] = pre_node(node % PW, node / PW, 0);
+        if (node < PN) win[node] = pre_node(node, 0);
     }
 
 #pragma unroll 1
@@ -297,10 +318,10 @@ void fused_tile_kernel(const IterArgs<T> a)
         for (int s = 0; s < NS; ++s) {
             const int f = tid + WG * s;
             if (f < K * PN) {
-                const int zl = 1 + f / PN, node = f % PN;
+                const int zq = dPN.div(f), zl = 1 + zq, node = f - zq * PN;
                 int slot = s0 + zl;
                 if (slot > K) slot -= K + 1;
-                win[slot * PNM + node] = pre_node(node % PW, node / PW, L * K + zl);
+                win[slot * PNM + node] = pre_node(node, L * K + zl);
             }
         }
         __syncthreads();
@@ -315,7 +336,7 @@ void fused_tile_kernel(const IterArgs<T> a)
             const int l = tid + WG * rr;
             if (l < nlines) {
                 const int c = l / n2, rem = l % n2, i = rem % n, j = rem / n;
-                const int cx = c % TXa, cy = c / TXa;
+                const int cy = dTX.div(c), cx = c - cy * TXa;
                 const int nodexy = cx * K + i + PW * (cy * K + j);
                 T u[n];
 #pragma unroll
@@ -450,14 +471,12 @@ void fused_tile_kernel(const IterArgs<T> a)
                 const int c = l / n2, rem = l % n2, i = rem % n, z = rem / n;
                 const int base = c * n3 + i + n2 * z;
                 T fy[n];
-                if (!MFCG_GPREF) {
-#pragma unroll
-                    for (int j = 0; j < n; ++j)
-#pragma unroll
-                        for (int c2 = 0; c2 < 6; ++c2) gp[rr][c2][j] = Gl[c2 * gcomp + j * gq + l];
-                }
 #pragma unroll
                 for (int j = 0; j < n; ++j) {
+                    if (!MFCG_GPREF) {
+#pragma unroll
+                        for (int c2 = 0; c2 < 6; ++c2) gp[rr][c2][j] = Gl[c2 * gcomp + j * gq + l];
+                    }
                     const T ux = TB[base + n * j], uy = gy[rr][j], uz = TA[base + n * j];
                     const T fx = gp[rr][0][j] * ux + gp[rr][3][j] * uy + gp[rr][4][j] * uz;
                     fy[j] = gp[rr][3][j] * ux + gp[rr][1][j] * uy + gp[rr][5][j] * uz;
@@ -596,10 +615,10 @@ void fused_tile_kernel(const IterArgs<T> a)
         for (int c = 0; c < NC; ++c) {
             const int node = tid + WG * c;
             if (node < PN) {
-                const int ax = node % PW, by = node / PW;
-                T v = sum_cells(ax, by, 0);
+                const int4 dsc = desc[node];
+                T v = sum_cells(dsc, 0);
                 if (L > 0) v = cv[(L & 1) * PNM + node] + v;
-                post_node(ax, by, L * K, s0, v);
+                post_node(dsc, node, L * K, s0, v);
             }
         }
         /* planes z = 1..K; the top plane is carried unless it is the tile's last */
@@ -607,15 +626,15 @@ void fused_tile_kernel(const IterArgs<T> a)
         for (int s = 0; s < NS; ++s) {
             const int f = tid + WG * s;
             if (f < K * PN) {
-                const int zl = 1 + f / PN, node = f % PN;
-                const int ax = node % PW, by = node / PW;
-                const T v = sum_cells(ax, by, zl);
+                const int zq = dPN.div(f), zl = 1 + zq, node = f - zq * PN;
+                const int4 dsc = desc[node];
+                const T v = sum_cells(dsc, zl);
                 if (zl == K && L + 1 < TZa) {
                     cv[((L + 1) & 1) * PNM + node] = v;
                 } else {
                     int slot = s0 + zl;
                     if (slot > K) slot -= K + 1;
-                    post_node(ax, by, L * K + zl, slot, v);
+                    post_node(dsc, node, L * K + zl, slot, v);
                 }
             }
         }
