@@ -4,7 +4,7 @@
  * inner products embedded in the cell loop of the matrix-free operator,
  * Sec. 5), written for gfx950 (wave64, 160 KB LDS per CU).
  *
- * One iteration k is two launches:
+ * One iteration k is three launches:
  *
  *  fused_tile_kernel   one workgroup per tile of TX x TY x TZ cells,
  *                      streaming the tile's cell layers along z:
@@ -30,10 +30,10 @@
  *
  *  shared_node_kernel  grid-stride over shared and Dirichlet nodes: adds the
  *                      partial sums in a fixed slot order, applies pre and
- *                      post there, and the last block to arrive (atomic
- *                      ticket) reduces all per-block sums in a fixed order
- *                      and computes alpha_k, beta_k and the convergence test
- *                      on the device (single-pass finish).
+ *                      post there, writes per-block partial inner products.
+ *  finish_kernel       one block: reduces all per-block partials in a fixed
+ *                      order and computes alpha_k, beta_k and the convergence
+ *                      test on the device (no host round trip).
  *
  * Every reduction and every summation of partial contributions runs in a
  * fixed order, so a solve is bitwise reproducible.
@@ -81,6 +81,10 @@ constexpr int SHARED_WG = 256;
 /* geometry loads issued before the derivative passes (1) or in the G pass (0) */
 #ifndef MFCG_GPREF
 #define MFCG_GPREF 1
+#endif
+/* pre loads of the next layer issued before the current layer's cell passes */
+#ifndef MFCG_PREPF
+#define MFCG_PREPF 0
 #endif
 #define MFCG_WPE_MIN(WG) ((MFCG_OCC * (WG) / 64 + 3) / 4)
 
@@ -264,6 +268,40 @@ void fused_tile_kernel(const IterArgs<T> a)
         return pn;
     };
 
+    /* the same pre split in two: loads (into registers) and update */
+    struct PreLd {
+        T r, v, p, d, x;
+        int idx, kind;
+    };
+    auto pre_load = [&](int node, int zz, PreLd &q) {
+        int pidx;
+        locate(desc[node], zz, q.idx, q.kind, pidx);
+        q.r = q.v = q.p = q.d = q.x = 0;
+        if (q.kind == KIND_C) return;
+        if (MODE == MODE_VMULT) {
+            q.p = a.src[q.idx];
+            return;
+        }
+        q.r = a.r[q.idx];
+        q.v = a.v[q.idx];
+        q.p = a.p[q.idx];
+        q.d = a.dinv[q.idx];
+        if (xupd && q.kind == KIND_I) q.x = a.x[q.idx];
+    };
+    auto pre_apply = [&](const PreLd &q) -> T {
+        if (q.kind == KIND_C) return (T)0;
+        if (MODE == MODE_VMULT) return q.p;
+        T rn, pn;
+        pre_update(q.r, q.v, q.p, q.d, alpha, beta, rn, pn);
+        if (q.kind == KIND_I) {
+            a.r[q.idx] = rn;
+            a.p[q.idx] = pn;
+            if (xupd) a.x[q.idx] = x_update(q.x, q.r, q.p, q.d, alpha, ratio);
+        }
+        return pn;
+    };
+    PreLd pq[NS];
+
     /* v of a layer node summed over the cells around it, fixed order */
     auto sum_cells = [&](const int4 &dsc, int zl) -> T {
         const int o00 = dsc.z & 0xffff, o01 = (int)((unsigned)dsc.z >> 16);
@@ -313,6 +351,19 @@ void fused_tile_kernel(const IterArgs<T> a)
     for (int L = 0; L < TZa; ++L) {
         const int s0 = (L * K) % (K + 1);
         asm volatile("" : "+v"(tid)); /* see above */
+        const T *Gl = a.G + td.gbase + (int64_t)L * 6 * gcomp;
+        T gp[R][6][n];
+        if (MFCG_GPREF == 2) {
+            /* G of this layer issued first: its latency overlaps the pre loads */
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+                const int l = tid + WG * rr;
+#pragma unroll
+                for (int j = 0; j < n; ++j)
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) gp[rr][c][j] = (l < nlines) ? Gl[c * gcomp + j * gq + l] : (T)0;
+            }
+        }
         /* ---- pre on the planes this layer touches first ---- */
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -321,13 +372,29 @@ void fused_tile_kernel(const IterArgs<T> a)
                 const int zq = dPN.div(f), zl = 1 + zq, node = f - zq * PN;
                 int slot = s0 + zl;
                 if (slot > K) slot -= K + 1;
-                win[slot * PNM + node] = pre_node(node, L * K + zl);
+                if (MFCG_PREPF) {
+                    if (L == 0) pre_load(node, zl, pq[s]);
+                    win[slot * PNM + node] = pre_apply(pq[s]);
+                } else {
+                    win[slot * PNM + node] = pre_node(node, L * K + zl);
+                }
             }
         }
         __syncthreads();
+        asm volatile("" : "+v"(tid)); /* see above */
+        if (MFCG_PREPF && L + 1 < TZa) {
+            /* loads of the next layer's pre: in flight during the cell passes */
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const int f = tid + WG * s;
+                if (f < K * PN) {
+                    const int zq = dPN.div(f), node = f - zq * PN;
+                    pre_load(node, (L + 1) * K + 1 + zq, pq[s]);
+                }
+            }
+        }
         asm volatile("" : "+v"(tid));
 
-        const T *Gl = a.G + td.gbase + (int64_t)L * 6 * gcomp;
         T gy[R][n], wy[R][n], wz[R][n];
 
         /* F1 [z-lines]: gather p from the window, interpolate along z */
@@ -409,8 +476,7 @@ void fused_tile_kernel(const IterArgs<T> a)
         asm volatile("" : "+v"(tid));
         /* G of this layer: loads issued here, consumed after the x and z
          * derivative passes */
-        T gp[R][6][n];
-        if (MFCG_GPREF) {
+        if (MFCG_GPREF == 1) {
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) {
                 const int l = tid + WG * rr;
@@ -652,13 +718,23 @@ void fused_tile_kernel(const IterArgs<T> a)
 template <typename T>
 __device__ void finish_iteration(const IterArgs<T> &a, int64_t nparts, T *red)
 {
-    /* fixed-order sums of the 7 inner products over all per-block partials */
+    /* fixed-order sums of the 7 inner products over all per-block partials;
+     * every thread owns a fixed strided subset, loads issued 4 records at a time */
     T acc[7];
 #pragma unroll
     for (int c = 0; c < 7; ++c) acc[c] = 0;
-    for (int64_t b = threadIdx.x; b < nparts; b += SHARED_WG) {
+    for (int64_t b0 = threadIdx.x; b0 < nparts; b0 += 4 * SHARED_WG) {
+        T rec[4][7];
 #pragma unroll
-        for (int c = 0; c < 7; ++c) acc[c] += a.dots[b * 8 + c];
+        for (int u = 0; u < 4; ++u) {
+            const int64_t b = b0 + (int64_t)u * SHARED_WG;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) rec[u][c] = b < nparts ? a.dots[b * 8 + c] : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < 7; ++c) acc[c] += rec[u][c];
     }
     __shared__ T tot[8];
     block_reduce<T, 7, SHARED_WG>(acc, red, tot);
@@ -698,11 +774,14 @@ __device__ void finish_iteration(const IterArgs<T> &a, int64_t nparts, T *red)
     }
 }
 
+/* nodes per thread of the shared-node kernel, processed with their loads
+ * issued together */
+constexpr int SH_UNROLL = 4;
+
 template <typename T, int MODE>
 __global__ __launch_bounds__(SHARED_WG) void shared_node_kernel(const IterArgs<T> a)
 {
     __shared__ T red[8 * (SHARED_WG / 64)];
-    __shared__ int last;
     if (MODE == MODE_CG && a.st->flag != FLAG_RUN) return;
     const LayoutView &L = a.L;
 
@@ -720,61 +799,81 @@ __global__ __launch_bounds__(SHARED_WG) void shared_node_kernel(const IterArgs<T
     for (int c = 0; c < 7; ++c) acc[c] = 0;
 
     const int64_t stride = (int64_t)gridDim.x * SHARED_WG;
-    for (int64_t i = L.offF + (int64_t)blockIdx.x * SHARED_WG + threadIdx.x; i < L.n; i += stride) {
-        T v = 0;
-        bool cons = false;
-        if (i < L.offE) {
-            const int64_t j = i - L.offF;
-            v = a.part[L.partF + j] + a.part[L.partF + L.nF + j];
-        } else if (i < L.offV) {
-            const int64_t j = i - L.offE;
-            const T *q = a.part + L.partE + j;
-            v = ((q[0] + q[L.nE]) + q[2 * L.nE]) + q[3 * L.nE];
-        } else if (i < L.offC) {
-            const int64_t j = i - L.offV;
-            const T *q = a.part + L.partV + j;
-            v = q[0];
+    for (int64_t i0 = L.offF + (int64_t)blockIdx.x * SHARED_WG + threadIdx.x; i0 < L.n; i0 += SH_UNROLL * stride) {
+        T vs[SH_UNROLL], r0[SH_UNROLL], v0[SH_UNROLL], p0[SH_UNROLL], dv[SH_UNROLL], x0[SH_UNROLL];
+        bool ok[SH_UNROLL], cons[SH_UNROLL];
 #pragma unroll
-            for (int s = 1; s < 8; ++s) v += q[s * L.nV];
-        } else {
-            cons = true;
+        for (int u = 0; u < SH_UNROLL; ++u) {
+            const int64_t i = i0 + u * stride;
+            ok[u] = i < L.n;
+            cons[u] = i >= L.offC;
+            T v = 0;
+            if (ok[u]) {
+                if (i < L.offE) {
+                    const int64_t j = i - L.offF;
+                    v = a.part[L.partF + j] + a.part[L.partF + L.nF + j];
+                } else if (i < L.offV) {
+                    const T *q = a.part + L.partE + (i - L.offE);
+                    v = ((q[0] + q[L.nE]) + q[2 * L.nE]) + q[3 * L.nE];
+                } else if (i < L.offC) {
+                    const T *q = a.part + L.partV + (i - L.offV);
+                    v = q[0];
+#pragma unroll
+                    for (int s = 1; s < 8; ++s) v += q[s * L.nV];
+                }
+                if (MODE == MODE_CG) {
+                    r0[u] = a.r[i];
+                    v0[u] = a.v[i];
+                    p0[u] = a.p[i];
+                    dv[u] = a.dinv[i];
+                    x0[u] = xupd ? a.x[i] : (T)0;
+                } else if (cons[u]) {
+                    v = a.src[i];
+                }
+            }
+            vs[u] = v;
         }
-        if (MODE == MODE_VMULT) {
-            a.dst[i] = cons ? a.src[i] : v;
-            continue;
+#pragma unroll
+        for (int u = 0; u < SH_UNROLL; ++u) {
+            if (!ok[u]) continue;
+            const int64_t i = i0 + u * stride;
+            if (MODE == MODE_VMULT) {
+                a.dst[i] = vs[u];
+                continue;
+            }
+            T rn, pn;
+            pre_update(r0[u], v0[u], p0[u], dv[u], alpha, beta, rn, pn);
+            if (xupd) a.x[i] = x_update(x0[u], r0[u], p0[u], dv[u], alpha, ratio);
+            const T v = cons[u] ? pn : vs[u]; /* identity rows on Dirichlet nodes */
+            a.r[i] = rn;
+            a.p[i] = pn;
+            a.v[i] = v;
+            const T zr = dv[u] * rn, zv = dv[u] * v;
+            acc[0] += rn * rn;
+            acc[1] += pn * v;
+            acc[2] += rn * v;
+            acc[3] += v * v;
+            acc[4] += rn * zr;
+            acc[5] += rn * zv;
+            acc[6] += v * zv;
         }
-        const T r0 = a.r[i], v0 = a.v[i], p0 = a.p[i], dv = a.dinv[i];
-        T rn, pn;
-        pre_update(r0, v0, p0, dv, alpha, beta, rn, pn);
-        if (xupd) a.x[i] = x_update(a.x[i], r0, p0, dv, alpha, ratio);
-        if (cons) v = pn; /* identity rows */
-        a.r[i] = rn;
-        a.p[i] = pn;
-        a.v[i] = v;
-        const T zr = dv * rn, zv = dv * v;
-        acc[0] += rn * rn;
-        acc[1] += pn * v;
-        acc[2] += rn * v;
-        acc[3] += v * v;
-        acc[4] += rn * zr;
-        acc[5] += rn * zv;
-        acc[6] += v * zv;
     }
     if (MODE == MODE_VMULT) return;
 
     block_reduce<T, 7, SHARED_WG>(acc, red, a.dots + (L.ntiles + blockIdx.x) * 8);
-    /* make this block's partials visible, then take a ticket */
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned prev = atomicAdd(&a.st->ticket, 1u);
-        last = (prev == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    finish_iteration<T>(a, L.ntiles + gridDim.x, red);
-    if (threadIdx.x == 0) a.st->ticket = 0;
+}
+
+/* One block: the seven inner products of the iteration from all per-block
+ * partials of the two kernels above (fixed order), then alpha, beta and the
+ * convergence test of Algorithm 5 into the device state.  A separate launch
+ * makes every partial visible without a device-wide cache write-back in
+ * each block of the shared-node kernel. */
+template <typename T>
+__global__ __launch_bounds__(SHARED_WG) void finish_kernel(const IterArgs<T> a)
+{
+    __shared__ T red[8 * (SHARED_WG / 64)];
+    if (a.st->flag != FLAG_RUN) return;
+    finish_iteration<T>(a, a.L.ntiles + a.nshared_blocks, red);
 }
 
 /* ------------------------------------------------------------------ */
@@ -812,10 +911,12 @@ template <typename T>
 hipError_t launch_shared(int mode, const IterArgs<T> &a, hipStream_t s)
 {
     dim3 grid((unsigned)a.nshared_blocks), block(SHARED_WG);
-    if (mode == MODE_CG)
+    if (mode == MODE_CG) {
         hipLaunchKernelGGL((shared_node_kernel<T, MODE_CG>), grid, block, 0, s, a);
-    else
+        hipLaunchKernelGGL((finish_kernel<T>), dim3(1), block, 0, s, a);
+    } else {
         hipLaunchKernelGGL((shared_node_kernel<T, MODE_VMULT>), grid, block, 0, s, a);
+    }
     return hipGetLastError();
 }
 
