@@ -166,6 +166,14 @@ int mfcg_layout_info(mfcg_handle h, int32_t *tile, int64_t *n_interior, int64_t 
 int mfcg_layout_permutation(const mfcg_mesh *mesh, int32_t degree, const int32_t *tile, int64_t *perm,
                             int64_t *n_interior, int64_t *n_shared, int64_t *n_dirichlet);
 
+/* Streaming reference kernels giving the device's measured bandwidth
+ * ceiling (the denominator of the "measured" roofline and the calibration
+ * kernel of the HBM byte counters).  kind 0: dst[0..n) = src[0..n) (one read
+ * and one write per element); kind 1: dst[b] = partial sum of src over block
+ * b of the grid (one read per element; dst holds nblocks doubles).  n even,
+ * 16-byte aligned device pointers; nblocks >= 1 workgroups of 256 threads. */
+int mfcg_stream_bench(int32_t kind, int64_t n, const double *src, double *dst, int32_t nblocks, void *hip_stream);
+
 int mfcg_destroy(mfcg_handle h);
 const char *mfcg_error_string(int code);
 const char *mfcg_last_error(mfcg_handle h);

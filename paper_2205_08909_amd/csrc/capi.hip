@@ -625,4 +625,12 @@ int mfcg_solve(mfcg_handle h, const double *b, double *x, double tol, int32_t ma
     return status;
 }
 
+int mfcg_stream_bench(int32_t kind, int64_t n, const double *src, double *dst, int32_t nblocks, void *hip_stream)
+{
+    if (n < 2 || (n & 1) || !src || !dst || (kind != 0 && kind != 1) || nblocks < 1)
+        return fail(nullptr, MFCG_EINVAL, "bad stream_bench arguments");
+    HIPCHK(nullptr, launch_stream(kind, n, src, dst, nblocks, (hipStream_t)hip_stream));
+    return MFCG_OK;
+}
+
 }  // extern "C"

@@ -454,3 +454,46 @@ hipError_t launch_convert(int64_t n, const double *in, float *out, hipStream_t s
 }
 
 }  // namespace mfcg
+
+namespace mfcg {
+
+/* ------------------------------------------------------------------ */
+/* Streaming reference kernels: the measured bandwidth ceiling of the    */
+/* device (copy: 1 read + 1 write per element; read: 1 read, reduced)    */
+/* ------------------------------------------------------------------ */
+
+__global__ __launch_bounds__(256) void stream_copy_kernel(int64_t n2, const double2 *__restrict__ src,
+                                                          double2 *__restrict__ dst)
+{
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n2; i += stride) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(256) void stream_read_kernel(int64_t n2, const double2 *__restrict__ src, double *out)
+{
+    __shared__ double red[4];
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n2; i += stride) {
+        const double2 v = src[i];
+        s += v.x + v.y;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+hipError_t launch_stream(int kind, int64_t n, const double *src, double *dst, int nblocks, hipStream_t s)
+{
+    const int64_t n2 = n / 2;
+    if (kind == 0)
+        hipLaunchKernelGGL(stream_copy_kernel, dim3(nblocks), dim3(256), 0, s, n2, (const double2 *)src,
+                           (double2 *)dst);
+    else
+        hipLaunchKernelGGL(stream_read_kernel, dim3(nblocks), dim3(256), 0, s, n2, (const double2 *)src, dst);
+    return hipGetLastError();
+}
+
+}  // namespace mfcg

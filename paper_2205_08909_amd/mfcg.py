@@ -22,6 +22,7 @@ EXPORTED = [
     "mfcg_setup", "mfcg_n_dofs", "mfcg_vmult", "mfcg_diagonal", "mfcg_assemble_rhs", "mfcg_solve",
     "mfcg_cg_begin", "mfcg_cg_iterate", "mfcg_cg_end", "mfcg_set_timing", "mfcg_get_timing",
     "mfcg_layout_info", "mfcg_layout_permutation", "mfcg_destroy", "mfcg_error_string", "mfcg_last_error",
+    "mfcg_stream_bench",
 ]
 
 
@@ -67,6 +68,7 @@ def lib():
         L.mfcg_layout_info.argtypes = [P, P, P, P, P, P, P]
         L.mfcg_layout_permutation.argtypes = [ctypes.POINTER(Mesh), I32, P, P, P, P, P]
         L.mfcg_destroy.argtypes = [P]
+        L.mfcg_stream_bench.argtypes = [I32, I64, P, P, I32, P]
         L.mfcg_error_string.argtypes = [ctypes.c_int]
         L.mfcg_error_string.restype = ctypes.c_char_p
         L.mfcg_last_error.argtypes = [P]
@@ -120,6 +122,11 @@ def _dev_vec(t, n, name):
             and t.numel() == n):
         raise ValueError(f"{name} must be a contiguous float64 device tensor of length {n}")
     return t
+
+
+def stream_bench(kind, src, dst, nblocks, stream=None):
+    """Streaming reference kernel (kind 0 copy, 1 read) on float64 device tensors."""
+    _check(lib().mfcg_stream_bench(int(kind), int(src.numel()), _ptr(src), _ptr(dst), int(nblocks), _stream(stream)))
 
 
 def layout_permutation(cells, degree, tile=None, map_kind=MAP_AFFINE, bc=BC_DIRICHLET0):
