@@ -53,6 +53,19 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
+def time_solve(P, b, torch):
+    """Plain fused FP64 solve to 1e-10 from x0 = 0, timed; true residual checked after."""
+    x = torch.zeros_like(b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    code, its, _, _ = P.solve(b, x, tol=1e-10, maxit=50000, want_hist=False, want_true_res=False)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    r = b - P.vmult(torch.empty_like(b), x)
+    tr = (torch.linalg.norm(r) / torch.linalg.norm(b)).item()
+    return {"iters": its, "seconds": round(t, 4), "status": int(code), "true_rel_res": float(f"{tr:.3e}"), "_x": x}
+
+
 def cpu_baseline(seconds_budget=20.0):
     """The oracle (CSR assembly + Algorithm 1) timed on the host cores on a
     bounded sample of the same workload: Q4, 24^3 cells of the same curved
@@ -144,35 +157,56 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
 
-    # ---- copy bandwidth of a plain device copy (context for the roofline) ----
+    # ---- measured bandwidth ceiling: the library's streaming copy / read kernels ----
     nb = 256 * 1024 * 1024  # 2 GiB per buffer
-    a_ = torch.empty(nb, dtype=torch.float64, device="cuda")
+    a_ = torch.ones(nb, dtype=torch.float64, device="cuda")
     c_ = torch.empty_like(a_)
-    a_.fill_(1.0)
-    c_.copy_(a_)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(5):
-        c_.copy_(a_)
-    torch.cuda.synchronize()
-    copy_gbs = 5 * 2 * 8 * nb / (time.perf_counter() - t0) / 1e9
-    del a_, c_
+    part = torch.empty(1024, dtype=torch.float64, device="cuda")
+    ceil = {}
+    for kind, name, dst, by in ((0, "copy", c_, 16 * nb), (1, "read", part, 8 * nb)):
+        mfcg.stream_bench(kind, a_, dst, 1024)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            mfcg.stream_bench(kind, a_, dst, 1024)
+        torch.cuda.synchronize()
+        ceil[name] = by * 5 / (time.perf_counter() - t0) / 1e9
+    del a_, c_, part
+    copy_gbs = ceil["copy"]
 
     # ---- time to 1e-10 with the plain fused FP64 solver ----
     solve = None
     if not args.no_solve:
-        x.zero_()
+        solve = {"plain_fp64": time_solve(P, b, torch)}
+        solve["plain_fp64"].pop("_x")
+        print(f"[bench] solve to 1e-10 (a=1): {solve['plain_fp64']}", file=sys.stderr, flush=True)
+    P.close()
+
+    # ---- precision: same mesh, coefficient exp(GRF), plain FP64 vs FP32-inner refinement ----
+    precision = None
+    if not args.no_solve:
+        from paper_2205_08909_amd import inputs
+        coeff = inputs.grf_coefficient(N, 0.1, 1.0, seed=0)
+        P2 = mfcg.Problem(N, k, coeff=coeff, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05, tile=args.tile)
+        P2.solve_ir(P2.rhs(), torch.zeros(P2.n, dtype=torch.float64, device="cuda"), tol=1e-10)  # builds the FP32 copy
+        b2 = P2.rhs(mfcg.RHS_SINE)
+        plain = time_solve(P2, b2, torch)
+        x_plain = plain.pop("_x")
+        x2 = torch.zeros_like(b2)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        code, its_s, hist, tr = P.solve(b, x, tol=1e-10, maxit=20000, want_hist=False, want_true_res=False)
+        code, outer, inner, hist, tr = P2.solve_ir(b2, x2, tol=1e-10, inner_tol=1e-4)
         torch.cuda.synchronize()
-        t_sol = time.perf_counter() - t0
-        xs = x.clone()
-        _, _, _, tr = P.solve(b, xs, tol=1e-10, maxit=1, want_hist=False, want_true_res=True)
-        solve = {"iters": its_s, "seconds": round(t_sol, 4), "status": int(code),
-                 "true_rel_res": float(f"{tr:.3e}")}
-        print(f"[bench] solve to 1e-10: {its_s} iterations, {t_sol:.3f} s, true rel res {tr:.2e}", file=sys.stderr,
-              flush=True)
+        t_ir = time.perf_counter() - t0
+        diff = (torch.linalg.norm(x2 - x_plain) / torch.linalg.norm(x_plain)).item()
+        precision = {"workload": f"{N}^3 cells Q{k} curved, a = exp(GRF l=0.1 var=1, seed 0)",
+                     "plain_fp64": plain,
+                     "fp32_inner_ir": {"seconds": round(t_ir, 4), "outer": outer, "inner_iters": inner,
+                                       "status": int(code), "true_rel_res": float(f"{tr:.3e}"),
+                                       "rel_diff_vs_plain_fp64_solution": float(f"{diff:.3e}")},
+                     "speedup": round(plain["seconds"] / t_ir, 3)}
+        print(f"[bench] precision: {precision}", file=sys.stderr, flush=True)
+        P2.close()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -202,12 +236,13 @@ def main():
                                "achieved_GBs": round(it_bytes / (ms_per_step * 1e-3) / 1e9, 1),
                                "frac": round(it_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "kernel_ms": {"fused": round(fused_avg_ms, 5), "shared": round(tm["shared_ms"] / max(1, tm["shared_launches"]), 5)},
-        "copy_GBs": round(copy_gbs, 1),
+        "measured_ceiling_GBs": {k_: round(v_, 1) for k_, v_ in ceil.items()},
+        "iteration_frac_of_measured_copy": round(it_bytes / (ms_per_step * 1e-3) / 1e9 / copy_gbs, 4),
         "time_to_1e-10": solve,
+        "precision": precision,
         "setup_s": round(setup_s, 3),
     }
     print(json.dumps(line), flush=True)
-    P.close()
 
 
 if __name__ == "__main__":

@@ -82,7 +82,7 @@ typedef struct {
     int32_t n_q_1d;          /* Gauss points per direction; 0: k+1 (only k+1 is supported) */
     int32_t tile[3];         /* cells per tile in x, y, z; 0: per-degree default */
     int32_t check_every;     /* iterations between host polls of the convergence flag; 0: 16 */
-    int32_t fp32;            /* 1: also build the FP32 operator copy needed by mfcg_solve_ir */
+    int32_t fp32;            /* 1: build the FP32 operator copy of mfcg_solve_ir at set-up (else on first use) */
 } mfcg_options;
 
 /* Builds the operator (Sec. 2, Eq. 3-5): tiles and DoF enumeration of the
@@ -135,6 +135,25 @@ int mfcg_assemble_rhs(mfcg_handle h, int32_t kind, const double *params, double 
  * ENOTCONV, EBREAKDOWN, EHIP.  Synchronises hip_stream. */
 int mfcg_solve(mfcg_handle h, const double *b, double *x, double tol, int32_t maxit,
                int32_t *iters, double *res_hist, double *true_rel_res, void *hip_stream);
+
+/* Mixed precision: FP64 iterative refinement around the fused solver run
+ * in FP32 (operator with an FP32 copy of G_q and D^{-1}, vector updates and
+ * inner products in FP32).  Outer loop in FP64 on the GPU:
+ *     r = b - A x (FP64 operator); stop when ||r||_2 < tol ||b||_2;
+ *     solve A d = r in FP32 to ||r - A d|| < inner_tol ||r|| (or max_inner
+ *     iterations); x += d (FP64).
+ *   x          device, x_0 on entry, solution on return
+ *   outer_its  host out: corrections applied; inner_its: FP32 iterations summed
+ *   res_hist   host or NULL, max_outer+1 doubles: ||b - A x_j|| / ||b||
+ *   true_rel_res host or NULL: the final ||b - A x|| / ||b|| (FP64)
+ * Errors: EINVAL (tol <= 0, inner_tol not in (0,1), max_* < 1), ENOTCONV
+ * (max_outer corrections without reaching tol), ESTAGNATION (the outer
+ * residual decreased by less than 10x in two consecutive corrections),
+ * EBREAKDOWN, EHIP.  The first call builds the FP32 copy (half the geometry
+ * bytes) unless mfcg_options.fp32 asked for it at set-up. */
+int mfcg_solve_ir(mfcg_handle h, const double *b, double *x, double tol, double inner_tol, int32_t max_outer,
+                  int32_t max_inner, int32_t *outer_its, int32_t *inner_its, double *res_hist,
+                  double *true_rel_res, void *hip_stream);
 
 /* Stepping interface used for throughput measurement: mfcg_cg_begin
  * initialises the solver state from (b, x0) exactly as mfcg_solve does;

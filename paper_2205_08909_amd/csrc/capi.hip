@@ -53,6 +53,12 @@ struct mfcg_ctx {
     int launched = 0;
     double bnorm = 0.0;
     bool zero_rhs = false;
+    /* FP32 copy of the operator and FP32 work vectors (iterative refinement) */
+    float *G32 = nullptr, *dinv32 = nullptr;
+    float *r32 = nullptr, *p32 = nullptr, *v32 = nullptr, *x32 = nullptr, *part32 = nullptr, *dots32 = nullptr;
+    CGState *st32 = nullptr;
+    double *hist32 = nullptr;
+    int hist32_cap = 0;
     /* timing */
     bool timing = false;
     std::vector<EventPair> ev_fused, ev_shared, ev_pool;
@@ -88,9 +94,10 @@ static hipError_t dalloc(T **p, size_t count)
 
 static void release(mfcg_ctx *h)
 {
-    void *bufs[] = {h->d_ent_base, h->d_tile_ent, h->d_tiles, h->d_coeff, h->G,    h->dinv, h->diag_lex,
-                    h->r,          h->p,          h->v,       h->x,       h->vin,  h->vout, h->part,
-                    h->dots,       h->sums,       h->hist,    h->st};
+    void *bufs[] = {h->d_ent_base, h->d_tile_ent, h->d_tiles, h->d_coeff, h->G,     h->dinv,   h->diag_lex,
+                    h->r,          h->p,          h->v,       h->x,       h->vin,   h->vout,   h->part,
+                    h->dots,       h->sums,       h->hist,    h->st,      h->G32,   h->dinv32, h->r32,
+                    h->p32,        h->v32,        h->x32,     h->part32,  h->dots32, h->st32,  h->hist32};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (auto &e : h->ev_pool) {
@@ -175,6 +182,8 @@ static int vmult_internal(mfcg_ctx *h, const double *src, double *dst, hipStream
     HIPCHK(h, launch_shared<double>(MODE_VMULT, a, s));
     return MFCG_OK;
 }
+
+static int ensure_fp32(mfcg_ctx *h, hipStream_t s);
 
 static int host_sumsq(mfcg_ctx *h, const double *a, const double *c, int64_t n, double *out, hipStream_t s)
 {
@@ -342,6 +351,9 @@ int mfcg_setup(const mfcg_mesh *mesh, int32_t degree, const double *cell_coeff, 
     g.coeff = h->d_coeff;
     SCHK(launch_geometry(g, h->G, s));
     SCHK(launch_diagonal(g, h->G, h->diag_lex, h->dinv, s));
+    if (opt && opt->fp32) {
+        if (ensure_fp32(h, s)) return bail(MFCG_EHIP);
+    }
     SCHK(hipStreamSynchronize(s));
 #undef SCHK
     *out = h;
@@ -622,6 +634,156 @@ int mfcg_solve(mfcg_handle h, const double *b, double *x, double tol, int32_t ma
             *true_rel_res = std::sqrt(rr) / h->bnorm;
         }
     }
+    return status;
+}
+
+/* FP32 copy of the geometry tensor and inverse diagonal plus FP32 work
+ * vectors, built on first use. */
+static int ensure_fp32(mfcg_ctx *h, hipStream_t s)
+{
+    if (h->G32) return MFCG_OK;
+    const HostLayout &L = h->hl;
+    HIPCHK(h, dalloc(&h->G32, L.g_elems));
+    HIPCHK(h, dalloc(&h->dinv32, L.n));
+    HIPCHK(h, dalloc(&h->r32, L.n));
+    HIPCHK(h, dalloc(&h->p32, L.n));
+    HIPCHK(h, dalloc(&h->v32, L.n));
+    HIPCHK(h, dalloc(&h->x32, L.n));
+    HIPCHK(h, dalloc(&h->part32, std::max<int64_t>(1, L.npart)));
+    HIPCHK(h, dalloc(&h->dots32, 8 * (L.ntiles + h->nshared_blocks)));
+    HIPCHK(h, dalloc(&h->st32, 1));
+    HIPCHK(h, hipMemsetAsync(h->part32, 0, sizeof(float) * std::max<int64_t>(1, L.npart), s));
+    HIPCHK(h, launch_convert(L.g_elems, h->G, h->G32, s));
+    HIPCHK(h, launch_convert(L.n, h->dinv, h->dinv32, s));
+    return MFCG_OK;
+}
+
+/* FP32 fused CG on A d = r32 from d = 0 (Algorithm 5 in single precision:
+ * operator, vector updates and inner products); stops at
+ * ||r_j|| < inner_tol * rnorm or after max_inner iterations. */
+static int fp32_cg(mfcg_ctx *h, double rnorm, double inner_tol, int max_inner, int *its, hipStream_t s)
+{
+    const int64_t n = h->hl.n;
+    if (max_inner + 1 > h->hist32_cap) {
+        if (h->hist32) HIPCHK(h, hipFree(h->hist32));
+        h->hist32 = nullptr;
+        HIPCHK(h, dalloc(&h->hist32, (size_t)max_inner + 1));
+        h->hist32_cap = max_inner + 1;
+    }
+    HIPCHK(h, hipMemsetAsync(h->x32, 0, sizeof(float) * n, s));
+    HIPCHK(h, hipMemsetAsync(h->p32, 0, sizeof(float) * n, s));
+    HIPCHK(h, hipMemsetAsync(h->v32, 0, sizeof(float) * n, s));
+    CGState st{};
+    st.eps = inner_tol * rnorm;
+    st.bnorm = rnorm;
+    st.r0norm = rnorm;
+    st.maxit = max_inner;
+    st.flag = rnorm > 0.0 ? FLAG_RUN : FLAG_CONV;
+    HIPCHK(h, hipMemcpyAsync(h->st32, &st, sizeof(CGState), hipMemcpyHostToDevice, s));
+    IterArgs<float> a{};
+    a.L = h->lv;
+    a.G = h->G32;
+    a.dinv = h->dinv32;
+    a.r = h->r32;
+    a.p = h->p32;
+    a.v = h->v32;
+    a.x = h->x32;
+    a.part = h->part32;
+    a.dots = h->dots32;
+    a.st = h->st32;
+    a.hist = h->hist32;
+    a.nshared_blocks = h->nshared_blocks;
+    int launched = 0;
+    while (st.flag == FLAG_RUN && launched < max_inner) {
+        const int chunk = std::min(h->check_every, max_inner - launched);
+        for (int it = 0; it < chunk; ++it) {
+            HIPCHK(h, launch_fused<float>(h->K, MODE_CG, a, s));
+            HIPCHK(h, launch_shared<float>(MODE_CG, a, s));
+        }
+        launched += chunk;
+        HIPCHK(h, hipMemcpyAsync(&st, h->st32, sizeof(CGState), hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+    }
+    HIPCHK(h, launch_reconstruct<float>(n, h->x32, h->p32, h->r32, h->dinv32, h->st32, s));
+    *its = st.k;
+    if (st.flag == FLAG_BREAK) return fail(h, MFCG_EBREAKDOWN, "breakdown in the FP32 inner solve");
+    return MFCG_OK;
+}
+
+int mfcg_solve_ir(mfcg_handle h, const double *b, double *x, double tol, double inner_tol, int32_t max_outer,
+                  int32_t max_inner, int32_t *outer_its, int32_t *inner_its, double *res_hist, double *true_rel_res,
+                  void *hip_stream)
+{
+    if (!h || !b || !x || !outer_its || !inner_its) return fail(h, MFCG_EINVAL, "null argument");
+    if (!(tol > 0.0) || !std::isfinite(tol) || !(inner_tol > 0.0) || !(inner_tol < 1.0))
+        return fail(h, MFCG_EINVAL, "need tol > 0 and 0 < inner_tol < 1");
+    if (max_outer < 1 || max_inner < 1) return fail(h, MFCG_EINVAL, "max_outer and max_inner must be >= 1");
+    hipStream_t s = (hipStream_t)hip_stream;
+    int rc = ensure_fp32(h, s);
+    if (rc) return rc;
+    const int64_t n = h->hl.n;
+    double *bint = h->vin, *ax = h->vout, *x64 = h->x, *r64 = h->r;
+    HIPCHK(h, launch_lex_to_int<double>(h->lv, b, bint, s));
+    HIPCHK(h, launch_lex_to_int<double>(h->lv, x, x64, s));
+    double bb = 0.0;
+    rc = host_sumsq(h, bint, nullptr, n, &bb, s);
+    if (rc) return rc;
+    const double bnorm = std::sqrt(bb);
+    *outer_its = 0;
+    *inner_its = 0;
+    if (bb == 0.0) {
+        HIPCHK(h, hipMemsetAsync(x, 0, sizeof(double) * n, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+        if (res_hist) res_hist[0] = 0.0;
+        if (true_rel_res) *true_rel_res = 0.0;
+        return MFCG_OK;
+    }
+    int status = MFCG_ENOTCONV;
+    double prev = 0.0;
+    int slow = 0;
+    for (int outer = 0;; ++outer) {
+        /* FP64 residual of the current iterate */
+        rc = vmult_internal(h, x64, ax, s);
+        if (rc) return rc;
+        HIPCHK(h, launch_residual(n, bint, ax, r64, s));
+        double rr = 0.0;
+        rc = host_sumsq(h, r64, nullptr, n, &rr, s);
+        if (rc) return rc;
+        const double rn = std::sqrt(rr);
+        if (res_hist) res_hist[outer] = rn / bnorm;
+        if (true_rel_res) *true_rel_res = rn / bnorm;
+        if (rn < tol * bnorm) {
+            status = MFCG_OK;
+            break;
+        }
+        if (!std::isfinite(rn)) {
+            status = fail(h, MFCG_EBREAKDOWN, "non-finite residual in iterative refinement");
+            break;
+        }
+        if (outer > 0 && rn > 0.1 * prev) {
+            if (++slow >= 2) {
+                status = fail(h, MFCG_ESTAGNATION, "outer residual stopped decreasing");
+                break;
+            }
+        } else {
+            slow = 0;
+        }
+        if (outer == max_outer) {
+            status = fail(h, MFCG_ENOTCONV, "max_outer reached");
+            break;
+        }
+        prev = rn;
+        /* inner FP32 solve of A d = r, then x += d in FP64 */
+        HIPCHK(h, launch_convert(n, r64, h->r32, s));
+        int its = 0;
+        rc = fp32_cg(h, rn, inner_tol, max_inner, &its, s);
+        if (rc) return rc;
+        *inner_its += its;
+        HIPCHK(h, launch_add_correction(n, x64, h->x32, s));
+        *outer_its = outer + 1;
+    }
+    HIPCHK(h, launch_int_to_lex<double>(h->lv, x64, x, s));
+    HIPCHK(h, hipStreamSynchronize(s));
     return status;
 }
 

@@ -61,6 +61,9 @@ hipError_t launch_reconstruct(int64_t n, T *x, const T *p, const T *r, const T *
 /* part[0..nb) = block sums of (a_i - c_i)^2 (c may be NULL); the caller adds them in order */
 hipError_t launch_sumsq(int64_t n, const double *a, const double *c, double *part, int nb, hipStream_t s);
 hipError_t launch_convert(int64_t n, const double *in, float *out, hipStream_t s);
+/* iterative refinement: r = b - v; x += d */
+hipError_t launch_residual(int64_t n, const double *b, const double *v, double *r, hipStream_t s);
+hipError_t launch_add_correction(int64_t n, double *x, const float *d, hipStream_t s);
 /* kind 0: dst = src (n doubles); kind 1: dst[b] = block partial sums of src */
 hipError_t launch_stream(int kind, int64_t n, const double *src, double *dst, int nblocks, hipStream_t s);
 

@@ -497,3 +497,33 @@ hipError_t launch_stream(int kind, int64_t n, const double *src, double *dst, in
 }
 
 }  // namespace mfcg
+
+namespace mfcg {
+
+/* r = b - v (FP64, internal order) */
+__global__ __launch_bounds__(256) void residual_kernel(int64_t n, const double *b, const double *v, double *r)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) r[i] = b[i] - v[i];
+}
+
+/* x += (double) d */
+__global__ __launch_bounds__(256) void add_correction_kernel(int64_t n, double *x, const float *d)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) x[i] += (double)d[i];
+}
+
+hipError_t launch_residual(int64_t n, const double *b, const double *v, double *r, hipStream_t s)
+{
+    hipLaunchKernelGGL(residual_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, b, v, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_correction(int64_t n, double *x, const float *d, hipStream_t s)
+{
+    hipLaunchKernelGGL(add_correction_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, x, d);
+    return hipGetLastError();
+}
+
+}  // namespace mfcg

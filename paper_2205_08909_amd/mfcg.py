@@ -22,7 +22,7 @@ EXPORTED = [
     "mfcg_setup", "mfcg_n_dofs", "mfcg_vmult", "mfcg_diagonal", "mfcg_assemble_rhs", "mfcg_solve",
     "mfcg_cg_begin", "mfcg_cg_iterate", "mfcg_cg_end", "mfcg_set_timing", "mfcg_get_timing",
     "mfcg_layout_info", "mfcg_layout_permutation", "mfcg_destroy", "mfcg_error_string", "mfcg_last_error",
-    "mfcg_stream_bench",
+    "mfcg_stream_bench", "mfcg_solve_ir",
 ]
 
 
@@ -69,6 +69,7 @@ def lib():
         L.mfcg_layout_permutation.argtypes = [ctypes.POINTER(Mesh), I32, P, P, P, P, P]
         L.mfcg_destroy.argtypes = [P]
         L.mfcg_stream_bench.argtypes = [I32, I64, P, P, I32, P]
+        L.mfcg_solve_ir.argtypes = [P, P, P, D, D, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), P, P, P]
         L.mfcg_error_string.argtypes = [ctypes.c_int]
         L.mfcg_error_string.restype = ctypes.c_char_p
         L.mfcg_last_error.argtypes = [P]
@@ -212,6 +213,22 @@ class Problem:
             _check(code, self.h)
         h = hist[: its.value + 1].copy() if want_hist else None
         return code, its.value, h, tr.value
+
+    def solve_ir(self, b, x, tol=1e-10, inner_tol=1e-4, max_outer=20, max_inner=10000, stream=None,
+                 raise_on=True):
+        """FP64 iterative refinement around the FP32 fused solver.
+        Returns (code, outer_its, inner_its, rel_res_hist, true_rel_res)."""
+        _dev_vec(b, self.n, "b")
+        _dev_vec(x, self.n, "x")
+        oi, ii = ctypes.c_int32(), ctypes.c_int32()
+        hist = np.zeros(max_outer + 1)
+        tr = ctypes.c_double(float("nan"))
+        code = lib().mfcg_solve_ir(self.h, _ptr(b), _ptr(x), float(tol), float(inner_tol), int(max_outer),
+                                   int(max_inner), ctypes.byref(oi), ctypes.byref(ii),
+                                   hist.ctypes.data_as(ctypes.c_void_p), ctypes.byref(tr), _stream(stream))
+        if raise_on and code != OK:
+            _check(code, self.h)
+        return code, oi.value, ii.value, hist[: oi.value + 1].copy(), tr.value
 
     # stepping interface (throughput measurement)
     def cg_begin(self, b, x0=None, tol=0.0, maxit=100, stream=None):
