@@ -44,12 +44,12 @@ def counter_traffic(kernel_prefix):
 
 
 def source_hash():
+    """Hash of the sources the fused CG kernel and its node layout are built from."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2205_08909_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h", ".cpp")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in ("kernels_cg.hip", "kernels.h", "tables_ct.h", "mfcg_internal.h", "setup_host.cpp"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
