@@ -92,6 +92,55 @@ def cpu_baseline(seconds_budget=20.0):
                       "assembly excluded"}
 
 
+def degree_sweep(args):
+    """Throughput of the fused iteration for k = 1..8 at two sizes per degree
+    (N = round(216/k) and round(456/k) cells per direction, about 1e7 and
+    1e8 DoFs), curved mesh, a = 1, random-normal right-hand side (seed 7),
+    tol = 0.  Prints one JSON line."""
+    import torch
+    from paper_2205_08909_amd import mfcg, inputs
+    rows = []
+    degrees = [int(v) for v in args.sweep_degrees.split(",")]
+    for k in degrees:
+        for N in (round(216 / k), round(456 / k)):
+            P = mfcg.Problem(N, k, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05)
+            info = P.layout_info()
+            n = P.n
+            b = torch.from_numpy(inputs.random_rhs(N, k, seed=7)).cuda()
+            P.cg_begin(b, None, tol=0.0, maxit=args.warmup + args.steps)
+            P.cg_iterate(args.warmup)
+            torch.cuda.synchronize()
+            P.set_timing(True)
+            t0 = time.perf_counter()
+            P.cg_iterate(args.steps)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            tm = P.get_timing()
+            P.set_timing(False)
+            x = torch.empty_like(b)
+            P.cg_end(x)
+            g_bytes = 8 * 6 * (k + 1) ** 3 * N ** 3
+            it_bytes = 64 * n + g_bytes
+            nI, nS = info["n_interior"], info["n_shared"]
+            fused_bytes = g_bytes + 64 * nI + 40 * nS
+            fused_ms = tm["fused_ms"] / max(1, tm["fused_launches"])
+            row = {"k": k, "cells": N, "n_dofs": n, "tile": list(info["tile"]),
+                   "ms_per_iter": round(wall * 1e3 / args.steps, 4),
+                   "GDoF_it_s": round(n * args.steps / wall / 1e9, 3),
+                   "model_bytes_per_dof": round(it_bytes / n, 2),
+                   "iteration_frac_8TBs": round(it_bytes * args.steps / wall / 1e9 / HBM_PEAK_GBS, 4),
+                   "fused_ms": round(fused_ms, 4),
+                   "fused_GBs": round(fused_bytes / (fused_ms * 1e-3) / 1e9, 1),
+                   "shared_ms": round(tm["shared_ms"] / max(1, tm["shared_launches"]), 4)}
+            print(f"[sweep] {row}", file=sys.stderr, flush=True)
+            rows.append(row)
+            del b, x
+            P.close()
+            torch.cuda.empty_cache()
+    print(json.dumps({"sweep": "fused FP64 CG iteration, curved mesh, a = 1", "steps": args.steps,
+                      "warmup": args.warmup, "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +151,9 @@ def main():
     ap.add_argument("--tile", type=int, nargs=3, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-ablation", action="store_true")
+    ap.add_argument("--sweep", action="store_true", help="degree sweep k = 1..8 instead of the main line")
+    ap.add_argument("--sweep-degrees", default="1,2,3,4,5,6,7,8")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the multi-GPU sharding is described in DESIGN.md); "
@@ -113,6 +165,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     torch.cuda.set_device(0)
+    if args.sweep:
+        degree_sweep(args)
+        return
     N, k, K, W = args.cells, args.degree, args.steps, args.warmup
     t0 = time.perf_counter()
     P = mfcg.Problem(N, k, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05, tile=args.tile)
@@ -143,6 +198,26 @@ def main():
     value = n * K / wall / 1e9
     print(f"[bench] {K} iterations in {wall * 1e3:.2f} ms: {ms_per_step:.4f} ms/it, {value:.3f} GDoF*it/s; "
           f"fused {tm['fused_ms'] / K:.4f} ms, shared {tm['shared_ms'] / K:.4f} ms", file=sys.stderr, flush=True)
+
+    # ---- comparison solvers on the same problem: what the fusion saves ----
+    ablation = None
+    if not args.no_ablation:
+        ablation = {"fused_ms": round(ms_per_step, 5)}
+        for solver, name in ((mfcg.SOLVER_ALG5_SPLIT, "alg5_3pass_ms"), (mfcg.SOLVER_PCG_BASIC, "basic_pcg_ms")):
+            P.set_solver(solver)
+            P.cg_begin(b, None, tol=0.0, maxit=W + K)
+            P.cg_iterate(W)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P.cg_iterate(K)
+            torch.cuda.synchronize()
+            ablation[name] = round((time.perf_counter() - t0) * 1e3 / K, 5)
+            code_a, its_a, _ = P.cg_end(x)
+            assert its_a == W + K, (name, code_a, its_a)
+        P.set_solver(mfcg.SOLVER_FUSED)
+        ablation["speedup_vs_3pass"] = round(ablation["alg5_3pass_ms"] / ms_per_step, 3)
+        ablation["speedup_vs_basic"] = round(ablation["basic_pcg_ms"] / ms_per_step, 3)
+        print(f"[bench] ablation {ablation}", file=sys.stderr, flush=True)
 
     # ---- algorithmic bytes (paper's ideal transfer, Table 1 with a scalar diagonal) ----
     nq = (k + 1) ** 3
@@ -238,6 +313,7 @@ def main():
         "kernel_ms": {"fused": round(fused_avg_ms, 5), "shared": round(tm["shared_ms"] / max(1, tm["shared_launches"]), 5)},
         "measured_ceiling_GBs": {k_: round(v_, 1) for k_, v_ in ceil.items()},
         "iteration_frac_of_measured_copy": round(it_bytes / (ms_per_step * 1e-3) / 1e9 / copy_gbs, 4),
+        "ablation_ms_per_iter": ablation,
         "time_to_1e-10": solve,
         "precision": precision,
         "setup_s": round(setup_s, 3),

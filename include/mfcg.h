@@ -66,6 +66,12 @@ enum {
     MFCG_RHS_BUMPS = 1          /* f = sum_m A_m exp(-|x - c_m|^2 / (2 s_m^2)) */
 };
 
+enum {
+    MFCG_SOLVER_FUSED = 0,      /* Algorithm 5, pre/post fused into the operator's cell loop (default) */
+    MFCG_SOLVER_ALG5_SPLIT = 1, /* Algorithm 5 as three passes: pre kernel, operator, post kernel */
+    MFCG_SOLVER_PCG_BASIC = 2   /* Algorithm 1: separate vector kernels and three reductions */
+};
+
 typedef struct mfcg_ctx *mfcg_handle;
 
 /* Mesh: cells per direction on [0,1]^3, the map applied to it, the
@@ -171,6 +177,17 @@ int mfcg_cg_end(mfcg_handle h, double *x, int32_t *iters, double *res_hist, void
 int mfcg_set_timing(mfcg_handle h, int32_t enable);
 int mfcg_get_timing(mfcg_handle h, double *fused_ms, int64_t *fused_launches, double *shared_ms,
                     int64_t *shared_launches);
+
+/* Selects the iteration used by mfcg_solve and the stepping interface
+ * (MFCG_SOLVER_*).  The two comparison solvers apply the same operator
+ * kernels in plain mat-vec mode and move the vector updates and inner
+ * products into separate streaming kernels: Algorithm 5 split into its
+ * pre / operator / post regions (Sec. 4.2, the paper's GPU scheme of
+ * Sec. 6), and the textbook Jacobi-PCG of Algorithm 1 (Sec. 3).  They give
+ * the same iterates in exact arithmetic; they exist to measure what the
+ * fusion saves.  Timing events cover MFCG_SOLVER_FUSED only.
+ * Errors: EINVAL (null handle, unknown solver). */
+int mfcg_set_solver(mfcg_handle h, int32_t solver);
 
 /* Layout facts of the handle (host out, any may be NULL): tile sizes in
  * cells, node counts of the classes of the enumeration (tile-interior,

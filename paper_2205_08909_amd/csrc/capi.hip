@@ -30,6 +30,7 @@ struct mfcg_ctx {
     mfcg_mesh mesh{};
     int K = 0;
     int check_every = 16;
+    int solver = MFCG_SOLVER_FUSED;
     HostLayout hl;
     LayoutView lv{};
     Tables<double> tab{};
@@ -331,7 +332,8 @@ int mfcg_setup(const mfcg_mesh *mesh, int32_t degree, const double *cell_coeff, 
     SCHK(dalloc(&h->vin, L.n));
     SCHK(dalloc(&h->vout, L.n));
     SCHK(dalloc(&h->part, L.npart));
-    SCHK(dalloc(&h->dots, 8 * (L.ntiles + h->nshared_blocks)));
+    /* per-block inner-product records of the fused path, or of the comparison solvers' vector kernels */
+    SCHK(dalloc(&h->dots, 8 * std::max<int64_t>(L.ntiles + h->nshared_blocks, MAX_VEC_BLOCKS)));
     SCHK(dalloc(&h->sums, h->nsum_blocks));
     SCHK(dalloc(&h->st, 1));
     h->hist_cap = 1024;
@@ -480,6 +482,15 @@ int mfcg_get_timing(mfcg_handle h, double *fused_ms, int64_t *fused_launches, do
     return MFCG_OK;
 }
 
+int mfcg_set_solver(mfcg_handle h, int32_t solver)
+{
+    if (!h) return fail(h, MFCG_EINVAL, "null handle");
+    if (solver != MFCG_SOLVER_FUSED && solver != MFCG_SOLVER_ALG5_SPLIT && solver != MFCG_SOLVER_PCG_BASIC)
+        return fail(h, MFCG_EINVAL, "unknown solver");
+    h->solver = solver;
+    return MFCG_OK;
+}
+
 int mfcg_cg_begin(mfcg_handle h, const double *b, const double *x0, double tol, int32_t maxit, void *hip_stream)
 {
     if (!h || !b) return fail(h, MFCG_EINVAL, "null argument");
@@ -545,7 +556,29 @@ int mfcg_cg_iterate(mfcg_handle h, int32_t n_it, void *hip_stream)
     a.st = h->st;
     a.hist = h->hist;
     a.nshared_blocks = h->nshared_blocks;
+    const int64_t n = h->hl.n;
     for (int it = 0; it < n_it; ++it) {
+        if (h->solver == MFCG_SOLVER_ALG5_SPLIT) {
+            /* pre, mat-vec v = A p, post + finish */
+            HIPCHK(h, launch_alg5_pre(a, n, s));
+            IterArgs<double> m = a;
+            m.src = h->p;
+            m.dst = h->v;
+            HIPCHK(h, launch_fused<double>(h->K, MODE_VMULT, m, s));
+            HIPCHK(h, launch_shared<double>(MODE_VMULT, m, s));
+            HIPCHK(h, launch_alg5_post(a, n, s));
+            continue;
+        }
+        if (h->solver == MFCG_SOLVER_PCG_BASIC) {
+            HIPCHK(h, launch_pcg_direction(a, n, s));
+            IterArgs<double> m = a;
+            m.src = h->p;
+            m.dst = h->v;
+            HIPCHK(h, launch_fused<double>(h->K, MODE_VMULT, m, s));
+            HIPCHK(h, launch_shared<double>(MODE_VMULT, m, s));
+            HIPCHK(h, launch_pcg_update(a, n, s));
+            continue;
+        }
         EventPair e1{}, e2{};
         if (h->timing) {
             int rc = get_events(h, e1);
@@ -591,7 +624,8 @@ int mfcg_cg_end(mfcg_handle h, double *x, int32_t *iters, double *res_hist, void
         HIPCHK(h, hipStreamSynchronize(s));
         return MFCG_OK;
     }
-    HIPCHK(h, launch_reconstruct<double>(h->hl.n, h->x, h->p, h->r, h->dinv, h->st, s));
+    if (h->solver != MFCG_SOLVER_PCG_BASIC) /* Algorithm 5 keeps x one or two steps behind */
+        HIPCHK(h, launch_reconstruct<double>(h->hl.n, h->x, h->p, h->r, h->dinv, h->st, s));
     HIPCHK(h, launch_int_to_lex<double>(h->lv, h->x, x, s));
     if (res_hist) HIPCHK(h, hipMemcpyAsync(res_hist, h->hist, sizeof(double) * (st.k + 1), hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));

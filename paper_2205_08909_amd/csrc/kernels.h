@@ -67,4 +67,15 @@ hipError_t launch_add_correction(int64_t n, double *x, const float *d, hipStream
 /* kind 0: dst = src (n doubles); kind 1: dst[b] = block partial sums of src */
 hipError_t launch_stream(int kind, int64_t n, const double *src, double *dst, int nblocks, hipStream_t s);
 
+/* Comparison solvers (unfused).  Their reductions write per-block records
+ * of 8 doubles into a.dots, at most MAX_VEC_BLOCKS of them. */
+constexpr int MAX_VEC_BLOCKS = 2048;
+int vec_blocks(int64_t n);
+/* Algorithm 5 in three passes: pre (r, p, x) ... mat-vec ... post (7 dots) + finish */
+hipError_t launch_alg5_pre(const IterArgs<double> &a, int64_t n, hipStream_t s);
+hipError_t launch_alg5_post(const IterArgs<double> &a, int64_t n, hipStream_t s);
+/* Algorithm 1: r^T D^{-1} r -> beta, p = D^{-1} r + beta p ... mat-vec ... p^T v -> alpha, x and r update, ||r|| */
+hipError_t launch_pcg_direction(const IterArgs<double> &a, int64_t n, hipStream_t s);
+hipError_t launch_pcg_update(const IterArgs<double> &a, int64_t n, hipStream_t s);
+
 }  // namespace mfcg

@@ -40,6 +40,7 @@
  */
 #include <hip/hip_runtime.h>
 
+#include "cg_common.h"
 #include "kernels.h"
 #include "tables_ct.h"
 
@@ -71,8 +72,6 @@ int fused_block_size(int K)
     static const int w[9] = {0, 256, 576, 448, 448, 384, 256, 256, 384};
     return (K >= 1 && K <= 8) ? w[K] : 0;
 }
-
-constexpr int SHARED_WG = 256;
 
 /* minimum waves per SIMD requested from the register allocator */
 #ifndef MFCG_OCC
@@ -112,42 +111,6 @@ struct FastDiv {
     __device__ __forceinline__ int div(int n) const { return d > 1 ? (int)__umulhi((uint32_t)n, m) : n; }
     __device__ __forceinline__ int mod(int n) const { return n - div(n) * (int)d; }
 };
-
-/* The "pre" update of one entry, shared by both kernels so that the value
- * a tile recomputes for a shared node is bitwise the value the shared-node
- * kernel stores. */
-template <typename T>
-__device__ __forceinline__ void pre_update(T r, T v, T p, T dinv, T alpha, T beta, T &rn, T &pn)
-{
-    rn = fma(-alpha, v, r);
-    pn = fma(dinv, rn, beta * p);
-}
-
-template <typename T>
-__device__ __forceinline__ T x_update(T x, T r, T p, T dinv, T alpha, T ratio)
-{
-    return fma(ratio, fma(-dinv, r, p), fma(alpha, p, x));
-}
-
-/* Deterministic reduction of NV values over a block into out[0..NV). */
-template <typename T, int NV, int WG>
-__device__ __forceinline__ void block_reduce(T (&acc)[NV], T *red, T *out)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int c = 0; c < NV; ++c) {
-        T s = acc[c];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-        if (lane == 0) red[wave * NV + c] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < NV) {
-        T s = 0;
-        for (int w = 0; w < WG / 64; ++w) s += red[w * NV + threadIdx.x];
-        out[threadIdx.x] = s;
-    }
-}
 
 /* ------------------------------------------------------------------ */
 /* Fused tile kernel                                                   */
@@ -714,65 +677,6 @@ void fused_tile_kernel(const IterArgs<T> a)
 /* ------------------------------------------------------------------ */
 /* Shared-node kernel with the single-pass finish                      */
 /* ------------------------------------------------------------------ */
-
-template <typename T>
-__device__ void finish_iteration(const IterArgs<T> &a, int64_t nparts, T *red)
-{
-    /* fixed-order sums of the 7 inner products over all per-block partials;
-     * every thread owns a fixed strided subset, loads issued 4 records at a time */
-    T acc[7];
-#pragma unroll
-    for (int c = 0; c < 7; ++c) acc[c] = 0;
-    for (int64_t b0 = threadIdx.x; b0 < nparts; b0 += 4 * SHARED_WG) {
-        T rec[4][7];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int64_t b = b0 + (int64_t)u * SHARED_WG;
-#pragma unroll
-            for (int c = 0; c < 7; ++c) rec[u][c] = b < nparts ? a.dots[b * 8 + c] : (T)0;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int c = 0; c < 7; ++c) acc[c] += rec[u][c];
-    }
-    __shared__ T tot[8];
-    block_reduce<T, 7, SHARED_WG>(acc, red, tot);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        CGState *st = a.st;
-        const T gam = tot[0], pa = tot[1], rb = tot[2], vc = tot[3], dd = tot[4], ee = tot[5], ff = tot[6];
-        const int k = st->k + 1;
-        const T prev_ratio = st->beta != 0.0 ? (T)(st->alpha / st->beta) : (T)0;
-        const bool bad = !(pa > 0) || !isfinite(pa) || !isfinite(gam) || !isfinite(dd) || !isfinite(vc);
-        if (bad) {
-            st->flag = FLAG_BREAK;
-            st->xa = 0.0;
-            st->xratio = (double)prev_ratio;
-            st->k = k;
-            return;
-        }
-        const T alpha = dd / pa;
-        T rho2 = gam - 2 * alpha * rb + alpha * alpha * vc;
-        const T rho = sqrt(rho2 > 0 ? rho2 : (T)0);
-        a.hist[k] = (double)rho;
-        st->xa = (double)alpha;
-        st->xratio = (double)prev_ratio;
-        if ((double)rho < st->eps) {
-            st->flag = FLAG_CONV;
-        } else {
-            const T beta = (dd - 2 * alpha * ee + alpha * alpha * ff) / dd;
-            if (!(beta != 0) || !isfinite(beta)) {
-                st->flag = (beta == 0) ? FLAG_CONV : FLAG_BREAK;
-            } else {
-                st->ratio = (double)prev_ratio;
-                st->alpha = (double)alpha;
-                st->beta = (double)beta;
-            }
-        }
-        st->k = k;
-    }
-}
 
 /* nodes per thread of the shared-node kernel, processed with their loads
  * issued together */

@@ -89,8 +89,8 @@ struct CGState {
     double r0norm;
     int32_t k;       /* completed iterations */
     int32_t flag;    /* FLAG_* */
-    uint32_t ticket; /* arrival counter of the shared-node kernel's blocks */
     int32_t maxit;
+    double rz;       /* r^T D^{-1} r of the basic PCG (Algorithm 1) */
 };
 
 }  // namespace mfcg

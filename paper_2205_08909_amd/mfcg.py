@@ -17,12 +17,13 @@ OK, EINVAL, ENOMEM, EHIP, ENOTCONV, EBREAKDOWN, ESTAGNATION = 0, -1, -2, -3, -4,
 MAP_AFFINE, MAP_SINE_SHEAR, MAP_SINE_PRODUCT = 0, 1, 2
 BC_DIRICHLET0, BC_NONE = 0, 1
 RHS_SINE, RHS_BUMPS = 0, 1
+SOLVER_FUSED, SOLVER_ALG5_SPLIT, SOLVER_PCG_BASIC = 0, 1, 2
 
 EXPORTED = [
     "mfcg_setup", "mfcg_n_dofs", "mfcg_vmult", "mfcg_diagonal", "mfcg_assemble_rhs", "mfcg_solve",
     "mfcg_cg_begin", "mfcg_cg_iterate", "mfcg_cg_end", "mfcg_set_timing", "mfcg_get_timing",
     "mfcg_layout_info", "mfcg_layout_permutation", "mfcg_destroy", "mfcg_error_string", "mfcg_last_error",
-    "mfcg_stream_bench", "mfcg_solve_ir",
+    "mfcg_stream_bench", "mfcg_solve_ir", "mfcg_set_solver",
 ]
 
 
@@ -247,6 +248,10 @@ class Problem:
         code = lib().mfcg_cg_end(self.h, _ptr(x), ctypes.byref(its),
                                  hist.ctypes.data_as(ctypes.c_void_p) if want_hist else None, _stream(stream))
         return code, its.value, (hist[: its.value + 1] if want_hist else None)
+
+    def set_solver(self, solver):
+        """SOLVER_FUSED (default), SOLVER_ALG5_SPLIT or SOLVER_PCG_BASIC."""
+        _check(lib().mfcg_set_solver(self.h, int(solver)), self.h)
 
     def set_timing(self, on=True):
         _check(lib().mfcg_set_timing(self.h, 1 if on else 0), self.h)
