@@ -104,6 +104,30 @@ typedef struct {
 int mfcg_setup(const mfcg_mesh *mesh, int32_t degree, const double *cell_coeff,
                const mfcg_options *opt, void *hip_stream, mfcg_handle *out);
 
+/* Replaces the cell coefficient a_e (host, nx*ny*nz positive finite values
+ * as in mfcg_setup; NULL: a = 1) and rebuilds G_q and the diagonal (and the
+ * FP32 copy if one exists) without rebuilding the enumeration.  Must not
+ * be called between mfcg_cg_begin and mfcg_cg_end.  Synchronises
+ * hip_stream.  Errors: EINVAL, ENOMEM, EHIP. */
+int mfcg_set_coefficient(mfcg_handle h, const double *cell_coeff, void *hip_stream);
+
+/* Initial guess from a predicted solution shape u (device, lexicographic):
+ * the Galerkin-optimal multiple x0 = s u', s = u'^T b / u'^T A u', where u'
+ * is u with its Dirichlet entries set to 0.  This minimises the A-norm of
+ * the error over multiples of u', so ||x* - x0||_A <= ||x*||_A: never
+ * worse than x0 = 0 in the norm CG minimises (Sec. 3).  x0 = 0 instead if
+ * u'^T A u' is not positive or s is 0 or not finite, or if
+ * ||b - A x0|| >= max_rel_res ||b|| (pass +inf to accept any residual).
+ *   x0       device out, lexicographic, may not alias b or u
+ *   scale    host out or NULL: s (0 when x0 = 0)
+ *   rel_res  host out or NULL: ||b - A x0|| / ||b|| (1 when x0 = 0)
+ *   used     host out or NULL: 1 if x0 = s u', 0 if x0 = 0
+ * Uses the handle's work vectors: must not be called between
+ * mfcg_cg_begin and mfcg_cg_end.  Synchronises hip_stream.
+ * Errors: EINVAL (null pointers, max_rel_res NaN), EHIP. */
+int mfcg_warmstart(mfcg_handle h, const double *b, const double *u, double max_rel_res, double *x0, double *scale,
+                   double *rel_res, int32_t *used, void *hip_stream);
+
 /* Number of nodes (vector length), Dirichlet nodes included. */
 int mfcg_n_dofs(mfcg_handle h, int64_t *n);
 

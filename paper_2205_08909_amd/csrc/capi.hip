@@ -198,6 +198,40 @@ static int host_sumsq(mfcg_ctx *h, const double *a, const double *c, int64_t n, 
     return MFCG_OK;
 }
 
+/* fixed-order host sum of the per-block partials of launch_pair_sum */
+static int host_pair_sum(mfcg_ctx *h, int mode, const double *a, const double *b, double sc, double *out,
+                         hipStream_t s)
+{
+    HIPCHK(h, launch_pair_sum(h->hl.n, mode, a, b, sc, h->sums, h->nsum_blocks, s));
+    std::vector<double> tmp(h->nsum_blocks);
+    HIPCHK(h, hipMemcpyAsync(tmp.data(), h->sums, sizeof(double) * h->nsum_blocks, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    double t = 0.0;
+    for (double v : tmp) t += v;
+    *out = t;
+    return MFCG_OK;
+}
+
+/* G and the diagonal from the current coefficient; the FP32 copy follows */
+static int rebuild_operator(mfcg_ctx *h, hipStream_t s)
+{
+    GeomArgs g{};
+    g.L = h->lv;
+    g.tab = h->tab;
+    g.K = h->K;
+    g.map_kind = h->mesh.map_kind;
+    g.amp = h->mesh.map_kind == MFCG_MAP_AFFINE ? 0.0 : h->mesh.map_amplitude;
+    g.bc = h->mesh.bc;
+    g.coeff = h->d_coeff;
+    HIPCHK(h, launch_geometry(g, h->G, s));
+    HIPCHK(h, launch_diagonal(g, h->G, h->diag_lex, h->dinv, s));
+    if (h->G32) {
+        HIPCHK(h, launch_convert(h->hl.g_elems, h->G, h->G32, s));
+        HIPCHK(h, launch_convert(h->hl.n, h->dinv, h->dinv32, s));
+    }
+    return MFCG_OK;
+}
+
 extern "C" {
 
 const char *mfcg_error_string(int code)
@@ -343,22 +377,76 @@ int mfcg_setup(const mfcg_mesh *mesh, int32_t degree, const double *cell_coeff, 
     SCHK(hipMemsetAsync(h->part, 0, sizeof(double) * std::max<int64_t>(1, L.npart), s));
     SCHK(hipMemsetAsync(h->st, 0, sizeof(CGState), s));
 
-    GeomArgs g{};
-    g.L = lv;
-    g.tab = h->tab;
-    g.K = degree;
-    g.map_kind = mesh->map_kind;
-    g.amp = mesh->map_kind == MFCG_MAP_AFFINE ? 0.0 : mesh->map_amplitude;
-    g.bc = mesh->bc;
-    g.coeff = h->d_coeff;
-    SCHK(launch_geometry(g, h->G, s));
-    SCHK(launch_diagonal(g, h->G, h->diag_lex, h->dinv, s));
+    if (rebuild_operator(h, s)) return bail(MFCG_EHIP);
     if (opt && opt->fp32) {
         if (ensure_fp32(h, s)) return bail(MFCG_EHIP);
     }
     SCHK(hipStreamSynchronize(s));
 #undef SCHK
     *out = h;
+    return MFCG_OK;
+}
+
+int mfcg_set_coefficient(mfcg_handle h, const double *cell_coeff, void *hip_stream)
+{
+    if (!h) return fail(h, MFCG_EINVAL, "null handle");
+    const int64_t ncell = (int64_t)h->mesh.cells[0] * h->mesh.cells[1] * h->mesh.cells[2];
+    if (cell_coeff) {
+        for (int64_t c = 0; c < ncell; ++c)
+            if (!(cell_coeff[c] > 0.0) || !std::isfinite(cell_coeff[c]))
+                return fail(h, MFCG_EINVAL, "cell coefficients must be positive and finite");
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (cell_coeff) {
+        if (!h->d_coeff) HIPCHK(h, dalloc(&h->d_coeff, ncell));
+        HIPCHK(h, hipMemcpyAsync(h->d_coeff, cell_coeff, sizeof(double) * ncell, hipMemcpyHostToDevice, s));
+    } else if (h->d_coeff) {
+        HIPCHK(h, hipStreamSynchronize(s));
+        HIPCHK(h, hipFree(h->d_coeff));
+        h->d_coeff = nullptr;
+    }
+    int rc = rebuild_operator(h, s);
+    if (rc) return rc;
+    HIPCHK(h, hipStreamSynchronize(s));
+    return MFCG_OK;
+}
+
+int mfcg_warmstart(mfcg_handle h, const double *b, const double *u, double max_rel_res, double *x0, double *scale,
+                   double *rel_res, int32_t *used, void *hip_stream)
+{
+    if (!h || !b || !u || !x0) return fail(h, MFCG_EINVAL, "null argument");
+    if (std::isnan(max_rel_res)) return fail(h, MFCG_EINVAL, "max_rel_res is NaN");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int64_t n = h->hl.n;
+    /* internal order: p = u with the Dirichlet block zeroed, v = A p, r = b */
+    HIPCHK(h, launch_lex_to_int<double>(h->lv, u, h->p, s));
+    if (h->lv.nC > 0) HIPCHK(h, hipMemsetAsync(h->p + h->lv.offC, 0, sizeof(double) * h->lv.nC, s));
+    int rc = vmult_internal(h, h->p, h->v, s);
+    if (rc) return rc;
+    HIPCHK(h, launch_lex_to_int<double>(h->lv, b, h->r, s));
+    double ub = 0.0, uau = 0.0, bb = 0.0;
+    if ((rc = host_pair_sum(h, 0, h->p, h->r, 0.0, &ub, s))) return rc;
+    if ((rc = host_pair_sum(h, 0, h->p, h->v, 0.0, &uau, s))) return rc;
+    if ((rc = host_pair_sum(h, 0, h->r, h->r, 0.0, &bb, s))) return rc;
+    double sc = (uau > 0.0 && std::isfinite(uau) && std::isfinite(ub)) ? ub / uau : 0.0;
+    bool ok = sc != 0.0 && std::isfinite(sc);
+    double rel = 1.0;
+    if (ok) {
+        double rr = 0.0; /* ||b - A (sc p)||^2 */
+        if ((rc = host_pair_sum(h, 1, h->r, h->v, sc, &rr, s))) return rc;
+        rel = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+        ok = std::isfinite(rr) && !(rel >= max_rel_res);
+    }
+    if (ok) {
+        HIPCHK(h, launch_scale(n, h->p, sc, h->vout, s));
+        HIPCHK(h, launch_int_to_lex<double>(h->lv, h->vout, x0, s));
+    } else {
+        HIPCHK(h, hipMemsetAsync(x0, 0, sizeof(double) * n, s));
+    }
+    HIPCHK(h, hipStreamSynchronize(s));
+    if (scale) *scale = ok ? sc : 0.0;
+    if (rel_res) *rel_res = ok ? rel : 1.0;
+    if (used) *used = ok ? 1 : 0;
     return MFCG_OK;
 }
 

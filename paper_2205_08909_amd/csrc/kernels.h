@@ -61,6 +61,11 @@ hipError_t launch_reconstruct(int64_t n, T *x, const T *p, const T *r, const T *
 /* part[0..nb) = block sums of (a_i - c_i)^2 (c may be NULL); the caller adds them in order */
 hipError_t launch_sumsq(int64_t n, const double *a, const double *c, double *part, int nb, hipStream_t s);
 hipError_t launch_convert(int64_t n, const double *in, float *out, hipStream_t s);
+/* part[0..nb) = block sums of a_i b_i (mode 0) or (a_i - sc b_i)^2 (mode 1) */
+hipError_t launch_pair_sum(int64_t n, int mode, const double *a, const double *b, double sc, double *part, int nb,
+                           hipStream_t s);
+/* out = sc a */
+hipError_t launch_scale(int64_t n, const double *a, double sc, double *out, hipStream_t s);
 /* iterative refinement: r = b - v; x += d */
 hipError_t launch_residual(int64_t n, const double *b, const double *v, double *r, hipStream_t s);
 hipError_t launch_add_correction(int64_t n, double *x, const float *d, hipStream_t s);

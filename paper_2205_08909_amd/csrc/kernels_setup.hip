@@ -410,6 +410,51 @@ hipError_t launch_sumsq(int64_t n, const double *b, const double *ax, double *pa
     return hipGetLastError();
 }
 
+/* part[block] = partial sums of a_i b_i (mode 0) or (a_i - s b_i)^2 (mode 1) */
+__global__ __launch_bounds__(SETUP_WG) void pair_sum_kernel(int64_t n, int mode, const double *a, const double *b,
+                                                            double sc, double *part)
+{
+    __shared__ double red[SETUP_WG / 64];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * SETUP_WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * SETUP_WG) {
+        if (mode == 0) {
+            s += a[i] * b[i];
+        } else {
+            const double d = fma(-sc, b[i], a[i]);
+            s += d * d;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < SETUP_WG / 64; ++w) t += red[w];
+        part[blockIdx.x] = t;
+    }
+}
+
+hipError_t launch_pair_sum(int64_t n, int mode, const double *a, const double *b, double sc, double *part, int nb,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(pair_sum_kernel, dim3((unsigned)nb), dim3(SETUP_WG), 0, s, n, mode, a, b, sc, part);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(SETUP_WG) void scale_kernel(int64_t n, const double *a, double sc, double *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * SETUP_WG + threadIdx.x;
+    if (i < n) out[i] = sc * a[i];
+}
+
+hipError_t launch_scale(int64_t n, const double *a, double sc, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(scale_kernel, dim3((unsigned)((n + SETUP_WG - 1) / SETUP_WG)), dim3(SETUP_WG), 0, s, n, a, sc,
+                       out);
+    return hipGetLastError();
+}
+
 /* Algorithm 5 exit: x_{k+1} = x_k + alpha_k p_k (k odd) or
  * x_{k-1} + alpha_k p_k + alpha_{k-1}/beta_{k-1} (p_k - D^{-1} r_k) (k even);
  * x_k on breakdown (xa = 0). */

@@ -102,3 +102,17 @@ def warmstart_sample(seed, ncells=48):
     length = float(rng.uniform(0.05, 0.2))
     logc = grf_log_coefficient(ncells, length, 1.0, seed=seed + 7_000_000)
     return {"length": length, "log_coeff": logc, "coeff": np.exp(logc), "bumps": bump_params(seed + 9_000_000)}
+
+
+def network_init(shapes, seed=0, last_scale=0.1):
+    """Initial weights of the warm-start network: for each weight shape
+    (c_out, c_in, kd, kh, kw) normal draws with standard deviation
+    sqrt(2 / fan_in), fan_in = c_in kd kh kw (the last shape scaled by
+    last_scale); biases zero.  Returns a list of (w, b) float32 arrays."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i, sh in enumerate(shapes):
+        fan_in = int(np.prod(sh[1:]))
+        std = np.sqrt(2.0 / fan_in) * (last_scale if i == len(shapes) - 1 else 1.0)
+        out.append((rng.standard_normal(sh).astype(np.float32) * np.float32(std), np.zeros(sh[0], np.float32)))
+    return out

@@ -23,7 +23,7 @@ EXPORTED = [
     "mfcg_setup", "mfcg_n_dofs", "mfcg_vmult", "mfcg_diagonal", "mfcg_assemble_rhs", "mfcg_solve",
     "mfcg_cg_begin", "mfcg_cg_iterate", "mfcg_cg_end", "mfcg_set_timing", "mfcg_get_timing",
     "mfcg_layout_info", "mfcg_layout_permutation", "mfcg_destroy", "mfcg_error_string", "mfcg_last_error",
-    "mfcg_stream_bench", "mfcg_solve_ir", "mfcg_set_solver",
+    "mfcg_stream_bench", "mfcg_solve_ir", "mfcg_set_solver", "mfcg_set_coefficient", "mfcg_warmstart",
 ]
 
 
@@ -71,6 +71,9 @@ def lib():
         L.mfcg_destroy.argtypes = [P]
         L.mfcg_stream_bench.argtypes = [I32, I64, P, P, I32, P]
         L.mfcg_solve_ir.argtypes = [P, P, P, D, D, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), P, P, P]
+        L.mfcg_set_solver.argtypes = [P, I32]
+        L.mfcg_set_coefficient.argtypes = [P, P, P]
+        L.mfcg_warmstart.argtypes = [P, P, P, D, P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I32), P]
         L.mfcg_error_string.argtypes = [ctypes.c_int]
         L.mfcg_error_string.restype = ctypes.c_char_p
         L.mfcg_last_error.argtypes = [P]
@@ -248,6 +251,24 @@ class Problem:
         code = lib().mfcg_cg_end(self.h, _ptr(x), ctypes.byref(its),
                                  hist.ctypes.data_as(ctypes.c_void_p) if want_hist else None, _stream(stream))
         return code, its.value, (hist[: its.value + 1] if want_hist else None)
+
+    def set_coefficient(self, coeff=None, stream=None):
+        """New cell coefficient (None: a = 1); rebuilds G_q and the diagonal."""
+        self._coeff = None if coeff is None else np.ascontiguousarray(coeff, dtype=np.float64).ravel()
+        cptr = self._coeff.ctypes.data_as(ctypes.c_void_p) if self._coeff is not None else None
+        _check(lib().mfcg_set_coefficient(self.h, cptr, _stream(stream)), self.h)
+
+    def warmstart(self, b, u, max_rel_res=float("inf"), x0=None, stream=None):
+        """x0 = s u' (Galerkin-scaled, Dirichlet entries zeroed) or 0.
+        Returns (x0, scale, rel_res, used)."""
+        _dev_vec(b, self.n, "b")
+        _dev_vec(u, self.n, "u")
+        x0 = self.empty() if x0 is None else _dev_vec(x0, self.n, "x0")
+        sc, rr = ctypes.c_double(), ctypes.c_double()
+        used = ctypes.c_int32()
+        _check(lib().mfcg_warmstart(self.h, _ptr(b), _ptr(u), float(max_rel_res), _ptr(x0), ctypes.byref(sc),
+                                    ctypes.byref(rr), ctypes.byref(used), _stream(stream)), self.h)
+        return x0, sc.value, rr.value, bool(used.value)
 
     def set_solver(self, solver):
         """SOLVER_FUSED (default), SOLVER_ALG5_SPLIT or SOLVER_PCG_BASIC."""

@@ -1,5 +1,5 @@
 """Host-side checks of the C-ABI library: it loads, exports every function
-that include/mfcg.h declares, rejects invalid arguments before any HIP call,
+that include/mfcg.h and include/mfnn.h declare, rejects invalid arguments before any HIP call,
 and its enumeration of unknowns (tile interiors, shared nodes, Dirichlet
 nodes; the GPU form of the paper's Sec. 5.3 numbering) is a bijection with
 the class sizes given by closed forms."""
@@ -15,10 +15,10 @@ from paper_2205_08909_amd import mfcg
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_functions():
-    src = open(os.path.join(ROOT, "include", "mfcg.h")).read()
+def declared_functions(header="mfcg.h", prefix="mfcg_"):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(mfcg_[a-z0-9_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(" + prefix + r"[a-z0-9_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -28,6 +28,39 @@ def test_library_exports_every_declared_symbol():
     for name in names:
         assert hasattr(L, name), name
     assert set(names) == set(mfcg.EXPORTED)
+
+
+def test_network_library_exports_every_declared_symbol():
+    from paper_2205_08909_amd import nn
+    L = nn.lib()
+    names = declared_functions("mfnn.h", "mfnn_")
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(nn.EXPORTED)
+
+
+def test_network_calls_reject_bad_descriptors():
+    """Validation happens on the host: no tensor is touched."""
+    from paper_2205_08909_amd import nn
+    L = nn.lib()
+    d = nn.desc(1, 3, 32, (145, 145, 145), 4, 4, 2, 1)
+    assert tuple(d.out) == (37, 37, 37)
+    bad = nn.ConvDesc.from_buffer_copy(d)
+    bad.out[1] = 36
+    fake = ctypes.c_void_p(64)
+    assert L.mfnn_conv3d_fwd(ctypes.byref(bad), fake, 0, fake, None, 0, fake, 0, None) == nn.EINVAL
+    assert b"out !=" in L.mfnn_last_error()
+    big = nn.desc(1, 32, 64, (16, 16, 16), 8, 1, 0, 1)  # 32*512*8 floats of LDS > 64 KiB
+    assert L.mfnn_conv3d_fwd(ctypes.byref(big), fake, 0, fake, None, 0, fake, 0, None) == nn.EINVAL
+    assert L.mfnn_conv3d_fwd(ctypes.byref(d), fake, 5, fake, None, 0, fake, 0, None) == nn.EINVAL
+    assert L.mfnn_conv3d_fwd(ctypes.byref(d), fake, 0, fake, None, 7, fake, 0, None) == nn.EINVAL
+    assert L.mfnn_conv3d_bwd_weight(ctypes.byref(d), fake, 0, fake, 0, fake, None, fake, 1, None) == nn.EINVAL
+    assert L.mfnn_conv3d_bwd_weight_work(ctypes.byref(bad)) == -1
+    assert L.mfnn_adam(10, fake, None, fake, fake, fake, 0, 1e-3, 0.9, 0.999, 1e-8, None) == nn.EINVAL
+    assert L.mfnn_convert(10, fake, 3, fake, 0, None) == nn.EINVAL
+    cells = (ctypes.c_int32 * 3)(4, 4, 0)
+    assert L.mfnn_features(cells, 3, fake, fake, fake, fake, fake, None) == nn.EINVAL
 
 
 def test_error_strings():

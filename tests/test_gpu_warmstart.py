@@ -1,0 +1,96 @@
+"""The learned warm start end to end on a reduced workload, and the two
+solver entry points it relies on (mfcg_set_coefficient, mfcg_warmstart).
+
+The network's quality has no reference (the paper has no learned part):
+it is judged by the CG residual only.  Checked here: the Galerkin-scaled
+guess never has a larger A-norm error than x0 = 0 (exactly, by
+construction), the solver still reaches 1e-10 from it, and a network
+trained for a few seconds on solver solutions saves iterations on held-out
+seeds on average.
+"""
+import numpy as np
+import pytest
+
+from paper_2205_08909_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def test_set_coefficient_matches_fresh_setup():
+    import torch
+    from paper_2205_08909_amd import mfcg
+    cells, k = 6, 3
+    c1 = inputs.grf_coefficient(cells, 0.1, 1.0, seed=1)
+    c2 = inputs.grf_coefficient(cells, 0.1, 1.0, seed=2)
+    P = mfcg.Problem(cells, k, coeff=c1, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05)
+    Q = mfcg.Problem(cells, k, coeff=c2, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05)
+    P.set_coefficient(c2)
+    u = torch.from_numpy(inputs.random_vector(P.n, 3)).cuda()
+    assert torch.equal(P.vmult(P.empty(), u), Q.vmult(Q.empty(), u))
+    assert torch.equal(P.diagonal(), Q.diagonal())
+    P.set_coefficient(None)
+    R = mfcg.Problem(cells, k, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05)
+    assert torch.equal(P.vmult(P.empty(), u), R.vmult(R.empty(), u))
+    with pytest.raises(mfcg.MfcgError):
+        P.set_coefficient(-np.ones(cells ** 3))
+    for X in (P, Q, R):
+        X.close()
+
+
+def test_galerkin_scaling_against_oracle(oracle_mod):
+    import torch
+    from paper_2205_08909_amd import mfcg
+    cells, k = (5, 6, 4), 2
+    coeff = inputs.grf_coefficient(cells, 0.1, 1.0, seed=4)
+    m = oracle_mod.Mesh(cells, k, map_kind=1, amp=0.05, coeff=coeff)
+    A = oracle_mod.assemble(m)
+    b = oracle_mod.rhs(m, oracle_mod.F_SINE)
+    P = mfcg.Problem(cells, k, coeff=coeff, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05)
+    xs, _, _, _ = oracle_mod.pcg(A, A.diagonal(), b, tol=1e-13, maxit=5000)
+    mask = m.constrained_mask()
+    rng = np.random.default_rng(5)
+    bt = torch.from_numpy(b).cuda()
+    for trial in range(1, 4):
+        u = xs * (1.0 + 0.02 * trial * rng.standard_normal(A.n)) + rng.standard_normal(A.n) * (0.01 * trial)
+        x0, sc, rel, used = P.warmstart(bt, torch.from_numpy(u).cuda())
+        up = np.where(mask, 0.0, u)
+        s_ref = up @ b / (up @ A.matvec(up))
+        assert used
+        assert abs(sc - s_ref) <= 1e-12 * abs(s_ref)
+        x0 = x0.cpu().numpy()
+        assert np.allclose(x0, s_ref * up, rtol=1e-12, atol=1e-300)
+        assert np.all(x0[mask] == 0.0)
+        e = xs - x0
+        assert e @ A.matvec(e) <= xs @ A.matvec(xs)
+        rel_ref = np.linalg.norm(b - A.matvec(x0)) / np.linalg.norm(b)
+        assert abs(rel - rel_ref) <= 1e-10 * max(rel_ref, 1e-3)
+        # the residual test: accepted below the threshold, rejected at or above it
+        _, _, _, used_lo = P.warmstart(bt, torch.from_numpy(u).cuda(), max_rel_res=rel_ref * 0.999)
+        _, _, _, used_hi = P.warmstart(bt, torch.from_numpy(u).cuda(), max_rel_res=rel_ref * 1.001)
+        assert not used_lo and used_hi
+    # a guess with no component along b: fallback to zero
+    x0, sc, rel, used = P.warmstart(bt, torch.zeros(A.n, dtype=torch.float64, device="cuda"))
+    assert not used and sc == 0.0 and rel == 1.0 and torch.count_nonzero(x0).item() == 0
+    P.close()
+
+
+def test_trained_network_saves_iterations():
+    import torch
+    from paper_2205_08909_amd import mfcg, warmstart
+    cells, k = 12, 3
+    P = mfcg.Problem(cells, k, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05)
+    nodes = (cells * k + 1,) * 3
+    X, T, gen = warmstart.generate(P, cells, k, list(range(48)), tol=1e-8)
+    net = warmstart.Net(nodes, channels=32, seed=0)
+    losses = warmstart.train(net, X, T, epochs=30, batch=8, lr=2e-3, seed=0)
+    print("losses", losses[0], losses[-1])
+    assert losses[-1] < 0.5 * losses[0]
+    rows = warmstart.evaluate(net, P, cells, k, list(range(10000, 10012)), tol=1e-10, log=print)
+    s = warmstart.summarize(rows)
+    print(s)
+    for r in rows:
+        assert r["status"] == (mfcg.OK, mfcg.OK)
+        assert r["true_rel_res"] <= 2e-10
+        assert r["energy_err0"] <= 1.0 + 1e-9  # Galerkin scaling: never worse than x0 = 0
+    assert s["iters_warm"]["mean"] < s["iters_zero"]["mean"]
+    P.close()
