@@ -141,6 +141,51 @@ def degree_sweep(args):
                       "warmup": args.warmup, "rows": rows}), flush=True)
 
 
+def warmstart_experiment(args):
+    """Learned warm start on Q3, 48^3 cells of the curved mesh (145^3 nodes):
+    coefficient exp(GRF) with length ~ U[0.05, 0.2], right-hand side a sum
+    of 8 Gaussian bumps; train on args.ws_train solver solutions (seeds
+    0..), evaluate on args.ws_eval held-out seeds (10000..): iterations and
+    time to 1e-10 against x0 = 0 (features, inference and scaling included).
+    Prints one JSON line."""
+    import torch
+    from paper_2205_08909_amd import mfcg, warmstart
+    cells, k = args.ws_cells, 3
+    log = lambda m: print(f"[warmstart] {m}", file=sys.stderr, flush=True)
+    P = mfcg.Problem(cells, k, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05)
+    nodes = (cells * k + 1,) * 3
+    X, T, gen = warmstart.generate(P, cells, k, list(range(args.ws_train)), tol=1e-4, log=log)
+    log(f"data: {gen}")
+    net = warmstart.Net(nodes, channels=32, seed=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = warmstart.train(net, X, T, epochs=args.ws_epochs, batch=8, lr=2e-3, seed=0, log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del X, T
+    torch.cuda.empty_cache()
+    # inference cost alone (features + 4 layers + Galerkin scaling), averaged
+    ws = warmstart.Workspace()
+    b, diag, logc, _ = warmstart.sample_problem(P, cells, k, 10000, ws)
+    warmstart.predict_x0(net, P, cells, k, b, diag, logc, ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        warmstart.predict_x0(net, P, cells, k, b, diag, logc, ws)
+    torch.cuda.synchronize()
+    infer_ms = (time.perf_counter() - t0) * 100
+    rows = warmstart.evaluate(net, P, cells, k, list(range(10000, 10000 + args.ws_eval)), tol=1e-10, log=log)
+    summ = warmstart.summarize(rows)
+    out = {"experiment": "learned warm start", "workload": f"Q3, {cells}^3 cells curved (sine shear 0.05), "
+           f"{P.n} DoFs, a = exp(GRF, l ~ U[0.05,0.2], var 1), f = 8 Gaussian bumps",
+           "train_samples": args.ws_train, "epochs": args.ws_epochs, "params": net.nparam,
+           "data_seconds": round(gen["seconds"], 2), "data_tol": gen["tol"], "data_mean_iters": gen["mean_iters"],
+           "train_seconds": round(train_s, 2), "loss_first_last": [losses[0], losses[-1]],
+           "inference_ms": round(infer_ms, 3), "eval": summ}
+    print(json.dumps(out), flush=True)
+    P.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,6 +199,11 @@ def main():
     ap.add_argument("--no-ablation", action="store_true")
     ap.add_argument("--sweep", action="store_true", help="degree sweep k = 1..8 instead of the main line")
     ap.add_argument("--sweep-degrees", default="1,2,3,4,5,6,7,8")
+    ap.add_argument("--warmstart", action="store_true", help="learned warm-start experiment instead of the main line")
+    ap.add_argument("--ws-cells", type=int, default=48)
+    ap.add_argument("--ws-train", type=int, default=2000)
+    ap.add_argument("--ws-eval", type=int, default=200)
+    ap.add_argument("--ws-epochs", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the multi-GPU sharding is described in DESIGN.md); "
@@ -167,6 +217,9 @@ def main():
     torch.cuda.set_device(0)
     if args.sweep:
         degree_sweep(args)
+        return
+    if args.warmstart:
+        warmstart_experiment(args)
         return
     N, k, K, W = args.cells, args.degree, args.steps, args.warmup
     t0 = time.perf_counter()

@@ -13,6 +13,8 @@ Layers on the (nx, ny, nz) node lattice (37^3 coarse points for 145^3 nodes):
   1  conv 4^3, stride 4, pad 2     3 -> 32 channels, fine -> coarse, leaky ReLU
   2  conv 3^3, pad 1               32 -> 32, leaky ReLU
   3  conv 3^3, dilation 3, pad 3   32 -> 32, leaky ReLU
+     (receptive field 9 coarse points without gaps; dilations (2, 6), with
+     17 points and gaps, trained to a larger energy-norm error)
   4  transposed conv 8^3, stride 4, pad 4   32 -> 1, coarse -> fine, + bias
 Input channels: mean log a around each node, b / rms(b), D^{-1} b / rms.
 Target: the solver's solution divided by its rms value (only the shape
@@ -30,7 +32,7 @@ from . import inputs, mfcg, nn
 
 
 class Net:
-    def __init__(self, nodes, channels=32, seed=0):
+    def __init__(self, nodes, channels=32, seed=0, dil=(1, 3)):
         import torch
         self.torch = torch
         nodes = tuple(int(v) for v in nodes)  # (D, H, W) = (nz, ny, nx)
@@ -39,8 +41,8 @@ class Net:
         self.g1 = nn.desc(1, 3, c, nodes, 4, 4, 2, 1)
         coarse = tuple(self.g1.out)
         self.coarse = coarse
-        self.g2 = nn.desc(1, c, c, coarse, 3, 1, 1, 1)
-        self.g3 = nn.desc(1, c, c, coarse, 3, 1, 3, 3)
+        self.g2 = nn.desc(1, c, c, coarse, 3, 1, dil[0], dil[0])
+        self.g3 = nn.desc(1, c, c, coarse, 3, 1, dil[1], dil[1])
         self.g4 = nn.desc(1, 1, c, nodes, 8, 4, 4, 1)  # conv fine -> coarse; layer 4 applies its transpose
         assert tuple(self.g4.out) == coarse
         shapes = [(c, 3, 4, 4, 4), (c, c, 3, 3, 3), (c, c, 3, 3, 3), (c, 1, 8, 8, 8)]
