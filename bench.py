@@ -186,6 +186,64 @@ def warmstart_experiment(args):
     P.close()
 
 
+def batch_experiment(args):
+    """32 independent problems (side N ~ U{16..96}, degree k ~ U{2..6}, draw
+    seed 0; curved mesh; a = exp(GRF l=0.1 var=1) with per-problem seed;
+    random-normal right-hand side) solved together to 1e-10 with autotuned
+    tiles; optionally the same problems solved one after another.
+    Prints one JSON line."""
+    import torch
+    from paper_2205_08909_amd import mfcg, inputs
+    log = lambda m: print(f"[batch] {m}", file=sys.stderr, flush=True)
+    draw = inputs.batch_draw(0, args.batch_n, args.batch_nmin, args.batch_nmax)
+    probs = []
+    for d in draw:
+        probs.append({"cells": (d["N"],) * 3, "degree": d["k"], "map_kind": mfcg.MAP_SINE_SHEAR, "amplitude": 0.05,
+                      "coeff": inputs.grf_coefficient(d["N"], 0.1, 1.0, seed=d["seed"]), "seed": d["seed"]})
+    t0 = time.perf_counter()
+    B = mfcg.Batch(probs, autotune=True)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    log(f"setup {setup_s:.1f} s (autotune + {len(probs)} operators)")
+    bs = []
+    for d in draw:
+        bs.append(torch.from_numpy(inputs.random_rhs(d["N"], d["k"], seed=d["seed"])).cuda())
+    xs = [torch.zeros_like(b) for b in bs]
+    ns = [P.n for P in B.problems]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    code, its, st = B.solve(bs, xs, tol=1e-10, maxit=args.batch_maxit)
+    torch.cuda.synchronize()
+    solve_s = time.perf_counter() - t0
+    work = sum(n * i for n, i in zip(ns, its))
+    log(f"batched solve {solve_s:.2f} s, status {code}, {work / solve_s / 1e9:.2f} GDoF*it/s")
+    # true residual of every problem with the FP64 operator
+    worst = 0.0
+    for P, b, x in zip(B.problems, bs, xs):
+        r = b - P.vmult(torch.empty_like(b), x)
+        worst = max(worst, (torch.linalg.norm(r) / torch.linalg.norm(b)).item())
+    seq_s = None
+    if args.batch_compare:
+        t0 = time.perf_counter()
+        for i, (P, b) in enumerate(zip(B.problems, bs)):
+            x = torch.zeros_like(b)
+            P.solve(b, x, tol=1e-10, maxit=args.batch_maxit, want_hist=False, raise_on=False)
+        torch.cuda.synchronize()
+        seq_s = time.perf_counter() - t0
+        log(f"one after another: {seq_s:.2f} s")
+    geo = sum(8 * 6 * (p["degree"] + 1) ** 3 * p["cells"][0] ** 3 for p in probs)
+    out = {"experiment": "batched solve", "problems": len(probs), "total_dofs": sum(ns),
+           "geometry_GB": round(geo / 1e9, 2), "footprint_GB_est": round((geo + 8 * 10 * sum(ns)) / 1e9, 1),
+           "setup_s": round(setup_s, 2), "solve_s": round(solve_s, 3), "status": int(code),
+           "GDoF_it_s": round(work / solve_s / 1e9, 3), "worst_true_rel_res": float(f"{worst:.3e}"),
+           "sequential_s": None if seq_s is None else round(seq_s, 3),
+           "speedup_vs_sequential": None if seq_s is None else round(seq_s / solve_s, 3),
+           "rows": [{"N": p["cells"][0], "k": p["degree"], "n": n, "iters": i, "tile": list(t), "status": int(c)}
+                    for p, n, i, t, c in zip(probs, ns, its, B.tiles, st)]}
+    print(json.dumps(out), flush=True)
+    B.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,6 +262,12 @@ def main():
     ap.add_argument("--ws-train", type=int, default=2000)
     ap.add_argument("--ws-eval", type=int, default=200)
     ap.add_argument("--ws-epochs", type=int, default=10)
+    ap.add_argument("--batch", action="store_true", help="batched-solve experiment instead of the main line")
+    ap.add_argument("--batch-n", type=int, default=32)
+    ap.add_argument("--batch-nmin", type=int, default=16)
+    ap.add_argument("--batch-nmax", type=int, default=96)
+    ap.add_argument("--batch-maxit", type=int, default=30000)
+    ap.add_argument("--batch-compare", action="store_true", help="also solve the problems one after another")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the multi-GPU sharding is described in DESIGN.md); "
@@ -220,6 +284,9 @@ def main():
         return
     if args.warmstart:
         warmstart_experiment(args)
+        return
+    if args.batch:
+        batch_experiment(args)
         return
     N, k, K, W = args.cells, args.degree, args.steps, args.warmup
     t0 = time.perf_counter()

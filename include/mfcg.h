@@ -73,6 +73,7 @@ enum {
 };
 
 typedef struct mfcg_ctx *mfcg_handle;
+typedef struct mfcg_batch_ctx *mfcg_batch;
 
 /* Mesh: cells per direction on [0,1]^3, the map applied to it, the
  * boundary treatment. */
@@ -233,6 +234,51 @@ int mfcg_layout_permutation(const mfcg_mesh *mesh, int32_t degree, const int32_t
  * b of the grid (one read per element; dst holds nblocks doubles).  n even,
  * 16-byte aligned device pointers; nblocks >= 1 workgroups of 256 threads. */
 int mfcg_stream_bench(int32_t kind, int64_t n, const double *src, double *dst, int32_t nblocks, void *hip_stream);
+
+/* Tile autotuner: times `iters` fused iterations (after 2 untimed ones)
+ * of a Poisson problem on `mesh` for each candidate tile (the compiled
+ * maximum extent in x and y and half of it, 8, 16 and 32 cell layers in z,
+ * clipped to the mesh) and returns the fastest in tile_out[3] and its time
+ * per iteration in *ms_out (may be NULL).  Builds and frees one handle per
+ * candidate.  Errors: EINVAL, ENOMEM, EHIP. */
+int mfcg_autotune_tile(const mfcg_mesh *mesh, int32_t degree, int32_t iters, int32_t *tile_out, double *ms_out,
+                       void *hip_stream);
+
+/* Batches of independent problems of different sizes and degrees solved
+ * together.  In every CG iteration of the batch, the problems too small to
+ * fill the device (fewer than 512 tiles) are packed: one launch of the
+ * fused tile kernel per degree present over a work list of
+ * (problem, tile) items, one shared-node launch over (problem, block)
+ * items and one finish launch with a block per problem; each larger
+ * problem runs its own three launches.  Each problem keeps its own scalars
+ * and convergence test (its own Algorithm 5 iteration, identical to
+ * mfcg_solve's, bitwise), and problems that have converged drop out of the
+ * work lists at the next poll (every 16 iterations).
+ *   meshes, degrees  nprob entries (as for mfcg_setup)
+ *   coeffs           host array of nprob host pointers (entries or the
+ *                    array itself NULL: a = 1)
+ *   autotune         1: one tile per degree from mfcg_autotune_tile on a
+ *                    cube of min(largest cells, 48) cells; 0: defaults
+ * Errors: EINVAL (the failing problem is named in the message), ENOMEM,
+ * EHIP.  On error *out is NULL. */
+int mfcg_batch_setup(int32_t nprob, const mfcg_mesh *meshes, const int32_t *degrees, const double *const *coeffs,
+                     int32_t autotune, void *hip_stream, mfcg_batch *out);
+
+/* Problem i of the batch: its handle (owned by the batch; valid for
+ * mfcg_vmult, mfcg_diagonal, mfcg_assemble_rhs, mfcg_n_dofs...) and the
+ * tile it uses; either output may be NULL. */
+int mfcg_batch_info(mfcg_batch hb, int32_t i, mfcg_handle *h, int32_t *tile);
+
+/* Solves all problems to ||r_i|| < tol ||b_i|| (each as mfcg_solve would)
+ * or maxit iterations.  b, x: host arrays of nprob device pointers (x: x0
+ * in, solution out).  iters, status: host arrays of nprob (status: MFCG_OK,
+ * MFCG_ENOTCONV or MFCG_EBREAKDOWN per problem).  Returns MFCG_OK if every
+ * problem converged, else the first non-OK status; EINVAL/EHIP on errors.
+ * Synchronises hip_stream. */
+int mfcg_batch_solve(mfcg_batch hb, const double *const *b, double *const *x, double tol, int32_t maxit,
+                     int32_t *iters, int32_t *status, void *hip_stream);
+int mfcg_batch_destroy(mfcg_batch hb);
+const char *mfcg_batch_last_error(mfcg_batch hb);
 
 int mfcg_destroy(mfcg_handle h);
 const char *mfcg_error_string(int code);

@@ -8,6 +8,8 @@
  */
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -169,7 +171,6 @@ static int vmult_internal(mfcg_ctx *h, const double *src, double *dst, hipStream
 {
     IterArgs<double> a{};
     a.L = h->lv;
-    a.tab = h->tab;
     a.G = h->G;
     a.dinv = h->dinv;
     a.src = src;
@@ -632,7 +633,6 @@ int mfcg_cg_iterate(mfcg_handle h, int32_t n_it, void *hip_stream)
     hipStream_t s = (hipStream_t)hip_stream;
     IterArgs<double> a{};
     a.L = h->lv;
-    a.tab = h->tab;
     a.G = h->G;
     a.dinv = h->dinv;
     a.r = h->r;
@@ -916,5 +916,322 @@ int mfcg_stream_bench(int32_t kind, int64_t n, const double *src, double *dst, i
     HIPCHK(nullptr, launch_stream(kind, n, src, dst, nblocks, (hipStream_t)hip_stream));
     return MFCG_OK;
 }
+
+
+/* ------------------------------------------------------------------ */
+/* Tile autotuner and batches of independent problems                 */
+/* ------------------------------------------------------------------ */
+
+int mfcg_autotune_tile(const mfcg_mesh *mesh, int32_t degree, int32_t iters, int32_t *tile_out, double *ms_out,
+                       void *hip_stream)
+{
+    std::string msg;
+    int rc = validate_mesh(mesh, degree, nullptr, msg);
+    if (rc) return fail(nullptr, rc, msg);
+    if (!tile_out || iters < 1) return fail(nullptr, MFCG_EINVAL, "bad autotune arguments");
+    hipStream_t s = (hipStream_t)hip_stream;
+    int tx = 0, ty = 0;
+    tile_limits(degree, &tx, &ty);
+    /* candidates: the compiled maximum and half of it in x and y, 8/16/32 cell layers in z */
+    std::vector<std::array<int, 3>> cand;
+    for (int h : {tx, (tx + 1) / 2})
+        for (int z : {8, 16, 32}) {
+            std::array<int, 3> t = {std::min(h, mesh->cells[0]), std::min(h, mesh->cells[1]),
+                                    std::min(z, mesh->cells[2])};
+            if (std::find(cand.begin(), cand.end(), t) == cand.end()) cand.push_back(t);
+        }
+    int64_t n = 1;
+    for (int d = 0; d < 3; ++d) n *= (int64_t)mesh->cells[d] * degree + 1;
+    double *b = nullptr;
+    HIPCHK(nullptr, dalloc(&b, n));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(nullptr, hipEventCreate(&e0));
+    HIPCHK(nullptr, hipEventCreate(&e1));
+    double best = 1e300;
+    std::array<int, 3> bt = cand[0];
+    int status = MFCG_OK;
+    for (const auto &t : cand) {
+        mfcg_options o{};
+        o.tile[0] = t[0];
+        o.tile[1] = t[1];
+        o.tile[2] = t[2];
+        mfcg_handle h = nullptr;
+        rc = mfcg_setup(mesh, degree, nullptr, &o, hip_stream, &h);
+        if (rc) {
+            status = rc;
+            break;
+        }
+        float ms = 0.f;
+        rc = mfcg_assemble_rhs(h, MFCG_RHS_SINE, nullptr, b, hip_stream);
+        if (!rc) rc = mfcg_cg_begin(h, b, nullptr, 0.0, iters + 2, hip_stream);
+        if (!rc) rc = mfcg_cg_iterate(h, 2, hip_stream);
+        if (!rc && hipEventRecord(e0, s) != hipSuccess) rc = MFCG_EHIP;
+        if (!rc) rc = mfcg_cg_iterate(h, iters, hip_stream);
+        if (!rc && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            rc = MFCG_EHIP;
+        mfcg_destroy(h);
+        if (rc) {
+            status = rc;
+            break;
+        }
+        if (ms < best) {
+            best = ms;
+            bt = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(b);
+    if (status) return fail(nullptr, status, "autotune: a candidate failed");
+    for (int d = 0; d < 3; ++d) tile_out[d] = bt[d];
+    if (ms_out) *ms_out = best / iters;
+    return MFCG_OK;
+}
+
+}  // extern "C"
+
+/* a batch problem with at least this many tiles (two per compute unit)
+ * runs its own kernel launches in each batch iteration */
+constexpr int64_t BATCH_OWN_LAUNCH_TILES = 512;
+
+struct mfcg_batch_ctx {
+    std::vector<mfcg_ctx *> probs;
+    std::vector<std::array<int32_t, 3>> tiles;
+    IterArgs<double> *d_args = nullptr;
+    int2 *d_items = nullptr;   /* all fused-kernel items, grouped by degree */
+    int2 *d_shared = nullptr;  /* shared-node items */
+    int *d_active = nullptr;
+    int64_t max_items = 0, max_shared = 0;
+    int check_every = 16;
+    std::string err;
+};
+
+static void batch_release(mfcg_batch_ctx *hb)
+{
+    for (mfcg_ctx *h : hb->probs)
+        if (h) mfcg_destroy(h);
+    (void)hipFree(hb->d_args);
+    (void)hipFree(hb->d_items);
+    (void)hipFree(hb->d_shared);
+    (void)hipFree(hb->d_active);
+}
+
+static int batch_fail(mfcg_batch_ctx *hb, int code, const std::string &msg)
+{
+    if (hb) hb->err = msg;
+    g_last_error = msg;
+    return code;
+}
+
+#define BCHK(hb, call)                                                                          \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return batch_fail((hb), e_ == hipErrorOutOfMemory ? MFCG_ENOMEM : MFCG_EHIP,        \
+                              std::string(#call) + ": " + hipGetErrorString(e_));                \
+    } while (0)
+
+static IterArgs<double> iter_args(const mfcg_ctx *h)
+{
+    IterArgs<double> a{};
+    a.L = h->lv;
+    a.G = h->G;
+    a.dinv = h->dinv;
+    a.r = h->r;
+    a.p = h->p;
+    a.v = h->v;
+    a.x = h->x;
+    a.part = h->part;
+    a.dots = h->dots;
+    a.st = h->st;
+    a.hist = h->hist;
+    a.nshared_blocks = h->nshared_blocks;
+    return a;
+}
+
+extern "C" {
+
+int mfcg_batch_setup(int32_t nprob, const mfcg_mesh *meshes, const int32_t *degrees, const double *const *coeffs,
+                     int32_t autotune, void *hip_stream, mfcg_batch *out)
+{
+    if (!out) return batch_fail(nullptr, MFCG_EINVAL, "null out");
+    *out = nullptr;
+    if (nprob < 1 || !meshes || !degrees) return batch_fail(nullptr, MFCG_EINVAL, "bad batch arguments");
+    for (int i = 0; i < nprob; ++i) {
+        std::string msg;
+        int rc = validate_mesh(&meshes[i], degrees[i], nullptr, msg);
+        if (rc) return batch_fail(nullptr, rc, "problem " + std::to_string(i) + ": " + msg);
+    }
+    mfcg_batch_ctx *hb = new (std::nothrow) mfcg_batch_ctx();
+    if (!hb) return batch_fail(nullptr, MFCG_ENOMEM, "host allocation failed");
+    hb->probs.assign(nprob, nullptr);
+    hb->tiles.assign(nprob, {0, 0, 0});
+    /* one autotuned tile per degree, on a cube of min(largest problem, 48) cells of the first problem's map */
+    if (autotune) {
+        for (int K = 1; K <= 8; ++K) {
+            int first = -1, cmax = 0;
+            for (int i = 0; i < nprob; ++i)
+                if (degrees[i] == K) {
+                    if (first < 0) first = i;
+                    cmax = std::max(cmax, std::min(meshes[i].cells[0], std::min(meshes[i].cells[1], meshes[i].cells[2])));
+                }
+            if (first < 0) continue;
+            mfcg_mesh m = meshes[first];
+            const int c = std::min(cmax, 48);
+            m.cells[0] = m.cells[1] = m.cells[2] = c;
+            int32_t t[3];
+            int rc = mfcg_autotune_tile(&m, K, 6, t, nullptr, hip_stream);
+            if (rc) {
+                batch_release(hb);
+                delete hb;
+                return rc;
+            }
+            for (int i = 0; i < nprob; ++i)
+                if (degrees[i] == K)
+                    for (int d = 0; d < 3; ++d) hb->tiles[i][d] = std::min(t[d], meshes[i].cells[d]);
+        }
+    }
+    for (int i = 0; i < nprob; ++i) {
+        mfcg_options o{};
+        for (int d = 0; d < 3; ++d) o.tile[d] = hb->tiles[i][d];
+        int rc = mfcg_setup(&meshes[i], degrees[i], coeffs ? coeffs[i] : nullptr, &o, hip_stream, &hb->probs[i]);
+        if (rc) {
+            std::string m = "problem " + std::to_string(i) + ": " + g_last_error;
+            batch_release(hb);
+            delete hb;
+            return batch_fail(nullptr, rc, m);
+        }
+        const HostLayout &L = hb->probs[i]->hl;
+        for (int d = 0; d < 3; ++d) hb->tiles[i][d] = L.d[d].T;
+        hb->max_items += L.ntiles;
+        hb->max_shared += hb->probs[i]->nshared_blocks;
+    }
+    auto bail = [&](hipError_t e) {
+        std::string m = std::string("batch allocation: ") + hipGetErrorString(e);
+        batch_release(hb);
+        delete hb;
+        return batch_fail(nullptr, e == hipErrorOutOfMemory ? MFCG_ENOMEM : MFCG_EHIP, m);
+    };
+    hipError_t e;
+    if ((e = dalloc(&hb->d_args, nprob)) != hipSuccess) return bail(e);
+    if ((e = dalloc(&hb->d_items, hb->max_items)) != hipSuccess) return bail(e);
+    if ((e = dalloc(&hb->d_shared, hb->max_shared)) != hipSuccess) return bail(e);
+    if ((e = dalloc(&hb->d_active, nprob)) != hipSuccess) return bail(e);
+    *out = hb;
+    return MFCG_OK;
+}
+
+int mfcg_batch_info(mfcg_batch hb, int32_t i, mfcg_handle *h, int32_t *tile)
+{
+    if (!hb || i < 0 || i >= (int32_t)hb->probs.size()) return batch_fail(hb, MFCG_EINVAL, "bad problem index");
+    if (h) *h = hb->probs[i];
+    if (tile)
+        for (int d = 0; d < 3; ++d) tile[d] = hb->tiles[i][d];
+    return MFCG_OK;
+}
+
+int mfcg_batch_solve(mfcg_batch hb, const double *const *b, double *const *x, double tol, int32_t maxit,
+                     int32_t *iters, int32_t *status, void *hip_stream)
+{
+    if (!hb || !b || !x || !iters || !status) return batch_fail(hb, MFCG_EINVAL, "null argument");
+    const int np = (int)hb->probs.size();
+    for (int i = 0; i < np; ++i)
+        if (!b[i] || !x[i]) return batch_fail(hb, MFCG_EINVAL, "null vector of problem " + std::to_string(i));
+    hipStream_t s = (hipStream_t)hip_stream;
+    /* every problem starts as mfcg_solve would start it */
+    for (int i = 0; i < np; ++i) {
+        int rc = mfcg_cg_begin(hb->probs[i], b[i], x[i], tol, maxit, hip_stream);
+        if (rc) return batch_fail(hb, rc, "problem " + std::to_string(i) + ": " + hb->probs[i]->err);
+    }
+    std::vector<IterArgs<double>> args(np);
+    for (int i = 0; i < np; ++i) args[i] = iter_args(hb->probs[i]);
+    BCHK(hb, hipMemcpyAsync(hb->d_args, args.data(), sizeof(IterArgs<double>) * np, hipMemcpyHostToDevice, s));
+    std::vector<CGState> st(np);
+    auto poll = [&]() -> int {
+        for (int i = 0; i < np; ++i)
+            BCHK(hb, hipMemcpyAsync(&st[i], hb->probs[i]->st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+        BCHK(hb, hipStreamSynchronize(s));
+        return MFCG_OK;
+    };
+    int rc = poll();
+    if (rc) return rc;
+    std::vector<int2> items, shared;
+    std::vector<int> active;
+    int launched = 0;
+    while (launched < maxit) {
+        /* work lists of the problems still running (converged ones drop out) */
+        BatchLaunch bl{};
+        bl.probs = hb->d_args;
+        items.clear();
+        shared.clear();
+        active.clear();
+        int off[10] = {0};
+        /* problems with enough tiles to fill the device run their own
+         * launches (kernel arguments, no register spills); the others are
+         * packed into the work lists */
+        std::vector<int> own;
+        for (int K = 1; K <= 8; ++K) {
+            off[K] = (int)items.size();
+            for (int i = 0; i < np; ++i) {
+                if (hb->probs[i]->K != K || st[i].flag != FLAG_RUN) continue;
+                if (hb->probs[i]->hl.ntiles >= BATCH_OWN_LAUNCH_TILES) {
+                    if (std::find(own.begin(), own.end(), i) == own.end()) own.push_back(i);
+                    continue;
+                }
+                for (int64_t t = 0; t < hb->probs[i]->hl.ntiles; ++t) items.push_back(make_int2(i, (int)t));
+            }
+            bl.nitems[K] = (int)items.size() - off[K];
+        }
+        for (int i = 0; i < np; ++i)
+            if (st[i].flag == FLAG_RUN && std::find(own.begin(), own.end(), i) == own.end()) {
+                active.push_back(i);
+                for (int q = 0; q < hb->probs[i]->nshared_blocks; ++q) shared.push_back(make_int2(i, q));
+            }
+        if (active.empty() && own.empty()) break;
+        if (!items.empty())
+            BCHK(hb, hipMemcpyAsync(hb->d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, s));
+        if (!shared.empty())
+            BCHK(hb, hipMemcpyAsync(hb->d_shared, shared.data(), sizeof(int2) * shared.size(), hipMemcpyHostToDevice, s));
+        if (!active.empty())
+            BCHK(hb, hipMemcpyAsync(hb->d_active, active.data(), sizeof(int) * active.size(), hipMemcpyHostToDevice, s));
+        for (int K = 1; K <= 8; ++K) bl.items[K] = hb->d_items + off[K];
+        bl.shared_items = hb->d_shared;
+        bl.nshared_items = (int)shared.size();
+        bl.active = hb->d_active;
+        bl.nactive = (int)active.size();
+        const int chunk = std::min(hb->check_every, maxit - launched);
+        for (int it = 0; it < chunk; ++it) {
+            for (int i : own) {
+                BCHK(hb, launch_fused<double>(hb->probs[i]->K, MODE_CG, args[i], s));
+                BCHK(hb, launch_shared<double>(MODE_CG, args[i], s));
+            }
+            if (!active.empty()) BCHK(hb, launch_batch_iteration(bl, s));
+        }
+        launched += chunk;
+        rc = poll();
+        if (rc) return rc;
+    }
+    int worst = MFCG_OK;
+    for (int i = 0; i < np; ++i) {
+        hb->probs[i]->launched = launched; /* the state holds each problem's own count */
+        const int r = mfcg_cg_end(hb->probs[i], x[i], &iters[i], nullptr, hip_stream);
+        status[i] = r;
+        if (r != MFCG_OK && r != MFCG_ENOTCONV && r != MFCG_EBREAKDOWN) return batch_fail(hb, r, hb->probs[i]->err);
+        if (r != MFCG_OK && worst == MFCG_OK) worst = r;
+    }
+    return worst;
+}
+
+int mfcg_batch_destroy(mfcg_batch hb)
+{
+    if (!hb) return MFCG_OK;
+    (void)hipDeviceSynchronize();
+    batch_release(hb);
+    delete hb;
+    return MFCG_OK;
+}
+
+const char *mfcg_batch_last_error(mfcg_batch hb) { return hb ? hb->err.c_str() : g_last_error.c_str(); }
 
 }  // extern "C"

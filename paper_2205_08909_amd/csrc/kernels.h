@@ -13,7 +13,6 @@ enum Mode : int { MODE_CG = 0, MODE_VMULT = 1 };
 template <typename T>
 struct IterArgs {
     LayoutView L;
-    Tables<T> tab;
     const T *G;     /* geometry tensor, tile-blocked */
     const T *dinv;  /* inverse diagonal, internal order (1 on Dirichlet nodes) */
     T *r, *p, *v, *x;
@@ -25,6 +24,21 @@ struct IterArgs {
     double *hist;
     int32_t nshared_blocks;
 };
+
+/* One CG iteration of a batch of independent problems (device work lists):
+ * per degree K, items[K][0..nitems[K]) = (problem, tile) pairs for the
+ * fused tile kernel; shared_items = (problem, block) pairs for the
+ * shared-node kernel; active = the problems whose finish runs. */
+struct BatchLaunch {
+    const IterArgs<double> *probs;
+    const int2 *items[9];
+    int nitems[9];
+    const int2 *shared_items;
+    int nshared_items;
+    const int *active;
+    int nactive;
+};
+hipError_t launch_batch_iteration(const BatchLaunch &b, hipStream_t s);
 
 /* Maximum tile extent in x and y (cells) compiled for degree K. */
 void tile_limits(int K, int *tx, int *ty);

@@ -102,6 +102,15 @@ __device__ inline int64_t xcd_remap(int64_t b, int64_t nb)
     return x * q + (x < r ? x : r) + i;
 }
 
+/* The batch's per-problem arguments live in device memory that no kernel
+ * writes during a launch: read them through the constant address space
+ * (scalar loads). */
+template <typename A>
+__device__ __forceinline__ const A *const_view(const A *p)
+{
+    return (const A *)(const __attribute__((address_space(4))) A *)p;
+}
+
 /* Division by a divisor fixed for a workgroup, for dividends below 2^16:
  * q = floor(n * ceil(2^32 / d) / 2^32) is exact when n, d < 2^16. */
 struct FastDiv {
@@ -116,10 +125,10 @@ struct FastDiv {
 /* Fused tile kernel                                                   */
 /* ------------------------------------------------------------------ */
 
+/* One tile of one problem: the pre / cell / sum / post passes over the
+ * tile's cell layers (called by one whole workgroup). */
 template <int K, typename T, int MODE>
-__global__ __launch_bounds__(Cfg<K>::WG)
-__attribute__((amdgpu_waves_per_eu(MFCG_WPE_MIN(Cfg<K>::WG), 8)))
-void fused_tile_kernel(const IterArgs<T> a)
+__device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t tile)
 {
     constexpr int n = K + 1, n2 = n * n, n3 = n * n * n;
     constexpr int WG = Cfg<K>::WG;
@@ -148,9 +157,6 @@ void fused_tile_kernel(const IterArgs<T> a)
     __shared__ int4 desc[PNM];
 
     const int tid0 = threadIdx.x;
-    if (MODE == MODE_CG && a.st->flag != FLAG_RUN) return;
-
-    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
     const TileDesc td = a.L.tiles[tile];
     if (tid0 < 27) ent[tid0] = a.L.tile_ent[tile * 27 + tid0];
     /* The thread index is re-made opaque to the compiler at every phase of
@@ -674,6 +680,30 @@ void fused_tile_kernel(const IterArgs<T> a)
     if (MODE == MODE_CG) block_reduce<T, 7, WG>(acc, red, a.dots + tile * 8);
 }
 
+template <int K, typename T, int MODE>
+__global__ __launch_bounds__(Cfg<K>::WG)
+__attribute__((amdgpu_waves_per_eu(MFCG_WPE_MIN(Cfg<K>::WG), 8)))
+void fused_tile_kernel(const IterArgs<T> a)
+{
+    if (MODE == MODE_CG && a.st->flag != FLAG_RUN) return;
+    fused_tile<K, T, MODE>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+/* Batch of problems of degree K: one workgroup per (problem, tile) item of
+ * the work list; problems that have left the running state are skipped. */
+template <int K, typename T>
+__global__ __launch_bounds__(Cfg<K>::WG)
+__attribute__((amdgpu_waves_per_eu(MFCG_WPE_MIN(Cfg<K>::WG), 8)))
+void fused_batch_kernel(const IterArgs<T> *__restrict__ probs, const int2 *__restrict__ items, int nitems)
+{
+    const int2 it = items[xcd_remap(blockIdx.x, nitems)];
+    const int p = __builtin_amdgcn_readfirstlane(it.x);
+    const int64_t tile = __builtin_amdgcn_readfirstlane(it.y);
+    const IterArgs<T> &a = *const_view(probs + p);
+    if (a.st->flag != FLAG_RUN) return;
+    fused_tile<K, T, MODE_CG>(a, tile);
+}
+
 /* ------------------------------------------------------------------ */
 /* Shared-node kernel with the single-pass finish                      */
 /* ------------------------------------------------------------------ */
@@ -682,11 +712,10 @@ void fused_tile_kernel(const IterArgs<T> a)
  * issued together */
 constexpr int SH_UNROLL = 4;
 
+/* Block blk of nblk of one problem's shared-node pass. */
 template <typename T, int MODE>
-__global__ __launch_bounds__(SHARED_WG) void shared_node_kernel(const IterArgs<T> a)
+__device__ __forceinline__ void shared_nodes(const IterArgs<T> &a, const int blk, const int nblk, T *red)
 {
-    __shared__ T red[8 * (SHARED_WG / 64)];
-    if (MODE == MODE_CG && a.st->flag != FLAG_RUN) return;
     const LayoutView &L = a.L;
 
     T alpha = 0, beta = 0, ratio = 0;
@@ -702,8 +731,8 @@ __global__ __launch_bounds__(SHARED_WG) void shared_node_kernel(const IterArgs<T
 #pragma unroll
     for (int c = 0; c < 7; ++c) acc[c] = 0;
 
-    const int64_t stride = (int64_t)gridDim.x * SHARED_WG;
-    for (int64_t i0 = L.offF + (int64_t)blockIdx.x * SHARED_WG + threadIdx.x; i0 < L.n; i0 += SH_UNROLL * stride) {
+    const int64_t stride = (int64_t)nblk * SHARED_WG;
+    for (int64_t i0 = L.offF + (int64_t)blk * SHARED_WG + threadIdx.x; i0 < L.n; i0 += SH_UNROLL * stride) {
         T vs[SH_UNROLL], r0[SH_UNROLL], v0[SH_UNROLL], p0[SH_UNROLL], dv[SH_UNROLL], x0[SH_UNROLL];
         bool ok[SH_UNROLL], cons[SH_UNROLL];
 #pragma unroll
@@ -764,7 +793,28 @@ __global__ __launch_bounds__(SHARED_WG) void shared_node_kernel(const IterArgs<T
     }
     if (MODE == MODE_VMULT) return;
 
-    block_reduce<T, 7, SHARED_WG>(acc, red, a.dots + (L.ntiles + blockIdx.x) * 8);
+    block_reduce<T, 7, SHARED_WG>(acc, red, a.dots + (L.ntiles + blk) * 8);
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(SHARED_WG) void shared_node_kernel(const IterArgs<T> a)
+{
+    __shared__ T red[8 * (SHARED_WG / 64)];
+    if (MODE == MODE_CG && a.st->flag != FLAG_RUN) return;
+    shared_nodes<T, MODE>(a, blockIdx.x, gridDim.x, red);
+}
+
+/* Batch: one workgroup per (problem, block) item. */
+template <typename T>
+__global__ __launch_bounds__(SHARED_WG) void shared_batch_kernel(const IterArgs<T> *__restrict__ probs,
+                                                                 const int2 *__restrict__ items)
+{
+    __shared__ T red[8 * (SHARED_WG / 64)];
+    const int2 it = items[blockIdx.x];
+    const int p = __builtin_amdgcn_readfirstlane(it.x);
+    const IterArgs<T> &a = *const_view(probs + p);
+    if (a.st->flag != FLAG_RUN) return;
+    shared_nodes<T, MODE_CG>(a, __builtin_amdgcn_readfirstlane(it.y), a.nshared_blocks, red);
 }
 
 /* One block: the seven inner products of the iteration from all per-block
@@ -776,6 +826,17 @@ template <typename T>
 __global__ __launch_bounds__(SHARED_WG) void finish_kernel(const IterArgs<T> a)
 {
     __shared__ T red[8 * (SHARED_WG / 64)];
+    if (a.st->flag != FLAG_RUN) return;
+    finish_iteration<T>(a, a.L.ntiles + a.nshared_blocks, red);
+}
+
+/* Batch: one block per listed problem. */
+template <typename T>
+__global__ __launch_bounds__(SHARED_WG) void finish_batch_kernel(const IterArgs<T> *__restrict__ probs,
+                                                                 const int *__restrict__ plist)
+{
+    __shared__ T red[8 * (SHARED_WG / 64)];
+    const IterArgs<T> &a = *const_view(probs + __builtin_amdgcn_readfirstlane(plist[blockIdx.x]));
     if (a.st->flag != FLAG_RUN) return;
     finish_iteration<T>(a, a.L.ntiles + a.nshared_blocks, red);
 }
@@ -821,6 +882,32 @@ hipError_t launch_shared(int mode, const IterArgs<T> &a, hipStream_t s)
     } else {
         hipLaunchKernelGGL((shared_node_kernel<T, MODE_VMULT>), grid, block, 0, s, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_iteration(const BatchLaunch &b, hipStream_t s)
+{
+    for (int K = 1; K <= 8; ++K) {
+        const int ni = b.nitems[K];
+        if (ni == 0) continue;
+        const dim3 grid((unsigned)ni);
+        switch (K) {
+        case 1: hipLaunchKernelGGL((fused_batch_kernel<1, double>), grid, dim3(Cfg<1>::WG), 0, s, b.probs, b.items[K], ni); break;
+        case 2: hipLaunchKernelGGL((fused_batch_kernel<2, double>), grid, dim3(Cfg<2>::WG), 0, s, b.probs, b.items[K], ni); break;
+        case 3: hipLaunchKernelGGL((fused_batch_kernel<3, double>), grid, dim3(Cfg<3>::WG), 0, s, b.probs, b.items[K], ni); break;
+        case 4: hipLaunchKernelGGL((fused_batch_kernel<4, double>), grid, dim3(Cfg<4>::WG), 0, s, b.probs, b.items[K], ni); break;
+        case 5: hipLaunchKernelGGL((fused_batch_kernel<5, double>), grid, dim3(Cfg<5>::WG), 0, s, b.probs, b.items[K], ni); break;
+        case 6: hipLaunchKernelGGL((fused_batch_kernel<6, double>), grid, dim3(Cfg<6>::WG), 0, s, b.probs, b.items[K], ni); break;
+        case 7: hipLaunchKernelGGL((fused_batch_kernel<7, double>), grid, dim3(Cfg<7>::WG), 0, s, b.probs, b.items[K], ni); break;
+        case 8: hipLaunchKernelGGL((fused_batch_kernel<8, double>), grid, dim3(Cfg<8>::WG), 0, s, b.probs, b.items[K], ni); break;
+        }
+    }
+    if (b.nshared_items > 0)
+        hipLaunchKernelGGL((shared_batch_kernel<double>), dim3((unsigned)b.nshared_items), dim3(SHARED_WG), 0, s,
+                           b.probs, b.shared_items);
+    if (b.nactive > 0)
+        hipLaunchKernelGGL((finish_batch_kernel<double>), dim3((unsigned)b.nactive), dim3(SHARED_WG), 0, s, b.probs,
+                           b.active);
     return hipGetLastError();
 }
 

@@ -24,6 +24,8 @@ EXPORTED = [
     "mfcg_cg_begin", "mfcg_cg_iterate", "mfcg_cg_end", "mfcg_set_timing", "mfcg_get_timing",
     "mfcg_layout_info", "mfcg_layout_permutation", "mfcg_destroy", "mfcg_error_string", "mfcg_last_error",
     "mfcg_stream_bench", "mfcg_solve_ir", "mfcg_set_solver", "mfcg_set_coefficient", "mfcg_warmstart",
+    "mfcg_autotune_tile", "mfcg_batch_setup", "mfcg_batch_info", "mfcg_batch_solve", "mfcg_batch_destroy",
+    "mfcg_batch_last_error",
 ]
 
 
@@ -74,6 +76,13 @@ def lib():
         L.mfcg_set_solver.argtypes = [P, I32]
         L.mfcg_set_coefficient.argtypes = [P, P, P]
         L.mfcg_warmstart.argtypes = [P, P, P, D, P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I32), P]
+        L.mfcg_autotune_tile.argtypes = [ctypes.POINTER(Mesh), I32, I32, P, ctypes.POINTER(D), P]
+        L.mfcg_batch_setup.argtypes = [I32, P, P, P, I32, P, ctypes.POINTER(P)]
+        L.mfcg_batch_info.argtypes = [P, I32, ctypes.POINTER(P), P]
+        L.mfcg_batch_solve.argtypes = [P, P, P, D, I32, P, P, P]
+        L.mfcg_batch_destroy.argtypes = [P]
+        L.mfcg_batch_last_error.argtypes = [P]
+        L.mfcg_batch_last_error.restype = ctypes.c_char_p
         L.mfcg_error_string.argtypes = [ctypes.c_int]
         L.mfcg_error_string.restype = ctypes.c_char_p
         L.mfcg_last_error.argtypes = [P]
@@ -291,3 +300,95 @@ class Problem:
                self.h)
         return {"tile": tuple(t), "n_interior": vals[0].value, "n_shared": vals[1].value,
                 "n_dirichlet": vals[2].value, "n_tiles": vals[3].value, "geometry_bytes": vals[4].value}
+
+
+def autotune_tile(cells, degree, map_kind=MAP_AFFINE, amplitude=0.0, iters=6, stream=None):
+    """(tile, ms_per_iter) of the fastest candidate tile for this mesh and degree."""
+    m = make_mesh(cells, map_kind, amplitude)
+    t = (ctypes.c_int32 * 3)()
+    ms = ctypes.c_double()
+    _check(lib().mfcg_autotune_tile(ctypes.byref(m), int(degree), int(iters), t, ctypes.byref(ms), _stream(stream)))
+    return tuple(t), ms.value
+
+
+class _View(Problem):
+    """A problem owned by a Batch (no setup, no destroy)."""
+
+    def __init__(self, h):
+        self.h = h
+        self.degree = None
+        n = ctypes.c_int64()
+        _check(lib().mfcg_n_dofs(self.h, ctypes.byref(n)), self.h)
+        self.n = n.value
+
+    def close(self):
+        self.h = ctypes.c_void_p()
+
+
+class Batch:
+    """Independent problems solved together (mfcg_batch_*).
+    problems: list of dicts with cells, degree and optional coeff, map_kind,
+    amplitude, bc."""
+
+    def __init__(self, problems, autotune=True, stream=None):
+        np_ = len(problems)
+        meshes = (Mesh * np_)()
+        degs = (ctypes.c_int32 * np_)()
+        self._coeffs = []
+        cptrs = (ctypes.c_void_p * np_)()
+        for i, p in enumerate(problems):
+            meshes[i] = make_mesh(p["cells"], p.get("map_kind", MAP_AFFINE), p.get("amplitude", 0.0),
+                                  p.get("bc", BC_DIRICHLET0))
+            degs[i] = int(p["degree"])
+            c = p.get("coeff")
+            if c is not None:
+                c = np.ascontiguousarray(c, dtype=np.float64).ravel()
+                self._coeffs.append(c)
+                cptrs[i] = c.ctypes.data
+            else:
+                cptrs[i] = None
+        self.h = ctypes.c_void_p()
+        code = lib().mfcg_batch_setup(np_, meshes, degs, cptrs, 1 if autotune else 0, _stream(stream),
+                                      ctypes.byref(self.h))
+        if code != OK:
+            raise MfcgError(code, lib().mfcg_batch_last_error(None).decode())
+        self.nprob = np_
+        self.problems = []
+        self.tiles = []
+        for i in range(np_):
+            hh = ctypes.c_void_p()
+            t = (ctypes.c_int32 * 3)()
+            self._chk(lib().mfcg_batch_info(self.h, i, ctypes.byref(hh), t))
+            self.problems.append(_View(hh))
+            self.tiles.append(tuple(t))
+
+    def _chk(self, code):
+        if code != OK:
+            raise MfcgError(code, lib().mfcg_batch_last_error(self.h).decode())
+
+    def solve(self, bs, xs, tol=1e-10, maxit=10000, stream=None):
+        """Returns (code, iters[], status[]); xs are overwritten."""
+        for i, (b, x) in enumerate(zip(bs, xs)):
+            _dev_vec(b, self.problems[i].n, f"b[{i}]")
+            _dev_vec(x, self.problems[i].n, f"x[{i}]")
+        bp = (ctypes.c_void_p * self.nprob)(*[b.data_ptr() for b in bs])
+        xp = (ctypes.c_void_p * self.nprob)(*[x.data_ptr() for x in xs])
+        its = (ctypes.c_int32 * self.nprob)()
+        st = (ctypes.c_int32 * self.nprob)()
+        code = lib().mfcg_batch_solve(self.h, bp, xp, float(tol), int(maxit), its, st, _stream(stream))
+        if code not in (OK, ENOTCONV, EBREAKDOWN):
+            self._chk(code)
+        return code, list(its), list(st)
+
+    def close(self):
+        if self.h:
+            for p in self.problems:
+                p.close()
+            lib().mfcg_batch_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
