@@ -171,8 +171,18 @@ int mfcg_solve(mfcg_handle h, const double *b, double *x, double tol, int32_t ma
  * in FP32 (operator with an FP32 copy of G_q and D^{-1}, vector updates and
  * inner products in FP32).  Outer loop in FP64 on the GPU:
  *     r = b - A x (FP64 operator); stop when ||r||_2 < tol ||b||_2;
- *     solve A d = r in FP32 to ||r - A d|| < inner_tol ||r|| (or max_inner
- *     iterations); x += d (FP64).
+ *     solve A d = r in FP32 until its recursive residual is below
+ *     max(inner_tol, tol ||b|| / (2 ||r||)) ||r|| (checked every 16
+ *     iterations; the second bound stops the last inner solve at what the
+ *     outer target needs) or max_inner iterations; x += d (FP64).
+ *   keep_direction  0: every inner solve is a fresh CG (classical
+ *                   refinement).  1: after the first, each inner solve
+ *                   continues the previous search direction with the
+ *                   replaced FP64 residual, p = D^{-1} r + beta p_prev (CG
+ *                   with residual replacement, "reliable updates"): the
+ *                   Krylov information survives the corrections.  A
+ *                   correction that reduced the residual less than 10x
+ *                   restarts the direction.
  *   x          device, x_0 on entry, solution on return
  *   outer_its  host out: corrections applied; inner_its: FP32 iterations summed
  *   res_hist   host or NULL, max_outer+1 doubles: ||b - A x_j|| / ||b||
@@ -183,8 +193,8 @@ int mfcg_solve(mfcg_handle h, const double *b, double *x, double tol, int32_t ma
  * EBREAKDOWN, EHIP.  The first call builds the FP32 copy (half the geometry
  * bytes) unless mfcg_options.fp32 asked for it at set-up. */
 int mfcg_solve_ir(mfcg_handle h, const double *b, double *x, double tol, double inner_tol, int32_t max_outer,
-                  int32_t max_inner, int32_t *outer_its, int32_t *inner_its, double *res_hist,
-                  double *true_rel_res, void *hip_stream);
+                  int32_t max_inner, int32_t keep_direction, int32_t *outer_its, int32_t *inner_its,
+                  double *res_hist, double *true_rel_res, void *hip_stream);
 
 /* Stepping interface used for throughput measurement: mfcg_cg_begin
  * initialises the solver state from (b, x0) exactly as mfcg_solve does;

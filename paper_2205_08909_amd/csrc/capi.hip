@@ -780,10 +780,16 @@ static int ensure_fp32(mfcg_ctx *h, hipStream_t s)
     return MFCG_OK;
 }
 
-/* FP32 fused CG on A d = r32 from d = 0 (Algorithm 5 in single precision:
- * operator, vector updates and inner products); stops at
- * ||r_j|| < inner_tol * rnorm or after max_inner iterations. */
-static int fp32_cg(mfcg_ctx *h, double rnorm, double inner_tol, int max_inner, int *its, hipStream_t s)
+/* One FP32 segment of the fused CG (Algorithm 5 in single precision:
+ * operator, vector updates and inner products) on A d = r32 from d = 0.
+ * keep_direction = 0: a fresh CG (p_0 = 0).  keep_direction = 1: the
+ * search direction of the previous segment is kept, p_1 = D^{-1} r + beta_in
+ * p_prev (the residual was replaced by the FP64 one, the Krylov direction
+ * continues).  The segment ends after the first poll at which the
+ * recursive residual norm is below inner_tol * rnorm, or after max_inner
+ * iterations; d is reconstructed into x32 and the last beta is returned. */
+static int fp32_cg(mfcg_ctx *h, double rnorm, double inner_tol, int max_inner, int keep_direction, double beta_in,
+                   int *its, double *beta_out, hipStream_t s)
 {
     const int64_t n = h->hl.n;
     if (max_inner + 1 > h->hist32_cap) {
@@ -793,13 +799,16 @@ static int fp32_cg(mfcg_ctx *h, double rnorm, double inner_tol, int max_inner, i
         h->hist32_cap = max_inner + 1;
     }
     HIPCHK(h, hipMemsetAsync(h->x32, 0, sizeof(float) * n, s));
-    HIPCHK(h, hipMemsetAsync(h->p32, 0, sizeof(float) * n, s));
-    HIPCHK(h, hipMemsetAsync(h->v32, 0, sizeof(float) * n, s));
+    if (!keep_direction) {
+        HIPCHK(h, hipMemsetAsync(h->p32, 0, sizeof(float) * n, s));
+        HIPCHK(h, hipMemsetAsync(h->v32, 0, sizeof(float) * n, s));
+    }
     CGState st{};
-    st.eps = inner_tol * rnorm;
+    st.eps = 0.0; /* the host ends the segment; beta is computed in every iteration */
     st.bnorm = rnorm;
     st.r0norm = rnorm;
     st.maxit = max_inner;
+    st.beta = keep_direction ? beta_in : 0.0; /* alpha = 0: r stays the replaced residual */
     st.flag = rnorm > 0.0 ? FLAG_RUN : FLAG_CONV;
     HIPCHK(h, hipMemcpyAsync(h->st32, &st, sizeof(CGState), hipMemcpyHostToDevice, s));
     IterArgs<float> a{};
@@ -816,7 +825,8 @@ static int fp32_cg(mfcg_ctx *h, double rnorm, double inner_tol, int max_inner, i
     a.hist = h->hist32;
     a.nshared_blocks = h->nshared_blocks;
     int launched = 0;
-    while (st.flag == FLAG_RUN && launched < max_inner) {
+    double rho = rnorm;
+    while (st.flag == FLAG_RUN && launched < max_inner && !(rho < inner_tol * rnorm)) {
         const int chunk = std::min(h->check_every, max_inner - launched);
         for (int it = 0; it < chunk; ++it) {
             HIPCHK(h, launch_fused<float>(h->K, MODE_CG, a, s));
@@ -825,16 +835,21 @@ static int fp32_cg(mfcg_ctx *h, double rnorm, double inner_tol, int max_inner, i
         launched += chunk;
         HIPCHK(h, hipMemcpyAsync(&st, h->st32, sizeof(CGState), hipMemcpyDeviceToHost, s));
         HIPCHK(h, hipStreamSynchronize(s));
+        if (st.k > 0) {
+            HIPCHK(h, hipMemcpyAsync(&rho, h->hist32 + st.k, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(h, hipStreamSynchronize(s));
+        }
     }
     HIPCHK(h, launch_reconstruct<float>(n, h->x32, h->p32, h->r32, h->dinv32, h->st32, s));
     *its = st.k;
+    if (beta_out) *beta_out = st.beta;
     if (st.flag == FLAG_BREAK) return fail(h, MFCG_EBREAKDOWN, "breakdown in the FP32 inner solve");
     return MFCG_OK;
 }
 
 int mfcg_solve_ir(mfcg_handle h, const double *b, double *x, double tol, double inner_tol, int32_t max_outer,
-                  int32_t max_inner, int32_t *outer_its, int32_t *inner_its, double *res_hist, double *true_rel_res,
-                  void *hip_stream)
+                  int32_t max_inner, int32_t keep_direction, int32_t *outer_its, int32_t *inner_its,
+                  double *res_hist, double *true_rel_res, void *hip_stream)
 {
     if (!h || !b || !x || !outer_its || !inner_its) return fail(h, MFCG_EINVAL, "null argument");
     if (!(tol > 0.0) || !std::isfinite(tol) || !(inner_tol > 0.0) || !(inner_tol < 1.0))
@@ -861,7 +876,7 @@ int mfcg_solve_ir(mfcg_handle h, const double *b, double *x, double tol, double 
         return MFCG_OK;
     }
     int status = MFCG_ENOTCONV;
-    double prev = 0.0;
+    double prev = 0.0, beta = 0.0;
     int slow = 0;
     for (int outer = 0;; ++outer) {
         /* FP64 residual of the current iterate */
@@ -898,7 +913,9 @@ int mfcg_solve_ir(mfcg_handle h, const double *b, double *x, double tol, double 
         /* inner FP32 solve of A d = r, then x += d in FP64 */
         HIPCHK(h, launch_convert(n, r64, h->r32, s));
         int its = 0;
-        rc = fp32_cg(h, rn, inner_tol, max_inner, &its, s);
+        /* never reduce further than the outer target needs */
+        const double itol = std::min(0.5, std::max(inner_tol, 0.5 * tol * bnorm / rn));
+        rc = fp32_cg(h, rn, itol, max_inner, keep_direction && outer > 0 && slow == 0, beta, &its, &beta, s);
         if (rc) return rc;
         *inner_its += its;
         HIPCHK(h, launch_add_correction(n, x64, h->x32, s));

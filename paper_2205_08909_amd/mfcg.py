@@ -72,7 +72,7 @@ def lib():
         L.mfcg_layout_permutation.argtypes = [ctypes.POINTER(Mesh), I32, P, P, P, P, P]
         L.mfcg_destroy.argtypes = [P]
         L.mfcg_stream_bench.argtypes = [I32, I64, P, P, I32, P]
-        L.mfcg_solve_ir.argtypes = [P, P, P, D, D, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), P, P, P]
+        L.mfcg_solve_ir.argtypes = [P, P, P, D, D, I32, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), P, P, P]
         L.mfcg_set_solver.argtypes = [P, I32]
         L.mfcg_set_coefficient.argtypes = [P, P, P]
         L.mfcg_warmstart.argtypes = [P, P, P, D, P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I32), P]
@@ -227,8 +227,8 @@ class Problem:
         h = hist[: its.value + 1].copy() if want_hist else None
         return code, its.value, h, tr.value
 
-    def solve_ir(self, b, x, tol=1e-10, inner_tol=1e-4, max_outer=20, max_inner=10000, stream=None,
-                 raise_on=True):
+    def solve_ir(self, b, x, tol=1e-10, inner_tol=1e-4, max_outer=20, max_inner=10000, keep_direction=False,
+                 stream=None, raise_on=True):
         """FP64 iterative refinement around the FP32 fused solver.
         Returns (code, outer_its, inner_its, rel_res_hist, true_rel_res)."""
         _dev_vec(b, self.n, "b")
@@ -237,7 +237,7 @@ class Problem:
         hist = np.zeros(max_outer + 1)
         tr = ctypes.c_double(float("nan"))
         code = lib().mfcg_solve_ir(self.h, _ptr(b), _ptr(x), float(tol), float(inner_tol), int(max_outer),
-                                   int(max_inner), ctypes.byref(oi), ctypes.byref(ii),
+                                   int(max_inner), 1 if keep_direction else 0, ctypes.byref(oi), ctypes.byref(ii),
                                    hist.ctypes.data_as(ctypes.c_void_p), ctypes.byref(tr), _stream(stream))
         if raise_on and code != OK:
             _check(code, self.h)

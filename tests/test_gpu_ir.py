@@ -1,9 +1,14 @@
-"""Mixed precision: FP64 iterative refinement around the FP32 fused solver.
+"""Mixed precision: FP64 iterative refinement around the FP32 fused solver,
+with fresh inner solves and with the search direction kept across
+corrections (residual replacement).
 
 Pinned: the final residual in FP64 (the library's and the oracle's own
 matrix) is below 1e-10 ||b||, and every correction reduces the outer residual
-by at least 100x (an FP32 inner solve to 1e-4 can only do that if the FP32
-operator equals A to single precision).  The forward error against the FP64
+by at least 100x except the last one, which only goes as far as the target
+needs (an FP32 inner solve to 1e-4 can only do that if the FP32 operator
+equals A to single precision).  The total FP32 iteration count
+stays below 1.6x the FP64 oracle's count plus the polling granularity (16
+iterations per correction).  The forward error against the FP64
 oracle solution is reported and only bounded (parity unpinned for its value:
 refinement follows a different iterate sequence than Algorithm 1).
 """
@@ -22,8 +27,9 @@ def torch_cuda():
     return torch
 
 
+@pytest.mark.parametrize("keep", [False, True])  # fresh inner solves to 1e-4 / residual replacement every 10x
 @pytest.mark.parametrize("cells,k,seed", [((16, 16, 16), 4, 0), ((7, 6, 8), 3, 1), ((4, 4, 4), 6, 2)])
-def test_ir_converges_to_fp64_tolerance(cells, k, seed, oracle_mod, torch_cuda):
+def test_ir_converges_to_fp64_tolerance(cells, k, seed, keep, oracle_mod, torch_cuda):
     torch = torch_cuda
     from paper_2205_08909_amd import mfcg
     coeff = inputs.grf_coefficient(cells, 0.1, 1.0, seed=seed)
@@ -31,18 +37,23 @@ def test_ir_converges_to_fp64_tolerance(cells, k, seed, oracle_mod, torch_cuda):
     A = oracle_mod.assemble(m)
     b = oracle_mod.rhs(m)
     xo, its_o, _, rc = oracle_mod.pcg(A, A.diagonal(), b, tol=1e-12, maxit=20000)
+    _, its10, _, _ = oracle_mod.pcg(A, A.diagonal(), b, tol=1e-10, maxit=20000)
     P = mfcg.Problem(cells, k, coeff=coeff, map_kind=1, amplitude=0.05)
     bt = torch.from_numpy(b).cuda()
     xt = torch.zeros_like(bt)
-    code, outer, inner, hist, tr = P.solve_ir(bt, xt, tol=1e-10, inner_tol=1e-4)
+    itol = 1e-1 if keep else 1e-4
+    code, outer, inner, hist, tr = P.solve_ir(bt, xt, tol=1e-10, inner_tol=itol, keep_direction=keep)
     assert code == 0 and tr < 1e-10 and hist[-1] < 1e-10
-    assert np.all(hist[1:] <= 1e-2 * hist[:-1]), hist
+    # every correction but the last (which stops at what the target needs) reduces the residual
+    assert np.all(hist[1:-1] <= (1e-1 if keep else 1e-2) * hist[:-2]), hist
     x = xt.cpu().numpy()
     nb = np.linalg.norm(b)
     assert np.linalg.norm(b - A.matvec(x)) <= 2e-10 * nb
     ferr = np.linalg.norm(x - xo) / np.linalg.norm(xo)
-    print(f"IR: outer {outer}, inner {inner}, true rel res {tr:.2e}, forward error vs oracle {ferr:.2e}")
+    print(f"IR (keep direction {keep}): outer {outer}, inner {inner} (FP64 oracle {its10}), true rel res {tr:.2e}, "
+          f"forward error vs oracle {ferr:.2e}")
     assert ferr < 1e-6
+    assert inner <= 1.6 * its10 + 16 * outer
     P.close()
 
 
