@@ -50,16 +50,21 @@ namespace mfcg {
 /* Per-degree configuration (compile time)                             */
 /* ------------------------------------------------------------------ */
 
+/* TX, TY: compiled maximum tile extent in x and y (cells); WG: workgroup
+ * size; GPREF: where a layer's geometry tensor is loaded (0: in the pass
+ * that applies it, 1: before the x and z derivative passes, held in
+ * registers across them); OCC: workgroups per CU the register allocator
+ * aims for.  Chosen per degree by timing on MI355X. */
 template <int K>
 struct Cfg;
-template <> struct Cfg<1> { static constexpr int TX = 8, TY = 8, WG = 256; };
-template <> struct Cfg<2> { static constexpr int TX = 8, TY = 8, WG = 576; };
-template <> struct Cfg<3> { static constexpr int TX = 5, TY = 5, WG = 448; };
-template <> struct Cfg<4> { static constexpr int TX = 4, TY = 4, WG = 448; };
-template <> struct Cfg<5> { static constexpr int TX = 3, TY = 3, WG = 384; };
-template <> struct Cfg<6> { static constexpr int TX = 2, TY = 2, WG = 256; };
-template <> struct Cfg<7> { static constexpr int TX = 2, TY = 2, WG = 256; };
-template <> struct Cfg<8> { static constexpr int TX = 2, TY = 2, WG = 384; };
+template <> struct Cfg<1> { static constexpr int TX = 8, TY = 8, WG = 256, GPREF = 0, OCC = 2; };
+template <> struct Cfg<2> { static constexpr int TX = 8, TY = 8, WG = 576, GPREF = 0, OCC = 2; };
+template <> struct Cfg<3> { static constexpr int TX = 5, TY = 5, WG = 448, GPREF = 0, OCC = 2; };
+template <> struct Cfg<4> { static constexpr int TX = 4, TY = 4, WG = 448, GPREF = 0, OCC = 2; };
+template <> struct Cfg<5> { static constexpr int TX = 3, TY = 3, WG = 384, GPREF = 0, OCC = 2; };
+template <> struct Cfg<6> { static constexpr int TX = 2, TY = 2, WG = 256, GPREF = 0, OCC = 2; };
+template <> struct Cfg<7> { static constexpr int TX = 2, TY = 2, WG = 256, GPREF = 1, OCC = 2; };
+template <> struct Cfg<8> { static constexpr int TX = 2, TY = 2, WG = 384, GPREF = 0, OCC = 1; };
 
 void tile_limits(int K, int *tx, int *ty)
 {
@@ -74,18 +79,23 @@ int fused_block_size(int K)
 }
 
 /* minimum waves per SIMD requested from the register allocator */
-#ifndef MFCG_OCC
-#define MFCG_OCC 2
+/* build-time overrides of the per-degree choices (timing experiments) */
+#ifdef MFCG_OCC
+#define MFCG_OCC_OF(K) (MFCG_OCC)
+#else
+#define MFCG_OCC_OF(K) (Cfg<K>::OCC)
 #endif
 /* geometry loads issued before the derivative passes (1) or in the G pass (0) */
-#ifndef MFCG_GPREF
-#define MFCG_GPREF 1
+#ifdef MFCG_GPREF
+#define MFCG_GPREF_OF(K) (MFCG_GPREF)
+#else
+#define MFCG_GPREF_OF(K) (Cfg<K>::GPREF)
 #endif
 /* pre loads of the next layer issued before the current layer's cell passes */
 #ifndef MFCG_PREPF
 #define MFCG_PREPF 0
 #endif
-#define MFCG_WPE_MIN(WG) ((MFCG_OCC * (WG) / 64 + 3) / 4)
+#define MFCG_WPE_MIN(K) ((MFCG_OCC_OF(K) * Cfg<K>::WG / 64 + 3) / 4)
 
 /* ------------------------------------------------------------------ */
 /* Helpers                                                             */
@@ -322,7 +332,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         asm volatile("" : "+v"(tid)); /* see above */
         const T *Gl = a.G + td.gbase + (int64_t)L * 6 * gcomp;
         T gp[R][6][n];
-        if (MFCG_GPREF == 2) {
+        if (MFCG_GPREF_OF(K) == 2) {
             /* G of this layer issued first: its latency overlaps the pre loads */
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) {
@@ -445,7 +455,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         asm volatile("" : "+v"(tid));
         /* G of this layer: loads issued here, consumed after the x and z
          * derivative passes */
-        if (MFCG_GPREF == 1) {
+        if (MFCG_GPREF_OF(K) == 1) {
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) {
                 const int l = tid + WG * rr;
@@ -508,7 +518,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
                 T fy[n];
 #pragma unroll
                 for (int j = 0; j < n; ++j) {
-                    if (!MFCG_GPREF) {
+                    if (!MFCG_GPREF_OF(K)) {
 #pragma unroll
                         for (int c2 = 0; c2 < 6; ++c2) gp[rr][c2][j] = Gl[c2 * gcomp + j * gq + l];
                     }
@@ -682,7 +692,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
 
 template <int K, typename T, int MODE>
 __global__ __launch_bounds__(Cfg<K>::WG)
-__attribute__((amdgpu_waves_per_eu(MFCG_WPE_MIN(Cfg<K>::WG), 8)))
+__attribute__((amdgpu_waves_per_eu(MFCG_WPE_MIN(K), 8)))
 void fused_tile_kernel(const IterArgs<T> a)
 {
     if (MODE == MODE_CG && a.st->flag != FLAG_RUN) return;
@@ -693,7 +703,7 @@ void fused_tile_kernel(const IterArgs<T> a)
  * the work list; problems that have left the running state are skipped. */
 template <int K, typename T>
 __global__ __launch_bounds__(Cfg<K>::WG)
-__attribute__((amdgpu_waves_per_eu(MFCG_WPE_MIN(Cfg<K>::WG), 8)))
+__attribute__((amdgpu_waves_per_eu(MFCG_WPE_MIN(K), 8)))
 void fused_batch_kernel(const IterArgs<T> *__restrict__ probs, const int2 *__restrict__ items, int nitems)
 {
     const int2 it = items[xcd_remap(blockIdx.x, nitems)];
