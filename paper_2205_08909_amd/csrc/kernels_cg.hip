@@ -61,7 +61,7 @@ template <> struct Cfg<1> { static constexpr int TX = 8, TY = 8, WG = 256, GPREF
 template <> struct Cfg<2> { static constexpr int TX = 8, TY = 8, WG = 576, GPREF = 0, OCC = 2; };
 template <> struct Cfg<3> { static constexpr int TX = 5, TY = 5, WG = 448, GPREF = 0, OCC = 2; };
 template <> struct Cfg<4> { static constexpr int TX = 4, TY = 4, WG = 448, GPREF = 0, OCC = 2; };
-template <> struct Cfg<5> { static constexpr int TX = 3, TY = 3, WG = 384, GPREF = 0, OCC = 2; };
+template <> struct Cfg<5> { static constexpr int TX = 3, TY = 3, WG = 384, GPREF = 0, OCC = 3; };
 template <> struct Cfg<6> { static constexpr int TX = 2, TY = 2, WG = 256, GPREF = 0, OCC = 2; };
 template <> struct Cfg<7> { static constexpr int TX = 2, TY = 2, WG = 256, GPREF = 1, OCC = 2; };
 template <> struct Cfg<8> { static constexpr int TX = 2, TY = 2, WG = 384, GPREF = 0, OCC = 1; };
@@ -96,6 +96,9 @@ int fused_block_size(int K)
 #define MFCG_PREPF 0
 #endif
 #define MFCG_WPE_MIN(K) ((MFCG_OCC_OF(K) * Cfg<K>::WG / 64 + 3) / 4)
+/* the batch kernel holds more uniform values (its arguments come from
+ * memory): it asks for at most two workgroups per CU to avoid spills */
+#define MFCG_WPE_MIN_BATCH(K) (((MFCG_OCC_OF(K) < 2 ? MFCG_OCC_OF(K) : 2) * Cfg<K>::WG / 64 + 3) / 4)
 
 /* ------------------------------------------------------------------ */
 /* Helpers                                                             */
@@ -703,7 +706,7 @@ void fused_tile_kernel(const IterArgs<T> a)
  * the work list; problems that have left the running state are skipped. */
 template <int K, typename T>
 __global__ __launch_bounds__(Cfg<K>::WG)
-__attribute__((amdgpu_waves_per_eu(MFCG_WPE_MIN(K), 8)))
+__attribute__((amdgpu_waves_per_eu(MFCG_WPE_MIN_BATCH(K), 8)))
 void fused_batch_kernel(const IterArgs<T> *__restrict__ probs, const int2 *__restrict__ items, int nitems)
 {
     const int2 it = items[xcd_remap(blockIdx.x, nitems)];
