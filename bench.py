@@ -96,14 +96,18 @@ def degree_sweep(args):
     """Throughput of the fused iteration for k = 1..8 at two sizes per degree
     (N = round(216/k) and round(456/k) cells per direction, about 1e7 and
     1e8 DoFs), curved mesh, a = 1, random-normal right-hand side (seed 7),
-    tol = 0.  Prints one JSON line."""
+    tol = 0, tiles from the autotuner (timed on the same mesh).  Prints one
+    JSON line."""
     import torch
     from paper_2205_08909_amd import mfcg, inputs
     rows = []
     degrees = [int(v) for v in args.sweep_degrees.split(",")]
     for k in degrees:
         for N in (round(216 / k), round(456 / k)):
-            P = mfcg.Problem(N, k, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05)
+            tile = None
+            if not args.sweep_default_tiles:
+                tile, _ = mfcg.autotune_tile(N, k, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05, iters=4)
+            P = mfcg.Problem(N, k, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05, tile=tile)
             info = P.layout_info()
             n = P.n
             b = torch.from_numpy(inputs.random_rhs(N, k, seed=7)).cuda()
@@ -257,6 +261,7 @@ def main():
     ap.add_argument("--no-ablation", action="store_true")
     ap.add_argument("--sweep", action="store_true", help="degree sweep k = 1..8 instead of the main line")
     ap.add_argument("--sweep-degrees", default="1,2,3,4,5,6,7,8")
+    ap.add_argument("--sweep-default-tiles", action="store_true", help="sweep without the tile autotuner")
     ap.add_argument("--warmstart", action="store_true", help="learned warm-start experiment instead of the main line")
     ap.add_argument("--ws-cells", type=int, default=48)
     ap.add_argument("--ws-train", type=int, default=2000)
@@ -306,10 +311,18 @@ def main():
     torch.cuda.synchronize()
     P.set_timing(True)
     torch.cuda.synchronize()
+    # the K steps run back to back; stream events split them into (up to) 5 blocks for min / median
+    nblk = min(5, K)
+    sizes = [K // nblk + (1 if i < K % nblk else 0) for i in range(nblk)]
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(nblk + 1)]
     t0 = time.perf_counter()
-    P.cg_iterate(K)
+    evs[0].record()
+    for i, m in enumerate(sizes):
+        P.cg_iterate(m)
+        evs[i + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    blk_ms = sorted(evs[i].elapsed_time(evs[i + 1]) / sizes[i] for i in range(nblk))
     tm = P.get_timing()
     P.set_timing(False)
     code, its, _ = P.cg_end(x)
@@ -419,6 +432,7 @@ def main():
         "steps": K,
         "warmup": W,
         "ms_per_step": round(ms_per_step, 5),
+        "ms_per_step_blocks": {"blocks": nblk, "min": round(blk_ms[0], 5), "median": round(blk_ms[nblk // 2], 5)},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

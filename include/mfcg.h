@@ -246,10 +246,12 @@ int mfcg_layout_permutation(const mfcg_mesh *mesh, int32_t degree, const int32_t
 int mfcg_stream_bench(int32_t kind, int64_t n, const double *src, double *dst, int32_t nblocks, void *hip_stream);
 
 /* Tile autotuner: times `iters` fused iterations (after 2 untimed ones)
- * of a Poisson problem on `mesh` for each candidate tile (the compiled
- * maximum extent in x and y and half of it, 8, 16 and 32 cell layers in z,
- * clipped to the mesh) and returns the fastest in tile_out[3] and its time
- * per iteration in *ms_out (may be NULL).  Builds and frees one handle per
+ * of a Poisson problem on `mesh` for each candidate tile and returns the
+ * fastest in tile_out[3] and its time per iteration in *ms_out (may be
+ * NULL).  Candidates: the compiled maximum extent in x and y with 8, 16 or
+ * 32 cell layers in z or the mesh's z extent split into 1..8 equal tile
+ * layers (4..64 cells deep), and half the x/y extent with 16 layers; all
+ * clipped to the mesh.  Builds and frees one handle per
  * candidate.  Errors: EINVAL, ENOMEM, EHIP. */
 int mfcg_autotune_tile(const mfcg_mesh *mesh, int32_t degree, int32_t iters, int32_t *tile_out, double *ms_out,
                        void *hip_stream);

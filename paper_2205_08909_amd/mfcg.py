@@ -54,6 +54,12 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2205_08909_amd.build` "
                                "(or __graft_entry__.build())")
+        # torch brings its own HIP runtime; it must own the device before this
+        # library's runtime (the system one) is loaded, or the latter can find
+        # no device when it is the first to initialise
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
         L = ctypes.CDLL(LIB_PATH)
         P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         L.mfcg_setup.argtypes = [ctypes.POINTER(Mesh), I32, P, ctypes.POINTER(Options), P, ctypes.POINTER(P)]
