@@ -54,17 +54,19 @@ namespace mfcg {
  * size; GPREF: where a layer's geometry tensor is loaded (0: in the pass
  * that applies it, 1: before the x and z derivative passes, held in
  * registers across them); OCC: workgroups per CU the register allocator
- * aims for.  Chosen per degree by timing on MI355X. */
+ * aims for; CARRY: r_k and D^{-1} of a node kept in registers from its pre
+ * to its post (1) or re-read there (0).  Chosen per degree by timing on
+ * MI355X. */
 template <int K>
 struct Cfg;
-template <> struct Cfg<1> { static constexpr int TX = 8, TY = 8, WG = 256, GPREF = 0, OCC = 2; };
-template <> struct Cfg<2> { static constexpr int TX = 8, TY = 8, WG = 576, GPREF = 0, OCC = 2; };
-template <> struct Cfg<3> { static constexpr int TX = 5, TY = 5, WG = 448, GPREF = 0, OCC = 2; };
-template <> struct Cfg<4> { static constexpr int TX = 4, TY = 4, WG = 448, GPREF = 0, OCC = 2; };
-template <> struct Cfg<5> { static constexpr int TX = 3, TY = 3, WG = 384, GPREF = 0, OCC = 3; };
-template <> struct Cfg<6> { static constexpr int TX = 2, TY = 2, WG = 256, GPREF = 0, OCC = 2; };
-template <> struct Cfg<7> { static constexpr int TX = 2, TY = 2, WG = 256, GPREF = 1, OCC = 2; };
-template <> struct Cfg<8> { static constexpr int TX = 2, TY = 2, WG = 384, GPREF = 0, OCC = 1; };
+template <> struct Cfg<1> { static constexpr int TX = 8, TY = 8, WG = 256, GPREF = 0, OCC = 2, CARRY = 0; };
+template <> struct Cfg<2> { static constexpr int TX = 8, TY = 8, WG = 576, GPREF = 0, OCC = 2, CARRY = 0; };
+template <> struct Cfg<3> { static constexpr int TX = 5, TY = 5, WG = 448, GPREF = 0, OCC = 2, CARRY = 1; };
+template <> struct Cfg<4> { static constexpr int TX = 4, TY = 4, WG = 448, GPREF = 0, OCC = 2, CARRY = 1; };
+template <> struct Cfg<5> { static constexpr int TX = 3, TY = 3, WG = 384, GPREF = 0, OCC = 3, CARRY = 1; };
+template <> struct Cfg<6> { static constexpr int TX = 2, TY = 2, WG = 256, GPREF = 0, OCC = 2, CARRY = 1; };
+template <> struct Cfg<7> { static constexpr int TX = 2, TY = 2, WG = 256, GPREF = 1, OCC = 2, CARRY = 1; };
+template <> struct Cfg<8> { static constexpr int TX = 2, TY = 2, WG = 384, GPREF = 0, OCC = 1, CARRY = 0; };
 
 void tile_limits(int K, int *tx, int *ty)
 {
@@ -90,10 +92,6 @@ int fused_block_size(int K)
 #define MFCG_GPREF_OF(K) (MFCG_GPREF)
 #else
 #define MFCG_GPREF_OF(K) (Cfg<K>::GPREF)
-#endif
-/* pre loads of the next layer issued before the current layer's cell passes */
-#ifndef MFCG_PREPF
-#define MFCG_PREPF 0
 #endif
 #define MFCG_WPE_MIN(K) ((MFCG_OCC_OF(K) * Cfg<K>::WG / 64 + 3) / 4)
 /* the batch kernel holds more uniform values (its arguments come from
@@ -233,8 +231,9 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
     };
 
     /* Algorithm 5's pre on one node; interior nodes are written back,
-     * shared nodes only recomputed; returns p_k (0 on Dirichlet nodes) */
-    auto pre_node = [&](int node, int zz) -> T {
+     * shared nodes only recomputed; returns p_k (0 on Dirichlet nodes) and
+     * r_k, D^{-1} in rk, dk (kept in registers for the post of the node) */
+    auto pre_node = [&](int node, int zz, T &rk, T &dk) -> T {
         int idx, kind, pidx;
         locate(desc[node], zz, idx, kind, pidx);
         if (kind == KIND_C) return (T)0;
@@ -242,6 +241,8 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         const T r0 = a.r[idx], v0 = a.v[idx], p0 = a.p[idx], dv = a.dinv[idx];
         T rn, pn;
         pre_update(r0, v0, p0, dv, alpha, beta, rn, pn);
+        rk = rn;
+        dk = dv;
         if (kind == KIND_I) {
             a.r[idx] = rn;
             a.p[idx] = pn;
@@ -249,40 +250,6 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         }
         return pn;
     };
-
-    /* the same pre split in two: loads (into registers) and update */
-    struct PreLd {
-        T r, v, p, d, x;
-        int idx, kind;
-    };
-    auto pre_load = [&](int node, int zz, PreLd &q) {
-        int pidx;
-        locate(desc[node], zz, q.idx, q.kind, pidx);
-        q.r = q.v = q.p = q.d = q.x = 0;
-        if (q.kind == KIND_C) return;
-        if (MODE == MODE_VMULT) {
-            q.p = a.src[q.idx];
-            return;
-        }
-        q.r = a.r[q.idx];
-        q.v = a.v[q.idx];
-        q.p = a.p[q.idx];
-        q.d = a.dinv[q.idx];
-        if (xupd && q.kind == KIND_I) q.x = a.x[q.idx];
-    };
-    auto pre_apply = [&](const PreLd &q) -> T {
-        if (q.kind == KIND_C) return (T)0;
-        if (MODE == MODE_VMULT) return q.p;
-        T rn, pn;
-        pre_update(q.r, q.v, q.p, q.d, alpha, beta, rn, pn);
-        if (q.kind == KIND_I) {
-            a.r[q.idx] = rn;
-            a.p[q.idx] = pn;
-            if (xupd) a.x[q.idx] = x_update(q.x, q.r, q.p, q.d, alpha, ratio);
-        }
-        return pn;
-    };
-    PreLd pq[NS];
 
     /* v of a layer node summed over the cells around it, fixed order */
     auto sum_cells = [&](const int4 &dsc, int zl) -> T {
@@ -296,9 +263,11 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         return ((v00 + v01) + v10) + v11;
     };
 
-    /* post on one node: r_k and D^{-1} are re-read (this workgroup wrote
-     * r_k in its pre, so the lines are cache resident), p_k from the window */
-    auto post_node = [&](const int4 &dsc, int node, int zz, int slot, T v) {
+    /* post on one node: r_k and D^{-1} from the registers of this thread's
+     * pre of the node (reg = true) or re-read (the tile's layer-top plane,
+     * whose pre ran in the layer below under another thread mapping), p_k
+     * from the window */
+    auto post_node = [&](const int4 &dsc, int node, int zz, int slot, T v, bool reg, T rk, T dk) {
         int idx, kind, pidx;
         locate(dsc, zz, idx, kind, pidx);
         if (kind == KIND_S) {
@@ -307,7 +276,8 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
             if (MODE == MODE_VMULT) {
                 a.dst[idx] = v;
             } else {
-                const T rn = a.r[idx], dv = a.dinv[idx];
+                const bool use = Cfg<K>::CARRY && reg;
+                const T rn = use ? rk : a.r[idx], dv = use ? dk : a.dinv[idx];
                 const T pn = win[slot * PNM + node];
                 const T zr = dv * rn, zv = dv * v;
                 acc[0] += rn * rn;
@@ -322,11 +292,20 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         }
     };
 
+    /* r_k and D^{-1} of the nodes this thread pre-processes, held until
+     * their post: the tile's bottom plane (kb*) and the planes 1..K of the
+     * current layer (kr, kd) */
+    T kbr[NC], kbd[NC], kr[NS], kd[NS];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) kbr[c] = kbd[c] = 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) kr[s] = kd[s] = 0;
+
     /* bottom plane of the tile into the window */
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         const int node = tid + WG * c;
-        if (node < PN) win[node] = pre_node(node, 0);
+        if (node < PN) win[node] = pre_node(node, 0, kbr[c], kbd[c]);
     }
 
 #pragma unroll 1
@@ -354,27 +333,11 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
                 const int zq = dPN.div(f), zl = 1 + zq, node = f - zq * PN;
                 int slot = s0 + zl;
                 if (slot > K) slot -= K + 1;
-                if (MFCG_PREPF) {
-                    if (L == 0) pre_load(node, zl, pq[s]);
-                    win[slot * PNM + node] = pre_apply(pq[s]);
-                } else {
-                    win[slot * PNM + node] = pre_node(node, L * K + zl);
-                }
+                win[slot * PNM + node] = pre_node(node, L * K + zl, kr[s], kd[s]);
             }
         }
         __syncthreads();
         asm volatile("" : "+v"(tid)); /* see above */
-        if (MFCG_PREPF && L + 1 < TZa) {
-            /* loads of the next layer's pre: in flight during the cell passes */
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                const int f = tid + WG * s;
-                if (f < K * PN) {
-                    const int zq = dPN.div(f), node = f - zq * PN;
-                    pre_load(node, (L + 1) * K + 1 + zq, pq[s]);
-                }
-            }
-        }
         asm volatile("" : "+v"(tid));
 
         T gy[R][n], wy[R][n], wz[R][n];
@@ -666,7 +629,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
                 const int4 dsc = desc[node];
                 T v = sum_cells(dsc, 0);
                 if (L > 0) v = cv[(L & 1) * PNM + node] + v;
-                post_node(dsc, node, L * K, s0, v);
+                post_node(dsc, node, L * K, s0, v, L == 0, kbr[c], kbd[c]);
             }
         }
         /* planes z = 1..K; the top plane is carried unless it is the tile's last */
@@ -682,7 +645,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
                 } else {
                     int slot = s0 + zl;
                     if (slot > K) slot -= K + 1;
-                    post_node(dsc, node, L * K + zl, slot, v);
+                    post_node(dsc, node, L * K + zl, slot, v, true, kr[s], kd[s]);
                 }
             }
         }
