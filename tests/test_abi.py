@@ -108,6 +108,35 @@ def test_null_handle_calls():
     assert L.mfcg_vmult(None, None, None, None) == mfcg.EINVAL
     assert L.mfcg_solve(None, None, None, 1e-10, 10, None, None, None, None) == mfcg.EINVAL
     assert L.mfcg_destroy(None) == mfcg.OK
+    # the later entry points validate on the host too
+    assert L.mfcg_set_solver(None, 0) == mfcg.EINVAL
+    assert L.mfcg_set_coefficient(None, None, None) == mfcg.EINVAL
+    d = ctypes.c_double()
+    i = ctypes.c_int32()
+    assert L.mfcg_warmstart(None, None, None, 1.0, None, ctypes.byref(d), ctypes.byref(d), ctypes.byref(i),
+                            None) == mfcg.EINVAL
+    oi, ii = ctypes.c_int32(), ctypes.c_int32()
+    assert L.mfcg_solve_ir(None, None, None, 1e-10, 1e-4, 10, 10, 0, ctypes.byref(oi), ctypes.byref(ii), None, None,
+                           None) == mfcg.EINVAL
+    assert L.mfcg_batch_destroy(None) == mfcg.OK
+    assert L.mfcg_batch_solve(None, None, None, 1e-10, 10, None, None, None) == mfcg.EINVAL
+    assert L.mfcg_batch_info(None, 0, None, None) == mfcg.EINVAL
+
+
+def test_batch_and_autotune_reject_bad_arguments_on_the_host():
+    L = mfcg.lib()
+    out = ctypes.c_void_p()
+    assert L.mfcg_batch_setup(0, None, None, None, 0, None, ctypes.byref(out)) == mfcg.EINVAL
+    meshes = (mfcg.Mesh * 2)(mfcg.make_mesh(4), mfcg.make_mesh(4))
+    degs = (ctypes.c_int32 * 2)(2, 9)
+    assert L.mfcg_batch_setup(2, meshes, degs, None, 0, None, ctypes.byref(out)) == mfcg.EINVAL
+    assert b"problem 1" in L.mfcg_batch_last_error(None)
+    assert not out.value
+    t = (ctypes.c_int32 * 3)()
+    ms = ctypes.c_double()
+    m = mfcg.make_mesh(4)
+    assert L.mfcg_autotune_tile(ctypes.byref(m), 0, 4, t, ctypes.byref(ms), None) == mfcg.EINVAL
+    assert L.mfcg_autotune_tile(ctypes.byref(m), 4, 0, t, ctypes.byref(ms), None) == mfcg.EINVAL
 
 
 def _closed_form_counts(cells, k, tile, bc):
