@@ -81,7 +81,7 @@ def cpu_baseline(seconds_budget=20.0):
     t = time.perf_counter()
     oracle.pcg(A, d, b, tol=0.0, maxit=5)
     per_it = (time.perf_counter() - t) / 5
-    its = int(max(10, min(400, seconds_budget / max(per_it, 1e-6))))
+    its = int(max(10, min(20000, seconds_budget / max(per_it, 1e-6))))
     t = time.perf_counter()
     _, done, _, _ = oracle.pcg(A, d, b, tol=0.0, maxit=its)
     dt = time.perf_counter() - t
