@@ -36,7 +36,6 @@ struct mfcg_ctx {
     HostLayout hl;
     LayoutView lv{};
     Tables<double> tab{};
-    Tables<float> tab32{};
     /* device buffers */
     int64_t *d_ent_base = nullptr;
     EntityRef *d_tile_ent = nullptr;
@@ -317,7 +316,6 @@ int mfcg_setup(const mfcg_mesh *mesh, int32_t degree, const double *cell_coeff, 
     int t[3] = {tile ? tile[0] : 0, tile ? tile[1] : 0, tile ? tile[2] : 0};
     build_layout(nc, degree, t, mesh->bc, h->hl);
     build_tables(degree, h->tab);
-    tables_to_float(h->tab, h->tab32);
     HostLayout &L = h->hl;
 
     SCHK(dalloc(&h->d_ent_base, L.ent_base.size()));

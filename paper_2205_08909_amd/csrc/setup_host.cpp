@@ -129,20 +129,6 @@ int build_tables(int K, Tables<double> &tab)
     return 0;
 }
 
-void tables_to_float(const Tables<double> &a, Tables<float> &b)
-{
-    for (int i = 0; i < MAXN * MAXN; ++i) {
-        b.S[i] = (float)a.S[i];
-        b.D[i] = (float)a.D[i];
-        b.Sd[i] = (float)a.Sd[i];
-    }
-    for (int i = 0; i < MAXN; ++i) {
-        b.xq[i] = (float)a.xq[i];
-        b.wq[i] = (float)a.wq[i];
-        b.gll[i] = (float)a.gll[i];
-    }
-}
-
 /* ---------------------------------------------------------------- */
 /* Tile partition and enumeration                                     */
 /* ---------------------------------------------------------------- */

@@ -25,7 +25,6 @@ struct HostLayout {
 };
 
 int build_tables(int K, Tables<double> &tab);
-void tables_to_float(const Tables<double> &a, Tables<float> &b);
 void default_tile(int K, int tile[3]);
 int build_layout(const int ncells[3], int K, const int tile[3], int bc, HostLayout &L);
 void dim_locate_host(const Dim1 &d, int64_t g, int64_t &e, int64_t &l, int64_t &len);
