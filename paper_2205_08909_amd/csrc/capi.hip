@@ -1236,7 +1236,6 @@ int mfcg_batch_solve(mfcg_batch hb, const double *const *b, double *const *x, do
     }
     int worst = MFCG_OK;
     for (int i = 0; i < np; ++i) {
-        hb->probs[i]->launched = launched; /* the state holds each problem's own count */
         const int r = mfcg_cg_end(hb->probs[i], x[i], &iters[i], nullptr, hip_stream);
         status[i] = r;
         if (r != MFCG_OK && r != MFCG_ENOTCONV && r != MFCG_EBREAKDOWN) return batch_fail(hb, r, hb->probs[i]->err);
