@@ -347,6 +347,38 @@ def main():
             ablation[name] = round((time.perf_counter() - t0) * 1e3 / K, 5)
             code_a, its_a, _ = P.cg_end(x)
             assert its_a == W + K, (name, code_a, its_a)
+        # the alternative CG methods of Sec. 4.1 (no preconditioner): pipelined CG,
+        # and s-step CG with s = 6 timed over whole phases
+        for solver, name, s in ((mfcg.SOLVER_PIPELINED, "pipelined_cg_ms", 1), (mfcg.SOLVER_SSTEP, "sstep6_cg_ms", 6)):
+            P.set_solver(solver)
+            if solver == mfcg.SOLVER_SSTEP:
+                P.set_sstep(s)
+            Ws, Ks = s * -(-W // s), s * -(-K // s)
+            P.cg_begin(b, None, tol=0.0, maxit=Ws + Ks)
+            P.cg_iterate(Ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P.cg_iterate(Ks)
+            torch.cuda.synchronize()
+            ablation[name] = round((time.perf_counter() - t0) * 1e3 / Ks, 5)
+            code_a, its_a, _ = P.cg_end(x)
+            if its_a != Ws + Ks:  # a breakdown ends the phases early: the time is not a rate
+                ablation[name] = None
+                ablation[name.replace("_ms", "_breakdown_at")] = its_a
+        # without preconditioner: Algorithm 4 fused (combined CG) and textbook CG
+        P.set_preconditioner(mfcg.PRECOND_NONE)
+        for solver, name in ((mfcg.SOLVER_FUSED, "combined_cg_ms"), (mfcg.SOLVER_PCG_BASIC, "basic_cg_ms")):
+            P.set_solver(solver)
+            P.cg_begin(b, None, tol=0.0, maxit=W + K)
+            P.cg_iterate(W)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P.cg_iterate(K)
+            torch.cuda.synchronize()
+            ablation[name] = round((time.perf_counter() - t0) * 1e3 / K, 5)
+            code_a, its_a, _ = P.cg_end(x)
+            assert its_a == W + K, (name, code_a, its_a)
+        P.set_preconditioner(mfcg.PRECOND_JACOBI)
         P.set_solver(mfcg.SOLVER_FUSED)
         ablation["speedup_vs_3pass"] = round(ablation["alg5_3pass_ms"] / ms_per_step, 3)
         ablation["speedup_vs_basic"] = round(ablation["basic_pcg_ms"] / ms_per_step, 3)

@@ -69,7 +69,14 @@ enum {
 enum {
     MFCG_SOLVER_FUSED = 0,      /* Algorithm 5, pre/post fused into the operator's cell loop (default) */
     MFCG_SOLVER_ALG5_SPLIT = 1, /* Algorithm 5 as three passes: pre kernel, operator, post kernel */
-    MFCG_SOLVER_PCG_BASIC = 2   /* Algorithm 1: separate vector kernels and three reductions */
+    MFCG_SOLVER_PCG_BASIC = 2,  /* Algorithm 1: separate vector kernels and three reductions */
+    MFCG_SOLVER_PIPELINED = 3,  /* Algorithm 2: pipelined CG, no preconditioner */
+    MFCG_SOLVER_SSTEP = 4       /* Algorithm 3: s-step CG (monomial basis), no preconditioner */
+};
+
+enum {
+    MFCG_PRECOND_JACOBI = 0,    /* M = diag(A), the point-Jacobi preconditioner (default) */
+    MFCG_PRECOND_NONE = 1       /* M = I */
 };
 
 typedef struct mfcg_ctx *mfcg_handle;
@@ -214,15 +221,47 @@ int mfcg_get_timing(mfcg_handle h, double *fused_ms, int64_t *fused_launches, do
                     int64_t *shared_launches);
 
 /* Selects the iteration used by mfcg_solve and the stepping interface
- * (MFCG_SOLVER_*).  The two comparison solvers apply the same operator
- * kernels in plain mat-vec mode and move the vector updates and inner
- * products into separate streaming kernels: Algorithm 5 split into its
- * pre / operator / post regions (Sec. 4.2, the paper's GPU scheme of
- * Sec. 6), and the textbook Jacobi-PCG of Algorithm 1 (Sec. 3).  They give
- * the same iterates in exact arithmetic; they exist to measure what the
- * fusion saves.  Timing events cover MFCG_SOLVER_FUSED only.
+ * (MFCG_SOLVER_*); it takes effect at the next mfcg_cg_begin / mfcg_solve.
+ * The comparison solvers apply the same operator kernels in plain mat-vec
+ * mode and move the vector updates and inner products into separate
+ * streaming kernels:
+ *  - Algorithm 5 split into its pre / operator / post regions (Sec. 4.2,
+ *    the paper's GPU scheme of Sec. 6) and the textbook Jacobi-PCG of
+ *    Algorithm 1 (Sec. 3): the iterates of the fused solver in exact
+ *    arithmetic;
+ *  - pipelined CG (Algorithm 2, Sec. 4.1): one mat-vec q = A w, then one
+ *    loop-fused kernel for the six vector updates and the two inner
+ *    products; stops on the recursively updated ||r||;
+ *  - s-step CG (Algorithm 3, Sec. 4.1, monomial basis, s from
+ *    mfcg_set_sstep): per phase of s iterations, s + 1 mat-vecs and four
+ *    vector passes with block inner products and s x s solves; stops on the
+ *    true residual ||b - A x|| checked at the end of each phase.  Iteration
+ *    counts are multiples of s; a phase runs only if it ends within maxit,
+ *    res_hist holds NaN inside a phase.  The monomial basis loses
+ *    orthogonality as s and the condition number grow (the paper's caveat),
+ *    so it may stall or break down (MFCG_EBREAKDOWN) where CG converges.
+ *  The last two are unpreconditioned, as the paper compares them, and need
+ *  3 (pipelined) or 2s+1 (s-step) extra vectors of n doubles, allocated at
+ *  the first mfcg_cg_begin that uses them.  Timing events cover
+ *  MFCG_SOLVER_FUSED only; the FP32 refinement, the warm start and the
+ *  batch always use the fused solver.
  * Errors: EINVAL (null handle, unknown solver). */
 int mfcg_set_solver(mfcg_handle h, int32_t solver);
+
+/* Preconditioner of the solvers that take one (MFCG_PRECOND_*): with
+ * MFCG_PRECOND_NONE the fused solver runs Algorithm 4 (the merged CG of
+ * Sec. 4.2, the same kernels with the diagonal never read), the split
+ * solver Algorithm 4 in three passes and the basic solver the textbook CG
+ * (Algorithm 1 with z = r).  Pipelined and s-step CG never precondition;
+ * the FP32 refinement, the warm start and the batch always use Jacobi.
+ * Takes effect at the next begin.
+ * Errors: EINVAL (null handle, unknown value). */
+int mfcg_set_preconditioner(mfcg_handle h, int32_t precond);
+
+/* Block size s of MFCG_SOLVER_SSTEP (Algorithm 3), 1..8; default 6, the
+ * value of the paper's comparison.  Takes effect at the next begin.
+ * Errors: EINVAL (null handle, s out of range). */
+int mfcg_set_sstep(mfcg_handle h, int32_t s);
 
 /* Layout facts of the handle (host out, any may be NULL): tile sizes in
  * cells, node counts of the classes of the enumeration (tile-interior,

@@ -87,7 +87,8 @@ def s_step_cg(matvec, b, s, x0=None, tol=1e-10, maxit=10000, return_iterates=Fal
     """Algorithm 3 with the monomial basis.  Per phase: s mat-vecs for the
     basis T = [r, A r, .., A^s r], the block products P_prev^T Q, Q^T P and
     P^T r, two s x s solves, x += P a, and one more mat-vec for the true
-    residual r = b - A x.  maxit is rounded up to a multiple of s."""
+    residual r = b - A x.  Only whole phases run: the iteration count is a
+    multiple of s and at most maxit."""
     assert 1 <= s <= 16
     b = np.asarray(b, dtype=np.float64)
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
@@ -104,7 +105,7 @@ def s_step_cg(matvec, b, s, x0=None, tol=1e-10, maxit=10000, return_iterates=Fal
         return out(0, OK)
     P_prev = W_prev = None
     k = 0
-    while k < maxit:
+    while k + s <= maxit:
         # basis T = [r, A r, .., A^s r]; R = first s columns, Q = last s
         T = [r]
         for _ in range(s):

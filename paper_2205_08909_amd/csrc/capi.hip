@@ -33,6 +33,12 @@ struct mfcg_ctx {
     int K = 0;
     int check_every = 16;
     int solver = MFCG_SOLVER_FUSED;
+    int sstep = 6;
+    int precond = MFCG_PRECOND_JACOBI;
+    /* solver, preconditioner and s fixed by cg_begin for the solve in progress */
+    int solver_active = MFCG_SOLVER_FUSED;
+    int sstep_active = 6;
+    bool prec_active = true;
     HostLayout hl;
     LayoutView lv{};
     Tables<double> tab{};
@@ -48,6 +54,11 @@ struct mfcg_ctx {
     double *hist = nullptr;
     int hist_cap = 0;
     CGState *st = nullptr;
+    /* work vectors, block records and scalars of the pipelined and s-step solvers */
+    double *kvec = nullptr;
+    int64_t kvec_cap = 0; /* vectors of length n */
+    double *kpart = nullptr;
+    KrylovState *ks = nullptr;
     int nshared_blocks = 1;
     int nsum_blocks = 1;
     /* solve bookkeeping */
@@ -99,7 +110,8 @@ static void release(mfcg_ctx *h)
     void *bufs[] = {h->d_ent_base, h->d_tile_ent, h->d_tiles, h->d_coeff, h->G,     h->dinv,   h->diag_lex,
                     h->r,          h->p,          h->v,       h->x,       h->vin,   h->vout,   h->part,
                     h->dots,       h->sums,       h->hist,    h->st,      h->G32,   h->dinv32, h->r32,
-                    h->p32,        h->v32,        h->x32,     h->part32,  h->dots32, h->st32,  h->hist32};
+                    h->p32,        h->v32,        h->x32,     h->part32,  h->dots32, h->st32,  h->hist32,
+                    h->kvec,       h->kpart,      h->ks};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (auto &e : h->ev_pool) {
@@ -572,10 +584,83 @@ int mfcg_get_timing(mfcg_handle h, double *fused_ms, int64_t *fused_launches, do
 int mfcg_set_solver(mfcg_handle h, int32_t solver)
 {
     if (!h) return fail(h, MFCG_EINVAL, "null handle");
-    if (solver != MFCG_SOLVER_FUSED && solver != MFCG_SOLVER_ALG5_SPLIT && solver != MFCG_SOLVER_PCG_BASIC)
-        return fail(h, MFCG_EINVAL, "unknown solver");
+    if (solver < MFCG_SOLVER_FUSED || solver > MFCG_SOLVER_SSTEP) return fail(h, MFCG_EINVAL, "unknown solver");
     h->solver = solver;
     return MFCG_OK;
+}
+
+int mfcg_set_preconditioner(mfcg_handle h, int32_t precond)
+{
+    if (!h) return fail(h, MFCG_EINVAL, "null handle");
+    if (precond != MFCG_PRECOND_JACOBI && precond != MFCG_PRECOND_NONE)
+        return fail(h, MFCG_EINVAL, "unknown preconditioner");
+    h->precond = precond;
+    return MFCG_OK;
+}
+
+int mfcg_set_sstep(mfcg_handle h, int32_t s)
+{
+    if (!h) return fail(h, MFCG_EINVAL, "null handle");
+    if (s < 1 || s > SSTEP_MAX) return fail(h, MFCG_EINVAL, "s must be in 1..8");
+    h->sstep = s;
+    return MFCG_OK;
+}
+
+/* Work space of the pipelined (w, s, z) and s-step (T[1..s], P[0..s), b)
+ * solvers, grown on demand. */
+static int ensure_krylov(mfcg_ctx *h, int64_t nvec, hipStream_t s)
+{
+    if (!h->kpart) {
+        HIPCHK(h, dalloc(&h->kpart, (size_t)MAX_VEC_BLOCKS * SSTEP_REC));
+        HIPCHK(h, dalloc(&h->ks, 1));
+    }
+    if (nvec > h->kvec_cap) {
+        HIPCHK(h, hipStreamSynchronize(s));
+        if (h->kvec) HIPCHK(h, hipFree(h->kvec));
+        h->kvec = nullptr;
+        h->kvec_cap = 0;
+        HIPCHK(h, dalloc(&h->kvec, (size_t)(nvec * h->hl.n)));
+        h->kvec_cap = nvec;
+    }
+    return MFCG_OK;
+}
+
+static PipeArgs pipe_args(mfcg_ctx *h)
+{
+    const int64_t n = h->hl.n;
+    PipeArgs a{};
+    a.x = h->x;
+    a.r = h->r;
+    a.p = h->p;
+    a.w = h->kvec;
+    a.s = h->kvec + n;
+    a.z = h->kvec + 2 * n;
+    a.q = h->v;
+    a.part = h->kpart;
+    a.st = h->st;
+    a.ks = h->ks;
+    a.hist = h->hist;
+    a.n = n;
+    return a;
+}
+
+static SStepArgs sstep_args(mfcg_ctx *h)
+{
+    const int64_t n = h->hl.n;
+    const int S = h->sstep_active;
+    SStepArgs a{};
+    a.T[0] = h->r;
+    for (int j = 1; j <= S; ++j) a.T[j] = h->kvec + (int64_t)(j - 1) * n;
+    for (int m = 0; m < S; ++m) a.P[m] = h->kvec + (int64_t)(S + m) * n;
+    a.b = h->kvec + (int64_t)(2 * S) * n;
+    a.x = h->x;
+    a.v = h->v;
+    a.part = h->kpart;
+    a.st = h->st;
+    a.ks = h->ks;
+    a.hist = h->hist;
+    a.n = n;
+    return a;
 }
 
 int mfcg_cg_begin(mfcg_handle h, const double *b, const double *x0, double tol, int32_t maxit, void *hip_stream)
@@ -592,10 +677,20 @@ int mfcg_cg_begin(mfcg_handle h, const double *b, const double *x0, double tol, 
         h->hist_cap = maxit;
     }
     const int64_t n = h->hl.n;
+    int rc = MFCG_OK;
+    if (h->solver == MFCG_SOLVER_PIPELINED) rc = ensure_krylov(h, 3, s);
+    if (h->solver == MFCG_SOLVER_SSTEP) rc = ensure_krylov(h, 2 * h->sstep + 1, s);
+    if (rc) return rc;
+    h->sstep_active = h->sstep;
+    h->solver_active = h->solver;
+    h->prec_active = h->precond == MFCG_PRECOND_JACOBI;
     /* r = b (internal order); x = x0 or 0 */
     HIPCHK(h, launch_lex_to_int<double>(h->lv, b, h->r, s));
+    if (h->solver == MFCG_SOLVER_SSTEP)
+        HIPCHK(h, hipMemcpyAsync(h->kvec + (int64_t)(2 * h->sstep) * n, h->r, sizeof(double) * n,
+                                 hipMemcpyDeviceToDevice, s));
     double bb = 0.0;
-    int rc = host_sumsq(h, h->r, nullptr, n, &bb, s);
+    rc = host_sumsq(h, h->r, nullptr, n, &bb, s);
     if (rc) return rc;
     h->bnorm = std::sqrt(bb);
     h->zero_rhs = (bb == 0.0);
@@ -619,6 +714,18 @@ int mfcg_cg_begin(mfcg_handle h, const double *b, const double *x0, double tol, 
     st.flag = (h->zero_rhs || st.r0norm < st.eps) ? FLAG_CONV : FLAG_RUN;
     HIPCHK(h, hipMemcpyAsync(h->st, &st, sizeof(CGState), hipMemcpyHostToDevice, s));
     HIPCHK(h, hipMemcpyAsync(h->hist, &st.r0norm, sizeof(double), hipMemcpyHostToDevice, s));
+    if (h->solver == MFCG_SOLVER_PIPELINED || h->solver == MFCG_SOLVER_SSTEP) {
+        KrylovState ks{};
+        ks.s = h->sstep;
+        HIPCHK(h, hipMemcpyAsync(h->ks, &ks, sizeof(KrylovState), hipMemcpyHostToDevice, s));
+    }
+    if (h->solver == MFCG_SOLVER_PIPELINED) {
+        /* w_0 = A r_0, p = s = z = 0, alpha_1 = gamma_0 / a_0 */
+        const PipeArgs pa = pipe_args(h);
+        rc = vmult_internal(h, pa.r, pa.w, s);
+        if (rc) return rc;
+        HIPCHK(h, launch_pipe_init(pa, s));
+    }
     h->maxit = maxit;
     h->launched = 0;
     return MFCG_OK;
@@ -643,20 +750,49 @@ int mfcg_cg_iterate(mfcg_handle h, int32_t n_it, void *hip_stream)
     a.hist = h->hist;
     a.nshared_blocks = h->nshared_blocks;
     const int64_t n = h->hl.n;
+    if (h->solver_active == MFCG_SOLVER_PIPELINED) {
+        const PipeArgs pa = pipe_args(h);
+        for (int it = 0; it < n_it; ++it) {
+            int rc = vmult_internal(h, pa.w, h->v, s); /* q = A w */
+            if (rc) return rc;
+            HIPCHK(h, launch_pipe_step(pa, s));
+        }
+        h->launched += n_it;
+        return MFCG_OK;
+    }
+    if (h->solver_active == MFCG_SOLVER_SSTEP) {
+        /* a phase starts at every multiple of s and runs only if it fits in maxit */
+        const int S = h->sstep_active;
+        const SStepArgs sa = sstep_args(h);
+        for (int it = 0; it < n_it; ++it) {
+            const int i = h->launched + it;
+            if (i % S != 0 || i + S > h->maxit) continue;
+            for (int j = 1; j <= S; ++j) {
+                int rc = vmult_internal(h, sa.T[j - 1], sa.T[j], s);
+                if (rc) return rc;
+            }
+            HIPCHK(h, launch_sstep_blocks(sa, S, s));
+            int rc = vmult_internal(h, sa.x, h->v, s);
+            if (rc) return rc;
+            HIPCHK(h, launch_sstep_residual(sa, S, s));
+        }
+        h->launched += n_it;
+        return MFCG_OK;
+    }
     for (int it = 0; it < n_it; ++it) {
-        if (h->solver == MFCG_SOLVER_ALG5_SPLIT) {
+        if (h->solver_active == MFCG_SOLVER_ALG5_SPLIT) {
             /* pre, mat-vec v = A p, post + finish */
-            HIPCHK(h, launch_alg5_pre(a, n, s));
+            HIPCHK(h, launch_alg5_pre(a, n, h->prec_active, s));
             IterArgs<double> m = a;
             m.src = h->p;
             m.dst = h->v;
             HIPCHK(h, launch_fused<double>(h->K, MODE_VMULT, m, s));
             HIPCHK(h, launch_shared<double>(MODE_VMULT, m, s));
-            HIPCHK(h, launch_alg5_post(a, n, s));
+            HIPCHK(h, launch_alg5_post(a, n, h->prec_active, s));
             continue;
         }
-        if (h->solver == MFCG_SOLVER_PCG_BASIC) {
-            HIPCHK(h, launch_pcg_direction(a, n, s));
+        if (h->solver_active == MFCG_SOLVER_PCG_BASIC) {
+            HIPCHK(h, launch_pcg_direction(a, n, h->prec_active, s));
             IterArgs<double> m = a;
             m.src = h->p;
             m.dst = h->v;
@@ -673,12 +809,13 @@ int mfcg_cg_iterate(mfcg_handle h, int32_t n_it, void *hip_stream)
             if (rc) return rc;
             HIPCHK(h, hipEventRecord(e1.a, s));
         }
-        HIPCHK(h, launch_fused<double>(h->K, MODE_CG, a, s));
+        const int mode = h->prec_active ? MODE_CG : MODE_CG_NOPREC;
+        HIPCHK(h, launch_fused<double>(h->K, mode, a, s));
         if (h->timing) {
             HIPCHK(h, hipEventRecord(e1.b, s));
             HIPCHK(h, hipEventRecord(e2.a, s));
         }
-        HIPCHK(h, launch_shared<double>(MODE_CG, a, s));
+        HIPCHK(h, launch_shared<double>(mode, a, s));
         if (h->timing) {
             HIPCHK(h, hipEventRecord(e2.b, s));
             h->ev_fused.push_back(e1);
@@ -710,8 +847,9 @@ int mfcg_cg_end(mfcg_handle h, double *x, int32_t *iters, double *res_hist, void
         HIPCHK(h, hipStreamSynchronize(s));
         return MFCG_OK;
     }
-    if (h->solver != MFCG_SOLVER_PCG_BASIC) /* Algorithm 5 keeps x one or two steps behind */
-        HIPCHK(h, launch_reconstruct<double>(h->hl.n, h->x, h->p, h->r, h->dinv, h->st, s));
+    if (h->solver_active == MFCG_SOLVER_FUSED || h->solver_active == MFCG_SOLVER_ALG5_SPLIT) /* Algorithm 5 keeps x behind */
+        HIPCHK(h, launch_reconstruct<double>(h->hl.n, h->x, h->p, h->r, h->prec_active ? h->dinv : nullptr,
+                                             h->st, s));
     HIPCHK(h, launch_int_to_lex<double>(h->lv, h->x, x, s));
     if (res_hist) HIPCHK(h, hipMemcpyAsync(res_hist, h->hist, sizeof(double) * (st.k + 1), hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));
@@ -1161,6 +1299,9 @@ int mfcg_batch_solve(mfcg_batch hb, const double *const *b, double *const *x, do
     for (int i = 0; i < np; ++i)
         if (!b[i] || !x[i]) return batch_fail(hb, MFCG_EINVAL, "null vector of problem " + std::to_string(i));
     hipStream_t s = (hipStream_t)hip_stream;
+    for (int i = 0; i < np; ++i)
+        if (hb->probs[i]->solver != MFCG_SOLVER_FUSED)
+            return batch_fail(hb, MFCG_EINVAL, "problem " + std::to_string(i) + ": the batch runs the fused solver only");
     /* every problem starts as mfcg_solve would start it */
     for (int i = 0; i < np; ++i) {
         int rc = mfcg_cg_begin(hb->probs[i], b[i], x[i], tol, maxit, hip_stream);

@@ -7,7 +7,11 @@
 
 namespace mfcg {
 
-enum Mode : int { MODE_CG = 0, MODE_VMULT = 1 };
+/* MODE_CG: one iteration of Algorithm 5 with the Jacobi preconditioner;
+ * MODE_CG_NOPREC: the same with M = I (Algorithm 4, the merged CG), the
+ * diagonal never read; MODE_VMULT: dst = A src. */
+enum Mode : int { MODE_CG = 0, MODE_VMULT = 1, MODE_CG_NOPREC = 2 };
+constexpr bool mode_is_cg(int m) { return m != MODE_VMULT; }
 
 /* Arguments of the fused tile kernel and the shared-node kernel. */
 template <typename T>
@@ -69,6 +73,7 @@ template <typename T>
 hipError_t launch_int_to_lex(const LayoutView &L, const T *in_int, double *out_lex, hipStream_t s);
 /* r = r - v (use_v), p = 0, v = 0 */
 hipError_t launch_init_cg(int64_t n, double *r, double *p, double *v, int use_v, hipStream_t s);
+/* dinv == NULL: unit diagonal (no preconditioner) */
 template <typename T>
 hipError_t launch_reconstruct(int64_t n, T *x, const T *p, const T *r, const T *dinv, const CGState *st,
                               hipStream_t s);
@@ -90,11 +95,50 @@ hipError_t launch_stream(int kind, int64_t n, const double *src, double *dst, in
  * of 8 doubles into a.dots, at most MAX_VEC_BLOCKS of them. */
 constexpr int MAX_VEC_BLOCKS = 2048;
 int vec_blocks(int64_t n);
-/* Algorithm 5 in three passes: pre (r, p, x) ... mat-vec ... post (7 dots) + finish */
-hipError_t launch_alg5_pre(const IterArgs<double> &a, int64_t n, hipStream_t s);
-hipError_t launch_alg5_post(const IterArgs<double> &a, int64_t n, hipStream_t s);
-/* Algorithm 1: r^T D^{-1} r -> beta, p = D^{-1} r + beta p ... mat-vec ... p^T v -> alpha, x and r update, ||r|| */
-hipError_t launch_pcg_direction(const IterArgs<double> &a, int64_t n, hipStream_t s);
+/* Algorithm 5 in three passes: pre (r, p, x) ... mat-vec ... post (7 dots) + finish;
+ * prec = false: M = I (Algorithm 4), a.dinv not read */
+hipError_t launch_alg5_pre(const IterArgs<double> &a, int64_t n, bool prec, hipStream_t s);
+hipError_t launch_alg5_post(const IterArgs<double> &a, int64_t n, bool prec, hipStream_t s);
+/* Algorithm 1: r^T D^{-1} r -> beta, p = D^{-1} r + beta p ... mat-vec ... p^T v -> alpha, x and r update, ||r||;
+ * prec = false: z = r */
+hipError_t launch_pcg_direction(const IterArgs<double> &a, int64_t n, bool prec, hipStream_t s);
 hipError_t launch_pcg_update(const IterArgs<double> &a, int64_t n, hipStream_t s);
+
+/* Pipelined CG (Algorithm 2), unpreconditioned.  q = A w comes from the
+ * operator's mat-vec mode; one fused vector kernel does the six updates and
+ * the two inner products, a one-block finish the scalars. */
+struct PipeArgs {
+    double *x, *r, *p, *w, *s, *z;
+    const double *q;
+    double *part; /* per-block records of 8 doubles, at most MAX_VEC_BLOCKS */
+    CGState *st;
+    KrylovState *ks;
+    double *hist;
+    int64_t n;
+};
+/* p = s = z = 0, gamma_0 = r^T r, a_0 = w^T r, alpha_1 = gamma_0 / a_0 */
+hipError_t launch_pipe_init(const PipeArgs &a, hipStream_t s);
+/* the vector updates of one iteration, its inner products and the next scalars */
+hipError_t launch_pipe_step(const PipeArgs &a, hipStream_t s);
+
+/* s-step CG (Algorithm 3, monomial basis), unpreconditioned.  T[0] = r and
+ * T[1..s] = A^j r (filled by the caller's mat-vecs), P[0..s) the direction
+ * block, b the right-hand side and v = A x (internal order). */
+constexpr int SSTEP_REC = 80; /* doubles per block record, >= s^2 + s */
+struct SStepArgs {
+    double *T[SSTEP_MAX + 1];
+    double *P[SSTEP_MAX];
+    double *x;
+    const double *b, *v;
+    double *part; /* per-block records of SSTEP_REC doubles, at most MAX_VEC_BLOCKS */
+    CGState *st;
+    KrylovState *ks;
+    double *hist;
+    int64_t n;
+};
+/* C = P_prev^T Q, B = -W_prev^{-1} C; P = R + P_prev B, W = Q^T P, g = P^T r, a = W^{-1} g; x += P a */
+hipError_t launch_sstep_blocks(const SStepArgs &a, int sdim, hipStream_t s);
+/* r = T[0] = b - v, ||r||, history, convergence test, next phase */
+hipError_t launch_sstep_residual(const SStepArgs &a, int sdim, hipStream_t s);
 
 }  // namespace mfcg

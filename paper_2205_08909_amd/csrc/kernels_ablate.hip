@@ -13,6 +13,9 @@
  *  search direction, the mat-vec, p^T v and the x/r update with ||r||,
  *  each reduction finished by one block on the device.
  *
+ * Both also run with M = I (PREC = false: the diagonal is never read),
+ * which makes them Algorithm 4 split into passes and the textbook CG.
+ *
  * The vector kernels are grid-stride loops over the internal vector order;
  * every partial sum is reduced in a fixed order, so runs are reproducible.
  */
@@ -28,6 +31,7 @@ constexpr int VEC_PER_THREAD = 4; /* entries per thread that size the grid */
 
 /* ---------------- Algorithm 5, three passes ---------------- */
 
+template <bool PREC>
 __global__ __launch_bounds__(VEC_WG) void alg5_pre_kernel(const IterArgs<double> a, int64_t n)
 {
     const CGState *st = a.st;
@@ -37,7 +41,7 @@ __global__ __launch_bounds__(VEC_WG) void alg5_pre_kernel(const IterArgs<double>
     const bool xupd = (kk > 1) && (kk & 1);
     const int64_t stride = (int64_t)gridDim.x * VEC_WG;
     for (int64_t i = (int64_t)blockIdx.x * VEC_WG + threadIdx.x; i < n; i += stride) {
-        const double r0 = a.r[i], v0 = a.v[i], p0 = a.p[i], dv = a.dinv[i];
+        const double r0 = a.r[i], v0 = a.v[i], p0 = a.p[i], dv = PREC ? a.dinv[i] : 1.0;
         double rn, pn;
         pre_update(r0, v0, p0, dv, alpha, beta, rn, pn);
         if (xupd) a.x[i] = x_update(a.x[i], r0, p0, dv, alpha, ratio);
@@ -46,6 +50,7 @@ __global__ __launch_bounds__(VEC_WG) void alg5_pre_kernel(const IterArgs<double>
     }
 }
 
+template <bool PREC>
 __global__ __launch_bounds__(VEC_WG) void alg5_post_kernel(const IterArgs<double> a, int64_t n)
 {
     __shared__ double red[8 * (VEC_WG / 64)];
@@ -55,7 +60,7 @@ __global__ __launch_bounds__(VEC_WG) void alg5_post_kernel(const IterArgs<double
     for (int c = 0; c < 7; ++c) acc[c] = 0;
     const int64_t stride = (int64_t)gridDim.x * VEC_WG;
     for (int64_t i = (int64_t)blockIdx.x * VEC_WG + threadIdx.x; i < n; i += stride) {
-        const double r = a.r[i], p = a.p[i], v = a.v[i], dv = a.dinv[i];
+        const double r = a.r[i], p = a.p[i], v = a.v[i], dv = PREC ? a.dinv[i] : 1.0;
         const double zr = dv * r, zv = dv * v;
         acc[0] += r * r;
         acc[1] += p * v;
@@ -77,8 +82,8 @@ __global__ __launch_bounds__(SHARED_WG) void alg5_finish_kernel(const IterArgs<d
 
 /* ---------------- Algorithm 1 (basic PCG) ---------------- */
 
-/* which == 0: sum r_i^2 dinv_i;  1: sum p_i v_i */
-template <int WHICH>
+/* which == 0: sum r_i^2 dinv_i (r_i^2 without preconditioner);  1: sum p_i v_i */
+template <int WHICH, bool PREC>
 __global__ __launch_bounds__(VEC_WG) void pcg_dot_kernel(const IterArgs<double> a, int64_t n)
 {
     __shared__ double red[8 * (VEC_WG / 64)];
@@ -88,7 +93,7 @@ __global__ __launch_bounds__(VEC_WG) void pcg_dot_kernel(const IterArgs<double> 
     for (int64_t i = (int64_t)blockIdx.x * VEC_WG + threadIdx.x; i < n; i += stride) {
         if (WHICH == 0) {
             const double r = a.r[i];
-            acc[0] += r * (a.dinv[i] * r);
+            acc[0] += r * ((PREC ? a.dinv[i] : 1.0) * r);
         } else {
             acc[0] += a.p[i] * a.v[i];
         }
@@ -97,13 +102,14 @@ __global__ __launch_bounds__(VEC_WG) void pcg_dot_kernel(const IterArgs<double> 
 }
 
 /* p = D^{-1} r + beta p */
+template <bool PREC>
 __global__ __launch_bounds__(VEC_WG) void pcg_p_kernel(const IterArgs<double> a, int64_t n)
 {
     if (a.st->flag != FLAG_RUN) return;
     const double beta = a.st->beta;
     const int64_t stride = (int64_t)gridDim.x * VEC_WG;
     for (int64_t i = (int64_t)blockIdx.x * VEC_WG + threadIdx.x; i < n; i += stride)
-        a.p[i] = fma(a.dinv[i], a.r[i], beta * a.p[i]);
+        a.p[i] = fma(PREC ? a.dinv[i] : 1.0, a.r[i], beta * a.p[i]);
 }
 
 /* x += alpha p, r -= alpha v, partial ||r||^2 */
@@ -181,33 +187,45 @@ int vec_blocks(int64_t n)
     return (int)b;
 }
 
-hipError_t launch_alg5_pre(const IterArgs<double> &a, int64_t n, hipStream_t s)
+hipError_t launch_alg5_pre(const IterArgs<double> &a, int64_t n, bool prec, hipStream_t s)
 {
-    hipLaunchKernelGGL(alg5_pre_kernel, dim3(vec_blocks(n)), dim3(VEC_WG), 0, s, a, n);
+    if (prec)
+        hipLaunchKernelGGL(alg5_pre_kernel<true>, dim3(vec_blocks(n)), dim3(VEC_WG), 0, s, a, n);
+    else
+        hipLaunchKernelGGL(alg5_pre_kernel<false>, dim3(vec_blocks(n)), dim3(VEC_WG), 0, s, a, n);
     return hipGetLastError();
 }
 
-hipError_t launch_alg5_post(const IterArgs<double> &a, int64_t n, hipStream_t s)
+hipError_t launch_alg5_post(const IterArgs<double> &a, int64_t n, bool prec, hipStream_t s)
 {
     const int nb = vec_blocks(n);
-    hipLaunchKernelGGL(alg5_post_kernel, dim3(nb), dim3(VEC_WG), 0, s, a, n);
+    if (prec)
+        hipLaunchKernelGGL(alg5_post_kernel<true>, dim3(nb), dim3(VEC_WG), 0, s, a, n);
+    else
+        hipLaunchKernelGGL(alg5_post_kernel<false>, dim3(nb), dim3(VEC_WG), 0, s, a, n);
     hipLaunchKernelGGL(alg5_finish_kernel, dim3(1), dim3(SHARED_WG), 0, s, a, (int64_t)nb);
     return hipGetLastError();
 }
 
-hipError_t launch_pcg_direction(const IterArgs<double> &a, int64_t n, hipStream_t s)
+hipError_t launch_pcg_direction(const IterArgs<double> &a, int64_t n, bool prec, hipStream_t s)
 {
     const int nb = vec_blocks(n);
-    hipLaunchKernelGGL(pcg_dot_kernel<0>, dim3(nb), dim3(VEC_WG), 0, s, a, n);
+    if (prec)
+        hipLaunchKernelGGL((pcg_dot_kernel<0, true>), dim3(nb), dim3(VEC_WG), 0, s, a, n);
+    else
+        hipLaunchKernelGGL((pcg_dot_kernel<0, false>), dim3(nb), dim3(VEC_WG), 0, s, a, n);
     hipLaunchKernelGGL(pcg_finish_kernel<0>, dim3(1), dim3(SHARED_WG), 0, s, a, (int64_t)nb);
-    hipLaunchKernelGGL(pcg_p_kernel, dim3(nb), dim3(VEC_WG), 0, s, a, n);
+    if (prec)
+        hipLaunchKernelGGL(pcg_p_kernel<true>, dim3(nb), dim3(VEC_WG), 0, s, a, n);
+    else
+        hipLaunchKernelGGL(pcg_p_kernel<false>, dim3(nb), dim3(VEC_WG), 0, s, a, n);
     return hipGetLastError();
 }
 
 hipError_t launch_pcg_update(const IterArgs<double> &a, int64_t n, hipStream_t s)
 {
     const int nb = vec_blocks(n);
-    hipLaunchKernelGGL(pcg_dot_kernel<1>, dim3(nb), dim3(VEC_WG), 0, s, a, n);
+    hipLaunchKernelGGL((pcg_dot_kernel<1, true>), dim3(nb), dim3(VEC_WG), 0, s, a, n);
     hipLaunchKernelGGL(pcg_finish_kernel<1>, dim3(1), dim3(SHARED_WG), 0, s, a, (int64_t)nb);
     hipLaunchKernelGGL(pcg_xr_kernel, dim3(nb), dim3(VEC_WG), 0, s, a, n);
     hipLaunchKernelGGL(pcg_finish_kernel<2>, dim3(1), dim3(SHARED_WG), 0, s, a, (int64_t)nb);

@@ -40,6 +40,8 @@
  */
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "cg_common.h"
 #include "kernels.h"
 #include "tables_ct.h"
@@ -179,7 +181,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
 
     T alpha = 0, beta = 0, ratio = 0;
     bool xupd = false;
-    if (MODE == MODE_CG) {
+    if (mode_is_cg(MODE)) {
         alpha = (T)a.st->alpha;
         beta = (T)a.st->beta;
         ratio = (T)a.st->ratio;
@@ -238,7 +240,8 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         locate(desc[node], zz, idx, kind, pidx);
         if (kind == KIND_C) return (T)0;
         if (MODE == MODE_VMULT) return a.src[idx];
-        const T r0 = a.r[idx], v0 = a.v[idx], p0 = a.p[idx], dv = a.dinv[idx];
+        const T r0 = a.r[idx], v0 = a.v[idx], p0 = a.p[idx];
+        const T dv = MODE == MODE_CG_NOPREC ? (T)1 : a.dinv[idx];
         T rn, pn;
         pre_update(r0, v0, p0, dv, alpha, beta, rn, pn);
         rk = rn;
@@ -277,7 +280,8 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
                 a.dst[idx] = v;
             } else {
                 const bool use = Cfg<K>::CARRY && reg;
-                const T rn = use ? rk : a.r[idx], dv = use ? dk : a.dinv[idx];
+                const T rn = use ? rk : a.r[idx];
+                const T dv = MODE == MODE_CG_NOPREC ? (T)1 : (use ? dk : a.dinv[idx]);
                 const T pn = win[slot * PNM + node];
                 const T zr = dv * rn, zv = dv * v;
                 acc[0] += rn * rn;
@@ -653,7 +657,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         asm volatile("" : "+v"(tid));
     }
 
-    if (MODE == MODE_CG) block_reduce<T, 7, WG>(acc, red, a.dots + tile * 8);
+    if (mode_is_cg(MODE)) block_reduce<T, 7, WG>(acc, red, a.dots + tile * 8);
 }
 
 template <int K, typename T, int MODE>
@@ -661,7 +665,7 @@ __global__ __launch_bounds__(Cfg<K>::WG)
 __attribute__((amdgpu_waves_per_eu(MFCG_WPE_MIN(K), 8)))
 void fused_tile_kernel(const IterArgs<T> a)
 {
-    if (MODE == MODE_CG && a.st->flag != FLAG_RUN) return;
+    if (mode_is_cg(MODE) && a.st->flag != FLAG_RUN) return;
     fused_tile<K, T, MODE>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
@@ -696,7 +700,7 @@ __device__ __forceinline__ void shared_nodes(const IterArgs<T> &a, const int blk
 
     T alpha = 0, beta = 0, ratio = 0;
     bool xupd = false;
-    if (MODE == MODE_CG) {
+    if (mode_is_cg(MODE)) {
         alpha = (T)a.st->alpha;
         beta = (T)a.st->beta;
         ratio = (T)a.st->ratio;
@@ -730,11 +734,11 @@ __device__ __forceinline__ void shared_nodes(const IterArgs<T> &a, const int blk
 #pragma unroll
                     for (int s = 1; s < 8; ++s) v += q[s * L.nV];
                 }
-                if (MODE == MODE_CG) {
+                if (mode_is_cg(MODE)) {
                     r0[u] = a.r[i];
                     v0[u] = a.v[i];
                     p0[u] = a.p[i];
-                    dv[u] = a.dinv[i];
+                    dv[u] = MODE == MODE_CG_NOPREC ? (T)1 : a.dinv[i];
                     x0[u] = xupd ? a.x[i] : (T)0;
                 } else if (cons[u]) {
                     v = a.src[i];
@@ -776,7 +780,7 @@ template <typename T, int MODE>
 __global__ __launch_bounds__(SHARED_WG) void shared_node_kernel(const IterArgs<T> a)
 {
     __shared__ T red[8 * (SHARED_WG / 64)];
-    if (MODE == MODE_CG && a.st->flag != FLAG_RUN) return;
+    if (mode_is_cg(MODE) && a.st->flag != FLAG_RUN) return;
     shared_nodes<T, MODE>(a, blockIdx.x, gridDim.x, red);
 }
 
@@ -825,10 +829,14 @@ template <int K, typename T>
 static hipError_t launch_fused_k(int mode, const IterArgs<T> &a, hipStream_t s)
 {
     dim3 grid((unsigned)a.L.ntiles), block(Cfg<K>::WG);
-    if (mode == MODE_CG)
+    if (mode == MODE_CG) {
         hipLaunchKernelGGL((fused_tile_kernel<K, T, MODE_CG>), grid, block, 0, s, a);
-    else
+    } else if (mode == MODE_CG_NOPREC) {
+        if constexpr (!std::is_same<T, double>::value) return hipErrorInvalidValue; /* FP64 only */
+        else hipLaunchKernelGGL((fused_tile_kernel<K, T, MODE_CG_NOPREC>), grid, block, 0, s, a);
+    } else {
         hipLaunchKernelGGL((fused_tile_kernel<K, T, MODE_VMULT>), grid, block, 0, s, a);
+    }
     return hipGetLastError();
 }
 
@@ -855,6 +863,12 @@ hipError_t launch_shared(int mode, const IterArgs<T> &a, hipStream_t s)
     if (mode == MODE_CG) {
         hipLaunchKernelGGL((shared_node_kernel<T, MODE_CG>), grid, block, 0, s, a);
         hipLaunchKernelGGL((finish_kernel<T>), dim3(1), block, 0, s, a);
+    } else if (mode == MODE_CG_NOPREC) {
+        if constexpr (!std::is_same<T, double>::value) return hipErrorInvalidValue;
+        else {
+            hipLaunchKernelGGL((shared_node_kernel<T, MODE_CG_NOPREC>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((finish_kernel<T>), dim3(1), block, 0, s, a);
+        }
     } else {
         hipLaunchKernelGGL((shared_node_kernel<T, MODE_VMULT>), grid, block, 0, s, a);
     }

@@ -468,7 +468,7 @@ __global__ __launch_bounds__(SETUP_WG) void reconstruct_kernel(int64_t n, T *x, 
     if (k == 0) return;
     const T xa = (T)st->xa, xr = (T)st->xratio;
     T xi = fma(xa, p[i], x[i]);
-    if ((k & 1) == 0) xi = fma(xr, fma(-dinv[i], r[i], p[i]), xi);
+    if ((k & 1) == 0) xi = fma(xr, fma(dinv ? -dinv[i] : (T)-1, r[i], p[i]), xi);
     x[i] = xi;
 }
 

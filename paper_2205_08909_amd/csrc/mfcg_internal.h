@@ -93,4 +93,19 @@ struct CGState {
     double rz;       /* r^T D^{-1} r of the basic PCG (Algorithm 1) */
 };
 
+/* Scalars of the comparison solvers of Sec. 4.1 kept in device memory. */
+constexpr int SSTEP_MAX = 8;
+struct KrylovState {
+    /* pipelined CG (Algorithm 2): the next iteration's alpha and beta and the
+     * gamma_k = r^T r, a_k = w^T r they were formed from */
+    double alpha, beta, gamma, a;
+    /* s-step CG (Algorithm 3): completed phases, W = Q^T P of the last phase,
+     * the block B and the coefficient vector a of the current phase
+     * (row-major s x s) */
+    int32_t phase, s;
+    double W[SSTEP_MAX * SSTEP_MAX];
+    double B[SSTEP_MAX * SSTEP_MAX];
+    double avec[SSTEP_MAX];
+};
+
 }  // namespace mfcg

@@ -17,7 +17,8 @@ OK, EINVAL, ENOMEM, EHIP, ENOTCONV, EBREAKDOWN, ESTAGNATION = 0, -1, -2, -3, -4,
 MAP_AFFINE, MAP_SINE_SHEAR, MAP_SINE_PRODUCT = 0, 1, 2
 BC_DIRICHLET0, BC_NONE = 0, 1
 RHS_SINE, RHS_BUMPS = 0, 1
-SOLVER_FUSED, SOLVER_ALG5_SPLIT, SOLVER_PCG_BASIC = 0, 1, 2
+SOLVER_FUSED, SOLVER_ALG5_SPLIT, SOLVER_PCG_BASIC, SOLVER_PIPELINED, SOLVER_SSTEP = 0, 1, 2, 3, 4
+PRECOND_JACOBI, PRECOND_NONE = 0, 1
 
 EXPORTED = [
     "mfcg_setup", "mfcg_n_dofs", "mfcg_vmult", "mfcg_diagonal", "mfcg_assemble_rhs", "mfcg_solve",
@@ -25,7 +26,7 @@ EXPORTED = [
     "mfcg_layout_info", "mfcg_layout_permutation", "mfcg_destroy", "mfcg_error_string", "mfcg_last_error",
     "mfcg_stream_bench", "mfcg_solve_ir", "mfcg_set_solver", "mfcg_set_coefficient", "mfcg_warmstart",
     "mfcg_autotune_tile", "mfcg_batch_setup", "mfcg_batch_info", "mfcg_batch_solve", "mfcg_batch_destroy",
-    "mfcg_batch_last_error",
+    "mfcg_batch_last_error", "mfcg_set_sstep", "mfcg_set_preconditioner",
 ]
 
 
@@ -80,6 +81,8 @@ def lib():
         L.mfcg_stream_bench.argtypes = [I32, I64, P, P, I32, P]
         L.mfcg_solve_ir.argtypes = [P, P, P, D, D, I32, I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), P, P, P]
         L.mfcg_set_solver.argtypes = [P, I32]
+        L.mfcg_set_sstep.argtypes = [P, I32]
+        L.mfcg_set_preconditioner.argtypes = [P, I32]
         L.mfcg_set_coefficient.argtypes = [P, P, P]
         L.mfcg_warmstart.argtypes = [P, P, P, D, P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I32), P]
         L.mfcg_autotune_tile.argtypes = [ctypes.POINTER(Mesh), I32, I32, P, ctypes.POINTER(D), P]
@@ -286,8 +289,17 @@ class Problem:
         return x0, sc.value, rr.value, bool(used.value)
 
     def set_solver(self, solver):
-        """SOLVER_FUSED (default), SOLVER_ALG5_SPLIT or SOLVER_PCG_BASIC."""
+        """SOLVER_FUSED (default), SOLVER_ALG5_SPLIT, SOLVER_PCG_BASIC,
+        SOLVER_PIPELINED or SOLVER_SSTEP (the last two unpreconditioned)."""
         _check(lib().mfcg_set_solver(self.h, int(solver)), self.h)
+
+    def set_preconditioner(self, precond):
+        """PRECOND_JACOBI (default) or PRECOND_NONE (fused, split and basic solvers)."""
+        _check(lib().mfcg_set_preconditioner(self.h, int(precond)), self.h)
+
+    def set_sstep(self, s):
+        """Block size of SOLVER_SSTEP, 1..8 (default 6)."""
+        _check(lib().mfcg_set_sstep(self.h, int(s)), self.h)
 
     def set_timing(self, on=True):
         _check(lib().mfcg_set_timing(self.h, 1 if on else 0), self.h)

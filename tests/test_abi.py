@@ -110,6 +110,8 @@ def test_null_handle_calls():
     assert L.mfcg_destroy(None) == mfcg.OK
     # the later entry points validate on the host too
     assert L.mfcg_set_solver(None, 0) == mfcg.EINVAL
+    assert L.mfcg_set_sstep(None, 6) == mfcg.EINVAL
+    assert L.mfcg_set_preconditioner(None, 0) == mfcg.EINVAL
     assert L.mfcg_set_coefficient(None, None, None) == mfcg.EINVAL
     d = ctypes.c_double()
     i = ctypes.c_int32()

@@ -1,5 +1,8 @@
 """The comparison solvers (Algorithm 5 in three passes, basic Algorithm 1)
-against the oracle and against the fused solver.
+against the oracle and against the fused solver, with the Jacobi
+preconditioner and without one (M = I: the fused and split solvers then run
+Algorithm 4, the basic one textbook CG; the oracle runs Algorithm 1 with a
+unit diagonal).
 
 All three produce the same iterates in exact arithmetic.  Checked: each
 solver's iteration count lies within the oracle's own summation-order range
@@ -25,18 +28,20 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("precond", [0, 1])
 @pytest.mark.parametrize("cells,k,kind,coeff_seed,tile", CASES)
-def test_comparison_solvers(cells, k, kind, coeff_seed, tile, oracle_mod):
+def test_comparison_solvers(cells, k, kind, coeff_seed, tile, precond, oracle_mod):
     import torch
     from paper_2205_08909_amd import mfcg
     coeff = inputs.grf_coefficient(cells, 0.1, 1.0, seed=coeff_seed) if coeff_seed is not None else None
     m = oracle_mod.Mesh(cells, k, map_kind=kind, amp=0.05, coeff=coeff)
     A = oracle_mod.assemble(m)
     b = oracle_mod.rhs(m, oracle_mod.F_SINE)
-    d = A.diagonal()
+    d = A.diagonal() if precond == mfcg.PRECOND_JACOBI else np.ones(A.n)
     xo, its_o, hist_o, _ = oracle_mod.pcg(A, d, b, tol=1e-10, maxit=5000)
-    lo, hi, _ = oracle_noise(oracle_mod, A, b)
+    lo, hi, _ = oracle_noise(oracle_mod, A, b, diag=d)
     P = mfcg.Problem(cells, k, coeff=coeff, map_kind=kind, amplitude=0.05, tile=tile)
+    P.set_preconditioner(precond)
     bt = torch.from_numpy(b).cuda()
     xs = {}
     for solver in (mfcg.SOLVER_FUSED, mfcg.SOLVER_ALG5_SPLIT, mfcg.SOLVER_PCG_BASIC):
@@ -47,7 +52,7 @@ def test_comparison_solvers(cells, k, kind, coeff_seed, tile, oracle_mod):
         xs[solver] = x
         err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
         res = np.linalg.norm(b - A.matvec(x)) / np.linalg.norm(b)
-        print(f"solver {solver}: its {its} (oracle {its_o}, range {lo}..{hi}), x err {err:.2e}, oracle res {res:.2e}")
+        print(f"precond {precond} solver {solver}: its {its} (oracle {its_o}, range {lo}..{hi}), x err {err:.2e}, oracle res {res:.2e}")
         assert code == mfcg.OK
         assert lo - 2 <= its <= hi + 2
         assert err <= 1e-10
@@ -63,8 +68,11 @@ def test_comparison_solvers(cells, k, kind, coeff_seed, tile, oracle_mod):
     P.close()
 
 
-def test_comparison_solvers_fixed_iterations(oracle_mod):
-    """tol = 0: exactly maxit iterations, both exit parities, ENOTCONV."""
+@pytest.mark.parametrize("precond", [0, 1])
+def test_comparison_solvers_fixed_iterations(precond, oracle_mod):
+    """tol = 0: exactly maxit iterations, both exit parities, ENOTCONV
+    (without preconditioner also for the fused solver: its exit
+    reconstruction of x then takes a unit diagonal)."""
     import torch
     from paper_2205_08909_amd import mfcg
     cells, k = (6, 6, 6), 3
@@ -72,10 +80,15 @@ def test_comparison_solvers_fixed_iterations(oracle_mod):
     A = oracle_mod.assemble(m)
     b = oracle_mod.rhs(m, oracle_mod.F_SINE)
     P = mfcg.Problem(cells, k, map_kind=1, amplitude=0.05)
+    P.set_preconditioner(precond)
+    d = A.diagonal() if precond == mfcg.PRECOND_JACOBI else np.ones(A.n)
     bt = torch.from_numpy(b).cuda()
+    solvers = (mfcg.SOLVER_ALG5_SPLIT, mfcg.SOLVER_PCG_BASIC)
+    if precond == mfcg.PRECOND_NONE:
+        solvers = (mfcg.SOLVER_FUSED,) + solvers
     for maxit in (1, 2, 5, 8):
-        xo, its_o, _, _ = oracle_mod.pcg(A, A.diagonal(), b, tol=0.0, maxit=maxit)
-        for solver in (mfcg.SOLVER_ALG5_SPLIT, mfcg.SOLVER_PCG_BASIC):
+        xo, its_o, _, _ = oracle_mod.pcg(A, d, b, tol=0.0, maxit=maxit)
+        for solver in solvers:
             P.set_solver(solver)
             xt = torch.zeros_like(bt)
             code, its, _, _ = P.solve(bt, xt, tol=0.0, maxit=maxit, raise_on=False)
@@ -84,4 +97,6 @@ def test_comparison_solvers_fixed_iterations(oracle_mod):
             assert np.linalg.norm(x - xo) <= 1e-12 * np.linalg.norm(xo), (solver, maxit)
     with pytest.raises(mfcg.MfcgError):
         P.set_solver(7)
+    with pytest.raises(mfcg.MfcgError):
+        P.set_preconditioner(2)
     P.close()

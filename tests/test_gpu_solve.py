@@ -35,13 +35,14 @@ def _problem(oracle_mod, cells, k, kind, amp, coeff_seed=None, tile=None, bc=0):
     return m, A, P
 
 
-def oracle_noise(oracle_mod, A, b, x0=None, tol=1e-10, maxit=5000, nperm=3):
+def oracle_noise(oracle_mod, A, b, x0=None, tol=1e-10, maxit=5000, nperm=3, diag=None):
     """The oracle's own sensitivity to summation order: the same system
     solved in other node orders (P A P^T, P b).  Returns the range of
     iteration counts and the largest relative deviation of the residual
-    history from the unpermuted solve."""
+    history from the unpermuted solve.  diag: the preconditioner's
+    diagonal (default diag(A); ones for plain CG)."""
     from oracle.oracle import CSR
-    d = A.diagonal()
+    d = A.diagonal() if diag is None else diag
     _, its1, h1, _ = oracle_mod.pcg(A, d, b, x0=x0, tol=tol, maxit=maxit)
     lo = hi = its1
     dev = 0.0

@@ -115,7 +115,7 @@ def test_edge_cases(oracle_mod):
         assert rc == KO.OK and its == 0 and np.all(x == 0)
     x, its, hist, rc = KO.pipelined_cg(A.matvec, b, tol=1e-10, maxit=2)
     assert rc == KO.NOT_CONVERGED and its == 2
-    x, its, hist, rc = KO.s_step_cg(A.matvec, b, 3, tol=1e-10, maxit=4)
+    x, its, hist, rc = KO.s_step_cg(A.matvec, b, 3, tol=1e-10, maxit=8)
     assert rc == KO.NOT_CONVERGED and its == 6
     # an indefinite (negated) operator breaks pipelined CG down at once
     x, its, hist, rc = KO.pipelined_cg(lambda u: -A.matvec(u), b, tol=1e-10)
