@@ -174,6 +174,24 @@ int mfcg_assemble_rhs(mfcg_handle h, int32_t kind, const double *params, double 
 int mfcg_solve(mfcg_handle h, const double *b, double *x, double tol, int32_t maxit,
                int32_t *iters, double *res_hist, double *true_rel_res, void *hip_stream);
 
+/* The vector-valued Laplacian of the paper's BP4 family (Sec. 6, the CEED
+ * benchmark problems): three uncoupled components u = (u_x, u_y, u_z), each
+ * with the handle's scalar operator, so the system is I_3 (x) A with the
+ * Jacobi preconditioner I_3 (x) diag(A), solved by one CG (Algorithm 5;
+ * every inner product runs over all 3n entries).  Each iteration applies
+ * the fused kernels once per component and one finish over the three
+ * components' inner-product records.  The quadrature stays the handle's
+ * (k+1)^3 Gauss points.
+ *   b, x   device vectors of 3n doubles, component-blocked: entries
+ *          [c*n, (c+1)*n) hold component c in lexicographic node order;
+ *          x holds x_0 on entry and the solution on return
+ *   other arguments, the stopping rule and res_hist as for mfcg_solve.
+ * Allocates 4 work vectors of 3n doubles at the first call.
+ * Errors: EINVAL (null pointers, tol < 0 or not finite, maxit < 1),
+ * ENOTCONV, EBREAKDOWN, ENOMEM, EHIP.  Synchronises hip_stream. */
+int mfcg_solve_vector(mfcg_handle h, const double *b, double *x, double tol, int32_t maxit, int32_t *iters,
+                      double *res_hist, double *true_rel_res, void *hip_stream);
+
 /* Mixed precision: FP64 iterative refinement around the fused solver run
  * in FP32 (operator with an FP32 copy of G_q and D^{-1}, vector updates and
  * inner products in FP32).  Outer loop in FP64 on the GPU:

@@ -59,6 +59,8 @@ struct mfcg_ctx {
     int64_t kvec_cap = 0; /* vectors of length n */
     double *kpart = nullptr;
     KrylovState *ks = nullptr;
+    /* three-component work vectors of the vector Laplacian (component-blocked) */
+    double *r3 = nullptr, *p3 = nullptr, *v3 = nullptr, *x3 = nullptr, *dots3 = nullptr;
     int nshared_blocks = 1;
     int nsum_blocks = 1;
     /* solve bookkeeping */
@@ -111,7 +113,8 @@ static void release(mfcg_ctx *h)
                     h->r,          h->p,          h->v,       h->x,       h->vin,   h->vout,   h->part,
                     h->dots,       h->sums,       h->hist,    h->st,      h->G32,   h->dinv32, h->r32,
                     h->p32,        h->v32,        h->x32,     h->part32,  h->dots32, h->st32,  h->hist32,
-                    h->kvec,       h->kpart,      h->ks};
+                    h->kvec,       h->kpart,      h->ks,      h->r3,      h->p3,    h->v3,     h->x3,
+                    h->dots3};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (auto &e : h->ev_pool) {
@@ -854,6 +857,123 @@ int mfcg_cg_end(mfcg_handle h, double *x, int32_t *iters, double *res_hist, void
     if (res_hist) HIPCHK(h, hipMemcpyAsync(res_hist, h->hist, sizeof(double) * (st.k + 1), hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));
     if (iters) *iters = st.k;
+    if (st.flag == FLAG_CONV) return MFCG_OK;
+    if (st.flag == FLAG_BREAK) return fail(h, MFCG_EBREAKDOWN, "breakdown: p^T A p <= 0 or non-finite scalar");
+    return fail(h, MFCG_ENOTCONV, "maxit reached");
+}
+
+/* Vector Laplacian (three uncoupled components sharing the operator, the
+ * diagonal and the CG scalars): each iteration runs the fused tile kernel and
+ * the shared-node kernel once per component, each component writing its own
+ * block of inner-product records, then one finish over all of them. */
+int mfcg_solve_vector(mfcg_handle h, const double *b, double *x, double tol, int32_t maxit, int32_t *iters,
+                      double *res_hist, double *true_rel_res, void *hip_stream)
+{
+    if (!h || !b || !x || !iters) return fail(h, MFCG_EINVAL, "null argument");
+    if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(h, MFCG_EINVAL, "tol must be finite and >= 0");
+    if (maxit < 1) return fail(h, MFCG_EINVAL, "maxit must be >= 1");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int64_t n = h->hl.n;
+    const int64_t nrec = h->hl.ntiles + h->nshared_blocks; /* records per component */
+    if (!h->r3) {
+        HIPCHK(h, dalloc(&h->r3, 3 * n));
+        HIPCHK(h, dalloc(&h->p3, 3 * n));
+        HIPCHK(h, dalloc(&h->v3, 3 * n));
+        HIPCHK(h, dalloc(&h->x3, 3 * n));
+        HIPCHK(h, dalloc(&h->dots3, 8 * 3 * nrec));
+    }
+    if (maxit > h->hist_cap) {
+        HIPCHK(h, hipStreamSynchronize(s));
+        HIPCHK(h, hipFree(h->hist));
+        h->hist = nullptr;
+        HIPCHK(h, dalloc(&h->hist, (size_t)maxit + 1));
+        h->hist_cap = maxit;
+    }
+    for (int c = 0; c < 3; ++c) HIPCHK(h, launch_lex_to_int<double>(h->lv, b + c * n, h->r3 + c * n, s));
+    double bb = 0.0;
+    int rc = host_sumsq(h, h->r3, nullptr, 3 * n, &bb, s);
+    if (rc) return rc;
+    const double bnorm = std::sqrt(bb);
+    if (bb == 0.0) {
+        HIPCHK(h, hipMemsetAsync(x, 0, sizeof(double) * 3 * n, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+        *iters = 0;
+        if (res_hist) res_hist[0] = 0.0;
+        if (true_rel_res) *true_rel_res = 0.0;
+        return MFCG_OK;
+    }
+    /* r = b - A x0, p = v = 0 */
+    for (int c = 0; c < 3; ++c) {
+        HIPCHK(h, launch_lex_to_int<double>(h->lv, x + c * n, h->x3 + c * n, s));
+        rc = vmult_internal(h, h->x3 + c * n, h->v3 + c * n, s);
+        if (rc) return rc;
+    }
+    HIPCHK(h, launch_init_cg(3 * n, h->r3, h->p3, h->v3, 1, s));
+    double rr = 0.0;
+    rc = host_sumsq(h, h->r3, nullptr, 3 * n, &rr, s);
+    if (rc) return rc;
+    CGState st{};
+    st.eps = tol * bnorm;
+    st.bnorm = bnorm;
+    st.r0norm = std::sqrt(rr);
+    st.maxit = maxit;
+    st.flag = st.r0norm < st.eps ? FLAG_CONV : FLAG_RUN;
+    HIPCHK(h, hipMemcpyAsync(h->st, &st, sizeof(CGState), hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(h->hist, &st.r0norm, sizeof(double), hipMemcpyHostToDevice, s));
+    IterArgs<double> ac[3];
+    for (int c = 0; c < 3; ++c) {
+        IterArgs<double> &a = ac[c];
+        a = IterArgs<double>{};
+        a.L = h->lv;
+        a.G = h->G;
+        a.dinv = h->dinv;
+        a.r = h->r3 + c * n;
+        a.p = h->p3 + c * n;
+        a.v = h->v3 + c * n;
+        a.x = h->x3 + c * n;
+        a.part = h->part;
+        a.dots = h->dots3 + 8 * c * nrec;
+        a.st = h->st;
+        a.hist = h->hist;
+        a.nshared_blocks = h->nshared_blocks;
+    }
+    int launched = 0;
+    rc = read_state(h, st, s);
+    if (rc) return rc;
+    while (st.flag == FLAG_RUN && launched < maxit) {
+        const int chunk = std::min(h->check_every, maxit - launched);
+        for (int it = 0; it < chunk; ++it) {
+            for (int c = 0; c < 3; ++c) {
+                HIPCHK(h, launch_fused<double>(h->K, MODE_CG, ac[c], s));
+                HIPCHK(h, launch_shared_nofinish(ac[c], s));
+            }
+            HIPCHK(h, launch_finish_parts(ac[0], 3 * nrec, s));
+        }
+        launched += chunk;
+        rc = read_state(h, st, s);
+        if (rc) return rc;
+    }
+    for (int c = 0; c < 3; ++c) {
+        HIPCHK(h, launch_reconstruct<double>(n, ac[c].x, ac[c].p, ac[c].r, h->dinv, h->st, s));
+        HIPCHK(h, launch_int_to_lex<double>(h->lv, ac[c].x, x + c * n, s));
+    }
+    if (res_hist) HIPCHK(h, hipMemcpyAsync(res_hist, h->hist, sizeof(double) * (st.k + 1), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    *iters = st.k;
+    if (true_rel_res) {
+        double tot = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            HIPCHK(h, launch_lex_to_int<double>(h->lv, x + c * n, h->vin, s));
+            rc = vmult_internal(h, h->vin, h->vout, s);
+            if (rc) return rc;
+            HIPCHK(h, launch_int_to_lex<double>(h->lv, h->vout, h->vin, s));
+            double part = 0.0;
+            rc = host_sumsq(h, b + c * n, h->vin, n, &part, s);
+            if (rc) return rc;
+            tot += part;
+        }
+        *true_rel_res = std::sqrt(tot) / bnorm;
+    }
     if (st.flag == FLAG_CONV) return MFCG_OK;
     if (st.flag == FLAG_BREAK) return fail(h, MFCG_EBREAKDOWN, "breakdown: p^T A p <= 0 or non-finite scalar");
     return fail(h, MFCG_ENOTCONV, "maxit reached");

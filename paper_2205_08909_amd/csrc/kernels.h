@@ -52,6 +52,11 @@ template <typename T>
 hipError_t launch_fused(int K, int mode, const IterArgs<T> &a, hipStream_t s);
 template <typename T>
 hipError_t launch_shared(int mode, const IterArgs<T> &a, hipStream_t s);
+/* Vector problems (several components sharing the operator): the
+ * shared-node kernel of one component without the finish, and the finish
+ * over nparts records starting at a.dots (all components' records). */
+hipError_t launch_shared_nofinish(const IterArgs<double> &a, hipStream_t s);
+hipError_t launch_finish_parts(const IterArgs<double> &a, int64_t nparts, hipStream_t s);
 
 /* Setup kernels (FP64). */
 struct GeomArgs {

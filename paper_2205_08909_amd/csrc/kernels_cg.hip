@@ -810,6 +810,15 @@ __global__ __launch_bounds__(SHARED_WG) void finish_kernel(const IterArgs<T> a)
     finish_iteration<T>(a, a.L.ntiles + a.nshared_blocks, red);
 }
 
+/* The same over an explicit record count (vector problems: every
+ * component's records in a row). */
+__global__ __launch_bounds__(SHARED_WG) void finish_parts_kernel(const IterArgs<double> a, int64_t nparts)
+{
+    __shared__ double red[8 * (SHARED_WG / 64)];
+    if (a.st->flag != FLAG_RUN) return;
+    finish_iteration<double>(a, nparts, red);
+}
+
 /* Batch: one block per listed problem. */
 template <typename T>
 __global__ __launch_bounds__(SHARED_WG) void finish_batch_kernel(const IterArgs<T> *__restrict__ probs,
@@ -872,6 +881,19 @@ hipError_t launch_shared(int mode, const IterArgs<T> &a, hipStream_t s)
     } else {
         hipLaunchKernelGGL((shared_node_kernel<T, MODE_VMULT>), grid, block, 0, s, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_shared_nofinish(const IterArgs<double> &a, hipStream_t s)
+{
+    hipLaunchKernelGGL((shared_node_kernel<double, MODE_CG>), dim3((unsigned)a.nshared_blocks), dim3(SHARED_WG), 0, s,
+                       a);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_parts(const IterArgs<double> &a, int64_t nparts, hipStream_t s)
+{
+    hipLaunchKernelGGL(finish_parts_kernel, dim3(1), dim3(SHARED_WG), 0, s, a, nparts);
     return hipGetLastError();
 }
 

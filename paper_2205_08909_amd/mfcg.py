@@ -26,7 +26,7 @@ EXPORTED = [
     "mfcg_layout_info", "mfcg_layout_permutation", "mfcg_destroy", "mfcg_error_string", "mfcg_last_error",
     "mfcg_stream_bench", "mfcg_solve_ir", "mfcg_set_solver", "mfcg_set_coefficient", "mfcg_warmstart",
     "mfcg_autotune_tile", "mfcg_batch_setup", "mfcg_batch_info", "mfcg_batch_solve", "mfcg_batch_destroy",
-    "mfcg_batch_last_error", "mfcg_set_sstep", "mfcg_set_preconditioner",
+    "mfcg_batch_last_error", "mfcg_set_sstep", "mfcg_set_preconditioner", "mfcg_solve_vector",
 ]
 
 
@@ -83,6 +83,7 @@ def lib():
         L.mfcg_set_solver.argtypes = [P, I32]
         L.mfcg_set_sstep.argtypes = [P, I32]
         L.mfcg_set_preconditioner.argtypes = [P, I32]
+        L.mfcg_solve_vector.argtypes = [P, P, P, D, I32, ctypes.POINTER(I32), P, P, P]
         L.mfcg_set_coefficient.argtypes = [P, P, P]
         L.mfcg_warmstart.argtypes = [P, P, P, D, P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I32), P]
         L.mfcg_autotune_tile.argtypes = [ctypes.POINTER(Mesh), I32, I32, P, ctypes.POINTER(D), P]
@@ -231,6 +232,24 @@ class Problem:
         code = lib().mfcg_solve(self.h, _ptr(b), _ptr(x), float(tol), int(maxit), ctypes.byref(its),
                                 hist.ctypes.data_as(ctypes.c_void_p) if want_hist else None,
                                 ctypes.byref(tr) if want_true_res else None, _stream(stream))
+        if raise_on and code not in (OK, ENOTCONV):
+            _check(code, self.h)
+        h = hist[: its.value + 1].copy() if want_hist else None
+        return code, its.value, h, tr.value
+
+    def solve_vector(self, b, x, tol=1e-10, maxit=10000, want_hist=True, want_true_res=False, stream=None,
+                     raise_on=True):
+        """Vector Laplacian (three uncoupled components, BP4 family): b and x
+        hold 3n entries, component-blocked.  Returns (code, iters, hist,
+        true_rel_res); x is overwritten."""
+        _dev_vec(b, 3 * self.n, "b")
+        _dev_vec(x, 3 * self.n, "x")
+        its = ctypes.c_int32()
+        hist = np.zeros(maxit + 1) if want_hist else None
+        tr = ctypes.c_double(float("nan"))
+        code = lib().mfcg_solve_vector(self.h, _ptr(b), _ptr(x), float(tol), int(maxit), ctypes.byref(its),
+                                       hist.ctypes.data_as(ctypes.c_void_p) if want_hist else None,
+                                       ctypes.byref(tr) if want_true_res else None, _stream(stream))
         if raise_on and code not in (OK, ENOTCONV):
             _check(code, self.h)
         h = hist[: its.value + 1].copy() if want_hist else None

@@ -112,6 +112,7 @@ def test_null_handle_calls():
     assert L.mfcg_set_solver(None, 0) == mfcg.EINVAL
     assert L.mfcg_set_sstep(None, 6) == mfcg.EINVAL
     assert L.mfcg_set_preconditioner(None, 0) == mfcg.EINVAL
+    assert L.mfcg_solve_vector(None, None, None, 1e-10, 10, None, None, None, None) == mfcg.EINVAL
     assert L.mfcg_set_coefficient(None, None, None) == mfcg.EINVAL
     d = ctypes.c_double()
     i = ctypes.c_int32()
