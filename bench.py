@@ -380,6 +380,23 @@ def main():
             assert its_a == W + K, (name, code_a, its_a)
         P.set_preconditioner(mfcg.PRECOND_JACOBI)
         P.set_solver(mfcg.SOLVER_FUSED)
+        # vector Laplacian (three components, one CG): per-iteration time from two
+        # solves with tol = 0 that differ by K iterations (the set-up cancels)
+        b3 = torch.cat([b, b, b])
+        x3 = torch.zeros_like(b3)
+        tv = []
+        for its_v in (W, W + K):
+            x3.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            code_v, got, _, _ = P.solve_vector(b3, x3, tol=0.0, maxit=its_v, want_hist=False, raise_on=False)
+            torch.cuda.synchronize()
+            tv.append(time.perf_counter() - t0)
+            assert got == its_v, (code_v, got)
+        vms = (tv[1] - tv[0]) * 1e3 / K
+        ablation["vector_laplacian_ms"] = round(vms, 5)
+        ablation["vector_laplacian_GDoF_it_s"] = round(3 * n / vms / 1e6, 3)
+        del b3, x3
         ablation["speedup_vs_3pass"] = round(ablation["alg5_3pass_ms"] / ms_per_step, 3)
         ablation["speedup_vs_basic"] = round(ablation["basic_pcg_ms"] / ms_per_step, 3)
         print(f"[bench] ablation {ablation}", file=sys.stderr, flush=True)

@@ -7,7 +7,9 @@ Checked: iteration count within the oracle's own summation-order range
 the first residual norms to rounding; with one non-zero component the
 vector solve reproduces the scalar solve of that component bitwise (the
 other components contribute exact zeros to every inner product); a zero
-right-hand side; iteration limits of both exit parities.
+right-hand side; iteration limits of both exit parities.  (For a non-zero
+component 1 or 2 its records sit at other offsets of the fixed-order finish,
+so there the agreement is to rounding.)
 """
 import numpy as np
 import pytest
@@ -75,11 +77,20 @@ def test_single_component_is_the_scalar_solve(oracle_mod, torch_cuda):
         code, its, hist, _ = P.solve_vector(bt, xt, tol=1e-10, maxit=5000)
         x1 = torch.zeros(n, dtype=torch.float64, device="cuda")
         code1, its1, hist1, _ = P.solve(torch.from_numpy(b1).cuda(), x1, tol=1e-10, maxit=5000)
-        assert code == code1 == mfcg.OK and its == its1
-        assert np.array_equal(hist, hist1)
         x = xt.cpu().numpy()
-        assert np.array_equal(x[c * n:(c + 1) * n], x1.cpu().numpy())
+        xs = x1.cpu().numpy()
+        assert code == code1 == mfcg.OK
         assert not np.delete(x, np.s_[c * n:(c + 1) * n]).any()
+        if c == 0:
+            # the zero records of components 1 and 2 come after component 0's
+            # in the fixed-order finish: every sum is the scalar one plus zeros
+            assert its == its1 and np.array_equal(hist, hist1)
+            assert np.array_equal(x[:n], xs)
+        else:
+            # the records sit at other offsets, so the finish groups the sums
+            # differently: agreement to rounding
+            assert abs(its - its1) <= 2
+            assert np.linalg.norm(x[c * n:(c + 1) * n] - xs) <= 1e-10 * np.linalg.norm(xs)
     P.close()
 
 
