@@ -174,10 +174,11 @@ int mfcg_assemble_rhs(mfcg_handle h, int32_t kind, const double *params, double 
 int mfcg_solve(mfcg_handle h, const double *b, double *x, double tol, int32_t maxit,
                int32_t *iters, double *res_hist, double *true_rel_res, void *hip_stream);
 
-/* The vector-valued Laplacian of the paper's BP4 family (Sec. 6, the CEED
- * benchmark problems): three uncoupled components u = (u_x, u_y, u_z), each
- * with the handle's scalar operator, so the system is I_3 (x) A with the
- * Jacobi preconditioner I_3 (x) diag(A), solved by one CG (Algorithm 5;
+/* The vector-valued Poisson problem of the paper's benchmark (Sec. 2, Eq. 1;
+ * BP4): three uncoupled components u = (u_x, u_y, u_z), each with the
+ * handle's scalar operator, so the system is I_3 (x) A with the one scalar
+ * diagonal applied to all components (Sec. 3), I_3 (x) diag(A), and it is
+ * solved by one CG (Algorithm 5;
  * every inner product runs over all 3n entries).  Each iteration applies
  * the fused kernels once per component and one finish over the three
  * components' inner-product records.  The quadrature stays the handle's
