@@ -9,8 +9,8 @@ the geometry tensor G_q stored per quadrature point, a = 1, f from the
 manufactured solution prod sin(pi x_j), FP64.  One step = one CG
 iteration (the fused tile kernel + the shared-node kernel).
 
-Prints one JSON line (the driver's contract).  With --gpus > 1 it exits:
-this build runs on one GPU.
+Prints one JSON line.  With --gpus > 1 it exits: the path runs on one
+GPU.
 """
 import argparse
 import json
@@ -275,7 +275,7 @@ def main():
     ap.add_argument("--batch-compare", action="store_true", help="also solve the problems one after another")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the multi-GPU sharding is described in DESIGN.md); "
+        print("bench.py: this benchmark runs on one GPU only (the path is single-GPU); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 

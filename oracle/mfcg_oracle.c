@@ -23,10 +23,10 @@
  * matrices are built by brute force over all (i, j, q) triples, no sum
  * factorization, no fusion.
  *
- * Readings where the paper is silent (also listed in the design doc):
+ * Readings where the paper is silent:
  *   - nodal points of the 1D basis: Gauss-Lobatto-Legendre points,
  *   - quadrature: Gauss-Legendre with nq1 points per direction (nq1 = k+1
- *     by default),
+ *     by default), or Gauss-Lobatto-Legendre with -nq1 points (nq1 < 0),
  *   - per-cell constant coefficient a_e multiplies the cell integral,
  *   - Dirichlet rows/columns replaced by the identity, b_C as given,
  *   - stopping rule: ||r_j||_2 < tol * ||b||_2.
@@ -102,6 +102,25 @@ int oracle_gll(int k, double *x)
             if (fabs(dt) < 1e-16) break;
         }
         x[i] = 0.5 * (1.0 + t);
+    }
+    return 0;
+}
+
+/* Gauss-Lobatto-Legendre quadrature weights on [0,1] for the k+1 points x
+ * of oracle_gll: w_i = 2 / (k (k+1) P_k(t_i)^2) on [-1,1], t = 2x - 1,
+ * halved for the unit interval (textbook). */
+int oracle_gll_weights(int k, const double *x, double *w)
+{
+    if (k < 1 || k > 32) return -1;
+    for (int i = 0; i <= k; ++i) {
+        double p, dp;
+        double t = 2.0 * x[i] - 1.0;
+        if (i == 0 || i == k) {
+            p = (i == 0 && (k & 1)) ? -1.0 : 1.0; /* P_k(+-1) = (+-1)^k */
+        } else {
+            legendre(k, t, &p, &dp);
+        }
+        w[i] = 1.0 / (k * (k + 1.0) * p * p);
     }
     return 0;
 }
@@ -271,12 +290,20 @@ typedef struct {
     double *phi, *dphi;
 } om_tab;
 
+/* nq1 > 0: Gauss-Legendre with nq1 points per direction; nq1 < 0:
+ * Gauss-Lobatto-Legendre with -nq1 points (for -nq1 = k+1 the points are
+ * the nodes: collocation). */
 static int tab_init(om_tab *t, int k, int nq1)
 {
     t->np = k + 1;
-    t->nq = nq1;
+    t->nq = nq1 > 0 ? nq1 : -nq1;
     if (oracle_gll(k, t->nodes) != 0) return -1;
-    if (oracle_gauss(nq1, t->xq, t->wq) != 0) return -1;
+    if (nq1 > 0) {
+        if (oracle_gauss(nq1, t->xq, t->wq) != 0) return -1;
+    } else {
+        if (oracle_gll(t->nq - 1, t->xq) != 0) return -1;
+        if (oracle_gll_weights(t->nq - 1, t->xq, t->wq) != 0) return -1;
+    }
     t->phi = malloc(sizeof(double) * t->np * t->nq);
     t->dphi = malloc(sizeof(double) * t->np * t->nq);
     if (!t->phi || !t->dphi) return -2;
@@ -346,7 +373,8 @@ static void local_to_global(const om_mesh *m, const int c[3], int np, int i, int
 
 static int mesh_check(const om_mesh *m)
 {
-    if (m->k < 1 || m->k > 16 || m->nq1 < 1 || m->nq1 > 32) return -1;
+    const int nq = m->nq1 > 0 ? m->nq1 : -m->nq1;
+    if (m->k < 1 || m->k > 16 || nq < 1 || nq > 32 || (m->nq1 < 0 && nq < 2)) return -1;
     for (int d = 0; d < 3; ++d)
         if (m->n[d] < 1) return -1;
     return 0;
@@ -548,7 +576,7 @@ int oracle_rhs(OM_MESH_ARGS, int fkind, const double *fparams, double *b)
     memset(b, 0, sizeof(double) * n);
     om_tab t;
     if (tab_init(&t, k, nq1)) return -2;
-    int np = k + 1, nb = np * np * np, nq = nq1;
+    int np = k + 1, nb = np * np * np, nq = t.nq;
     for (int colour = 0; colour < 8; ++colour) {
         int64_t ncol[3];
         for (int d = 0; d < 3; ++d) ncol[d] = (m.n[d] - ((colour >> d) & 1) + 1) / 2;
@@ -630,7 +658,7 @@ int oracle_apply_rows(OM_MESH_ARGS, const double *u, int64_t nrows, const int64_
     if (mesh_check(&m)) return -1;
     om_tab t;
     if (tab_init(&t, k, nq1)) return -2;
-    int np = k + 1, nb = np * np * np, nq = nq1;
+    int np = k + 1, nb = np * np * np, nq = t.nq;
     int rc = 0;
 #pragma omp parallel
     {

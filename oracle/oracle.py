@@ -58,6 +58,7 @@ _D = ctypes.c_double
 def _declare(L):
     L.oracle_gauss.argtypes = [_I, _P, _P]
     L.oracle_gll.argtypes = [_I, _P]
+    L.oracle_gll_weights.argtypes = [_I, _P, _P]
     L.oracle_lagrange.argtypes = [_I, _P, _I, _D]
     L.oracle_lagrange.restype = _D
     L.oracle_lagrange_deriv.argtypes = [_I, _P, _I, _D]
@@ -90,6 +91,13 @@ def gauss(n):
     w = np.zeros(n)
     assert lib().oracle_gauss(n, _ptr(x), _ptr(w)) == 0
     return x, w
+
+
+def gll_weights(k):
+    """Weights of the k+1 point Gauss-Lobatto-Legendre rule on [0,1]."""
+    x, w = gll(k), np.zeros(k + 1)
+    assert lib().oracle_gll_weights(k, _ptr(x), _ptr(w)) == 0
+    return w
 
 
 def gll(k):
@@ -127,12 +135,19 @@ class Mesh:
     Node numbering is lexicographic: i = gx + (n0 k + 1) (gy + (n1 k + 1) gz).
     Cell numbering: c = cx + n0 (cy + n1 cz)."""
 
-    def __init__(self, ncells, k, nq1=None, map_kind=MAP_AFFINE, amp=0.0, bc=BC_DIRICHLET, coeff=None):
+    def __init__(self, ncells, k, nq1=None, map_kind=MAP_AFFINE, amp=0.0, bc=BC_DIRICHLET, coeff=None,
+                 quad="gauss"):
+        """quad: "gauss" (Gauss-Legendre, nq1 points, default k+1) or "gll"
+        (Gauss-Lobatto-Legendre on nq1 points, default k+1: collocation at
+        the nodes)."""
         if np.isscalar(ncells):
             ncells = (ncells, ncells, ncells)
         self.ncells = np.ascontiguousarray(ncells, dtype=np.int32)
         self.k = int(k)
         self.nq1 = int(nq1) if nq1 else self.k + 1
+        assert quad in ("gauss", "gll")
+        if quad == "gll":
+            self.nq1 = -self.nq1
         self.map_kind = int(map_kind)
         self.amp = float(amp)
         self.bc = int(bc)

@@ -69,9 +69,21 @@ def exact_1d_matrices(k):
     return K, M
 
 
-def global_1d(k, ncell, h):
-    """Assembled 1D stiffness/mass on a uniform lattice of ncell cells of size h."""
+def gll_weights_exact(k):
+    """GLL quadrature weights as the exact integrals of the nodal Lagrange
+    basis over [0,1] (24-point Gauss rule on degree-k polynomials)."""
+    xq, wq = gauss_rule(24)
+    val, _ = basis_1d(gll_nodes(k), xq)
+    return wq @ val
+
+
+def global_1d(k, ncell, h, lumped=False):
+    """Assembled 1D stiffness/mass on a uniform lattice of ncell cells of size h.
+    lumped: the mass of (k+1)-point GLL quadrature at the nodes (diagonal,
+    the basis integrals); the stiffness is exact under that rule too."""
     K, M = exact_1d_matrices(k)
+    if lumped:
+        M = np.diag(gll_weights_exact(k))
     n = ncell * k + 1
     Kg = np.zeros((n, n))
     Mg = np.zeros((n, n))
@@ -82,13 +94,13 @@ def global_1d(k, ncell, h):
     return Kg, Mg
 
 
-def kronecker_laplacian(k, ncells):
+def kronecker_laplacian(k, ncells, lumped=False):
     """A = Kz(x)My(x)Mx + Mz(x)Ky(x)Mx + Mz(x)My(x)Kx for the affine unit cube
-    (lexicographic numbering, x fastest)."""
+    (lexicographic numbering, x fastest); lumped: GLL collocation."""
     nx, ny, nz = ncells
-    Kx, Mx = global_1d(k, nx, 1.0 / nx)
-    Ky, My = global_1d(k, ny, 1.0 / ny)
-    Kz, Mz = global_1d(k, nz, 1.0 / nz)
+    Kx, Mx = global_1d(k, nx, 1.0 / nx, lumped)
+    Ky, My = global_1d(k, ny, 1.0 / ny, lumped)
+    Kz, Mz = global_1d(k, nz, 1.0 / nz, lumped)
     return (np.kron(Kz, np.kron(My, Mx)) + np.kron(Mz, np.kron(Ky, Mx))
             + np.kron(Mz, np.kron(My, Kx)))
 
@@ -124,10 +136,15 @@ def fd_jacobian(kind, amp, X, h=1e-6):
     return J
 
 
-def element_matrix_fd(k, nq1, ncells, cell, kind, amp, a_e=1.0):
-    """Element stiffness matrix with numpy's rules and an FD Jacobian."""
+def element_matrix_fd(k, nq1, ncells, cell, kind, amp, a_e=1.0, quad="gauss"):
+    """Element stiffness matrix with numpy's rules and an FD Jacobian
+    (quad "gll": the k+1 nodes with the basis integrals as weights)."""
     nodes = gll_nodes(k)
-    xq, wq = gauss_rule(nq1)
+    if quad == "gll":
+        nq1 = k + 1
+        xq, wq = nodes, gll_weights_exact(k)
+    else:
+        xq, wq = gauss_rule(nq1)
     val, der = basis_1d(nodes, xq)  # [q, i]
     n = k + 1
     nb = n ** 3

@@ -3,8 +3,8 @@
 The GPU operator (sum-factorised cell integrals of Eq. 5 summed by Eq. 4,
 with the tile enumeration of Sec. 5.3) must equal the oracle's brute-force
 CSR matrix applied to the same vector: relative 1e-12 in the max and 2
-norms for random-normal input (the tolerance the benchmark spec fixes for the
-FP64 operator), and componentwise within 1e-13 of (|A| |u|)_i, the scale
+norms for random-normal input (the tolerance required of the FP64
+operator), and componentwise within 1e-13 of (|A| |u|)_i, the scale
 of rounding in any FP64 evaluation.
 """
 import numpy as np

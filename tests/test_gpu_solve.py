@@ -6,7 +6,7 @@ history are compared against the oracle's own sensitivity to summation
 order (the same system solved in permuted node orders): the GPU's count
 must lie within that range +-2 and its history within 10x that deviation;
 the first iterations must agree to rounding; the converged solutions must
-agree to 1e-10 relative (the benchmark spec's solution tolerance) and the GPU
+agree to 1e-10 relative (the required solution tolerance) and the GPU
 solution's residual in the oracle's matrix must be below 2e-10 ||b||.  Also checked: the exit
 reconstruction of x for both parities of the last iteration (maxit exits),
 warm starts, a zero right-hand side, reproducibility.

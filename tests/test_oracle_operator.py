@@ -6,7 +6,10 @@
 * curved maps: element matrices agree with an FD-Jacobian numpy build,
   the assembled matrix is symmetric, positive definite on the free nodes
   and annihilates constants without boundary conditions,
-* the diagonal equals the Kronecker closed form on affine meshes.
+* the diagonal equals the Kronecker closed form on affine meshes,
+* with GLL collocation (quadrature at the k+1 nodes, BP5): the affine matrix
+  is the Kronecker sum with the diagonal (lumped) 1D mass of the basis
+  integrals, and curved element matrices match the FD-Jacobian build.
 """
 import os
 
@@ -25,6 +28,29 @@ def test_kronecker_closed_form(oracle_mod, k, ncells):
     A = O.assemble(m).to_scipy().toarray()
     ref = fe_numpy.kronecker_laplacian(k, ncells)
     assert np.abs(A - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("k,ncells", [(1, (2, 3, 2)), (2, (2, 2, 3)), (4, (1, 2, 1)), (6, (1, 1, 2))])
+def test_kronecker_gll_collocation(oracle_mod, k, ncells):
+    O = oracle_mod
+    m = O.Mesh(ncells, k, bc=O.BC_NONE, quad="gll")
+    A = O.assemble(m).to_scipy().toarray()
+    ref = fe_numpy.kronecker_laplacian(k, ncells, lumped=True)
+    assert np.abs(A - ref).max() <= 1e-13 * np.abs(ref).max()
+    # and it differs from the Gauss-integrated operator (the mass is lumped)
+    if k > 1:
+        assert np.abs(A - fe_numpy.kronecker_laplacian(k, ncells)).max() > 1e-6 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("kind,amp,k", [(1, 0.05, 2), (2, 0.05, 4)])
+def test_element_matrix_fd_jacobian_gll(oracle_mod, kind, amp, k):
+    O = oracle_mod
+    ncells = (2, 3, 2)
+    m = O.Mesh(ncells, k, map_kind=kind, amp=amp, quad="gll")
+    for cell in [(0, 0, 0), (1, 2, 1)]:
+        A = O.element_matrix(m, cell)
+        ref = fe_numpy.element_matrix_fd(k, 0, ncells, cell, kind, amp, quad="gll")
+        assert np.abs(A - ref).max() <= 1e-8 * np.abs(ref).max()
 
 
 @pytest.mark.parametrize("k", [1, 3])

@@ -68,3 +68,19 @@ def test_lagrange_properties(oracle_mod, k):
         assert abs(sum(d)) < 1e-11 * k * k        # derivative of 1
         np.testing.assert_allclose(v, val[xi], atol=1e-12)
         np.testing.assert_allclose(d, der[xi], atol=1e-10 * k * k)
+
+
+@pytest.mark.parametrize("k", range(1, 10))
+def test_gll_weights(oracle_mod, k):
+    """The (k+1)-point GLL rule: weights are the integrals of the nodal
+    basis, positive, symmetric; exact to degree 2k-1 and not for 2k."""
+    w = oracle_mod.gll_weights(k)
+    x = oracle_mod.gll(k)
+    np.testing.assert_allclose(w, fe_numpy.gll_weights_exact(k), rtol=0, atol=2e-15)
+    assert np.all(w > 0) and np.allclose(w, w[::-1], atol=1e-15)
+    for m in range(2 * k):
+        assert abs(np.sum(w * x ** m) - 1.0 / (m + 1)) < 1e-14
+    assert abs(np.sum(w * x ** (2 * k)) - 1.0 / (2 * k + 1)) > 1e-12
+    if k == 2:  # Simpson's rule
+        np.testing.assert_allclose(w, [1 / 6, 4 / 6, 1 / 6], atol=1e-16)
+
