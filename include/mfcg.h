@@ -91,12 +91,21 @@ typedef struct {
     int32_t bc;              /* MFCG_BC_* */
 } mfcg_mesh;
 
+/* Quadrature of the operator, the diagonal and the load vector. */
+enum {
+    MFCG_QUAD_GAUSS = 0, /* (k+1)^3 Gauss-Legendre points (default; the stored tensor of Sec. 2.2) */
+    MFCG_QUAD_GLL = 1    /* (k+1)^3 Gauss-Lobatto-Legendre points = the nodes: collocation, the
+                          * BP5 variation of Sec. 6; the interpolation passes drop out.  FP64 only:
+                          * not with fp32 / mfcg_solve_ir, not in a batch */
+};
+
 /* Options.  Zero-initialised fields select the defaults. */
 typedef struct {
-    int32_t n_q_1d;          /* Gauss points per direction; 0: k+1 (only k+1 is supported) */
+    int32_t n_q_1d;          /* quadrature points per direction; 0: k+1 (only k+1 is supported) */
     int32_t tile[3];         /* cells per tile in x, y, z; 0: per-degree default */
     int32_t check_every;     /* iterations between host polls of the convergence flag; 0: 16 */
     int32_t fp32;            /* 1: build the FP32 operator copy of mfcg_solve_ir at set-up (else on first use) */
+    int32_t quad_rule;       /* MFCG_QUAD_* */
 } mfcg_options;
 
 /* Builds the operator (Sec. 2, Eq. 3-5): tiles and DoF enumeration of the

@@ -35,6 +35,7 @@ struct mfcg_ctx {
     int solver = MFCG_SOLVER_FUSED;
     int sstep = 6;
     int precond = MFCG_PRECOND_JACOBI;
+    bool gll = false; /* quadrature on the GLL nodes (collocation) */
     /* solver, preconditioner and s fixed by cg_begin for the solve in progress */
     int solver_active = MFCG_SOLVER_FUSED;
     int sstep_active = 6;
@@ -181,6 +182,8 @@ static int validate_mesh(const mfcg_mesh *mesh, int32_t degree, const int32_t *t
 }
 
 /* vmult on internal vectors: dst = A src */
+static int gll_flag(const mfcg_ctx *h) { return h->gll ? MODE_GLL : 0; }
+
 static int vmult_internal(mfcg_ctx *h, const double *src, double *dst, hipStream_t s)
 {
     IterArgs<double> a{};
@@ -194,7 +197,7 @@ static int vmult_internal(mfcg_ctx *h, const double *src, double *dst, hipStream
     a.st = h->st;
     a.hist = h->hist;
     a.nshared_blocks = h->nshared_blocks;
-    HIPCHK(h, launch_fused<double>(h->K, MODE_VMULT, a, s));
+    HIPCHK(h, launch_fused<double>(h->K, MODE_VMULT | gll_flag(h), a, s));
     HIPCHK(h, launch_shared<double>(MODE_VMULT, a, s));
     return MFCG_OK;
 }
@@ -297,6 +300,10 @@ int mfcg_setup(const mfcg_mesh *mesh, int32_t degree, const double *cell_coeff, 
     if (opt && opt->n_q_1d != 0 && opt->n_q_1d != degree + 1)
         return fail(nullptr, MFCG_EINVAL, "only n_q_1d = k+1 is supported");
     if (opt && opt->check_every < 0) return fail(nullptr, MFCG_EINVAL, "check_every must be >= 0");
+    if (opt && opt->quad_rule != MFCG_QUAD_GAUSS && opt->quad_rule != MFCG_QUAD_GLL)
+        return fail(nullptr, MFCG_EINVAL, "unknown quad_rule");
+    if (opt && opt->quad_rule == MFCG_QUAD_GLL && opt->fp32)
+        return fail(nullptr, MFCG_EINVAL, "the FP32 operator is built for Gauss quadrature only");
     const int64_t ncell = (int64_t)mesh->cells[0] * mesh->cells[1] * mesh->cells[2];
     if (cell_coeff) {
         for (int64_t c = 0; c < ncell; ++c)
@@ -309,6 +316,7 @@ int mfcg_setup(const mfcg_mesh *mesh, int32_t degree, const double *cell_coeff, 
     h->mesh = *mesh;
     h->K = degree;
     if (opt && opt->check_every > 0) h->check_every = opt->check_every;
+    h->gll = opt && opt->quad_rule == MFCG_QUAD_GLL;
     hipStream_t s = (hipStream_t)hip_stream;
 
     auto bail = [&](int code) {
@@ -330,7 +338,7 @@ int mfcg_setup(const mfcg_mesh *mesh, int32_t degree, const double *cell_coeff, 
     int nc[3] = {mesh->cells[0], mesh->cells[1], mesh->cells[2]};
     int t[3] = {tile ? tile[0] : 0, tile ? tile[1] : 0, tile ? tile[2] : 0};
     build_layout(nc, degree, t, mesh->bc, h->hl);
-    build_tables(degree, h->tab);
+    build_tables(degree, h->tab, h->gll);
     HostLayout &L = h->hl;
 
     SCHK(dalloc(&h->d_ent_base, L.ent_base.size()));
@@ -789,7 +797,7 @@ int mfcg_cg_iterate(mfcg_handle h, int32_t n_it, void *hip_stream)
             IterArgs<double> m = a;
             m.src = h->p;
             m.dst = h->v;
-            HIPCHK(h, launch_fused<double>(h->K, MODE_VMULT, m, s));
+            HIPCHK(h, launch_fused<double>(h->K, MODE_VMULT | gll_flag(h), m, s));
             HIPCHK(h, launch_shared<double>(MODE_VMULT, m, s));
             HIPCHK(h, launch_alg5_post(a, n, h->prec_active, s));
             continue;
@@ -799,7 +807,7 @@ int mfcg_cg_iterate(mfcg_handle h, int32_t n_it, void *hip_stream)
             IterArgs<double> m = a;
             m.src = h->p;
             m.dst = h->v;
-            HIPCHK(h, launch_fused<double>(h->K, MODE_VMULT, m, s));
+            HIPCHK(h, launch_fused<double>(h->K, MODE_VMULT | gll_flag(h), m, s));
             HIPCHK(h, launch_shared<double>(MODE_VMULT, m, s));
             HIPCHK(h, launch_pcg_update(a, n, s));
             continue;
@@ -813,7 +821,7 @@ int mfcg_cg_iterate(mfcg_handle h, int32_t n_it, void *hip_stream)
             HIPCHK(h, hipEventRecord(e1.a, s));
         }
         const int mode = h->prec_active ? MODE_CG : MODE_CG_NOPREC;
-        HIPCHK(h, launch_fused<double>(h->K, mode, a, s));
+        HIPCHK(h, launch_fused<double>(h->K, mode | gll_flag(h), a, s));
         if (h->timing) {
             HIPCHK(h, hipEventRecord(e1.b, s));
             HIPCHK(h, hipEventRecord(e2.a, s));
@@ -944,7 +952,7 @@ int mfcg_solve_vector(mfcg_handle h, const double *b, double *x, double tol, int
         const int chunk = std::min(h->check_every, maxit - launched);
         for (int it = 0; it < chunk; ++it) {
             for (int c = 0; c < 3; ++c) {
-                HIPCHK(h, launch_fused<double>(h->K, MODE_CG, ac[c], s));
+                HIPCHK(h, launch_fused<double>(h->K, MODE_CG | gll_flag(h), ac[c], s));
                 HIPCHK(h, launch_shared_nofinish(ac[c], s));
             }
             HIPCHK(h, launch_finish_parts(ac[0], 3 * nrec, s));
@@ -1020,6 +1028,7 @@ int mfcg_solve(mfcg_handle h, const double *b, double *x, double tol, int32_t ma
 static int ensure_fp32(mfcg_ctx *h, hipStream_t s)
 {
     if (h->G32) return MFCG_OK;
+    if (h->gll) return fail(h, MFCG_EINVAL, "the FP32 operator is built for Gauss quadrature only");
     const HostLayout &L = h->hl;
     HIPCHK(h, dalloc(&h->G32, L.g_elems));
     HIPCHK(h, dalloc(&h->dinv32, L.n));
@@ -1111,6 +1120,7 @@ int mfcg_solve_ir(mfcg_handle h, const double *b, double *x, double tol, double 
     if (!(tol > 0.0) || !std::isfinite(tol) || !(inner_tol > 0.0) || !(inner_tol < 1.0))
         return fail(h, MFCG_EINVAL, "need tol > 0 and 0 < inner_tol < 1");
     if (max_outer < 1 || max_inner < 1) return fail(h, MFCG_EINVAL, "max_outer and max_inner must be >= 1");
+    if (h->gll) return fail(h, MFCG_EINVAL, "mixed precision runs with Gauss quadrature only");
     hipStream_t s = (hipStream_t)hip_stream;
     int rc = ensure_fp32(h, s);
     if (rc) return rc;
@@ -1420,8 +1430,9 @@ int mfcg_batch_solve(mfcg_batch hb, const double *const *b, double *const *x, do
         if (!b[i] || !x[i]) return batch_fail(hb, MFCG_EINVAL, "null vector of problem " + std::to_string(i));
     hipStream_t s = (hipStream_t)hip_stream;
     for (int i = 0; i < np; ++i)
-        if (hb->probs[i]->solver != MFCG_SOLVER_FUSED)
-            return batch_fail(hb, MFCG_EINVAL, "problem " + std::to_string(i) + ": the batch runs the fused solver only");
+        if (hb->probs[i]->solver != MFCG_SOLVER_FUSED || hb->probs[i]->gll)
+            return batch_fail(hb, MFCG_EINVAL,
+                              "problem " + std::to_string(i) + ": the batch runs the fused Gauss-quadrature solver only");
     /* every problem starts as mfcg_solve would start it */
     for (int i = 0; i < np; ++i) {
         int rc = mfcg_cg_begin(hb->probs[i], b[i], x[i], tol, maxit, hip_stream);

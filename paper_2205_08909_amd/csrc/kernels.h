@@ -12,6 +12,9 @@ namespace mfcg {
  * diagonal never read; MODE_VMULT: dst = A src. */
 enum Mode : int { MODE_CG = 0, MODE_VMULT = 1, MODE_CG_NOPREC = 2 };
 constexpr bool mode_is_cg(int m) { return m != MODE_VMULT; }
+/* or-ed into the mode argument of launch_fused (FP64 only): quadrature on
+ * the GLL nodes (collocation) instead of the Gauss points */
+constexpr int MODE_GLL = 8;
 
 /* Arguments of the fused tile kernel and the shared-node kernel. */
 template <typename T>

@@ -139,8 +139,10 @@ struct FastDiv {
 /* ------------------------------------------------------------------ */
 
 /* One tile of one problem: the pre / cell / sum / post passes over the
- * tile's cell layers (called by one whole workgroup). */
-template <int K, typename T, int MODE>
+ * tile's cell layers (called by one whole workgroup).  GLLQ: quadrature on
+ * the GLL nodes (collocation), where the interpolation passes are the
+ * identity and are skipped. */
+template <int K, typename T, int MODE, bool GLLQ = false>
 __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t tile)
 {
     constexpr int n = K + 1, n2 = n * n, n3 = n * n * n;
@@ -152,7 +154,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
     constexpr int NC = (PNM + WG - 1) / WG;
     /* compile-time 1D tables: S (GLL basis at Gauss points), D (collocation
      * derivative on the Gauss points) */
-    constexpr ct::Tab<n> TT = ct::make_tab<n>();
+    constexpr ct::Tab<n> TT = ct::make_tab<n, GLLQ>();
     constexpr auto cS = [](int q, int i) { return (T)TT.S[q * n + i]; };
     constexpr auto cD = [](int q, int i) { return (T)TT.D[q * n + i]; };
 
@@ -364,8 +366,12 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
 #pragma unroll
                 for (int q = 0; q < n; ++q) {
                     T t = 0;
+                    if (GLLQ) {
+                        t = u[q];
+                    } else {
 #pragma unroll
-                    for (int z = 0; z < n; ++z) t = fma(cS(q, z), u[z], t);
+                        for (int z = 0; z < n; ++z) t = fma(cS(q, z), u[z], t);
+                    }
                     TA[c * n3 + rem + n2 * q] = t;
                 }
             }
@@ -374,7 +380,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         asm volatile("" : "+v"(tid));
         /* F2 [x-lines]: interpolate along x */
 #pragma unroll
-        for (int rr = 0; rr < R; ++rr) {
+        for (int rr = 0; rr < R && !GLLQ; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlines) {
                 const int c = l / n2, rem = l % n2;
@@ -403,14 +409,18 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
                 const int base = c * n3 + i + n2 * z;
                 T u[n], uq[n];
 #pragma unroll
-                for (int j = 0; j < n; ++j) u[j] = TB[base + n * j];
+                for (int j = 0; j < n; ++j) u[j] = GLLQ ? TA[base + n * j] : TB[base + n * j];
 #pragma unroll
                 for (int q = 0; q < n; ++q) {
-                    T t = 0;
+                    if (GLLQ) {
+                        uq[q] = u[q]; /* values already in TA */
+                    } else {
+                        T t = 0;
 #pragma unroll
-                    for (int j = 0; j < n; ++j) t = fma(cS(q, j), u[j], t);
-                    uq[q] = t;
-                    TA[base + n * q] = t;
+                        for (int j = 0; j < n; ++j) t = fma(cS(q, j), u[j], t);
+                        uq[q] = t;
+                        TA[base + n * q] = t;
+                    }
                 }
 #pragma unroll
                 for (int q = 0; q < n; ++q) {
@@ -573,8 +583,12 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
 #pragma unroll
                 for (int z = 0; z < n; ++z) {
                     T t = 0;
+                    if (GLLQ) {
+                        t = w[z];
+                    } else {
 #pragma unroll
-                    for (int q = 0; q < n; ++q) t = fma(cS(q, z), w[q], t);
+                        for (int q = 0; q < n; ++q) t = fma(cS(q, z), w[q], t);
+                    }
                     TB[base + n2 * z] = t;
                 }
             }
@@ -583,7 +597,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         asm volatile("" : "+v"(tid));
         /* B6 [x-lines]: transposed interpolation along x */
 #pragma unroll
-        for (int rr = 0; rr < R; ++rr) {
+        for (int rr = 0; rr < R && !GLLQ; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlines) {
                 const int c = l / n2, rem = l % n2;
@@ -604,7 +618,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         asm volatile("" : "+v"(tid));
         /* B7 [y-lines]: transposed interpolation along y -> cell vectors */
 #pragma unroll
-        for (int rr = 0; rr < R; ++rr) {
+        for (int rr = 0; rr < R && !GLLQ; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlines) {
                 const int c = l / n2, rem = l % n2, i = rem % n, z = rem / n;
@@ -660,13 +674,13 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
     if (mode_is_cg(MODE)) block_reduce<T, 7, WG>(acc, red, a.dots + tile * 8);
 }
 
-template <int K, typename T, int MODE>
+template <int K, typename T, int MODE, bool GLLQ = false>
 __global__ __launch_bounds__(Cfg<K>::WG)
 __attribute__((amdgpu_waves_per_eu(MFCG_WPE_MIN(K), 8)))
 void fused_tile_kernel(const IterArgs<T> a)
 {
     if (mode_is_cg(MODE) && a.st->flag != FLAG_RUN) return;
-    fused_tile<K, T, MODE>(a, xcd_remap(blockIdx.x, gridDim.x));
+    fused_tile<K, T, MODE, GLLQ>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 /* Batch of problems of degree K: one workgroup per (problem, tile) item of
@@ -838,6 +852,20 @@ template <int K, typename T>
 static hipError_t launch_fused_k(int mode, const IterArgs<T> &a, hipStream_t s)
 {
     dim3 grid((unsigned)a.L.ntiles), block(Cfg<K>::WG);
+    if (mode & MODE_GLL) {
+        if constexpr (!std::is_same<T, double>::value) {
+            return hipErrorInvalidValue; /* FP64 only */
+        } else {
+            mode &= ~MODE_GLL;
+            if (mode == MODE_CG)
+                hipLaunchKernelGGL((fused_tile_kernel<K, T, MODE_CG, true>), grid, block, 0, s, a);
+            else if (mode == MODE_CG_NOPREC)
+                hipLaunchKernelGGL((fused_tile_kernel<K, T, MODE_CG_NOPREC, true>), grid, block, 0, s, a);
+            else
+                hipLaunchKernelGGL((fused_tile_kernel<K, T, MODE_VMULT, true>), grid, block, 0, s, a);
+            return hipGetLastError();
+        }
+    }
     if (mode == MODE_CG) {
         hipLaunchKernelGGL((fused_tile_kernel<K, T, MODE_CG>), grid, block, 0, s, a);
     } else if (mode == MODE_CG_NOPREC) {

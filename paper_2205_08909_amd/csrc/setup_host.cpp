@@ -93,13 +93,26 @@ static long double lagrange_value(int n, const long double *x, int i, long doubl
     return v;
 }
 
-int build_tables(int K, Tables<double> &tab)
+int build_tables(int K, Tables<double> &tab, bool gll_quadrature)
 {
     if (K < 1 || K + 1 > MAXN) return -1;
     const int n = K + 1;
     long double xg[MAXN], wg[MAXN], xl[MAXN], bw[MAXN];
     gauss_points(n, xg, wg);
     lobatto_points(K, xl);
+    if (gll_quadrature) {
+        /* quadrature on the nodes: weights 2 / (k (k+1) P_k(t_i)^2) on
+         * [-1,1], halved for [0,1]; P_k(+-1) = (+-1)^k */
+        for (int i = 0; i <= K; ++i) {
+            long double p = 1.0L, dp = 0.0L;
+            if (i == 0)
+                p = (K & 1) ? -1.0L : 1.0L;
+            else if (i < K)
+                legendre_ld(K, 2.0L * xl[i] - 1.0L, p, dp);
+            xg[i] = xl[i];
+            wg[i] = 1.0L / ((long double)K * (K + 1) * p * p);
+        }
+    }
     bary_weights(n, xg, bw);
     long double S[MAXN * MAXN], D[MAXN * MAXN];
     for (int q = 0; q < n; ++q)

@@ -24,7 +24,9 @@ struct HostLayout {
     std::vector<TileDesc> tiles;
 };
 
-int build_tables(int K, Tables<double> &tab);
+/* Gauss points (default) or, with gll_quadrature, the GLL nodes themselves
+ * as quadrature points (S = identity). */
+int build_tables(int K, Tables<double> &tab, bool gll_quadrature = false);
 void default_tile(int K, int tile[3]);
 int build_layout(const int ncells[3], int K, const int tile[3], int bc, HostLayout &L);
 void dim_locate_host(const Dim1 &d, int64_t g, int64_t &e, int64_t &l, int64_t &len);

@@ -64,13 +64,16 @@ struct Tab {
     double gll[NP];
 };
 
-template <int NP>
+/* GLLQ = false: quadrature on the NP Gauss points; true: on the NP GLL
+ * points themselves (collocation: S is the identity, D the nodal
+ * differentiation matrix). */
+template <int NP, bool GLLQ = false>
 constexpr Tab<NP> make_tab()
 {
     Tab<NP> t{};
     constexpr int n = NP, k = NP - 1;
     /* Gauss points on [0,1], ascending */
-    for (int i = 0; i < n; ++i) {
+    for (int i = 0; i < n && !GLLQ; ++i) {
         double x = -ccos(PI * (i + 0.75) / (n + 0.5));
         for (int it = 0; it < 100; ++it) {
             double p = 0, dp = 0;
@@ -96,6 +99,8 @@ constexpr Tab<NP> make_tab()
         }
         t.gll[i] = 0.5 * (1.0 + x);
     }
+    if (GLLQ)
+        for (int i = 0; i < n; ++i) t.xq[i] = t.gll[i];
     /* S[q][i] = phi_i(xq_q) */
     for (int q = 0; q < n; ++q)
         for (int i = 0; i < n; ++i) {
