@@ -251,6 +251,7 @@ typedef struct {
     double amp;
     int bc;         /* 0: Dirichlet on the whole boundary, 1: none */
     const double *coeff; /* per cell, index cx + nx*(cy + ny*cz); NULL -> 1 */
+    int op;         /* 0: Laplacian (Eq. 5), 1: mass matrix */
 } om_mesh;
 
 static int64_t lat(const om_mesh *m, int d) { return (int64_t)m->n[d] * m->k + 1; }
@@ -323,6 +324,7 @@ static void tab_free(om_tab *t)
 
 /* Element matrix of Eq. 5 by brute force:
  *   (A_e)_ij = a_e sum_q w_q det J_q (J_q^{-T} grad phi_i) . (J_q^{-T} grad phi_j)
+ * or, for the mass operator, a_e sum_q w_q det J_q phi_i phi_j.
  * Local index i = ix + np*(iy + np*iz).  Ae has nb*nb entries. */
 static int element_matrix(const om_mesh *m, const om_tab *t, const int c[3],
                           double *Ae, double *grad /* 3*nb scratch */)
@@ -342,6 +344,15 @@ static int element_matrix(const om_mesh *m, const om_tab *t, const int c[3],
                 if (!(det > 0.0)) return -5;
                 inv3(J, det, Ji);
                 double wdet = ae * t->wq[qx] * t->wq[qy] * t->wq[qz] * det;
+                if (m->op == 1) {
+                    for (int i = 0; i < nb; ++i) {
+                        const int ix = i % np, iy = (i / np) % np, iz = i / (np * np);
+                        grad[i] = t->phi[qx * np + ix] * t->phi[qy * np + iy] * t->phi[qz * np + iz];
+                    }
+                    for (int i = 0; i < nb; ++i)
+                        for (int j = 0; j < nb; ++j) Ae[i * nb + j] += wdet * grad[i] * grad[j];
+                    continue;
+                }
                 for (int iz = 0; iz < np; ++iz)
                     for (int iy = 0; iy < np; ++iy)
                         for (int ix = 0; ix < np; ++ix) {
@@ -375,13 +386,14 @@ static int mesh_check(const om_mesh *m)
 {
     const int nq = m->nq1 > 0 ? m->nq1 : -m->nq1;
     if (m->k < 1 || m->k > 16 || nq < 1 || nq > 32 || (m->nq1 < 0 && nq < 2)) return -1;
+    if (m->op != 0 && m->op != 1) return -1;
     for (int d = 0; d < 3; ++d)
         if (m->n[d] < 1) return -1;
     return 0;
 }
 
-#define OM_MESH_ARGS const int *ncells, int k, int nq1, int map_kind, double amp, int bc, const double *coeff
-#define OM_MESH_INIT {{ncells[0], ncells[1], ncells[2]}, k, nq1, map_kind, amp, bc, coeff}
+#define OM_MESH_ARGS const int *ncells, int k, int nq1, int map_kind, double amp, int bc, const double *coeff, int op
+#define OM_MESH_INIT {{ncells[0], ncells[1], ncells[2]}, k, nq1, map_kind, amp, bc, coeff, op}
 
 int64_t oracle_n_nodes(const int *ncells, int k)
 {
@@ -656,6 +668,7 @@ int oracle_apply_rows(OM_MESH_ARGS, const double *u, int64_t nrows, const int64_
 {
     om_mesh m = OM_MESH_INIT;
     if (mesh_check(&m)) return -1;
+    if (m.op != 0) return -3; /* Laplacian rows only */
     om_tab t;
     if (tab_init(&t, k, nq1)) return -2;
     int np = k + 1, nb = np * np * np, nq = t.nq;

@@ -66,7 +66,7 @@ def _declare(L):
     L.oracle_map.argtypes = [_I, _D, _P, _P]
     L.oracle_map_det.argtypes = [_I, _D, _P]
     L.oracle_map_det.restype = _D
-    mesh = [_P, _I, _I, _I, _D, _I, _P]
+    mesh = [_P, _I, _I, _I, _D, _I, _P, _I]
     L.oracle_n_nodes.argtypes = [_P, _I]
     L.oracle_n_nodes.restype = _I64
     L.oracle_element_matrix.argtypes = mesh + [_P, _P]
@@ -136,10 +136,13 @@ class Mesh:
     Cell numbering: c = cx + n0 (cy + n1 cz)."""
 
     def __init__(self, ncells, k, nq1=None, map_kind=MAP_AFFINE, amp=0.0, bc=BC_DIRICHLET, coeff=None,
-                 quad="gauss"):
+                 quad="gauss", op="laplace"):
         """quad: "gauss" (Gauss-Legendre, nq1 points, default k+1) or "gll"
         (Gauss-Lobatto-Legendre on nq1 points, default k+1: collocation at
-        the nodes)."""
+        the nodes); op: "laplace" (Eq. 5) or "mass" (a_e w_q det J phi_i
+        phi_j)."""
+        assert op in ("laplace", "mass")
+        self.op = 0 if op == "laplace" else 1
         if np.isscalar(ncells):
             ncells = (ncells, ncells, ncells)
         self.ncells = np.ascontiguousarray(ncells, dtype=np.int32)
@@ -164,7 +167,7 @@ class Mesh:
         return int(lib().oracle_n_nodes(_ptr(self.ncells), self.k))
 
     def args(self):
-        return [_ptr(self.ncells), self.k, self.nq1, self.map_kind, self.amp, self.bc, _ptr(self.coeff)]
+        return [_ptr(self.ncells), self.k, self.nq1, self.map_kind, self.amp, self.bc, _ptr(self.coeff), self.op]
 
     def constrained_mask(self):
         L = self.lattice

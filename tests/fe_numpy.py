@@ -136,6 +136,34 @@ def fd_jacobian(kind, amp, X, h=1e-6):
     return J
 
 
+def kronecker_mass(k, ncells, lumped=False):
+    """Mass matrix Mz(x)My(x)Mx of the affine unit cube."""
+    nx, ny, nz = ncells
+    _, Mx = global_1d(k, nx, 1.0 / nx, lumped)
+    _, My = global_1d(k, ny, 1.0 / ny, lumped)
+    _, Mz = global_1d(k, nz, 1.0 / nz, lumped)
+    return np.kron(Mz, np.kron(My, Mx))
+
+
+def element_mass_fd(k, ncells, cell, kind, amp, a_e=1.0):
+    """Element mass matrix with numpy's (k+1)-point Gauss rule and an FD
+    Jacobian determinant."""
+    nodes = gll_nodes(k)
+    xq, wq = gauss_rule(k + 1)
+    val, _ = basis_1d(nodes, xq)
+    n = k + 1
+    ncells = np.asarray(ncells, dtype=np.float64)
+    A = np.zeros((n ** 3, n ** 3))
+    for qz in range(n):
+        for qy in range(n):
+            for qx in range(n):
+                X = (np.asarray(cell) + np.array([xq[qx], xq[qy], xq[qz]])) / ncells
+                det = np.linalg.det(fd_jacobian(kind, amp, X) / ncells[None, :])
+                phi = np.einsum("k,j,i->kji", val[qz], val[qy], val[qx]).ravel()
+                A += a_e * wq[qx] * wq[qy] * wq[qz] * det * np.outer(phi, phi)
+    return A
+
+
 def element_matrix_fd(k, nq1, ncells, cell, kind, amp, a_e=1.0, quad="gauss"):
     """Element stiffness matrix with numpy's rules and an FD Jacobian
     (quad "gll": the k+1 nodes with the basis integrals as weights)."""

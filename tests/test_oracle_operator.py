@@ -7,6 +7,8 @@
   the assembled matrix is symmetric, positive definite on the free nodes
   and annihilates constants without boundary conditions,
 * the diagonal equals the Kronecker closed form on affine meshes,
+* the mass operator (BP1): the affine Kronecker product of 1D masses (lumped
+  under GLL), total mass 1, curved element matrices against the FD build,
 * with GLL collocation (quadrature at the k+1 nodes, BP5): the affine matrix
   is the Kronecker sum with the diagonal (lumped) 1D mass of the basis
   integrals, and curved element matrices match the FD-Jacobian build.
@@ -50,6 +52,33 @@ def test_element_matrix_fd_jacobian_gll(oracle_mod, kind, amp, k):
     for cell in [(0, 0, 0), (1, 2, 1)]:
         A = O.element_matrix(m, cell)
         ref = fe_numpy.element_matrix_fd(k, 0, ncells, cell, kind, amp, quad="gll")
+        assert np.abs(A - ref).max() <= 1e-8 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("k,ncells,quad", [(1, (2, 3, 2), "gauss"), (3, (2, 1, 2), "gauss"), (4, (1, 2, 1), "gauss"),
+                                           (2, (2, 2, 3), "gll"), (5, (1, 1, 2), "gll")])
+def test_mass_kronecker_closed_form(oracle_mod, k, ncells, quad):
+    """The mass operator (BP1): (k+1)-point Gauss integrates the affine mass
+    exactly (degree 2k per direction); GLL collocation gives the lumped mass."""
+    O = oracle_mod
+    m = O.Mesh(ncells, k, bc=O.BC_NONE, quad=quad, op="mass")
+    A = O.assemble(m).to_scipy().toarray()
+    ref = fe_numpy.kronecker_mass(k, ncells, lumped=(quad == "gll"))
+    assert np.abs(A - ref).max() <= 1e-14 * np.abs(ref).max() + 1e-17
+    # total mass = volume of the unit cube
+    assert A.sum() == pytest.approx(1.0, rel=1e-13)
+
+
+@pytest.mark.parametrize("kind,amp,k", [(1, 0.05, 2), (2, 0.05, 3)])
+def test_mass_element_fd_jacobian(oracle_mod, kind, amp, k):
+    O = oracle_mod
+    ncells = (2, 3, 2)
+    coeff = np.linspace(0.5, 2.0, 12)
+    m = O.Mesh(ncells, k, map_kind=kind, amp=amp, coeff=coeff, op="mass")
+    for cell in [(0, 0, 0), (1, 2, 1)]:
+        A = O.element_matrix(m, cell)
+        ae = coeff[cell[0] + 2 * (cell[1] + 3 * cell[2])]
+        ref = fe_numpy.element_mass_fd(k, ncells, cell, kind, amp, a_e=ae)
         assert np.abs(A - ref).max() <= 1e-8 * np.abs(ref).max()
 
 
