@@ -397,21 +397,38 @@ def main():
         ablation["vector_laplacian_ms"] = round(vms, 5)
         ablation["vector_laplacian_GDoF_it_s"] = round(3 * n / vms / 1e6, 3)
         del b3, x3
-        # GLL collocation (quadrature on the nodes, the BP5 variation): fused CG on its own handle
-        Pg = mfcg.Problem(N, k, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05, tile=args.tile, quad=mfcg.QUAD_GLL)
-        bg = Pg.rhs(mfcg.RHS_SINE)
-        xg = torch.zeros_like(bg)
-        Pg.cg_begin(bg, None, tol=0.0, maxit=W + K)
-        Pg.cg_iterate(W)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        Pg.cg_iterate(K)
-        torch.cuda.synchronize()
-        ablation["gll_collocation_ms"] = round((time.perf_counter() - t0) * 1e3 / K, 5)
-        code_g, its_g, _ = Pg.cg_end(xg)
-        assert its_g == W + K, (code_g, its_g)
-        Pg.close()
-        del bg, xg
+        # the operator variations of the paper's benchmark list, fused CG on handles of their own:
+        # GLL collocation (quadrature on the nodes, BP5) and the mass operator (BP1; BP2 = three
+        # components through the vector solve)
+        for name, extra in (("gll_collocation_ms", {"quad": mfcg.QUAD_GLL}), ("mass_bp1_ms", {"op": mfcg.OP_MASS})):
+            Pg = mfcg.Problem(N, k, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05, tile=args.tile, **extra)
+            bg = Pg.rhs(mfcg.RHS_SINE)
+            xg = torch.zeros_like(bg)
+            Pg.cg_begin(bg, None, tol=0.0, maxit=W + K)
+            Pg.cg_iterate(W)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Pg.cg_iterate(K)
+            torch.cuda.synchronize()
+            ablation[name] = round((time.perf_counter() - t0) * 1e3 / K, 5)
+            code_g, its_g, _ = Pg.cg_end(xg)
+            assert its_g == W + K, (name, code_g, its_g)
+            if "op" in extra:
+                b3 = torch.cat([bg, bg, bg])
+                x3 = torch.zeros_like(b3)
+                tv = []
+                for its_v in (W, W + K):
+                    x3.zero_()
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    _, got, _, _ = Pg.solve_vector(b3, x3, tol=0.0, maxit=its_v, want_hist=False, raise_on=False)
+                    torch.cuda.synchronize()
+                    tv.append(time.perf_counter() - t0)
+                    assert got == its_v
+                ablation["mass_bp2_vector_ms"] = round((tv[1] - tv[0]) * 1e3 / K, 5)
+                del b3, x3
+            Pg.close()
+            del bg, xg
         ablation["speedup_vs_3pass"] = round(ablation["alg5_3pass_ms"] / ms_per_step, 3)
         ablation["speedup_vs_basic"] = round(ablation["basic_pcg_ms"] / ms_per_step, 3)
         print(f"[bench] ablation {ablation}", file=sys.stderr, flush=True)

@@ -99,6 +99,14 @@ enum {
                           * not with fp32 / mfcg_solve_ir, not in a batch */
 };
 
+/* Operator (Sec. 6's benchmark variations). */
+enum {
+    MFCG_OP_LAPLACE = 0, /* a_e grad u . grad v, Eq. 5 (default) */
+    MFCG_OP_MASS = 1     /* a_e u v: the mass matrix of BP1 (scalar) and, through
+                          * mfcg_solve_vector, BP2 (vector); Gauss points, FP64 only: not with
+                          * fp32 / mfcg_solve_ir, not in a batch */
+};
+
 /* Options.  Zero-initialised fields select the defaults. */
 typedef struct {
     int32_t n_q_1d;          /* quadrature points per direction; 0: k+1 (only k+1 is supported) */
@@ -106,6 +114,7 @@ typedef struct {
     int32_t check_every;     /* iterations between host polls of the convergence flag; 0: 16 */
     int32_t fp32;            /* 1: build the FP32 operator copy of mfcg_solve_ir at set-up (else on first use) */
     int32_t quad_rule;       /* MFCG_QUAD_* */
+    int32_t op;              /* MFCG_OP_* */
 } mfcg_options;
 
 /* Builds the operator (Sec. 2, Eq. 3-5): tiles and DoF enumeration of the

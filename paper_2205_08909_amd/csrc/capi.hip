@@ -36,6 +36,7 @@ struct mfcg_ctx {
     int sstep = 6;
     int precond = MFCG_PRECOND_JACOBI;
     bool gll = false; /* quadrature on the GLL nodes (collocation) */
+    bool mass = false; /* the mass operator instead of the Laplacian */
     /* solver, preconditioner and s fixed by cg_begin for the solve in progress */
     int solver_active = MFCG_SOLVER_FUSED;
     int sstep_active = 6;
@@ -182,7 +183,8 @@ static int validate_mesh(const mfcg_mesh *mesh, int32_t degree, const int32_t *t
 }
 
 /* vmult on internal vectors: dst = A src */
-static int gll_flag(const mfcg_ctx *h) { return h->gll ? MODE_GLL : 0; }
+/* operator-variant flags for launch_fused */
+static int gll_flag(const mfcg_ctx *h) { return (h->gll ? MODE_GLL : 0) | (h->mass ? MODE_MASS : 0); }
 
 static int vmult_internal(mfcg_ctx *h, const double *src, double *dst, hipStream_t s)
 {
@@ -241,6 +243,7 @@ static int rebuild_operator(mfcg_ctx *h, hipStream_t s)
     g.amp = h->mesh.map_kind == MFCG_MAP_AFFINE ? 0.0 : h->mesh.map_amplitude;
     g.bc = h->mesh.bc;
     g.coeff = h->d_coeff;
+    g.op = h->mass ? 1 : 0;
     HIPCHK(h, launch_geometry(g, h->G, s));
     HIPCHK(h, launch_diagonal(g, h->G, h->diag_lex, h->dinv, s));
     if (h->G32) {
@@ -304,6 +307,10 @@ int mfcg_setup(const mfcg_mesh *mesh, int32_t degree, const double *cell_coeff, 
         return fail(nullptr, MFCG_EINVAL, "unknown quad_rule");
     if (opt && opt->quad_rule == MFCG_QUAD_GLL && opt->fp32)
         return fail(nullptr, MFCG_EINVAL, "the FP32 operator is built for Gauss quadrature only");
+    if (opt && opt->op != MFCG_OP_LAPLACE && opt->op != MFCG_OP_MASS)
+        return fail(nullptr, MFCG_EINVAL, "unknown operator");
+    if (opt && opt->op == MFCG_OP_MASS && (opt->quad_rule != MFCG_QUAD_GAUSS || opt->fp32))
+        return fail(nullptr, MFCG_EINVAL, "the mass operator runs in FP64 on the Gauss points only");
     const int64_t ncell = (int64_t)mesh->cells[0] * mesh->cells[1] * mesh->cells[2];
     if (cell_coeff) {
         for (int64_t c = 0; c < ncell; ++c)
@@ -317,6 +324,7 @@ int mfcg_setup(const mfcg_mesh *mesh, int32_t degree, const double *cell_coeff, 
     h->K = degree;
     if (opt && opt->check_every > 0) h->check_every = opt->check_every;
     h->gll = opt && opt->quad_rule == MFCG_QUAD_GLL;
+    h->mass = opt && opt->op == MFCG_OP_MASS;
     hipStream_t s = (hipStream_t)hip_stream;
 
     auto bail = [&](int code) {
@@ -1028,7 +1036,7 @@ int mfcg_solve(mfcg_handle h, const double *b, double *x, double tol, int32_t ma
 static int ensure_fp32(mfcg_ctx *h, hipStream_t s)
 {
     if (h->G32) return MFCG_OK;
-    if (h->gll) return fail(h, MFCG_EINVAL, "the FP32 operator is built for Gauss quadrature only");
+    if (h->gll || h->mass) return fail(h, MFCG_EINVAL, "the FP32 operator is built for the Gauss-point Laplacian only");
     const HostLayout &L = h->hl;
     HIPCHK(h, dalloc(&h->G32, L.g_elems));
     HIPCHK(h, dalloc(&h->dinv32, L.n));
@@ -1120,7 +1128,7 @@ int mfcg_solve_ir(mfcg_handle h, const double *b, double *x, double tol, double 
     if (!(tol > 0.0) || !std::isfinite(tol) || !(inner_tol > 0.0) || !(inner_tol < 1.0))
         return fail(h, MFCG_EINVAL, "need tol > 0 and 0 < inner_tol < 1");
     if (max_outer < 1 || max_inner < 1) return fail(h, MFCG_EINVAL, "max_outer and max_inner must be >= 1");
-    if (h->gll) return fail(h, MFCG_EINVAL, "mixed precision runs with Gauss quadrature only");
+    if (h->gll || h->mass) return fail(h, MFCG_EINVAL, "mixed precision runs the Gauss-point Laplacian only");
     hipStream_t s = (hipStream_t)hip_stream;
     int rc = ensure_fp32(h, s);
     if (rc) return rc;
@@ -1430,7 +1438,7 @@ int mfcg_batch_solve(mfcg_batch hb, const double *const *b, double *const *x, do
         if (!b[i] || !x[i]) return batch_fail(hb, MFCG_EINVAL, "null vector of problem " + std::to_string(i));
     hipStream_t s = (hipStream_t)hip_stream;
     for (int i = 0; i < np; ++i)
-        if (hb->probs[i]->solver != MFCG_SOLVER_FUSED || hb->probs[i]->gll)
+        if (hb->probs[i]->solver != MFCG_SOLVER_FUSED || hb->probs[i]->gll || hb->probs[i]->mass)
             return batch_fail(hb, MFCG_EINVAL,
                               "problem " + std::to_string(i) + ": the batch runs the fused Gauss-quadrature solver only");
     /* every problem starts as mfcg_solve would start it */

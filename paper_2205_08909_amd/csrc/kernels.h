@@ -15,6 +15,8 @@ constexpr bool mode_is_cg(int m) { return m != MODE_VMULT; }
 /* or-ed into the mode argument of launch_fused (FP64 only): quadrature on
  * the GLL nodes (collocation) instead of the Gauss points */
 constexpr int MODE_GLL = 8;
+/* or-ed likewise: the mass operator (Gauss points; FP64 only) */
+constexpr int MODE_MASS = 16;
 
 /* Arguments of the fused tile kernel and the shared-node kernel. */
 template <typename T>
@@ -69,6 +71,7 @@ struct GeomArgs {
     double amp;
     int32_t bc;
     const double *coeff; /* per cell, device */
+    int32_t op;          /* 0: Laplacian (6-component tensor), 1: mass (component 0: a_e w_q det J_q) */
 };
 hipError_t launch_geometry(const GeomArgs &g, double *G, hipStream_t s);
 hipError_t launch_diagonal(const GeomArgs &g, const double *G, double *diag_lex, double *dinv_int, hipStream_t s);

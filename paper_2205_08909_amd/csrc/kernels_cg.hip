@@ -138,13 +138,20 @@ struct FastDiv {
 /* Fused tile kernel                                                   */
 /* ------------------------------------------------------------------ */
 
+/* Operator variants of the fused kernel: the Laplacian on the Gauss points
+ * (default), the Laplacian with quadrature on the GLL nodes (collocation:
+ * the interpolation passes are the identity and are skipped), and the mass
+ * operator on the Gauss points (no derivative passes; component 0 of the
+ * stored tensor holds a_e w_q det J_q). */
+enum OpVariant : int { OPV_LAPLACE = 0, OPV_LAPLACE_GLL = 1, OPV_MASS = 2 };
+
 /* One tile of one problem: the pre / cell / sum / post passes over the
- * tile's cell layers (called by one whole workgroup).  GLLQ: quadrature on
- * the GLL nodes (collocation), where the interpolation passes are the
- * identity and are skipped. */
-template <int K, typename T, int MODE, bool GLLQ = false>
+ * tile's cell layers (called by one whole workgroup). */
+template <int K, typename T, int MODE, int OPV = OPV_LAPLACE>
 __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t tile)
 {
+    constexpr bool GLLQ = OPV == OPV_LAPLACE_GLL, MASS = OPV == OPV_MASS;
+    constexpr int NG = MASS ? 1 : 6; /* tensor components read */
     constexpr int n = K + 1, n2 = n * n, n3 = n * n * n;
     constexpr int WG = Cfg<K>::WG;
     constexpr int NLC = Cfg<K>::TX * Cfg<K>::TY;
@@ -328,7 +335,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
 #pragma unroll
                 for (int j = 0; j < n; ++j)
 #pragma unroll
-                    for (int c = 0; c < 6; ++c) gp[rr][c][j] = (l < nlines) ? Gl[c * gcomp + j * gq + l] : (T)0;
+                    for (int c = 0; c < NG; ++c) gp[rr][c][j] = (l < nlines) ? Gl[c * gcomp + j * gq + l] : (T)0;
             }
         }
         /* ---- pre on the planes this layer touches first ---- */
@@ -423,7 +430,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
                     }
                 }
 #pragma unroll
-                for (int q = 0; q < n; ++q) {
+                for (int q = 0; q < n && !MASS; ++q) {
                     T t = 0;
 #pragma unroll
                     for (int m = 0; m < n; ++m) t = fma(cD(q, m), uq[m], t);
@@ -442,12 +449,12 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
 #pragma unroll
                 for (int j = 0; j < n; ++j)
 #pragma unroll
-                    for (int c = 0; c < 6; ++c) gp[rr][c][j] = (l < nlines) ? Gl[c * gcomp + j * gq + l] : (T)0;
+                    for (int c = 0; c < NG; ++c) gp[rr][c][j] = (l < nlines) ? Gl[c * gcomp + j * gq + l] : (T)0;
             }
         }
         /* F4 [x-lines]: x derivative */
 #pragma unroll
-        for (int rr = 0; rr < R; ++rr) {
+        for (int rr = 0; rr < R && !MASS; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlines) {
                 const int c = l / n2, rem = l % n2;
@@ -468,7 +475,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         asm volatile("" : "+v"(tid));
         /* F5 [z-lines]: z derivative, in place */
 #pragma unroll
-        for (int rr = 0; rr < R; ++rr) {
+        for (int rr = 0; rr < R && !MASS; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlines) {
                 const int c = l / n2, rem = l % n2;
@@ -488,9 +495,23 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         __syncthreads();
         asm volatile("" : "+v"(tid));
         /* G [y-lines]: flux = G_q grad u at each Gauss point; y part of the
-         * transposed derivative in registers */
+         * transposed derivative in registers.  Mass operator: the values
+         * scaled by a_e w_q det J_q, into TB. */
 #pragma unroll
-        for (int rr = 0; rr < R; ++rr) {
+        for (int rr = 0; rr < R && MASS; ++rr) {
+            const int l = tid + WG * rr;
+            if (l < nlines) {
+                const int c = l / n2, rem = l % n2, i = rem % n, z = rem / n;
+                const int base = c * n3 + i + n2 * z;
+#pragma unroll
+                for (int j = 0; j < n; ++j) {
+                    if (!MFCG_GPREF_OF(K)) gp[rr][0][j] = Gl[j * gq + l];
+                    TB[base + n * j] = gp[rr][0][j] * TA[base + n * j];
+                }
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < R && !MASS; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlines) {
                 const int c = l / n2, rem = l % n2, i = rem % n, z = rem / n;
@@ -523,7 +544,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         /* B2 [x-lines]: transposed x derivative, in place; B3 [z-lines]:
          * transposed z derivative into registers */
 #pragma unroll
-        for (int rr = 0; rr < R; ++rr) {
+        for (int rr = 0; rr < R && !MASS; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlines) {
                 const int c = l / n2, rem = l % n2;
@@ -559,7 +580,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         asm volatile("" : "+v"(tid));
         /* B4 [y-lines]: add the y part */
 #pragma unroll
-        for (int rr = 0; rr < R; ++rr) {
+        for (int rr = 0; rr < R && !MASS; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlines) {
                 const int c = l / n2, rem = l % n2, i = rem % n, z = rem / n;
@@ -579,7 +600,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
                 const int base = c * n3 + rem;
                 T w[n];
 #pragma unroll
-                for (int q = 0; q < n; ++q) w[q] = TB[base + n2 * q] + wz[rr][q];
+                for (int q = 0; q < n; ++q) w[q] = MASS ? TB[base + n2 * q] : TB[base + n2 * q] + wz[rr][q];
 #pragma unroll
                 for (int z = 0; z < n; ++z) {
                     T t = 0;
@@ -674,13 +695,13 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
     if (mode_is_cg(MODE)) block_reduce<T, 7, WG>(acc, red, a.dots + tile * 8);
 }
 
-template <int K, typename T, int MODE, bool GLLQ = false>
+template <int K, typename T, int MODE, int OPV = OPV_LAPLACE>
 __global__ __launch_bounds__(Cfg<K>::WG)
 __attribute__((amdgpu_waves_per_eu(MFCG_WPE_MIN(K), 8)))
 void fused_tile_kernel(const IterArgs<T> a)
 {
     if (mode_is_cg(MODE) && a.st->flag != FLAG_RUN) return;
-    fused_tile<K, T, MODE, GLLQ>(a, xcd_remap(blockIdx.x, gridDim.x));
+    fused_tile<K, T, MODE, OPV>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 /* Batch of problems of degree K: one workgroup per (problem, tile) item of
@@ -852,17 +873,29 @@ template <int K, typename T>
 static hipError_t launch_fused_k(int mode, const IterArgs<T> &a, hipStream_t s)
 {
     dim3 grid((unsigned)a.L.ntiles), block(Cfg<K>::WG);
-    if (mode & MODE_GLL) {
+    if (mode & (MODE_GLL | MODE_MASS)) {
         if constexpr (!std::is_same<T, double>::value) {
             return hipErrorInvalidValue; /* FP64 only */
         } else {
-            mode &= ~MODE_GLL;
-            if (mode == MODE_CG)
-                hipLaunchKernelGGL((fused_tile_kernel<K, T, MODE_CG, true>), grid, block, 0, s, a);
-            else if (mode == MODE_CG_NOPREC)
-                hipLaunchKernelGGL((fused_tile_kernel<K, T, MODE_CG_NOPREC, true>), grid, block, 0, s, a);
-            else
-                hipLaunchKernelGGL((fused_tile_kernel<K, T, MODE_VMULT, true>), grid, block, 0, s, a);
+            const bool mass = mode & MODE_MASS;
+            if ((mode & MODE_GLL) && mass) return hipErrorInvalidValue;
+            mode &= ~(MODE_GLL | MODE_MASS);
+            if (mass) {
+                if (mode == MODE_CG)
+                    hipLaunchKernelGGL((fused_tile_kernel<K, T, MODE_CG, OPV_MASS>), grid, block, 0, s, a);
+                else if (mode == MODE_CG_NOPREC)
+                    hipLaunchKernelGGL((fused_tile_kernel<K, T, MODE_CG_NOPREC, OPV_MASS>), grid, block, 0, s, a);
+                else
+                    hipLaunchKernelGGL((fused_tile_kernel<K, T, MODE_VMULT, OPV_MASS>), grid, block, 0, s, a);
+            } else {
+                if (mode == MODE_CG)
+                    hipLaunchKernelGGL((fused_tile_kernel<K, T, MODE_CG, OPV_LAPLACE_GLL>), grid, block, 0, s, a);
+                else if (mode == MODE_CG_NOPREC)
+                    hipLaunchKernelGGL((fused_tile_kernel<K, T, MODE_CG_NOPREC, OPV_LAPLACE_GLL>), grid, block, 0, s,
+                                       a);
+                else
+                    hipLaunchKernelGGL((fused_tile_kernel<K, T, MODE_VMULT, OPV_LAPLACE_GLL>), grid, block, 0, s, a);
+            }
             return hipGetLastError();
         }
     }

@@ -119,6 +119,11 @@ __global__ __launch_bounds__(SETUP_WG) void geometry_kernel(const GeomArgs g, do
     auto m = [&](int p, int r) { return w * (Ji[p][0] * Ji[r][0] + Ji[p][1] * Ji[r][1] + Ji[p][2] * Ji[r][2]); };
     int64_t cs;
     const int64_t o = g_offset(g.L, K, c, qx, qy, qz, cs);
+    if (g.op == 1) { /* mass operator: a_e w_q det J_q */
+        G[o] = w;
+        for (int comp = 1; comp < 6; ++comp) G[o + comp * cs] = 0.0;
+        return;
+    }
     G[o] = m(0, 0);
     G[o + cs] = m(1, 1);
     G[o + 2 * cs] = m(2, 2);
@@ -234,6 +239,12 @@ __global__ __launch_bounds__(SETUP_WG) void diagonal_kernel(const GeomArgs g, co
                                 const double gz = g.tab.S[qx * n + ix] * g.tab.S[qy * n + iy] * g.tab.Sd[qz * n + iz];
                                 int64_t cs;
                                 const int64_t o = g_offset(L, K, c, qx, qy, qz, cs);
+                                if (g.op == 1) { /* mass: sum_q a_e w_q det J_q phi_i^2 */
+                                    const double phi =
+                                        g.tab.S[qx * n + ix] * g.tab.S[qy * n + iy] * g.tab.S[qz * n + iz];
+                                    dsum += G[o] * phi * phi;
+                                    continue;
+                                }
                                 const double g00 = G[o], g11 = G[o + cs], g22 = G[o + 2 * cs], g01 = G[o + 3 * cs],
                                              g02 = G[o + 4 * cs], g12 = G[o + 5 * cs];
                                 dsum += g00 * gx * gx + g11 * gy * gy + g22 * gz * gz +
