@@ -196,11 +196,14 @@ int mfcg_solve(mfcg_handle h, const double *b, double *x, double tol, int32_t ma
  * BP4): three uncoupled components u = (u_x, u_y, u_z), each with the
  * handle's scalar operator, so the system is I_3 (x) A with the one scalar
  * diagonal applied to all components (Sec. 3), I_3 (x) diag(A), and it is
- * solved by one CG (Algorithm 5;
- * every inner product runs over all 3n entries).  Each iteration applies
- * the fused kernels once per component and one finish over the three
- * components' inner-product records.  The quadrature stays the handle's
- * (k+1)^3 Gauss points.
+ * solved by one CG (Algorithm 5; every inner product runs over all 3n
+ * entries).  Each iteration is one launch of the fused tile kernel over
+ * (tile, component) pairs -- a tile's three components run side by side,
+ * so the geometry tensor they share is read from HBM about once -- the
+ * shared-node kernel per component and one finish over all components'
+ * inner-product records.  The operator is the handle's: the Laplacian on
+ * (k+1)^3 Gauss points (BP4 with the configured quadrature), GLL
+ * collocation, or the mass operator (BP2).
  *   b, x   device vectors of 3n doubles, component-blocked: entries
  *          [c*n, (c+1)*n) hold component c in lexicographic node order;
  *          x holds x_0 on entry and the solution on return

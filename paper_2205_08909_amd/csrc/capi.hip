@@ -62,7 +62,7 @@ struct mfcg_ctx {
     double *kpart = nullptr;
     KrylovState *ks = nullptr;
     /* three-component work vectors of the vector Laplacian (component-blocked) */
-    double *r3 = nullptr, *p3 = nullptr, *v3 = nullptr, *x3 = nullptr, *dots3 = nullptr;
+    double *r3 = nullptr, *p3 = nullptr, *v3 = nullptr, *x3 = nullptr, *dots3 = nullptr, *part3 = nullptr;
     int nshared_blocks = 1;
     int nsum_blocks = 1;
     /* solve bookkeeping */
@@ -116,7 +116,7 @@ static void release(mfcg_ctx *h)
                     h->dots,       h->sums,       h->hist,    h->st,      h->G32,   h->dinv32, h->r32,
                     h->p32,        h->v32,        h->x32,     h->part32,  h->dots32, h->st32,  h->hist32,
                     h->kvec,       h->kpart,      h->ks,      h->r3,      h->p3,    h->v3,     h->x3,
-                    h->dots3};
+                    h->dots3,      h->part3};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (auto &e : h->ev_pool) {
@@ -878,10 +878,11 @@ int mfcg_cg_end(mfcg_handle h, double *x, int32_t *iters, double *res_hist, void
     return fail(h, MFCG_ENOTCONV, "maxit reached");
 }
 
-/* Vector Laplacian (three uncoupled components sharing the operator, the
- * diagonal and the CG scalars): each iteration runs the fused tile kernel and
- * the shared-node kernel once per component, each component writing its own
- * block of inner-product records, then one finish over all of them. */
+/* Vector problem (three uncoupled components sharing the operator, the
+ * diagonal and the CG scalars): each iteration runs one fused launch over
+ * (tile, component) pairs and the shared-node kernel per component, each
+ * component writing its own block of inner-product records and shared
+ * partial sums, then one finish over all records. */
 int mfcg_solve_vector(mfcg_handle h, const double *b, double *x, double tol, int32_t maxit, int32_t *iters,
                       double *res_hist, double *true_rel_res, void *hip_stream)
 {
@@ -897,6 +898,8 @@ int mfcg_solve_vector(mfcg_handle h, const double *b, double *x, double tol, int
         HIPCHK(h, dalloc(&h->v3, 3 * n));
         HIPCHK(h, dalloc(&h->x3, 3 * n));
         HIPCHK(h, dalloc(&h->dots3, 8 * 3 * nrec));
+        HIPCHK(h, dalloc(&h->part3, 3 * std::max<int64_t>(1, h->hl.npart)));
+        HIPCHK(h, hipMemsetAsync(h->part3, 0, sizeof(double) * 3 * std::max<int64_t>(1, h->hl.npart), s));
     }
     if (maxit > h->hist_cap) {
         HIPCHK(h, hipStreamSynchronize(s));
@@ -947,7 +950,7 @@ int mfcg_solve_vector(mfcg_handle h, const double *b, double *x, double tol, int
         a.p = h->p3 + c * n;
         a.v = h->v3 + c * n;
         a.x = h->x3 + c * n;
-        a.part = h->part;
+        a.part = h->part3 + c * std::max<int64_t>(1, h->hl.npart);
         a.dots = h->dots3 + 8 * c * nrec;
         a.st = h->st;
         a.hist = h->hist;
@@ -959,10 +962,10 @@ int mfcg_solve_vector(mfcg_handle h, const double *b, double *x, double tol, int
     while (st.flag == FLAG_RUN && launched < maxit) {
         const int chunk = std::min(h->check_every, maxit - launched);
         for (int it = 0; it < chunk; ++it) {
-            for (int c = 0; c < 3; ++c) {
-                HIPCHK(h, launch_fused<double>(h->K, MODE_CG | gll_flag(h), ac[c], s));
-                HIPCHK(h, launch_shared_nofinish(ac[c], s));
-            }
+            /* the three components' tiles in one launch (geometry shared in L2) */
+            HIPCHK(h, launch_fused_vec(h->K, MODE_CG | gll_flag(h), ac[0], n, std::max<int64_t>(1, h->hl.npart),
+                                       8 * nrec, s));
+            for (int c = 0; c < 3; ++c) HIPCHK(h, launch_shared_nofinish(ac[c], s));
             HIPCHK(h, launch_finish_parts(ac[0], 3 * nrec, s));
         }
         launched += chunk;

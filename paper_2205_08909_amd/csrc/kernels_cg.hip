@@ -704,6 +704,30 @@ void fused_tile_kernel(const IterArgs<T> a)
     fused_tile<K, T, MODE, OPV>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
+/* Vector problems: one launch over (tile, component) pairs, the component
+ * fastest, so the workgroups of one tile's three components are
+ * dispatched together on one XCD and the geometry tensor they all apply is
+ * fetched from HBM about once and then served from that XCD's L2.
+ * Component c works on the vectors at offset c*nstride, its shared-node
+ * partial sums at c*pstride and its inner-product records at c*dstride. */
+template <int K, int MODE, int OPV>
+__global__ __launch_bounds__(Cfg<K>::WG)
+__attribute__((amdgpu_waves_per_eu(MFCG_WPE_MIN(K), 8)))
+void fused_tile_vec_kernel(const IterArgs<double> a, int64_t nstride, int64_t pstride, int64_t dstride)
+{
+    if (a.st->flag != FLAG_RUN) return;
+    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int c = (int)(lb % 3);
+    IterArgs<double> b = a;
+    b.r += c * nstride;
+    b.p += c * nstride;
+    b.v += c * nstride;
+    b.x += c * nstride;
+    b.part += c * pstride;
+    b.dots += c * dstride;
+    fused_tile<K, double, MODE, OPV>(b, lb / 3);
+}
+
 /* Batch of problems of degree K: one workgroup per (problem, tile) item of
  * the work list; problems that have left the running state are skipped. */
 template <int K, typename T>
@@ -943,6 +967,41 @@ hipError_t launch_shared(int mode, const IterArgs<T> &a, hipStream_t s)
         hipLaunchKernelGGL((shared_node_kernel<T, MODE_VMULT>), grid, block, 0, s, a);
     }
     return hipGetLastError();
+}
+
+template <int K>
+static hipError_t launch_fused_vec_k(int mode, const IterArgs<double> &a, int64_t nstride, int64_t pstride,
+                                     int64_t dstride, hipStream_t s)
+{
+    dim3 grid((unsigned)(3 * a.L.ntiles)), block(Cfg<K>::WG);
+    if (mode == MODE_CG)
+        hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_LAPLACE>), grid, block, 0, s, a, nstride, pstride,
+                           dstride);
+    else if (mode == (MODE_CG | MODE_GLL))
+        hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_LAPLACE_GLL>), grid, block, 0, s, a, nstride, pstride,
+                           dstride);
+    else if (mode == (MODE_CG | MODE_MASS))
+        hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_MASS>), grid, block, 0, s, a, nstride, pstride,
+                           dstride);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_fused_vec(int K, int mode, const IterArgs<double> &a, int64_t nstride, int64_t pstride,
+                            int64_t dstride, hipStream_t s)
+{
+    switch (K) {
+    case 1: return launch_fused_vec_k<1>(mode, a, nstride, pstride, dstride, s);
+    case 2: return launch_fused_vec_k<2>(mode, a, nstride, pstride, dstride, s);
+    case 3: return launch_fused_vec_k<3>(mode, a, nstride, pstride, dstride, s);
+    case 4: return launch_fused_vec_k<4>(mode, a, nstride, pstride, dstride, s);
+    case 5: return launch_fused_vec_k<5>(mode, a, nstride, pstride, dstride, s);
+    case 6: return launch_fused_vec_k<6>(mode, a, nstride, pstride, dstride, s);
+    case 7: return launch_fused_vec_k<7>(mode, a, nstride, pstride, dstride, s);
+    case 8: return launch_fused_vec_k<8>(mode, a, nstride, pstride, dstride, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_shared_nofinish(const IterArgs<double> &a, hipStream_t s)
