@@ -231,6 +231,18 @@ __global__ __launch_bounds__(SETUP_WG) void diagonal_kernel(const GeomArgs g, co
                     const int c[3] = {cx, cy, cz};
                     const int ix = (int)(gc[0] - (int64_t)cx * K), iy = (int)(gc[1] - (int64_t)cy * K),
                               iz = (int)(gc[2] - (int64_t)cz * K);
+                    if (g.op == 1) { /* mass: sum_q a_e w_q det J_q phi_i^2 */
+                        for (int qz = 0; qz < n; ++qz)
+                            for (int qy = 0; qy < n; ++qy)
+                                for (int qx = 0; qx < n; ++qx) {
+                                    int64_t cs;
+                                    const int64_t o = g_offset(L, K, c, qx, qy, qz, cs);
+                                    const double phi =
+                                        g.tab.S[qx * n + ix] * g.tab.S[qy * n + iy] * g.tab.S[qz * n + iz];
+                                    dsum += G[o] * phi * phi;
+                                }
+                        continue;
+                    }
                     for (int qz = 0; qz < n; ++qz)
                         for (int qy = 0; qy < n; ++qy)
                             for (int qx = 0; qx < n; ++qx) {
@@ -239,12 +251,6 @@ __global__ __launch_bounds__(SETUP_WG) void diagonal_kernel(const GeomArgs g, co
                                 const double gz = g.tab.S[qx * n + ix] * g.tab.S[qy * n + iy] * g.tab.Sd[qz * n + iz];
                                 int64_t cs;
                                 const int64_t o = g_offset(L, K, c, qx, qy, qz, cs);
-                                if (g.op == 1) { /* mass: sum_q a_e w_q det J_q phi_i^2 */
-                                    const double phi =
-                                        g.tab.S[qx * n + ix] * g.tab.S[qy * n + iy] * g.tab.S[qz * n + iz];
-                                    dsum += G[o] * phi * phi;
-                                    continue;
-                                }
                                 const double g00 = G[o], g11 = G[o + cs], g22 = G[o + 2 * cs], g01 = G[o + 3 * cs],
                                              g02 = G[o + 4 * cs], g12 = G[o + 5 * cs];
                                 dsum += g00 * gx * gx + g11 * gy * gy + g22 * gz * gz +
