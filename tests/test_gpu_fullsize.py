@@ -1,5 +1,6 @@
 """Parity at the benchmark's full size, in the configuration bench.py times
-(Q4, 64^3 cells of the sine-shear mesh, 16,974,593 DoFs, default tiles).
+(Q4, 64^3 cells of the sine-shear mesh, 16,974,593 DoFs, default tiles),
+and the GLL-collocation operator at the same size.
 
 The oracle cannot assemble this matrix in a test (3.7e9 nonzeros), so it
 evaluates sampled rows of A u cell by cell (oracle_apply_rows): random rows
@@ -76,3 +77,21 @@ def test_fullsize_operator_and_solve(oracle_mod):
     # the sampled residual entries are small on the scale of the whole residual norm
     assert np.max(np.abs(res_rows)) <= 1.5e-10 * np.linalg.norm(bh)
     P.close()
+
+
+def test_fullsize_collocation_operator(oracle_mod):
+    """GLL collocation (BP5) at the same full size: sampled operator rows
+    against the oracle's Gauss-Lobatto rows."""
+    import torch
+    from paper_2205_08909_amd import mfcg
+    P = mfcg.Problem(N, K, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05, quad=mfcg.QUAD_GLL)
+    m = oracle_mod.Mesh(N, K, map_kind=oracle_mod.MAP_SINE_SHEAR, amp=0.05, quad="gll")
+    rows = _rows(P, nsample=1500, seed=1)
+    u = inputs.random_vector(P.n, seed=22)
+    v = P.vmult(P.empty(), torch.from_numpy(u).cuda()).cpu().numpy()
+    ref = oracle_mod.apply_rows(m, u, rows)
+    err = np.max(np.abs(v[rows] - ref)) / np.max(np.abs(ref))
+    print("sampled rows", rows.size, "operator max rel err", err)
+    assert err <= 1e-12
+    P.close()
+
