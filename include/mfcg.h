@@ -208,7 +208,9 @@ int mfcg_solve(mfcg_handle h, const double *b, double *x, double tol, int32_t ma
  *          [c*n, (c+1)*n) hold component c in lexicographic node order;
  *          x holds x_0 on entry and the solution on return
  *   other arguments, the stopping rule and res_hist as for mfcg_solve.
- * Allocates 4 work vectors of 3n doubles at the first call.
+ * Allocates 4 work vectors of 3n doubles at the first call.  Ends a
+ * stepping-interface solve in progress (its state is reused): call
+ * mfcg_cg_begin again before mfcg_cg_iterate.
  * Errors: EINVAL (null pointers, tol < 0 or not finite, maxit < 1),
  * ENOTCONV, EBREAKDOWN, ENOMEM, EHIP.  Synchronises hip_stream. */
 int mfcg_solve_vector(mfcg_handle h, const double *b, double *x, double tol, int32_t maxit, int32_t *iters,

@@ -892,6 +892,9 @@ int mfcg_solve_vector(mfcg_handle h, const double *b, double *x, double tol, int
     hipStream_t s = (hipStream_t)hip_stream;
     const int64_t n = h->hl.n;
     const int64_t nrec = h->hl.ntiles + h->nshared_blocks; /* records per component */
+    /* the device CG state is reused: a scalar solve in progress ends here */
+    h->maxit = 0;
+    h->launched = 0;
     if (!h->r3) {
         HIPCHK(h, dalloc(&h->r3, 3 * n));
         HIPCHK(h, dalloc(&h->p3, 3 * n));
