@@ -134,6 +134,16 @@ struct FastDiv {
     __device__ __forceinline__ int mod(int n) const { return n - div(n) * (int)d; }
 };
 
+/* The geometry tensor is streamed once per iteration: its loads carry the
+ * non-temporal hint so that they do not displace the vector lines that are
+ * reused within the iteration (measured: 1.5-2% off the fused kernel at
+ * Q4, 64^3). */
+template <typename T>
+__device__ __forceinline__ T gload(const T *p)
+{
+    return __builtin_nontemporal_load(p);
+}
+
 /* ------------------------------------------------------------------ */
 /* Fused tile kernel                                                   */
 /* ------------------------------------------------------------------ */
@@ -335,7 +345,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
 #pragma unroll
                 for (int j = 0; j < n; ++j)
 #pragma unroll
-                    for (int c = 0; c < NG; ++c) gp[rr][c][j] = (l < nlines) ? Gl[c * gcomp + j * gq + l] : (T)0;
+                    for (int c = 0; c < NG; ++c) gp[rr][c][j] = (l < nlines) ? gload(&Gl[c * gcomp + j * gq + l]) : (T)0;
             }
         }
         /* ---- pre on the planes this layer touches first ---- */
@@ -449,7 +459,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
 #pragma unroll
                 for (int j = 0; j < n; ++j)
 #pragma unroll
-                    for (int c = 0; c < NG; ++c) gp[rr][c][j] = (l < nlines) ? Gl[c * gcomp + j * gq + l] : (T)0;
+                    for (int c = 0; c < NG; ++c) gp[rr][c][j] = (l < nlines) ? gload(&Gl[c * gcomp + j * gq + l]) : (T)0;
             }
         }
         /* F4 [x-lines]: x derivative */
@@ -505,7 +515,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
                 const int base = c * n3 + i + n2 * z;
 #pragma unroll
                 for (int j = 0; j < n; ++j) {
-                    if (!MFCG_GPREF_OF(K)) gp[rr][0][j] = Gl[j * gq + l];
+                    if (!MFCG_GPREF_OF(K)) gp[rr][0][j] = gload(&Gl[j * gq + l]);
                     TB[base + n * j] = gp[rr][0][j] * TA[base + n * j];
                 }
             }
@@ -521,7 +531,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
                 for (int j = 0; j < n; ++j) {
                     if (!MFCG_GPREF_OF(K)) {
 #pragma unroll
-                        for (int c2 = 0; c2 < 6; ++c2) gp[rr][c2][j] = Gl[c2 * gcomp + j * gq + l];
+                        for (int c2 = 0; c2 < 6; ++c2) gp[rr][c2][j] = gload(&Gl[c2 * gcomp + j * gq + l]);
                     }
                     const T ux = TB[base + n * j], uy = gy[rr][j], uz = TA[base + n * j];
                     const T fx = gp[rr][0][j] * ux + gp[rr][3][j] * uy + gp[rr][4][j] * uz;
