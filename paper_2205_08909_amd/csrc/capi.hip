@@ -866,6 +866,10 @@ int mfcg_cg_end(mfcg_handle h, double *x, int32_t *iters, double *res_hist, void
         HIPCHK(h, hipStreamSynchronize(s));
         return MFCG_OK;
     }
+    if (h->solver_active == MFCG_SOLVER_PIPELINED) {
+        HIPCHK(h, launch_pipe_exit(pipe_args(h), s));
+        HIPCHK(h, hipMemsetAsync(&h->ks->xpend, 0, sizeof(int32_t), s)); /* the step is paid */
+    }
     if (h->solver_active == MFCG_SOLVER_FUSED || h->solver_active == MFCG_SOLVER_ALG5_SPLIT) /* Algorithm 5 keeps x behind */
         HIPCHK(h, launch_reconstruct<double>(h->hl.n, h->x, h->p, h->r, h->prec_active ? h->dinv : nullptr,
                                              h->st, s));

@@ -137,6 +137,8 @@ struct PipeArgs {
 hipError_t launch_pipe_init(const PipeArgs &a, hipStream_t s);
 /* the vector updates of one iteration, its inner products and the next scalars */
 hipError_t launch_pipe_step(const PipeArgs &a, hipStream_t s);
+/* at exit: the step still owed to x after an odd iteration count */
+hipError_t launch_pipe_exit(const PipeArgs &a, hipStream_t s);
 
 /* s-step CG (Algorithm 3, monomial basis), unpreconditioned.  T[0] = r and
  * T[1..s] = A^j r (filled by the caller's mat-vecs), P[0..s) the direction

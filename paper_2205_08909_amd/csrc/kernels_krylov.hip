@@ -7,8 +7,12 @@
  *  Pipelined CG (Algorithm 2).  The scalars of iteration k depend only on
  *  the two inner products of iteration k-1, so after q = A w one kernel
  *  applies all six vector updates (p, x, s, r, z, w) and forms the partial
- *  sums of gamma = r^T r and a = w^T r: 7 vectors read, 6 written.  A
- *  one-block finish turns them into the next alpha and beta.
+ *  sums of gamma = r^T r and a = w^T r: 7 vectors read, 6 written.  As the
+ *  paper suggests, x takes two steps at once every other iteration
+ *  (x += alpha_{k-1} p_{k-1} + alpha_k p_k, with p_{k-1} read before its
+ *  update), 6.5 reads and 5.5 writes on average; an odd exit owes x one
+ *  step, added at the end.  A one-block finish turns the inner products
+ *  into the next alpha and beta.
  *
  *  s-step CG (Algorithm 3, monomial basis).  Per phase of s iterations the
  *  caller runs the s mat-vecs of the basis T = [r, A r, .., A^s r], then
@@ -72,21 +76,21 @@ __global__ __launch_bounds__(KV_WG) void pipe_vec_kernel(const PipeArgs a)
 {
     __shared__ double red[2 * (KV_WG / 64)];
     if (a.st->flag != FLAG_RUN) return;
-    const double alpha = a.ks->alpha, beta = a.ks->beta;
+    const double alpha = a.ks->alpha, beta = a.ks->beta, alpha_prev = a.ks->alpha_prev;
+    const bool xupd = ((a.st->k + 1) & 1) == 0; /* even iterations update x */
     double acc[2] = {0.0, 0.0};
     const int64_t stride = (int64_t)gridDim.x * KV_WG;
     for (int64_t i = (int64_t)blockIdx.x * KV_WG + threadIdx.x; i < a.n; i += stride) {
-        const double r = a.r[i], w = a.w[i], q = a.q[i];
-        const double p = fma(beta, a.p[i], r);
+        const double r = a.r[i], w = a.w[i], q = a.q[i], pold = a.p[i];
+        const double p = fma(beta, pold, r);
         const double sv = fma(beta, a.s[i], w);
         const double z = fma(beta, a.z[i], q);
-        const double x = fma(alpha, p, a.x[i]);
         const double rn = fma(-alpha, sv, r);
         const double wn = fma(-alpha, z, w);
+        if (xupd) a.x[i] = fma(alpha, p, fma(alpha_prev, pold, a.x[i]));
         a.p[i] = p;
         a.s[i] = sv;
         a.z[i] = z;
-        a.x[i] = x;
         a.r[i] = rn;
         a.w[i] = wn;
         acc[0] += rn * rn;
@@ -110,11 +114,14 @@ __global__ __launch_bounds__(SHARED_WG) void pipe_finish_kernel(const PipeArgs a
     if (threadIdx.x != 0) return;
     KrylovState *ks = a.ks;
     const double g = tot[0], wr = tot[1];
+    if (INIT) ks->xpend = 0;
     if (!INIT) {
         const int k = st->k + 1;
         const double rho = sqrt(g);
         a.hist[k] = rho;
         st->k = k;
+        ks->alpha_x = ks->alpha; /* the step of iteration k */
+        ks->xpend = k & 1;
         if (!isfinite(g)) {
             st->flag = FLAG_BREAK;
             return;
@@ -132,10 +139,26 @@ __global__ __launch_bounds__(SHARED_WG) void pipe_finish_kernel(const PipeArgs a
         st->k += 1;
         return;
     }
+    ks->alpha_prev = ks->alpha;
     ks->alpha = g / den;
     ks->beta = beta;
     ks->gamma = g;
     ks->a = wr;
+}
+
+/* exit: an odd iteration count leaves the last step alpha_k p_k owed to x */
+__global__ __launch_bounds__(KV_WG) void pipe_exit_kernel(const PipeArgs a)
+{
+    if (!a.ks->xpend) return;
+    const double alpha = a.ks->alpha_x;
+    const int64_t stride = (int64_t)gridDim.x * KV_WG;
+    for (int64_t i = (int64_t)blockIdx.x * KV_WG + threadIdx.x; i < a.n; i += stride) a.x[i] = fma(alpha, a.p[i], a.x[i]);
+}
+
+hipError_t launch_pipe_exit(const PipeArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(pipe_exit_kernel, dim3(vec_blocks(a.n)), dim3(KV_WG), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_pipe_init(const PipeArgs &a, hipStream_t s)

@@ -99,6 +99,11 @@ struct KrylovState {
     /* pipelined CG (Algorithm 2): the next iteration's alpha and beta and the
      * gamma_k = r^T r, a_k = w^T r they were formed from */
     double alpha, beta, gamma, a;
+    /* x is updated every other iteration (two steps at once): alpha_x is
+     * the alpha of the last completed iteration, alpha_prev the one before;
+     * xpend = 1 while the last iteration's step is still owed to x */
+    double alpha_x, alpha_prev;
+    int32_t xpend, pad_;
     /* s-step CG (Algorithm 3): completed phases, W = Q^T P of the last phase,
      * the block B and the coefficient vector a of the current phase
      * (row-major s x s) */
