@@ -119,3 +119,29 @@ def test_vector_edge_cases(oracle_mod, torch_cuda):
         P.solve_vector(torch.zeros(n, dtype=torch.float64, device="cuda"), torch.zeros(n, dtype=torch.float64,
                                                                                          device="cuda"))
     P.close()
+
+
+def test_vector_solve_with_collocation(oracle_mod, torch_cuda):
+    """The vector problem on a GLL-collocation handle (the one-launch kernel's
+    collocation variant) against the block-diagonal oracle."""
+    torch = torch_cuda
+    from paper_2205_08909_amd import mfcg
+    cells, k = (5, 4, 6), 3
+    coeff = inputs.grf_coefficient(cells, 0.1, 1.0, seed=8)
+    m = oracle_mod.Mesh(cells, k, map_kind=1, amp=0.05, coeff=coeff, quad="gll")
+    A = oracle_mod.assemble(m)
+    P = mfcg.Problem(cells, k, coeff=coeff, map_kind=1, amplitude=0.05, tile=(2, 3, 2), quad=mfcg.QUAD_GLL)
+    A3 = _block3(A)
+    d3 = np.tile(A.diagonal(), 3)
+    b = _rhs3(cells, k, 70)
+    xo, its_o, _, rc_o = oracle_mod.pcg(A3, d3, b, tol=1e-10, maxit=5000)
+    lo, hi, _ = oracle_noise(oracle_mod, A3, b, nperm=2, diag=d3)
+    bt = torch.from_numpy(b).cuda()
+    xt = torch.zeros_like(bt)
+    code, its, hist, tr = P.solve_vector(bt, xt, tol=1e-10, maxit=5000, want_true_res=True)
+    x = xt.cpu().numpy()
+    print("GLL vector its", its, "oracle", its_o, (lo, hi), "true res", tr)
+    assert rc_o == 0 and code == mfcg.OK and lo - 2 <= its <= hi + 2
+    assert np.linalg.norm(x - xo) <= 1e-10 * np.linalg.norm(xo) and tr <= 2e-10
+    P.close()
+
