@@ -38,18 +38,38 @@ namespace mfcg {
 
 constexpr int KV_WG = 256; /* the block size vec_blocks() sizes grids for */
 
-/* Fixed-order sums of NV values over nparts records of REC doubles. */
+/* Fixed-order sums of NV values over nparts records of REC doubles.  The
+ * block splits into SHARED_WG / NV groups of NV threads; thread c of group
+ * g adds value c of records g, g + groups, ... (neighbouring threads read
+ * neighbouring values of one record; eight records in flight per thread),
+ * then one thread per value adds the groups' sums in group order.  red
+ * holds SHARED_WG doubles. */
 template <int NV, int REC>
 __device__ void sum_records(const double *part, int64_t nparts, double *red, double *tot)
 {
-    double acc[NV];
+    static_assert(NV <= SHARED_WG, "one thread per value at least");
+    constexpr int NG = SHARED_WG / NV;
+    const int g = threadIdx.x / NV, c = threadIdx.x - g * NV;
+    constexpr int U = 8; /* records in flight per thread */
+    double acc = 0.0;
+    if (g < NG)
+        for (int64_t b0 = g; b0 < nparts; b0 += (int64_t)NG * U) {
+            double v[U];
 #pragma unroll
-    for (int c = 0; c < NV; ++c) acc[c] = 0.0;
-    for (int64_t b = threadIdx.x; b < nparts; b += SHARED_WG) {
+            for (int u = 0; u < U; ++u) {
+                const int64_t b = b0 + (int64_t)u * NG;
+                v[u] = b < nparts ? part[b * REC + c] : 0.0;
+            }
 #pragma unroll
-        for (int c = 0; c < NV; ++c) acc[c] += part[b * REC + c];
+            for (int u = 0; u < U; ++u) acc += v[u];
+        }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double t = 0.0;
+        for (int gg = 0; gg < NG; ++gg) t += red[gg * NV + threadIdx.x];
+        tot[threadIdx.x] = t;
     }
-    block_reduce<double, NV, SHARED_WG>(acc, red, tot);
     __syncthreads();
 }
 
@@ -106,7 +126,7 @@ __global__ __launch_bounds__(KV_WG) void pipe_vec_kernel(const PipeArgs a)
 template <int INIT>
 __global__ __launch_bounds__(SHARED_WG) void pipe_finish_kernel(const PipeArgs a, int64_t nparts)
 {
-    __shared__ double red[2 * (SHARED_WG / 64)];
+    __shared__ double red[SHARED_WG];
     __shared__ double tot[2];
     CGState *st = a.st;
     if (st->flag != FLAG_RUN) return;
@@ -251,7 +271,7 @@ __global__ __launch_bounds__(KV_WG) void sstep_c_kernel(const SStepArgs a)
 template <int S>
 __global__ __launch_bounds__(SHARED_WG) void sstep_b_finish(const SStepArgs a, int64_t nparts)
 {
-    __shared__ double red[S * S * (SHARED_WG / 64)];
+    __shared__ double red[SHARED_WG];
     __shared__ double tot[S * S];
     CGState *st = a.st;
     KrylovState *ks = a.ks;
@@ -325,7 +345,7 @@ template <int S>
 __global__ __launch_bounds__(SHARED_WG) void sstep_a_finish(const SStepArgs a, int64_t nparts)
 {
     constexpr int NV = S * S + S;
-    __shared__ double red[NV * (SHARED_WG / 64)];
+    __shared__ double red[SHARED_WG];
     __shared__ double tot[NV];
     CGState *st = a.st;
     KrylovState *ks = a.ks;
@@ -384,7 +404,7 @@ __global__ __launch_bounds__(KV_WG) void sstep_r_kernel(const SStepArgs a)
 /* end of a phase: k += s, history (NaN inside the phase), convergence */
 __global__ __launch_bounds__(SHARED_WG) void sstep_r_finish(const SStepArgs a, int64_t nparts, int sdim)
 {
-    __shared__ double red[SHARED_WG / 64];
+    __shared__ double red[SHARED_WG];
     __shared__ double tot[1];
     CGState *st = a.st;
     if (st->flag != FLAG_RUN) return;
