@@ -109,7 +109,10 @@ enum {
 
 /* Options.  Zero-initialised fields select the defaults. */
 typedef struct {
-    int32_t n_q_1d;          /* quadrature points per direction; 0: k+1 (only k+1 is supported) */
+    int32_t n_q_1d;          /* Gauss points per direction: 0 or k+1 (default), or k+2 (the
+                              * n_q = (k+2)^3 rule of the BP1-BP4 benchmarks of Sec. 6; k <= 7,
+                              * Gauss only, FP64 only: not with fp32 / mfcg_solve_ir, not in a
+                              * batch; the stored tensor grows to (k+2)^3 points per cell) */
     int32_t tile[3];         /* cells per tile in x, y, z; 0: per-degree default */
     int32_t check_every;     /* iterations between host polls of the convergence flag; 0: 16 */
     int32_t fp32;            /* 1: build the FP32 operator copy of mfcg_solve_ir at set-up (else on first use) */

@@ -37,6 +37,7 @@ struct mfcg_ctx {
     int precond = MFCG_PRECOND_JACOBI;
     bool gll = false; /* quadrature on the GLL nodes (collocation) */
     bool mass = false; /* the mass operator instead of the Laplacian */
+    bool q2 = false;   /* k + 2 Gauss points per direction instead of k + 1 */
     /* solver, preconditioner and s fixed by cg_begin for the solve in progress */
     int solver_active = MFCG_SOLVER_FUSED;
     int sstep_active = 6;
@@ -184,7 +185,11 @@ static int validate_mesh(const mfcg_mesh *mesh, int32_t degree, const int32_t *t
 
 /* vmult on internal vectors: dst = A src */
 /* operator-variant flags for launch_fused */
-static int gll_flag(const mfcg_ctx *h) { return (h->gll ? MODE_GLL : 0) | (h->mass ? MODE_MASS : 0); }
+static int gll_flag(const mfcg_ctx *h)
+{
+    return (h->gll ? MODE_GLL : 0) | (h->mass ? MODE_MASS : 0) | (h->q2 ? MODE_Q2 : 0);
+}
+static int n_q(const mfcg_ctx *h) { return h->K + (h->q2 ? 2 : 1); }
 
 static int vmult_internal(mfcg_ctx *h, const double *src, double *dst, hipStream_t s)
 {
@@ -244,6 +249,7 @@ static int rebuild_operator(mfcg_ctx *h, hipStream_t s)
     g.bc = h->mesh.bc;
     g.coeff = h->d_coeff;
     g.op = h->mass ? 1 : 0;
+    g.nq = n_q(h);
     HIPCHK(h, launch_geometry(g, h->G, s));
     HIPCHK(h, launch_diagonal(g, h->G, h->diag_lex, h->dinv, s));
     if (h->G32) {
@@ -300,8 +306,11 @@ int mfcg_setup(const mfcg_mesh *mesh, int32_t degree, const double *cell_coeff, 
     const int32_t *tile = opt ? opt->tile : nullptr;
     int rc = validate_mesh(mesh, degree, tile, msg);
     if (rc) return fail(nullptr, rc, msg);
-    if (opt && opt->n_q_1d != 0 && opt->n_q_1d != degree + 1)
-        return fail(nullptr, MFCG_EINVAL, "only n_q_1d = k+1 is supported");
+    if (opt && opt->n_q_1d != 0 && opt->n_q_1d != degree + 1 && opt->n_q_1d != degree + 2)
+        return fail(nullptr, MFCG_EINVAL, "n_q_1d must be k+1 or k+2");
+    const bool q2 = opt && opt->n_q_1d == degree + 2;
+    if (q2 && (degree > 7 || opt->quad_rule != MFCG_QUAD_GAUSS || opt->fp32))
+        return fail(nullptr, MFCG_EINVAL, "n_q_1d = k+2: Gauss points, FP64, k <= 7 only");
     if (opt && opt->check_every < 0) return fail(nullptr, MFCG_EINVAL, "check_every must be >= 0");
     if (opt && opt->quad_rule != MFCG_QUAD_GAUSS && opt->quad_rule != MFCG_QUAD_GLL)
         return fail(nullptr, MFCG_EINVAL, "unknown quad_rule");
@@ -325,6 +334,7 @@ int mfcg_setup(const mfcg_mesh *mesh, int32_t degree, const double *cell_coeff, 
     if (opt && opt->check_every > 0) h->check_every = opt->check_every;
     h->gll = opt && opt->quad_rule == MFCG_QUAD_GLL;
     h->mass = opt && opt->op == MFCG_OP_MASS;
+    h->q2 = q2;
     hipStream_t s = (hipStream_t)hip_stream;
 
     auto bail = [&](int code) {
@@ -345,8 +355,11 @@ int mfcg_setup(const mfcg_mesh *mesh, int32_t degree, const double *cell_coeff, 
     SCHK(hipGetDevice(&h->device));
     int nc[3] = {mesh->cells[0], mesh->cells[1], mesh->cells[2]};
     int t[3] = {tile ? tile[0] : 0, tile ? tile[1] : 0, tile ? tile[2] : 0};
-    build_layout(nc, degree, t, mesh->bc, h->hl);
-    build_tables(degree, h->tab, h->gll);
+    build_layout(nc, degree, t, mesh->bc, h->hl, n_q(h));
+    if (build_tables(degree, h->tab, h->gll, n_q(h))) {
+        h->err = "quadrature tables";
+        return bail(MFCG_EINVAL);
+    }
     HostLayout &L = h->hl;
 
     SCHK(dalloc(&h->d_ent_base, L.ent_base.size()));
@@ -549,6 +562,7 @@ int mfcg_assemble_rhs(mfcg_handle h, int32_t kind, const double *params, double 
     g.amp = h->mesh.map_kind == MFCG_MAP_AFFINE ? 0.0 : h->mesh.map_amplitude;
     g.bc = h->mesh.bc;
     g.coeff = h->d_coeff;
+    g.nq = n_q(h);
     HIPCHK(h, launch_rhs(g, kind, params, np, b, (hipStream_t)hip_stream));
     return MFCG_OK;
 }
@@ -1046,7 +1060,8 @@ int mfcg_solve(mfcg_handle h, const double *b, double *x, double tol, int32_t ma
 static int ensure_fp32(mfcg_ctx *h, hipStream_t s)
 {
     if (h->G32) return MFCG_OK;
-    if (h->gll || h->mass) return fail(h, MFCG_EINVAL, "the FP32 operator is built for the Gauss-point Laplacian only");
+    if (h->gll || h->mass || h->q2)
+        return fail(h, MFCG_EINVAL, "the FP32 operator is built for the Gauss-point Laplacian (k+1 points) only");
     const HostLayout &L = h->hl;
     HIPCHK(h, dalloc(&h->G32, L.g_elems));
     HIPCHK(h, dalloc(&h->dinv32, L.n));
@@ -1138,7 +1153,8 @@ int mfcg_solve_ir(mfcg_handle h, const double *b, double *x, double tol, double 
     if (!(tol > 0.0) || !std::isfinite(tol) || !(inner_tol > 0.0) || !(inner_tol < 1.0))
         return fail(h, MFCG_EINVAL, "need tol > 0 and 0 < inner_tol < 1");
     if (max_outer < 1 || max_inner < 1) return fail(h, MFCG_EINVAL, "max_outer and max_inner must be >= 1");
-    if (h->gll || h->mass) return fail(h, MFCG_EINVAL, "mixed precision runs the Gauss-point Laplacian only");
+    if (h->gll || h->mass || h->q2)
+        return fail(h, MFCG_EINVAL, "mixed precision runs the Gauss-point Laplacian (k+1 points) only");
     hipStream_t s = (hipStream_t)hip_stream;
     int rc = ensure_fp32(h, s);
     if (rc) return rc;
@@ -1448,7 +1464,7 @@ int mfcg_batch_solve(mfcg_batch hb, const double *const *b, double *const *x, do
         if (!b[i] || !x[i]) return batch_fail(hb, MFCG_EINVAL, "null vector of problem " + std::to_string(i));
     hipStream_t s = (hipStream_t)hip_stream;
     for (int i = 0; i < np; ++i)
-        if (hb->probs[i]->solver != MFCG_SOLVER_FUSED || hb->probs[i]->gll || hb->probs[i]->mass)
+        if (hb->probs[i]->solver != MFCG_SOLVER_FUSED || hb->probs[i]->gll || hb->probs[i]->mass || hb->probs[i]->q2)
             return batch_fail(hb, MFCG_EINVAL,
                               "problem " + std::to_string(i) + ": the batch runs the fused Gauss-quadrature solver only");
     /* every problem starts as mfcg_solve would start it */

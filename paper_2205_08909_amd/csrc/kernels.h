@@ -17,6 +17,9 @@ constexpr bool mode_is_cg(int m) { return m != MODE_VMULT; }
 constexpr int MODE_GLL = 8;
 /* or-ed likewise: the mass operator (Gauss points; FP64 only) */
 constexpr int MODE_MASS = 16;
+/* or-ed likewise: k + 2 Gauss points per direction instead of k + 1
+ * (k <= 7, Laplacian or mass; FP64 only) */
+constexpr int MODE_Q2 = 32;
 
 /* Arguments of the fused tile kernel and the shared-node kernel. */
 template <typename T>
@@ -62,7 +65,8 @@ hipError_t launch_shared(int mode, const IterArgs<T> &a, hipStream_t s);
  * over nparts records starting at a.dots (all components' records). */
 hipError_t launch_shared_nofinish(const IterArgs<double> &a, hipStream_t s);
 /* The fused tile kernel over all three components of a vector problem in
- * one launch (mode: MODE_CG, optionally with MODE_GLL or MODE_MASS); the
+ * one launch (mode: MODE_CG, optionally with MODE_GLL or MODE_MASS, and
+ * MODE_Q2 without MODE_GLL); the
  * vectors, shared partial sums and records of component c sit at c times
  * the given strides (elements). */
 hipError_t launch_fused_vec(int K, int mode, const IterArgs<double> &a, int64_t nstride, int64_t pstride,
@@ -78,6 +82,7 @@ struct GeomArgs {
     int32_t bc;
     const double *coeff; /* per cell, device */
     int32_t op;          /* 0: Laplacian (6-component tensor), 1: mass (component 0: a_e w_q det J_q) */
+    int32_t nq;          /* quadrature points per direction (k + 1 or k + 2); tab.S, tab.Sd are nq x (k+1), tab.D nq x nq */
 };
 hipError_t launch_geometry(const GeomArgs &g, double *G, hipStream_t s);
 hipError_t launch_diagonal(const GeomArgs &g, const double *G, double *diag_lex, double *dinv_int, hipStream_t s);

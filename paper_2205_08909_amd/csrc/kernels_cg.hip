@@ -96,6 +96,12 @@ int fused_block_size(int K)
 #define MFCG_GPREF_OF(K) (Cfg<K>::GPREF)
 #endif
 #define MFCG_WPE_MIN(K) ((MFCG_OCC_OF(K) * Cfg<K>::WG / 64 + 3) / 4)
+/* the k+2-point variants: no more waves than their larger cell scratch
+ * lets fit per CU (LDS per workgroup 32 KB at k = 1, 83 KB at k = 2,
+ * 67-77 KB at k = 3..5, 49 KB at k = 6, 69 KB at k = 7), geometry loads in
+ * the G pass */
+constexpr int WPE_Q2[8] = {0, 2, 3, 4, 4, 3, 2, 2};
+#define MFCG_WPE_MIN_Q(K, QX) ((QX) ? WPE_Q2[(K) < 8 ? (K) : 0] : MFCG_WPE_MIN(K))
 /* the batch kernel holds more uniform values (its arguments come from
  * memory): it asks for at most two workgroups per CU to avoid spills */
 #define MFCG_WPE_MIN_BATCH(K) (((MFCG_OCC_OF(K) < 2 ? MFCG_OCC_OF(K) : 2) * Cfg<K>::WG / 64 + 3) / 4)
@@ -161,28 +167,40 @@ __device__ __forceinline__ T gload(const T *p)
 enum OpVariant : int { OPV_LAPLACE = 0, OPV_LAPLACE_GLL = 1, OPV_MASS = 2 };
 
 /* One tile of one problem: the pre / cell / sum / post passes over the
- * tile's cell layers (called by one whole workgroup). */
-template <int K, typename T, int MODE, int OPV = OPV_LAPLACE, bool NTG = true>
+ * tile's cell layers (called by one whole workgroup).  QX = 1: k + 2
+ * Gauss points per direction instead of k + 1 (Gauss variants only); the
+ * passes on the quadrature grid then run over (k + 2)^2 lines per cell and
+ * the interpolation passes map k + 1 values to k + 2 and back. */
+template <int K, typename T, int MODE, int OPV = OPV_LAPLACE, bool NTG = true, int QX = 0>
 __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t tile)
 {
     constexpr bool GLLQ = OPV == OPV_LAPLACE_GLL, MASS = OPV == OPV_MASS;
+    static_assert(QX == 0 || (QX == 1 && !GLLQ && K <= 7), "k+2 points: Gauss rules up to k = 7");
     constexpr int NG = MASS ? 1 : 6; /* tensor components read */
-    constexpr int n = K + 1, n2 = n * n, n3 = n * n * n;
+    constexpr int GPF = QX ? 0 : MFCG_GPREF_OF(K); /* when the geometry loads are issued */
+    constexpr int n = K + 1, n2 = n * n;
+    /* nq points per direction; the cell scratch holds nq^3 values with the
+     * strides (1, nq, nq^2) in every stage (fewer entries used where a
+     * direction still has n values) */
+    constexpr int nq = n + QX, q2 = nq * nq, CS = nq * nq * nq, nnq = n * nq;
     constexpr int WG = Cfg<K>::WG;
     constexpr int NLC = Cfg<K>::TX * Cfg<K>::TY;
-    constexpr int R = (NLC * n2 + WG - 1) / WG;
+    constexpr int RA = (NLC * n2 + WG - 1) / WG;  /* lines of the F1 and B7 passes */
+    constexpr int RB = (NLC * nnq + WG - 1) / WG; /* F2 and B6 */
+    constexpr int R = (NLC * q2 + WG - 1) / WG;   /* passes on the quadrature grid */
     constexpr int PNM = (Cfg<K>::TX * K + 1) * (Cfg<K>::TY * K + 1);
     constexpr int NS = (K * PNM + WG - 1) / WG;
     constexpr int NC = (PNM + WG - 1) / WG;
-    /* compile-time 1D tables: S (GLL basis at Gauss points), D (collocation
-     * derivative on the Gauss points) */
+    /* compile-time 1D tables: S (GLL basis at Gauss points, nq x n), D
+     * (collocation derivative on the Gauss points, nq x nq) */
     constexpr ct::Tab<n> TT = ct::make_tab<n, GLLQ>();
-    constexpr auto cS = [](int q, int i) { return (T)TT.S[q * n + i]; };
-    constexpr auto cD = [](int q, int i) { return (T)TT.D[q * n + i]; };
+    constexpr ct::Tab2<n, nq> TQ = QX ? ct::make_tab2<n, nq>() : ct::Tab2<n, nq>{};
+    constexpr auto cS = [](int q, int i) { return QX ? (T)TQ.S[q * n + i] : (T)TT.S[q * n + i]; };
+    constexpr auto cD = [](int q, int m) { return QX ? (T)TQ.D[q * nq + m] : (T)TT.D[q * n + m]; };
 
     __shared__ T win[(K + 1) * PNM];
-    __shared__ T TA[NLC * n3];
-    __shared__ T TB[NLC * n3];
+    __shared__ T TA[NLC * CS];
+    __shared__ T TB[NLC * CS];
     __shared__ T cv[2 * PNM];
     __shared__ T red[8 * (WG / 64)];
     __shared__ EntityRef ent[27];
@@ -217,9 +235,10 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
     const int EX = TXa * K, EY = TYa * K, EZ = TZa * K;
     const int PW = EX + 1;
     const int PN = (EX + 1) * (EY + 1);
-    const int nlines = TXa * TYa * n2;
-    const int gcomp = n3 * TXa * TYa; /* stride between components of G in a layer */
-    const int gq = TXa * TYa * n2;    /* stride of the y-index of G in a component */
+    const int nlines = TXa * TYa * q2;
+    const int nlA = QX ? TXa * TYa * n2 : nlines, nlB = QX ? TXa * TYa * nnq : nlines;
+    const int gcomp = CS * TXa * TYa; /* stride between components of G in a layer */
+    const int gq = TXa * TYa * q2;    /* stride of the y-index of G in a component */
     const FastDiv dPW(PW), dPN(PN), dTX(TXa);
     for (int node = tid0; node < PN; node += WG) {
         const int by = dPW.div(node), ax = node - by * PW;
@@ -230,7 +249,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         const int cx1 = ax / K, cy1 = by / K;
         const bool xl = (ax % K) == 0 && cx1 > 0, xr = cx1 < TXa;
         const bool yl = (by % K) == 0 && cy1 > 0, yr = cy1 < TYa;
-        auto off = [&](int cx, int cy) { return (cx + TXa * cy) * n3 + (ax - cx * K) + n * (by - cy * K); };
+        auto off = [&](int cx, int cy) { return (cx + TXa * cy) * CS + (ax - cx * K) + nq * (by - cy * K); };
         const int o00 = (xl && yl) ? off(cx1 - 1, cy1 - 1) : 0xffff;
         const int o01 = (xr && yl) ? off(cx1, cy1 - 1) : 0xffff;
         const int o10 = (xl && yr) ? off(cx1 - 1, cy1) : 0xffff;
@@ -282,7 +301,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
     auto sum_cells = [&](const int4 &dsc, int zl) -> T {
         const int o00 = dsc.z & 0xffff, o01 = (int)((unsigned)dsc.z >> 16);
         const int o10 = dsc.w & 0xffff, o11 = (int)((unsigned)dsc.w >> 16);
-        const int zo = n2 * zl;
+        const int zo = q2 * zl;
         const T v00 = o00 != 0xffff ? TB[o00 + zo] : (T)0;
         const T v01 = o01 != 0xffff ? TB[o01 + zo] : (T)0;
         const T v10 = o10 != 0xffff ? TB[o10 + zo] : (T)0;
@@ -341,14 +360,14 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         const int s0 = (L * K) % (K + 1);
         asm volatile("" : "+v"(tid)); /* see above */
         const T *Gl = a.G + td.gbase + (int64_t)L * 6 * gcomp;
-        T gp[R][6][n];
-        if (MFCG_GPREF_OF(K) == 2) {
+        T gp[R][6][nq];
+        if (GPF == 2) {
             /* G of this layer issued first: its latency overlaps the pre loads */
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) {
                 const int l = tid + WG * rr;
 #pragma unroll
-                for (int j = 0; j < n; ++j)
+                for (int j = 0; j < nq; ++j)
 #pragma unroll
                     for (int c = 0; c < NG; ++c) gp[rr][c][j] = (l < nlines) ? gload<NTG>(&Gl[c * gcomp + j * gq + l]) : (T)0;
             }
@@ -368,13 +387,14 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         asm volatile("" : "+v"(tid)); /* see above */
         asm volatile("" : "+v"(tid));
 
-        T gy[R][n], wy[R][n], wz[R][n];
+        T gy[R][nq], wy[R][nq], wz[R][nq];
 
-        /* F1 [z-lines]: gather p from the window, interpolate along z */
+        /* F1 [z-lines (i, j)]: gather p from the window, interpolate along z
+         * -> TA at i + n j + n^2 qz */
 #pragma unroll
-        for (int rr = 0; rr < R; ++rr) {
+        for (int rr = 0; rr < RA; ++rr) {
             const int l = tid + WG * rr;
-            if (l < nlines) {
+            if (l < nlA) {
                 const int c = l / n2, rem = l % n2, i = rem % n, j = rem / n;
                 const int cy = dTX.div(c), cx = c - cy * TXa;
                 const int nodexy = cx * K + i + PW * (cy * K + j);
@@ -386,7 +406,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
                     u[z] = win[slot * PNM + nodexy];
                 }
 #pragma unroll
-                for (int q = 0; q < n; ++q) {
+                for (int q = 0; q < nq; ++q) {
                     T t = 0;
                     if (GLLQ) {
                         t = u[q];
@@ -394,46 +414,47 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
 #pragma unroll
                         for (int z = 0; z < n; ++z) t = fma(cS(q, z), u[z], t);
                     }
-                    TA[c * n3 + rem + n2 * q] = t;
+                    TA[c * CS + rem + n2 * q] = t;
                 }
             }
         }
         __syncthreads();
         asm volatile("" : "+v"(tid));
-        /* F2 [x-lines]: interpolate along x */
+        /* F2 [x-lines (j, qz)]: interpolate along x -> TB at qx + nq j + nq n qz */
 #pragma unroll
-        for (int rr = 0; rr < R && !GLLQ; ++rr) {
+        for (int rr = 0; rr < RB && !GLLQ; ++rr) {
             const int l = tid + WG * rr;
-            if (l < nlines) {
-                const int c = l / n2, rem = l % n2;
-                const int base = c * n3 + n * rem;
+            if (l < nlB) {
+                const int c = l / nnq, rem = l % nnq;
+                const int base = c * CS + n * rem, bout = QX ? c * CS + nq * rem : base;
                 T u[n];
 #pragma unroll
                 for (int i = 0; i < n; ++i) u[i] = TA[base + i];
 #pragma unroll
-                for (int q = 0; q < n; ++q) {
+                for (int q = 0; q < nq; ++q) {
                     T t = 0;
 #pragma unroll
                     for (int i = 0; i < n; ++i) t = fma(cS(q, i), u[i], t);
-                    TB[base + q] = t;
+                    TB[bout + q] = t;
                 }
             }
         }
         __syncthreads();
         asm volatile("" : "+v"(tid));
-        /* F3 [y-lines]: interpolate along y -> values at the Gauss points,
-         * y derivative kept in registers */
+        /* F3 [y-lines (qx, qz)]: interpolate along y -> values at the Gauss
+         * points in TA at qx + nq qy + nq^2 qz, y derivative kept in registers */
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlines) {
-                const int c = l / n2, rem = l % n2, i = rem % n, z = rem / n;
-                const int base = c * n3 + i + n2 * z;
-                T u[n], uq[n];
+                const int c = l / q2, rem = l % q2, i = rem % nq, z = rem / nq;
+                const int base = c * CS + i + q2 * z;
+                const int bin = QX ? c * CS + i + nnq * z : base;
+                T u[n], uq[nq];
 #pragma unroll
-                for (int j = 0; j < n; ++j) u[j] = GLLQ ? TA[base + n * j] : TB[base + n * j];
+                for (int j = 0; j < n; ++j) u[j] = GLLQ ? TA[base + nq * j] : TB[bin + nq * j];
 #pragma unroll
-                for (int q = 0; q < n; ++q) {
+                for (int q = 0; q < nq; ++q) {
                     if (GLLQ) {
                         uq[q] = u[q]; /* values already in TA */
                     } else {
@@ -441,14 +462,14 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
 #pragma unroll
                         for (int j = 0; j < n; ++j) t = fma(cS(q, j), u[j], t);
                         uq[q] = t;
-                        TA[base + n * q] = t;
+                        TA[base + nq * q] = t;
                     }
                 }
 #pragma unroll
-                for (int q = 0; q < n && !MASS; ++q) {
+                for (int q = 0; q < nq && !MASS; ++q) {
                     T t = 0;
 #pragma unroll
-                    for (int m = 0; m < n; ++m) t = fma(cD(q, m), uq[m], t);
+                    for (int m = 0; m < nq; ++m) t = fma(cD(q, m), uq[m], t);
                     gy[rr][q] = t;
                 }
             }
@@ -457,71 +478,71 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         asm volatile("" : "+v"(tid));
         /* G of this layer: loads issued here, consumed after the x and z
          * derivative passes */
-        if (MFCG_GPREF_OF(K) == 1) {
+        if (GPF == 1) {
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) {
                 const int l = tid + WG * rr;
 #pragma unroll
-                for (int j = 0; j < n; ++j)
+                for (int j = 0; j < nq; ++j)
 #pragma unroll
                     for (int c = 0; c < NG; ++c) gp[rr][c][j] = (l < nlines) ? gload<NTG>(&Gl[c * gcomp + j * gq + l]) : (T)0;
             }
         }
-        /* F4 [x-lines]: x derivative */
+        /* F4 [x-lines (qy, qz)]: x derivative */
 #pragma unroll
         for (int rr = 0; rr < R && !MASS; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlines) {
-                const int c = l / n2, rem = l % n2;
-                const int base = c * n3 + n * rem;
-                T u[n];
+                const int c = l / q2, rem = l % q2;
+                const int base = c * CS + nq * rem;
+                T u[nq];
 #pragma unroll
-                for (int i = 0; i < n; ++i) u[i] = TA[base + i];
+                for (int i = 0; i < nq; ++i) u[i] = TA[base + i];
 #pragma unroll
-                for (int q = 0; q < n; ++q) {
+                for (int q = 0; q < nq; ++q) {
                     T t = 0;
 #pragma unroll
-                    for (int m = 0; m < n; ++m) t = fma(cD(q, m), u[m], t);
+                    for (int m = 0; m < nq; ++m) t = fma(cD(q, m), u[m], t);
                     TB[base + q] = t;
                 }
             }
         }
         __syncthreads();
         asm volatile("" : "+v"(tid));
-        /* F5 [z-lines]: z derivative, in place */
+        /* F5 [z-lines (qx, qy)]: z derivative, in place */
 #pragma unroll
         for (int rr = 0; rr < R && !MASS; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlines) {
-                const int c = l / n2, rem = l % n2;
-                const int base = c * n3 + rem;
-                T u[n];
+                const int c = l / q2, rem = l % q2;
+                const int base = c * CS + rem;
+                T u[nq];
 #pragma unroll
-                for (int z = 0; z < n; ++z) u[z] = TA[base + n2 * z];
+                for (int z = 0; z < nq; ++z) u[z] = TA[base + q2 * z];
 #pragma unroll
-                for (int q = 0; q < n; ++q) {
+                for (int q = 0; q < nq; ++q) {
                     T t = 0;
 #pragma unroll
-                    for (int m = 0; m < n; ++m) t = fma(cD(q, m), u[m], t);
-                    TA[base + n2 * q] = t;
+                    for (int m = 0; m < nq; ++m) t = fma(cD(q, m), u[m], t);
+                    TA[base + q2 * q] = t;
                 }
             }
         }
         __syncthreads();
         asm volatile("" : "+v"(tid));
-        /* G [y-lines]: flux = G_q grad u at each Gauss point; y part of the
-         * transposed derivative in registers.  Mass operator: the values
-         * scaled by a_e w_q det J_q, into TB. */
+        /* G [y-lines (qx, qz)]: flux = G_q grad u at each Gauss point; y part
+         * of the transposed derivative in registers.  Mass operator: the
+         * values scaled by a_e w_q det J_q, into TB. */
 #pragma unroll
         for (int rr = 0; rr < R && MASS; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlines) {
-                const int c = l / n2, rem = l % n2, i = rem % n, z = rem / n;
-                const int base = c * n3 + i + n2 * z;
+                const int c = l / q2, rem = l % q2, i = rem % nq, z = rem / nq;
+                const int base = c * CS + i + q2 * z;
 #pragma unroll
-                for (int j = 0; j < n; ++j) {
-                    if (!MFCG_GPREF_OF(K)) gp[rr][0][j] = gload<NTG>(&Gl[j * gq + l]);
-                    TB[base + n * j] = gp[rr][0][j] * TA[base + n * j];
+                for (int j = 0; j < nq; ++j) {
+                    if (!GPF) gp[rr][0][j] = gload<NTG>(&Gl[j * gq + l]);
+                    TB[base + nq * j] = gp[rr][0][j] * TA[base + nq * j];
                 }
             }
         }
@@ -529,63 +550,63 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         for (int rr = 0; rr < R && !MASS; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlines) {
-                const int c = l / n2, rem = l % n2, i = rem % n, z = rem / n;
-                const int base = c * n3 + i + n2 * z;
-                T fy[n];
+                const int c = l / q2, rem = l % q2, i = rem % nq, z = rem / nq;
+                const int base = c * CS + i + q2 * z;
+                T fy[nq];
 #pragma unroll
-                for (int j = 0; j < n; ++j) {
-                    if (!MFCG_GPREF_OF(K)) {
+                for (int j = 0; j < nq; ++j) {
+                    if (!GPF) {
 #pragma unroll
                         for (int c2 = 0; c2 < 6; ++c2) gp[rr][c2][j] = gload<NTG>(&Gl[c2 * gcomp + j * gq + l]);
                     }
-                    const T ux = TB[base + n * j], uy = gy[rr][j], uz = TA[base + n * j];
+                    const T ux = TB[base + nq * j], uy = gy[rr][j], uz = TA[base + nq * j];
                     const T fx = gp[rr][0][j] * ux + gp[rr][3][j] * uy + gp[rr][4][j] * uz;
                     fy[j] = gp[rr][3][j] * ux + gp[rr][1][j] * uy + gp[rr][5][j] * uz;
                     const T fz = gp[rr][4][j] * ux + gp[rr][5][j] * uy + gp[rr][2][j] * uz;
-                    TB[base + n * j] = fx;
-                    TA[base + n * j] = fz;
+                    TB[base + nq * j] = fx;
+                    TA[base + nq * j] = fz;
                 }
 #pragma unroll
-                for (int m = 0; m < n; ++m) {
+                for (int m = 0; m < nq; ++m) {
                     T t = 0;
 #pragma unroll
-                    for (int q = 0; q < n; ++q) t = fma(cD(q, m), fy[q], t);
+                    for (int q = 0; q < nq; ++q) t = fma(cD(q, m), fy[q], t);
                     wy[rr][m] = t;
                 }
             }
         }
         __syncthreads();
         asm volatile("" : "+v"(tid));
-        /* B2 [x-lines]: transposed x derivative, in place; B3 [z-lines]:
-         * transposed z derivative into registers */
+        /* B2 [x-lines (qy, qz)]: transposed x derivative, in place; B3
+         * [z-lines (qx, qy)]: transposed z derivative into registers */
 #pragma unroll
         for (int rr = 0; rr < R && !MASS; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlines) {
-                const int c = l / n2, rem = l % n2;
+                const int c = l / q2, rem = l % q2;
                 {
-                    const int base = c * n3 + n * rem;
-                    T f[n];
+                    const int base = c * CS + nq * rem;
+                    T f[nq];
 #pragma unroll
-                    for (int q = 0; q < n; ++q) f[q] = TB[base + q];
+                    for (int q = 0; q < nq; ++q) f[q] = TB[base + q];
 #pragma unroll
-                    for (int m = 0; m < n; ++m) {
+                    for (int m = 0; m < nq; ++m) {
                         T t = 0;
 #pragma unroll
-                        for (int q = 0; q < n; ++q) t = fma(cD(q, m), f[q], t);
+                        for (int q = 0; q < nq; ++q) t = fma(cD(q, m), f[q], t);
                         TB[base + m] = t;
                     }
                 }
                 {
-                    const int base = c * n3 + rem;
-                    T f[n];
+                    const int base = c * CS + rem;
+                    T f[nq];
 #pragma unroll
-                    for (int q = 0; q < n; ++q) f[q] = TA[base + n2 * q];
+                    for (int q = 0; q < nq; ++q) f[q] = TA[base + q2 * q];
 #pragma unroll
-                    for (int m = 0; m < n; ++m) {
+                    for (int m = 0; m < nq; ++m) {
                         T t = 0;
 #pragma unroll
-                        for (int q = 0; q < n; ++q) t = fma(cD(q, m), f[q], t);
+                        for (int q = 0; q < nq; ++q) t = fma(cD(q, m), f[q], t);
                         wz[rr][m] = t;
                     }
                 }
@@ -593,29 +614,30 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         }
         __syncthreads();
         asm volatile("" : "+v"(tid));
-        /* B4 [y-lines]: add the y part */
+        /* B4 [y-lines (qx, qz)]: add the y part */
 #pragma unroll
         for (int rr = 0; rr < R && !MASS; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlines) {
-                const int c = l / n2, rem = l % n2, i = rem % n, z = rem / n;
-                const int base = c * n3 + i + n2 * z;
+                const int c = l / q2, rem = l % q2, i = rem % nq, z = rem / nq;
+                const int base = c * CS + i + q2 * z;
 #pragma unroll
-                for (int j = 0; j < n; ++j) TB[base + n * j] += wy[rr][j];
+                for (int j = 0; j < nq; ++j) TB[base + nq * j] += wy[rr][j];
             }
         }
         __syncthreads();
         asm volatile("" : "+v"(tid));
-        /* B5 [z-lines]: add the z part, transposed interpolation along z */
+        /* B5 [z-lines (qx, qy)]: add the z part, transposed interpolation
+         * along z -> qx + nq qy + nq^2 z */
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlines) {
-                const int c = l / n2, rem = l % n2;
-                const int base = c * n3 + rem;
-                T w[n];
+                const int c = l / q2, rem = l % q2;
+                const int base = c * CS + rem;
+                T w[nq];
 #pragma unroll
-                for (int q = 0; q < n; ++q) w[q] = MASS ? TB[base + n2 * q] : TB[base + n2 * q] + wz[rr][q];
+                for (int q = 0; q < nq; ++q) w[q] = MASS ? TB[base + q2 * q] : TB[base + q2 * q] + wz[rr][q];
 #pragma unroll
                 for (int z = 0; z < n; ++z) {
                     T t = 0;
@@ -623,51 +645,52 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
                         t = w[z];
                     } else {
 #pragma unroll
-                        for (int q = 0; q < n; ++q) t = fma(cS(q, z), w[q], t);
+                        for (int q = 0; q < nq; ++q) t = fma(cS(q, z), w[q], t);
                     }
-                    TB[base + n2 * z] = t;
+                    TB[base + q2 * z] = t;
                 }
             }
         }
         __syncthreads();
         asm volatile("" : "+v"(tid));
-        /* B6 [x-lines]: transposed interpolation along x */
+        /* B6 [x-lines (qy, z)]: transposed interpolation along x -> i + nq qy + nq^2 z */
 #pragma unroll
-        for (int rr = 0; rr < R && !GLLQ; ++rr) {
+        for (int rr = 0; rr < RB && !GLLQ; ++rr) {
             const int l = tid + WG * rr;
-            if (l < nlines) {
-                const int c = l / n2, rem = l % n2;
-                const int base = c * n3 + n * rem;
-                T w[n];
+            if (l < nlB) {
+                const int c = l / nnq, rem = l % nnq;
+                const int base = c * CS + nq * rem;
+                T w[nq];
 #pragma unroll
-                for (int q = 0; q < n; ++q) w[q] = TB[base + q];
+                for (int q = 0; q < nq; ++q) w[q] = TB[base + q];
 #pragma unroll
                 for (int i = 0; i < n; ++i) {
                     T t = 0;
 #pragma unroll
-                    for (int q = 0; q < n; ++q) t = fma(cS(q, i), w[q], t);
+                    for (int q = 0; q < nq; ++q) t = fma(cS(q, i), w[q], t);
                     TB[base + i] = t;
                 }
             }
         }
         __syncthreads();
         asm volatile("" : "+v"(tid));
-        /* B7 [y-lines]: transposed interpolation along y -> cell vectors */
+        /* B7 [y-lines (i, z)]: transposed interpolation along y -> cell
+         * vectors at i + nq j + nq^2 z */
 #pragma unroll
-        for (int rr = 0; rr < R && !GLLQ; ++rr) {
+        for (int rr = 0; rr < RA && !GLLQ; ++rr) {
             const int l = tid + WG * rr;
-            if (l < nlines) {
+            if (l < nlA) {
                 const int c = l / n2, rem = l % n2, i = rem % n, z = rem / n;
-                const int base = c * n3 + i + n2 * z;
-                T w[n];
+                const int base = c * CS + i + q2 * z;
+                T w[nq];
 #pragma unroll
-                for (int q = 0; q < n; ++q) w[q] = TB[base + n * q];
+                for (int q = 0; q < nq; ++q) w[q] = TB[base + nq * q];
 #pragma unroll
                 for (int j = 0; j < n; ++j) {
                     T t = 0;
 #pragma unroll
-                    for (int q = 0; q < n; ++q) t = fma(cS(q, j), w[q], t);
-                    TB[base + n * j] = t;
+                    for (int q = 0; q < nq; ++q) t = fma(cS(q, j), w[q], t);
+                    TB[base + nq * j] = t;
                 }
             }
         }
@@ -710,13 +733,13 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
     if (mode_is_cg(MODE)) block_reduce<T, 7, WG>(acc, red, a.dots + tile * 8);
 }
 
-template <int K, typename T, int MODE, int OPV = OPV_LAPLACE>
+template <int K, typename T, int MODE, int OPV = OPV_LAPLACE, int QX = 0>
 __global__ __launch_bounds__(Cfg<K>::WG)
-__attribute__((amdgpu_waves_per_eu(MFCG_WPE_MIN(K), 8)))
+__attribute__((amdgpu_waves_per_eu(MFCG_WPE_MIN_Q(K, QX), 8)))
 void fused_tile_kernel(const IterArgs<T> a)
 {
     if (mode_is_cg(MODE) && a.st->flag != FLAG_RUN) return;
-    fused_tile<K, T, MODE, OPV>(a, xcd_remap(blockIdx.x, gridDim.x));
+    fused_tile<K, T, MODE, OPV, true, QX>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 /* Vector problems: one launch over (tile, component) pairs, the component
@@ -725,9 +748,9 @@ void fused_tile_kernel(const IterArgs<T> a)
  * fetched from HBM about once and then served from that XCD's L2.
  * Component c works on the vectors at offset c*nstride, its shared-node
  * partial sums at c*pstride and its inner-product records at c*dstride. */
-template <int K, int MODE, int OPV>
+template <int K, int MODE, int OPV, int QX = 0>
 __global__ __launch_bounds__(Cfg<K>::WG)
-__attribute__((amdgpu_waves_per_eu(MFCG_WPE_MIN(K), 8)))
+__attribute__((amdgpu_waves_per_eu(MFCG_WPE_MIN_Q(K, QX), 8)))
 void fused_tile_vec_kernel(const IterArgs<double> a, int64_t nstride, int64_t pstride, int64_t dstride)
 {
     if (a.st->flag != FLAG_RUN) return;
@@ -740,7 +763,7 @@ void fused_tile_vec_kernel(const IterArgs<double> a, int64_t nstride, int64_t ps
     b.x += c * nstride;
     b.part += c * pstride;
     b.dots += c * dstride;
-    fused_tile<K, double, MODE, OPV, false>(b, lb / 3);
+    fused_tile<K, double, MODE, OPV, false, QX>(b, lb / 3);
 }
 
 /* Batch of problems of degree K: one workgroup per (problem, tile) item of
@@ -908,32 +931,41 @@ __global__ __launch_bounds__(SHARED_WG) void finish_batch_kernel(const IterArgs<
 /* Launch wrappers                                                     */
 /* ------------------------------------------------------------------ */
 
+/* one operator variant in one of the three modes */
+template <int K, int OPV, int QX>
+static void launch_fused_variant(int mode, dim3 grid, dim3 block, const IterArgs<double> &a, hipStream_t s)
+{
+    if (mode == MODE_CG)
+        hipLaunchKernelGGL((fused_tile_kernel<K, double, MODE_CG, OPV, QX>), grid, block, 0, s, a);
+    else if (mode == MODE_CG_NOPREC)
+        hipLaunchKernelGGL((fused_tile_kernel<K, double, MODE_CG_NOPREC, OPV, QX>), grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL((fused_tile_kernel<K, double, MODE_VMULT, OPV, QX>), grid, block, 0, s, a);
+}
+
 template <int K, typename T>
 static hipError_t launch_fused_k(int mode, const IterArgs<T> &a, hipStream_t s)
 {
     dim3 grid((unsigned)a.L.ntiles), block(Cfg<K>::WG);
-    if (mode & (MODE_GLL | MODE_MASS)) {
+    if (mode & (MODE_GLL | MODE_MASS | MODE_Q2)) {
         if constexpr (!std::is_same<T, double>::value) {
             return hipErrorInvalidValue; /* FP64 only */
         } else {
-            const bool mass = mode & MODE_MASS;
-            if ((mode & MODE_GLL) && mass) return hipErrorInvalidValue;
-            mode &= ~(MODE_GLL | MODE_MASS);
-            if (mass) {
-                if (mode == MODE_CG)
-                    hipLaunchKernelGGL((fused_tile_kernel<K, T, MODE_CG, OPV_MASS>), grid, block, 0, s, a);
-                else if (mode == MODE_CG_NOPREC)
-                    hipLaunchKernelGGL((fused_tile_kernel<K, T, MODE_CG_NOPREC, OPV_MASS>), grid, block, 0, s, a);
-                else
-                    hipLaunchKernelGGL((fused_tile_kernel<K, T, MODE_VMULT, OPV_MASS>), grid, block, 0, s, a);
+            const bool mass = mode & MODE_MASS, gll = mode & MODE_GLL, q2 = mode & MODE_Q2;
+            if (gll && (mass || q2)) return hipErrorInvalidValue;
+            mode &= ~(MODE_GLL | MODE_MASS | MODE_Q2);
+            if (mode != MODE_CG && mode != MODE_CG_NOPREC && mode != MODE_VMULT) return hipErrorInvalidValue;
+            if (q2) {
+                if constexpr (K <= 7) {
+                    if (mass) launch_fused_variant<K, OPV_MASS, 1>(mode, grid, block, a, s);
+                    else launch_fused_variant<K, OPV_LAPLACE, 1>(mode, grid, block, a, s);
+                } else {
+                    return hipErrorInvalidValue;
+                }
+            } else if (mass) {
+                launch_fused_variant<K, OPV_MASS, 0>(mode, grid, block, a, s);
             } else {
-                if (mode == MODE_CG)
-                    hipLaunchKernelGGL((fused_tile_kernel<K, T, MODE_CG, OPV_LAPLACE_GLL>), grid, block, 0, s, a);
-                else if (mode == MODE_CG_NOPREC)
-                    hipLaunchKernelGGL((fused_tile_kernel<K, T, MODE_CG_NOPREC, OPV_LAPLACE_GLL>), grid, block, 0, s,
-                                       a);
-                else
-                    hipLaunchKernelGGL((fused_tile_kernel<K, T, MODE_VMULT, OPV_LAPLACE_GLL>), grid, block, 0, s, a);
+                launch_fused_variant<K, OPV_LAPLACE_GLL, 0>(mode, grid, block, a, s);
             }
             return hipGetLastError();
         }
@@ -989,6 +1021,19 @@ static hipError_t launch_fused_vec_k(int mode, const IterArgs<double> &a, int64_
                                      int64_t dstride, hipStream_t s)
 {
     dim3 grid((unsigned)(3 * a.L.ntiles)), block(Cfg<K>::WG);
+    if (mode == (MODE_CG | MODE_Q2) || mode == (MODE_CG | MODE_MASS | MODE_Q2)) {
+        if constexpr (K <= 7) {
+            if (mode & MODE_MASS)
+                hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_MASS, 1>), grid, block, 0, s, a, nstride,
+                                   pstride, dstride);
+            else
+                hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_LAPLACE, 1>), grid, block, 0, s, a, nstride,
+                                   pstride, dstride);
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     if (mode == MODE_CG)
         hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_LAPLACE>), grid, block, 0, s, a, nstride, pstride,
                            dstride);

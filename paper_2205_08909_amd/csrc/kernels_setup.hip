@@ -70,11 +70,11 @@ __device__ inline double cell_jacobian(const GeomArgs &g, const int c[3], const 
 }
 
 /* Offset of component 0 of G at (cell, q) in the tile-blocked layout read
- * by the fused kernel, and the component stride. */
-__device__ inline int64_t g_offset(const LayoutView &L, int K, const int c[3], int qx, int qy, int qz,
+ * by the fused kernel (nq points per direction), and the component stride. */
+__device__ inline int64_t g_offset(const LayoutView &L, int nq, const int c[3], int qx, int qy, int qz,
                                    int64_t &cstride)
 {
-    const int n = K + 1, n2 = n * n, n3 = n2 * n;
+    const int n = nq, n2 = n * n, n3 = n2 * n;
     int t[3], cl[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -92,7 +92,7 @@ __device__ inline int64_t g_offset(const LayoutView &L, int K, const int c[3], i
 
 __global__ __launch_bounds__(SETUP_WG) void geometry_kernel(const GeomArgs g, double *G)
 {
-    const int K = g.K, n = K + 1, n3 = n * n * n;
+    const int n = g.nq, n3 = n * n * n;
     const int64_t ncell = (int64_t)g.L.d[0].ncells * g.L.d[1].ncells * g.L.d[2].ncells;
     const int64_t t = (int64_t)blockIdx.x * SETUP_WG + threadIdx.x;
     if (t >= ncell * n3) return;
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(SETUP_WG) void geometry_kernel(const GeomArgs g, do
     const double w = ae * g.tab.wq[qx] * g.tab.wq[qy] * g.tab.wq[qz] * det;
     auto m = [&](int p, int r) { return w * (Ji[p][0] * Ji[r][0] + Ji[p][1] * Ji[r][1] + Ji[p][2] * Ji[r][2]); };
     int64_t cs;
-    const int64_t o = g_offset(g.L, K, c, qx, qy, qz, cs);
+    const int64_t o = g_offset(g.L, n, c, qx, qy, qz, cs);
     if (g.op == 1) { /* mass operator: a_e w_q det J_q */
         G[o] = w;
         for (int comp = 1; comp < 6; ++comp) G[o + comp * cs] = 0.0;
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(SETUP_WG) void geometry_kernel(const GeomArgs g, do
 
 hipError_t launch_geometry(const GeomArgs &g, double *G, hipStream_t s)
 {
-    const int n = g.K + 1;
+    const int n = g.nq;
     const int64_t tot = (int64_t)g.L.d[0].ncells * g.L.d[1].ncells * g.L.d[2].ncells * n * n * n;
     const int64_t nb = (tot + SETUP_WG - 1) / SETUP_WG;
     hipLaunchKernelGGL(geometry_kernel, dim3((unsigned)nb), dim3(SETUP_WG), 0, s, g, G);
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(SETUP_WG) void diagonal_kernel(const GeomArgs g, co
                                                             double *dinv_int)
 {
     const LayoutView &L = g.L;
-    const int K = g.K, n = K + 1;
+    const int K = g.K, n = K + 1, nq = g.nq;
     const int64_t t = (int64_t)blockIdx.x * SETUP_WG + threadIdx.x;
     if (t >= L.n) return;
     int64_t gc[3];
@@ -232,25 +232,25 @@ __global__ __launch_bounds__(SETUP_WG) void diagonal_kernel(const GeomArgs g, co
                     const int ix = (int)(gc[0] - (int64_t)cx * K), iy = (int)(gc[1] - (int64_t)cy * K),
                               iz = (int)(gc[2] - (int64_t)cz * K);
                     if (g.op == 1) { /* mass: sum_q a_e w_q det J_q phi_i^2 */
-                        for (int qz = 0; qz < n; ++qz)
-                            for (int qy = 0; qy < n; ++qy)
-                                for (int qx = 0; qx < n; ++qx) {
+                        for (int qz = 0; qz < nq; ++qz)
+                            for (int qy = 0; qy < nq; ++qy)
+                                for (int qx = 0; qx < nq; ++qx) {
                                     int64_t cs;
-                                    const int64_t o = g_offset(L, K, c, qx, qy, qz, cs);
+                                    const int64_t o = g_offset(L, nq, c, qx, qy, qz, cs);
                                     const double phi =
                                         g.tab.S[qx * n + ix] * g.tab.S[qy * n + iy] * g.tab.S[qz * n + iz];
                                     dsum += G[o] * phi * phi;
                                 }
                         continue;
                     }
-                    for (int qz = 0; qz < n; ++qz)
-                        for (int qy = 0; qy < n; ++qy)
-                            for (int qx = 0; qx < n; ++qx) {
+                    for (int qz = 0; qz < nq; ++qz)
+                        for (int qy = 0; qy < nq; ++qy)
+                            for (int qx = 0; qx < nq; ++qx) {
                                 const double gx = g.tab.Sd[qx * n + ix] * g.tab.S[qy * n + iy] * g.tab.S[qz * n + iz];
                                 const double gy = g.tab.S[qx * n + ix] * g.tab.Sd[qy * n + iy] * g.tab.S[qz * n + iz];
                                 const double gz = g.tab.S[qx * n + ix] * g.tab.S[qy * n + iy] * g.tab.Sd[qz * n + iz];
                                 int64_t cs;
-                                const int64_t o = g_offset(L, K, c, qx, qy, qz, cs);
+                                const int64_t o = g_offset(L, nq, c, qx, qy, qz, cs);
                                 const double g00 = G[o], g11 = G[o + cs], g22 = G[o + 2 * cs], g01 = G[o + 3 * cs],
                                              g02 = G[o + 4 * cs], g12 = G[o + 5 * cs];
                                 dsum += g00 * gx * gx + g11 * gy * gy + g22 * gz * gz +
@@ -294,7 +294,7 @@ __device__ inline double forcing(const RhsParams &f, const double x[3])
 __global__ __launch_bounds__(SETUP_WG) void rhs_kernel(const GeomArgs g, const RhsParams f, double *b)
 {
     const LayoutView &L = g.L;
-    const int K = g.K, n = K + 1;
+    const int K = g.K, n = K + 1, nq = g.nq;
     const int64_t t = (int64_t)blockIdx.x * SETUP_WG + threadIdx.x;
     if (t >= L.n) return;
     int64_t gc[3];
@@ -309,9 +309,9 @@ __global__ __launch_bounds__(SETUP_WG) void rhs_kernel(const GeomArgs g, const R
                     const int c[3] = {cx, cy, cz};
                     const int ix = (int)(gc[0] - (int64_t)cx * K), iy = (int)(gc[1] - (int64_t)cy * K),
                               iz = (int)(gc[2] - (int64_t)cz * K);
-                    for (int qz = 0; qz < n; ++qz)
-                        for (int qy = 0; qy < n; ++qy)
-                            for (int qx = 0; qx < n; ++qx) {
+                    for (int qz = 0; qz < nq; ++qz)
+                        for (int qy = 0; qy < nq; ++qy)
+                            for (int qx = 0; qx < nq; ++qx) {
                                 const double xi[3] = {g.tab.xq[qx], g.tab.xq[qy], g.tab.xq[qz]};
                                 double x[3], J[3][3];
                                 const double det = cell_jacobian(g, c, xi, x, J);

@@ -93,12 +93,13 @@ static long double lagrange_value(int n, const long double *x, int i, long doubl
     return v;
 }
 
-int build_tables(int K, Tables<double> &tab, bool gll_quadrature)
+int build_tables(int K, Tables<double> &tab, bool gll_quadrature, int nq)
 {
-    if (K < 1 || K + 1 > MAXN) return -1;
+    if (nq == 0) nq = K + 1;
+    if (K < 1 || K + 1 > MAXN || nq > MAXN || nq < K + 1 || nq > K + 2 || (gll_quadrature && nq != K + 1)) return -1;
     const int n = K + 1;
     long double xg[MAXN], wg[MAXN], xl[MAXN], bw[MAXN];
-    gauss_points(n, xg, wg);
+    gauss_points(nq, xg, wg);
     lobatto_points(K, xl);
     if (gll_quadrature) {
         /* quadrature on the nodes: weights 2 / (k (k+1) P_k(t_i)^2) on
@@ -113,29 +114,31 @@ int build_tables(int K, Tables<double> &tab, bool gll_quadrature)
             wg[i] = 1.0L / ((long double)K * (K + 1) * p * p);
         }
     }
-    bary_weights(n, xg, bw);
+    /* S: nq x n (basis at the points), D: nq x nq (collocation derivative
+     * on the points), Sd = D S: nq x n (basis derivatives at the points) */
+    bary_weights(nq, xg, bw);
     long double S[MAXN * MAXN], D[MAXN * MAXN];
-    for (int q = 0; q < n; ++q)
+    for (int q = 0; q < nq; ++q)
         for (int i = 0; i < n; ++i) S[q * n + i] = lagrange_value(n, xl, i, xg[q]);
-    for (int q = 0; q < n; ++q) {
+    for (int q = 0; q < nq; ++q) {
         long double diag = 0.0L;
-        for (int m = 0; m < n; ++m) {
+        for (int m = 0; m < nq; ++m) {
             if (m == q) continue;
-            D[q * n + m] = (bw[m] / bw[q]) / (xg[q] - xg[m]);
-            diag -= D[q * n + m];
+            D[q * nq + m] = (bw[m] / bw[q]) / (xg[q] - xg[m]);
+            diag -= D[q * nq + m];
         }
-        D[q * n + q] = diag;
+        D[q * nq + q] = diag;
     }
     std::memset(&tab, 0, sizeof(tab));
-    for (int q = 0; q < n; ++q) {
+    for (int i = 0; i < n; ++i) tab.gll[i] = (double)xl[i];
+    for (int q = 0; q < nq; ++q) {
         tab.xq[q] = (double)xg[q];
         tab.wq[q] = (double)wg[q];
-        tab.gll[q] = (double)xl[q];
+        for (int m = 0; m < nq; ++m) tab.D[q * nq + m] = (double)D[q * nq + m];
         for (int i = 0; i < n; ++i) {
             tab.S[q * n + i] = (double)S[q * n + i];
-            tab.D[q * n + i] = (double)D[q * n + i];
             long double sd = 0.0L;
-            for (int m = 0; m < n; ++m) sd += D[q * n + m] * S[m * n + i];
+            for (int m = 0; m < nq; ++m) sd += D[q * nq + m] * S[m * n + i];
             tab.Sd[q * n + i] = (double)sd;
         }
     }
@@ -187,7 +190,7 @@ static int64_t piece_len(const Dim1 &d, int64_t e)
     return cells * d.K - 1;
 }
 
-int build_layout(const int ncells[3], int K, const int tile_in[3], int bc, HostLayout &L)
+int build_layout(const int ncells[3], int K, const int tile_in[3], int bc, HostLayout &L, int nq)
 {
     L = HostLayout();
     L.K = K;
@@ -231,7 +234,7 @@ int build_layout(const int ncells[3], int K, const int tile_in[3], int bc, HostL
     int64_t pos = 0;
     L.tiles.resize(L.ntiles);
     int64_t gpos = 0;
-    const int n = K + 1;
+    const int n = nq > 0 ? nq : K + 1; /* quadrature points per direction */
     for (int64_t tz = 0; tz < L.d[2].ntiles; ++tz)
         for (int64_t ty = 0; ty < L.d[1].ntiles; ++ty)
             for (int64_t tx = 0; tx < L.d[0].ntiles; ++tx) {

@@ -24,11 +24,13 @@ struct HostLayout {
     std::vector<TileDesc> tiles;
 };
 
-/* Gauss points (default) or, with gll_quadrature, the GLL nodes themselves
- * as quadrature points (S = identity). */
-int build_tables(int K, Tables<double> &tab, bool gll_quadrature = false);
+/* nq Gauss points per direction (default k + 1; k + 2 allowed) or, with
+ * gll_quadrature, the k + 1 GLL nodes themselves as quadrature points
+ * (S = identity).  S and Sd are nq x (k+1), D is nq x nq, row-major. */
+int build_tables(int K, Tables<double> &tab, bool gll_quadrature = false, int nq = 0);
 void default_tile(int K, int tile[3]);
-int build_layout(const int ncells[3], int K, const int tile[3], int bc, HostLayout &L);
+/* nq: quadrature points per direction of the geometry tensor (0: k + 1) */
+int build_layout(const int ncells[3], int K, const int tile[3], int bc, HostLayout &L, int nq = 0);
 void dim_locate_host(const Dim1 &d, int64_t g, int64_t &e, int64_t &l, int64_t &len);
 void host_permutation(const HostLayout &L, int64_t *perm);
 

@@ -128,6 +128,72 @@ constexpr Tab<NP> make_tab()
     return t;
 }
 
+/* NQ = NP + 1 Gauss points with the NP-node GLL basis (the (k+2)-point
+ * rules of the benchmark problems): S is NQ x NP, D is NQ x NQ (the
+ * collocation derivative on the Gauss points), both row-major. */
+template <int NP, int NQ>
+struct Tab2 {
+    double S[NQ * NP];
+    double D[NQ * NQ];
+    double xq[NQ];
+    double gll[NP];
+};
+
+template <int NP, int NQ>
+constexpr Tab2<NP, NQ> make_tab2()
+{
+    Tab2<NP, NQ> t{};
+    constexpr int k = NP - 1;
+    for (int i = 0; i < NQ; ++i) {
+        double x = -ccos(PI * (i + 0.75) / (NQ + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double p = 0, dp = 0;
+            legendre(NQ, x, p, dp);
+            const double dx = p / dp;
+            x -= dx;
+            if (cabs(dx) < 1e-17) break;
+        }
+        t.xq[i] = 0.5 * (1.0 + x);
+    }
+    t.gll[0] = 0.0;
+    t.gll[k] = 1.0;
+    for (int i = 1; i < k; ++i) {
+        double x = -ccos(PI * i / k);
+        for (int it = 0; it < 100; ++it) {
+            double p = 0, dp = 0;
+            legendre(k, x, p, dp);
+            const double ddp = (2.0 * x * dp - k * (k + 1.0) * p) / (1.0 - x * x);
+            const double dx = dp / ddp;
+            x -= dx;
+            if (cabs(dx) < 1e-17) break;
+        }
+        t.gll[i] = 0.5 * (1.0 + x);
+    }
+    for (int q = 0; q < NQ; ++q)
+        for (int i = 0; i < NP; ++i) {
+            double v = 1.0;
+            for (int j = 0; j < NP; ++j)
+                if (j != i) v *= (t.xq[q] - t.gll[j]) / (t.gll[i] - t.gll[j]);
+            t.S[q * NP + i] = v;
+        }
+    double w[NQ] = {};
+    for (int i = 0; i < NQ; ++i) {
+        w[i] = 1.0;
+        for (int j = 0; j < NQ; ++j)
+            if (j != i) w[i] /= (t.xq[i] - t.xq[j]);
+    }
+    for (int q = 0; q < NQ; ++q) {
+        double diag = 0.0;
+        for (int m = 0; m < NQ; ++m) {
+            if (m == q) continue;
+            t.D[q * NQ + m] = (w[m] / w[q]) / (t.xq[q] - t.xq[m]);
+            diag -= t.D[q * NQ + m];
+        }
+        t.D[q * NQ + q] = diag;
+    }
+    return t;
+}
+
 template <int NP>
 struct Tables1D {
     static constexpr Tab<NP> t = make_tab<NP>();

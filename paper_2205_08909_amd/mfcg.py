@@ -122,9 +122,9 @@ def make_mesh(cells, map_kind=MAP_AFFINE, amplitude=0.0, bc=BC_DIRICHLET0):
     return m
 
 
-def make_options(tile=None, check_every=0, fp32=0, quad=QUAD_GAUSS, op=OP_LAPLACE):
+def make_options(tile=None, check_every=0, fp32=0, quad=QUAD_GAUSS, op=OP_LAPLACE, n_q_1d=0):
     o = Options()
-    o.n_q_1d = 0
+    o.n_q_1d = int(n_q_1d)
     for d in range(3):
         o.tile[d] = 0 if tile is None else int(tile[d])
     o.check_every = int(check_every)
@@ -176,10 +176,10 @@ class Problem:
     """mfcg_setup on a mesh + degree + per-cell coefficient."""
 
     def __init__(self, cells, degree, coeff=None, map_kind=MAP_AFFINE, amplitude=0.0, bc=BC_DIRICHLET0, tile=None,
-                 check_every=0, stream=None, quad=QUAD_GAUSS, op=OP_LAPLACE):
+                 check_every=0, stream=None, quad=QUAD_GAUSS, op=OP_LAPLACE, n_q_1d=0):
         self.mesh = make_mesh(cells, map_kind, amplitude, bc)
         self.degree = int(degree)
-        self.opt = make_options(tile, check_every, quad=quad, op=op)
+        self.opt = make_options(tile, check_every, quad=quad, op=op, n_q_1d=n_q_1d)
         self.h = ctypes.c_void_p()
         self._coeff = None
         if coeff is not None:

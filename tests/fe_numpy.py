@@ -145,18 +145,19 @@ def kronecker_mass(k, ncells, lumped=False):
     return np.kron(Mz, np.kron(My, Mx))
 
 
-def element_mass_fd(k, ncells, cell, kind, amp, a_e=1.0):
-    """Element mass matrix with numpy's (k+1)-point Gauss rule and an FD
-    Jacobian determinant."""
+def element_mass_fd(k, ncells, cell, kind, amp, a_e=1.0, nq1=None):
+    """Element mass matrix with numpy's nq1-point Gauss rule (default k+1)
+    and an FD Jacobian determinant."""
     nodes = gll_nodes(k)
-    xq, wq = gauss_rule(k + 1)
+    nq1 = k + 1 if nq1 is None else nq1
+    xq, wq = gauss_rule(nq1)
     val, _ = basis_1d(nodes, xq)
     n = k + 1
     ncells = np.asarray(ncells, dtype=np.float64)
     A = np.zeros((n ** 3, n ** 3))
-    for qz in range(n):
-        for qy in range(n):
-            for qx in range(n):
+    for qz in range(nq1):
+        for qy in range(nq1):
+            for qx in range(nq1):
                 X = (np.asarray(cell) + np.array([xq[qx], xq[qy], xq[qz]])) / ncells
                 det = np.linalg.det(fd_jacobian(kind, amp, X) / ncells[None, :])
                 phi = np.einsum("k,j,i->kji", val[qz], val[qy], val[qx]).ravel()

@@ -11,7 +11,11 @@
   under GLL), total mass 1, curved element matrices against the FD build,
 * with GLL collocation (quadrature at the k+1 nodes, BP5): the affine matrix
   is the Kronecker sum with the diagonal (lumped) 1D mass of the basis
-  integrals, and curved element matrices match the FD-Jacobian build.
+  integrals, and curved element matrices match the FD-Jacobian build,
+* with k+2 Gauss points per direction (the BP1-BP4 rule): affine matrices
+  equal the same exact Kronecker forms (both rules integrate them exactly),
+  curved element matrices (Laplacian and mass) match the FD build on k+2
+  points and differ from the (k+1)-point ones.
 """
 import os
 
@@ -190,3 +194,35 @@ def test_maps_invertible(oracle_mod):
     for kind, lo, hi in [(1, 0.85, 1.15), (2, 0.6, 1.4)]:
         dets = np.array([O.map_det(kind, 0.05, x) for x in X])
         assert dets.min() > lo and dets.max() < hi
+
+
+@pytest.mark.parametrize("k,ncells", [(1, (2, 3, 2)), (3, (2, 1, 2)), (5, (1, 1, 2))])
+def test_kplus2_kronecker_closed_form(oracle_mod, k, ncells):
+    """k+2 Gauss points integrate the affine Laplacian and mass exactly, like k+1."""
+    O = oracle_mod
+    A = O.assemble(O.Mesh(ncells, k, nq1=k + 2, bc=O.BC_NONE)).to_scipy().toarray()
+    ref = fe_numpy.kronecker_laplacian(k, ncells)
+    assert np.abs(A - ref).max() <= 1e-13 * np.abs(ref).max()
+    M = O.assemble(O.Mesh(ncells, k, nq1=k + 2, bc=O.BC_NONE, op="mass")).to_scipy().toarray()
+    refm = fe_numpy.kronecker_mass(k, ncells)
+    assert np.abs(M - refm).max() <= 1e-14 * np.abs(refm).max() + 1e-17
+
+
+@pytest.mark.parametrize("kind,amp,k", [(1, 0.05, 2), (2, 0.05, 3), (1, 0.1, 1)])
+def test_kplus2_element_fd_jacobian(oracle_mod, kind, amp, k):
+    O = oracle_mod
+    ncells = (2, 3, 2)
+    coeff = np.linspace(0.5, 2.0, 12)
+    m2 = O.Mesh(ncells, k, nq1=k + 2, map_kind=kind, amp=amp)
+    m1 = O.Mesh(ncells, k, map_kind=kind, amp=amp)
+    mm = O.Mesh(ncells, k, nq1=k + 2, map_kind=kind, amp=amp, coeff=coeff, op="mass")
+    for cell in [(0, 0, 0), (1, 2, 1)]:
+        A = O.element_matrix(m2, cell)
+        ref = fe_numpy.element_matrix_fd(k, k + 2, ncells, cell, kind, amp)
+        assert np.abs(A - ref).max() <= 1e-8 * np.abs(ref).max()
+        # under the curved map the two rules give different matrices
+        assert np.abs(A - O.element_matrix(m1, cell)).max() > 1e-7 * np.abs(ref).max()
+        M = O.element_matrix(mm, cell)
+        ae = coeff[cell[0] + 2 * (cell[1] + 3 * cell[2])]
+        refm = fe_numpy.element_mass_fd(k, ncells, cell, kind, amp, a_e=ae, nq1=k + 2)
+        assert np.abs(M - refm).max() <= 1e-8 * np.abs(refm).max()
