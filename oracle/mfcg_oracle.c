@@ -23,6 +23,8 @@
  * matrices are built by brute force over all (i, j, q) triples, no sum
  * factorization, no fusion.
  *
+ *   - optionally, the map replaced by its per-cell quadratic interpolant
+ *     (quadratic geometry, Sec. 2.2; map kind bit OR_MAP_QUADRATIC).
  * Readings where the paper is silent:
  *   - nodal points of the 1D basis: Gauss-Lobatto-Legendre points,
  *   - quadrature: Gauss-Legendre with nq1 points per direction (nq1 = k+1
@@ -188,13 +190,50 @@ static void map_point(int kind, double A, const double X[3], double x[3],
     }
 }
 
+/* Map kinds with this bit set: in every cell the map is replaced by its
+ * tensor-product quadratic interpolant through the 27 points
+ * (c + (a, b, d) / 2) / n, a, b, d in {0, 1, 2} -- the quadratic geometry
+ * of Sec. 2.2 whose Jacobians are evaluated at the quadrature points
+ * instead of being stored. */
+#define OR_MAP_QUADRATIC 16
+
 /* Point of cell (cx,cy,cz) at reference coordinate xi in [0,1]^3: the
  * Cartesian position X, the mapped position x and the Jacobian
- * J = dx/dxi = DF(X) * diag(1/n). */
+ * J = dx/dxi = DF(X) * diag(1/n) (of the interpolant for quadratic
+ * geometry: x = sum_node x_node N_node(xi), J = sum_node x_node grad N_node). */
 static void cell_point(const int n[3], int kind, double A, const int c[3],
                        const double xi[3], double x[3], double J[3][3])
 {
     double X[3], DF[3][3];
+    if (kind & OR_MAP_QUADRATIC) {
+        static const double q2nodes[3] = {0.0, 0.5, 1.0};
+        double N[3][3], dN[3][3]; /* [direction][node] */
+        for (int d = 0; d < 3; ++d)
+            for (int a = 0; a < 3; ++a) {
+                N[d][a] = oracle_lagrange(3, q2nodes, a, xi[d]);
+                dN[d][a] = oracle_lagrange_deriv(3, q2nodes, a, xi[d]);
+            }
+        for (int i = 0; i < 3; ++i) {
+            x[i] = 0.0;
+            for (int j = 0; j < 3; ++j) J[i][j] = 0.0;
+        }
+        for (int cz = 0; cz < 3; ++cz)
+            for (int cy = 0; cy < 3; ++cy)
+                for (int cx = 0; cx < 3; ++cx) {
+                    double xn[3];
+                    const int a[3] = {cx, cy, cz};
+                    for (int d = 0; d < 3; ++d) X[d] = (c[d] + q2nodes[a[d]]) / n[d];
+                    map_point(kind & ~OR_MAP_QUADRATIC, A, X, xn, DF);
+                    const double v = N[0][cx] * N[1][cy] * N[2][cz];
+                    const double g[3] = {dN[0][cx] * N[1][cy] * N[2][cz], N[0][cx] * dN[1][cy] * N[2][cz],
+                                         N[0][cx] * N[1][cy] * dN[2][cz]};
+                    for (int i = 0; i < 3; ++i) {
+                        x[i] += xn[i] * v;
+                        for (int j = 0; j < 3; ++j) J[i][j] += xn[i] * g[j];
+                    }
+                }
+        return;
+    }
     for (int d = 0; d < 3; ++d) X[d] = (c[d] + xi[d]) / n[d];
     map_point(kind, A, X, x, DF);
     for (int i = 0; i < 3; ++i)

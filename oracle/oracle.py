@@ -136,11 +136,15 @@ class Mesh:
     Cell numbering: c = cx + n0 (cy + n1 cz)."""
 
     def __init__(self, ncells, k, nq1=None, map_kind=MAP_AFFINE, amp=0.0, bc=BC_DIRICHLET, coeff=None,
-                 quad="gauss", op="laplace"):
+                 quad="gauss", op="laplace", geometry="exact"):
         """quad: "gauss" (Gauss-Legendre, nq1 points, default k+1) or "gll"
         (Gauss-Lobatto-Legendre on nq1 points, default k+1: collocation at
         the nodes); op: "laplace" (Eq. 5) or "mass" (a_e w_q det J phi_i
-        phi_j)."""
+        phi_j); geometry: "exact" (the map itself) or "quadratic" (in every
+        cell the map's tensor-product quadratic interpolant through 27
+        points, Sec. 2.2)."""
+        assert geometry in ("exact", "quadratic")
+        self.geom_bit = 16 if geometry == "quadratic" else 0
         assert op in ("laplace", "mass")
         self.op = 0 if op == "laplace" else 1
         if np.isscalar(ncells):
@@ -167,7 +171,8 @@ class Mesh:
         return int(lib().oracle_n_nodes(_ptr(self.ncells), self.k))
 
     def args(self):
-        return [_ptr(self.ncells), self.k, self.nq1, self.map_kind, self.amp, self.bc, _ptr(self.coeff), self.op]
+        return [_ptr(self.ncells), self.k, self.nq1, self.map_kind | self.geom_bit, self.amp, self.bc,
+                _ptr(self.coeff), self.op]
 
     def constrained_mask(self):
         L = self.lattice

@@ -136,6 +136,40 @@ def fd_jacobian(kind, amp, X, h=1e-6):
     return J
 
 
+def quadratic_map_numpy(kind, amp, ncells, cell, xi):
+    """The map's quadratic interpolant in one cell at reference points xi
+    (shape (..., 3)): sum over the 27 points X_abd = (cell + (a, b, d)/2) / n
+    of F(X_abd) N_a(xi_0) N_b(xi_1) N_d(xi_2), with the closed-form quadratic
+    Lagrange basis on {0, 1/2, 1}."""
+    xi = np.asarray(xi, dtype=np.float64)
+
+    def basis(t):
+        return np.stack([(2 * t - 1) * (t - 1), 4 * t * (1 - t), t * (2 * t - 1)], axis=-1)
+
+    Nx, Ny, Nz = basis(xi[..., 0]), basis(xi[..., 1]), basis(xi[..., 2])
+    out = np.zeros(xi.shape)
+    n = np.asarray(ncells, dtype=np.float64)
+    for d in range(3):
+        for b in range(3):
+            for a in range(3):
+                X = (np.asarray(cell, dtype=np.float64) + np.array([a, b, d]) / 2.0) / n
+                F = map_numpy(kind, amp, X)
+                out += F * (Nx[..., a] * Ny[..., b] * Nz[..., d])[..., None]
+    return out
+
+
+def quadratic_jacobian(kind, amp, ncells, cell, xi, h=1e-2):
+    """dx/dxi of the quadratic interpolant by central differences, which
+    are exact for a polynomial of degree 2 in the differentiated variable."""
+    J = np.zeros((3, 3))
+    for j in range(3):
+        e = np.zeros(3)
+        e[j] = h
+        J[:, j] = (quadratic_map_numpy(kind, amp, ncells, cell, xi + e)
+                   - quadratic_map_numpy(kind, amp, ncells, cell, xi - e)) / (2 * h)
+    return J
+
+
 def kronecker_mass(k, ncells, lumped=False):
     """Mass matrix Mz(x)My(x)Mx of the affine unit cube."""
     nx, ny, nz = ncells
@@ -165,9 +199,10 @@ def element_mass_fd(k, ncells, cell, kind, amp, a_e=1.0, nq1=None):
     return A
 
 
-def element_matrix_fd(k, nq1, ncells, cell, kind, amp, a_e=1.0, quad="gauss"):
+def element_matrix_fd(k, nq1, ncells, cell, kind, amp, a_e=1.0, quad="gauss", geometry="exact"):
     """Element stiffness matrix with numpy's rules and an FD Jacobian
-    (quad "gll": the k+1 nodes with the basis integrals as weights)."""
+    (quad "gll": the k+1 nodes with the basis integrals as weights;
+    geometry "quadratic": the Jacobian of the map's quadratic interpolant)."""
     nodes = gll_nodes(k)
     if quad == "gll":
         nq1 = k + 1
@@ -184,7 +219,10 @@ def element_matrix_fd(k, nq1, ncells, cell, kind, amp, a_e=1.0, quad="gauss"):
             for qx in range(nq1):
                 xi = np.array([xq[qx], xq[qy], xq[qz]])
                 X = (np.asarray(cell) + xi) / ncells
-                J = fd_jacobian(kind, amp, X) / ncells[None, :]
+                if geometry == "quadratic":
+                    J = quadratic_jacobian(kind, amp, ncells, cell, xi)
+                else:
+                    J = fd_jacobian(kind, amp, X) / ncells[None, :]
                 det = np.linalg.det(J)
                 Jinv = np.linalg.inv(J)
                 w = wq[qx] * wq[qy] * wq[qz] * det * a_e

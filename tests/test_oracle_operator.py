@@ -12,6 +12,11 @@
 * with GLL collocation (quadrature at the k+1 nodes, BP5): the affine matrix
   is the Kronecker sum with the diagonal (lumped) 1D mass of the basis
   integrals, and curved element matrices match the FD-Jacobian build,
+* quadratic geometry (the map replaced per cell by its quadratic
+  interpolant through 27 points, Sec. 2.2): element matrices against a numpy
+  build from the closed-form quadratic basis with exact central
+  differences, identical to the exact geometry for an affine map, and
+  converging to the exact-geometry matrices at second order in h,
 * with k+2 Gauss points per direction (the BP1-BP4 rule): affine matrices
   equal the same exact Kronecker forms (both rules integrate them exactly),
   curved element matrices (Laplacian and mass) match the FD build on k+2
@@ -226,3 +231,35 @@ def test_kplus2_element_fd_jacobian(oracle_mod, kind, amp, k):
         ae = coeff[cell[0] + 2 * (cell[1] + 3 * cell[2])]
         refm = fe_numpy.element_mass_fd(k, ncells, cell, kind, amp, a_e=ae, nq1=k + 2)
         assert np.abs(M - refm).max() <= 1e-8 * np.abs(refm).max()
+
+
+@pytest.mark.parametrize("kind,amp,k", [(1, 0.05, 2), (2, 0.05, 4), (1, 0.1, 1)])
+def test_quadratic_geometry_element_fd(oracle_mod, kind, amp, k):
+    O = oracle_mod
+    ncells = (2, 3, 2)
+    m = O.Mesh(ncells, k, map_kind=kind, amp=amp, geometry="quadratic")
+    me = O.Mesh(ncells, k, map_kind=kind, amp=amp)
+    for cell in [(0, 0, 0), (1, 2, 1)]:
+        A = O.element_matrix(m, cell)
+        ref = fe_numpy.element_matrix_fd(k, k + 1, ncells, cell, kind, amp, geometry="quadratic")
+        assert np.abs(A - ref).max() <= 1e-11 * np.abs(ref).max()
+        assert np.abs(A - O.element_matrix(me, cell)).max() > 1e-6 * np.abs(ref).max()
+
+
+def test_quadratic_geometry_affine_and_convergence(oracle_mod):
+    O = oracle_mod
+    # an affine map is reproduced exactly
+    A = O.assemble(O.Mesh((2, 2, 3), 3, bc=O.BC_NONE, geometry="quadratic")).to_scipy().toarray()
+    ref = fe_numpy.kronecker_laplacian(3, (2, 2, 3))
+    assert np.abs(A - ref).max() <= 1e-13 * np.abs(ref).max()
+    # curved: the element matrix error against the exact map falls like h^2
+    # (the same physical cell, refined; ratios 3.6, 3.9, 4.0 -> 4)
+    errs = []
+    for n in (16, 32, 64, 128):
+        c = (n // 4, n // 2, n // 4)
+        me = O.Mesh((n, n, n), 2, map_kind=1, amp=0.1)
+        mq = O.Mesh((n, n, n), 2, map_kind=1, amp=0.1, geometry="quadratic")
+        Ae = O.element_matrix(me, c)
+        errs.append(np.abs(O.element_matrix(mq, c) - Ae).max() / np.abs(Ae).max())
+    rates = [errs[i] / errs[i + 1] for i in range(3)]
+    assert rates[0] > 3.3 and rates[1] > 3.7 and 3.8 < rates[2] < 4.2, errs
