@@ -400,11 +400,13 @@ def main():
         # the operator variations of the paper's benchmark list, fused CG on handles of their own:
         # GLL collocation (quadrature on the nodes, BP5), the mass operator (BP1; BP2 = three
         # components through the vector solve), and both operators on k+2 Gauss points per
-        # direction (the BP1-BP4 rule: BP3 scalar / BP4 vector Laplacian, BP1 / BP2 mass)
+        # direction (the BP1-BP4 rule: BP3 scalar / BP4 vector Laplacian, BP1 / BP2 mass), and the
+        # Laplacian with quadratic geometry evaluated in the kernel instead of the stored tensor
         variants = (("gll_collocation_ms", {"quad": mfcg.QUAD_GLL}, None),
                     ("mass_bp1_ms", {"op": mfcg.OP_MASS}, "mass_bp2_vector_ms"),
                     ("kplus2_bp3_ms", {"n_q_1d": k + 2}, "kplus2_bp4_vector_ms"),
-                    ("kplus2_mass_bp1_ms", {"op": mfcg.OP_MASS, "n_q_1d": k + 2}, "kplus2_mass_bp2_vector_ms"))
+                    ("kplus2_mass_bp1_ms", {"op": mfcg.OP_MASS, "n_q_1d": k + 2}, "kplus2_mass_bp2_vector_ms"),
+                    ("quadratic_geometry_ms", {"geometry": mfcg.GEOM_QUADRATIC}, None))
         for name, extra, vname in variants:
             if extra.get("n_q_1d", 0) > 9:  # k + 2 points up to k = 7
                 continue

@@ -107,6 +107,19 @@ enum {
                           * fp32 / mfcg_solve_ir, not in a batch */
 };
 
+/* Geometry representation of the operator (Sec. 2.2). */
+enum {
+    MFCG_GEOM_STORED = 0,   /* G_q = a_e w_q det J_q J_q^{-1} J_q^{-T} stored per quadrature point and read
+                             * by every mat-vec ("final tensor load"; default) */
+    MFCG_GEOM_QUADRATIC = 1 /* quadratic geometry: per cell the map's values at the 27 points
+                             * (c + (a, b, d) / 2) / n and a_e are stored (82 doubles); the mat-vec
+                             * evaluates J_q of their quadratic interpolant at each Gauss point and forms
+                             * G_q on the fly.  The operator is that of the interpolated map (diagonal and
+                             * load vector too).  Laplacian on k+1 Gauss points, FP64: not with n_q_1d =
+                             * k+2, GLL, the mass operator, fp32 / mfcg_solve_ir, mfcg_solve_vector or a
+                             * batch */
+};
+
 /* Options.  Zero-initialised fields select the defaults. */
 typedef struct {
     int32_t n_q_1d;          /* Gauss points per direction: 0 or k+1 (default), or k+2 (the
@@ -118,6 +131,7 @@ typedef struct {
     int32_t fp32;            /* 1: build the FP32 operator copy of mfcg_solve_ir at set-up (else on first use) */
     int32_t quad_rule;       /* MFCG_QUAD_* */
     int32_t op;              /* MFCG_OP_* */
+    int32_t geometry;        /* MFCG_GEOM_* */
 } mfcg_options;
 
 /* Builds the operator (Sec. 2, Eq. 3-5): tiles and DoF enumeration of the

@@ -38,6 +38,8 @@ struct mfcg_ctx {
     bool gll = false; /* quadrature on the GLL nodes (collocation) */
     bool mass = false; /* the mass operator instead of the Laplacian */
     bool q2 = false;   /* k + 2 Gauss points per direction instead of k + 1 */
+    bool qgeom = false; /* quadratic geometry evaluated in the operator kernel */
+    double *Xq = nullptr; /* its per-cell array (QGEOM_STRIDE doubles per cell) */
     /* solver, preconditioner and s fixed by cg_begin for the solve in progress */
     int solver_active = MFCG_SOLVER_FUSED;
     int sstep_active = 6;
@@ -117,7 +119,7 @@ static void release(mfcg_ctx *h)
                     h->dots,       h->sums,       h->hist,    h->st,      h->G32,   h->dinv32, h->r32,
                     h->p32,        h->v32,        h->x32,     h->part32,  h->dots32, h->st32,  h->hist32,
                     h->kvec,       h->kpart,      h->ks,      h->r3,      h->p3,    h->v3,     h->x3,
-                    h->dots3,      h->part3};
+                    h->dots3,      h->part3,      h->Xq};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (auto &e : h->ev_pool) {
@@ -187,15 +189,18 @@ static int validate_mesh(const mfcg_mesh *mesh, int32_t degree, const int32_t *t
 /* operator-variant flags for launch_fused */
 static int gll_flag(const mfcg_ctx *h)
 {
-    return (h->gll ? MODE_GLL : 0) | (h->mass ? MODE_MASS : 0) | (h->q2 ? MODE_Q2 : 0);
+    return (h->gll ? MODE_GLL : 0) | (h->mass ? MODE_MASS : 0) | (h->q2 ? MODE_Q2 : 0) | (h->qgeom ? MODE_QGEOM : 0);
 }
+/* what the operator kernels read as geometry: the stored tensor, or the
+ * per-cell quadratic geometry */
+static const double *op_geometry(const mfcg_ctx *h) { return h->qgeom ? h->Xq : h->G; }
 static int n_q(const mfcg_ctx *h) { return h->K + (h->q2 ? 2 : 1); }
 
 static int vmult_internal(mfcg_ctx *h, const double *src, double *dst, hipStream_t s)
 {
     IterArgs<double> a{};
     a.L = h->lv;
-    a.G = h->G;
+    a.G = op_geometry(h);
     a.dinv = h->dinv;
     a.src = src;
     a.dst = dst;
@@ -250,6 +255,10 @@ static int rebuild_operator(mfcg_ctx *h, hipStream_t s)
     g.coeff = h->d_coeff;
     g.op = h->mass ? 1 : 0;
     g.nq = n_q(h);
+    if (h->qgeom) {
+        HIPCHK(h, launch_qgeom_nodes(g, h->Xq, s));
+        g.X = h->Xq; /* the stored tensor (read by the diagonal) from the same interpolant */
+    }
     HIPCHK(h, launch_geometry(g, h->G, s));
     HIPCHK(h, launch_diagonal(g, h->G, h->diag_lex, h->dinv, s));
     if (h->G32) {
@@ -311,6 +320,11 @@ int mfcg_setup(const mfcg_mesh *mesh, int32_t degree, const double *cell_coeff, 
     const bool q2 = opt && opt->n_q_1d == degree + 2;
     if (q2 && (degree > 7 || opt->quad_rule != MFCG_QUAD_GAUSS || opt->fp32))
         return fail(nullptr, MFCG_EINVAL, "n_q_1d = k+2: Gauss points, FP64, k <= 7 only");
+    if (opt && opt->geometry != MFCG_GEOM_STORED && opt->geometry != MFCG_GEOM_QUADRATIC)
+        return fail(nullptr, MFCG_EINVAL, "unknown geometry");
+    const bool qgeom = opt && opt->geometry == MFCG_GEOM_QUADRATIC;
+    if (qgeom && (q2 || opt->quad_rule != MFCG_QUAD_GAUSS || opt->op != MFCG_OP_LAPLACE || opt->fp32))
+        return fail(nullptr, MFCG_EINVAL, "quadratic geometry: Laplacian on k+1 Gauss points, FP64 only");
     if (opt && opt->check_every < 0) return fail(nullptr, MFCG_EINVAL, "check_every must be >= 0");
     if (opt && opt->quad_rule != MFCG_QUAD_GAUSS && opt->quad_rule != MFCG_QUAD_GLL)
         return fail(nullptr, MFCG_EINVAL, "unknown quad_rule");
@@ -335,6 +349,7 @@ int mfcg_setup(const mfcg_mesh *mesh, int32_t degree, const double *cell_coeff, 
     h->gll = opt && opt->quad_rule == MFCG_QUAD_GLL;
     h->mass = opt && opt->op == MFCG_OP_MASS;
     h->q2 = q2;
+    h->qgeom = qgeom;
     hipStream_t s = (hipStream_t)hip_stream;
 
     auto bail = [&](int code) {
@@ -400,6 +415,7 @@ int mfcg_setup(const mfcg_mesh *mesh, int32_t degree, const double *cell_coeff, 
     h->nsum_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (L.n + 1023) / 1024));
 
     SCHK(dalloc(&h->G, L.g_elems));
+    if (h->qgeom) SCHK(dalloc(&h->Xq, ncell * QGEOM_STRIDE));
     SCHK(dalloc(&h->dinv, L.n));
     SCHK(dalloc(&h->diag_lex, L.n));
     SCHK(dalloc(&h->r, L.n));
@@ -563,6 +579,7 @@ int mfcg_assemble_rhs(mfcg_handle h, int32_t kind, const double *params, double 
     g.bc = h->mesh.bc;
     g.coeff = h->d_coeff;
     g.nq = n_q(h);
+    g.X = h->qgeom ? h->Xq : nullptr;
     HIPCHK(h, launch_rhs(g, kind, params, np, b, (hipStream_t)hip_stream));
     return MFCG_OK;
 }
@@ -771,7 +788,7 @@ int mfcg_cg_iterate(mfcg_handle h, int32_t n_it, void *hip_stream)
     hipStream_t s = (hipStream_t)hip_stream;
     IterArgs<double> a{};
     a.L = h->lv;
-    a.G = h->G;
+    a.G = op_geometry(h);
     a.dinv = h->dinv;
     a.r = h->r;
     a.p = h->p;
@@ -907,6 +924,7 @@ int mfcg_solve_vector(mfcg_handle h, const double *b, double *x, double tol, int
     if (!h || !b || !x || !iters) return fail(h, MFCG_EINVAL, "null argument");
     if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(h, MFCG_EINVAL, "tol must be finite and >= 0");
     if (maxit < 1) return fail(h, MFCG_EINVAL, "maxit must be >= 1");
+    if (h->qgeom) return fail(h, MFCG_EINVAL, "the vector solve runs on the stored tensor only");
     hipStream_t s = (hipStream_t)hip_stream;
     const int64_t n = h->hl.n;
     const int64_t nrec = h->hl.ntiles + h->nshared_blocks; /* records per component */
@@ -965,7 +983,7 @@ int mfcg_solve_vector(mfcg_handle h, const double *b, double *x, double tol, int
         IterArgs<double> &a = ac[c];
         a = IterArgs<double>{};
         a.L = h->lv;
-        a.G = h->G;
+        a.G = op_geometry(h);
         a.dinv = h->dinv;
         a.r = h->r3 + c * n;
         a.p = h->p3 + c * n;
@@ -1060,8 +1078,9 @@ int mfcg_solve(mfcg_handle h, const double *b, double *x, double tol, int32_t ma
 static int ensure_fp32(mfcg_ctx *h, hipStream_t s)
 {
     if (h->G32) return MFCG_OK;
-    if (h->gll || h->mass || h->q2)
-        return fail(h, MFCG_EINVAL, "the FP32 operator is built for the Gauss-point Laplacian (k+1 points) only");
+    if (h->gll || h->mass || h->q2 || h->qgeom)
+        return fail(h, MFCG_EINVAL,
+                    "the FP32 operator is built for the Gauss-point Laplacian (k+1 points, stored tensor) only");
     const HostLayout &L = h->hl;
     HIPCHK(h, dalloc(&h->G32, L.g_elems));
     HIPCHK(h, dalloc(&h->dinv32, L.n));
@@ -1153,8 +1172,8 @@ int mfcg_solve_ir(mfcg_handle h, const double *b, double *x, double tol, double 
     if (!(tol > 0.0) || !std::isfinite(tol) || !(inner_tol > 0.0) || !(inner_tol < 1.0))
         return fail(h, MFCG_EINVAL, "need tol > 0 and 0 < inner_tol < 1");
     if (max_outer < 1 || max_inner < 1) return fail(h, MFCG_EINVAL, "max_outer and max_inner must be >= 1");
-    if (h->gll || h->mass || h->q2)
-        return fail(h, MFCG_EINVAL, "mixed precision runs the Gauss-point Laplacian (k+1 points) only");
+    if (h->gll || h->mass || h->q2 || h->qgeom)
+        return fail(h, MFCG_EINVAL, "mixed precision runs the Gauss-point Laplacian (k+1 points, stored tensor) only");
     hipStream_t s = (hipStream_t)hip_stream;
     int rc = ensure_fp32(h, s);
     if (rc) return rc;
@@ -1360,7 +1379,7 @@ static IterArgs<double> iter_args(const mfcg_ctx *h)
 {
     IterArgs<double> a{};
     a.L = h->lv;
-    a.G = h->G;
+    a.G = op_geometry(h);
     a.dinv = h->dinv;
     a.r = h->r;
     a.p = h->p;
@@ -1464,7 +1483,8 @@ int mfcg_batch_solve(mfcg_batch hb, const double *const *b, double *const *x, do
         if (!b[i] || !x[i]) return batch_fail(hb, MFCG_EINVAL, "null vector of problem " + std::to_string(i));
     hipStream_t s = (hipStream_t)hip_stream;
     for (int i = 0; i < np; ++i)
-        if (hb->probs[i]->solver != MFCG_SOLVER_FUSED || hb->probs[i]->gll || hb->probs[i]->mass || hb->probs[i]->q2)
+        if (hb->probs[i]->solver != MFCG_SOLVER_FUSED || hb->probs[i]->gll || hb->probs[i]->mass || hb->probs[i]->q2 ||
+            hb->probs[i]->qgeom)
             return batch_fail(hb, MFCG_EINVAL,
                               "problem " + std::to_string(i) + ": the batch runs the fused Gauss-quadrature solver only");
     /* every problem starts as mfcg_solve would start it */

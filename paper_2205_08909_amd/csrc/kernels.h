@@ -20,6 +20,14 @@ constexpr int MODE_MASS = 16;
 /* or-ed likewise: k + 2 Gauss points per direction instead of k + 1
  * (k <= 7, Laplacian or mass; FP64 only) */
 constexpr int MODE_Q2 = 32;
+/* or-ed likewise: quadratic geometry evaluated in the kernel (Laplacian on
+ * k+1 Gauss points, FP64): the geometry argument is the per-cell node array
+ * below instead of the stored tensor */
+constexpr int MODE_QGEOM = 64;
+/* doubles per cell of the quadratic geometry array: the 27 interpolation
+ * points' coordinates (x, y and z blocks of 27, point a + 3 b + 9 d at
+ * reference position (a, b, d) / 2) and a_e */
+constexpr int QGEOM_STRIDE = 82;
 
 /* Arguments of the fused tile kernel and the shared-node kernel. */
 template <typename T>
@@ -83,8 +91,14 @@ struct GeomArgs {
     const double *coeff; /* per cell, device */
     int32_t op;          /* 0: Laplacian (6-component tensor), 1: mass (component 0: a_e w_q det J_q) */
     int32_t nq;          /* quadrature points per direction (k + 1 or k + 2); tab.S, tab.Sd are nq x (k+1), tab.D nq x nq */
+    const double *X;     /* quadratic geometry per cell (QGEOM_STRIDE doubles, tile-blocked like G), device; NULL:
+                          * the map itself */
 };
 hipError_t launch_geometry(const GeomArgs &g, double *G, hipStream_t s);
+/* The quadratic geometry array X (QGEOM_STRIDE doubles per cell, tile-blocked:
+ * a tile's cells after those of earlier tiles, layer by layer, x fastest):
+ * the map at the 27 interpolation points of each cell and a_e. */
+hipError_t launch_qgeom_nodes(const GeomArgs &g, double *X, hipStream_t s);
 hipError_t launch_diagonal(const GeomArgs &g, const double *G, double *diag_lex, double *dinv_int, hipStream_t s);
 hipError_t launch_rhs(const GeomArgs &g, int kind, const double *params, int nparams, double *b_lex, hipStream_t s);
 

@@ -101,7 +101,12 @@ int fused_block_size(int K)
  * 67-77 KB at k = 3..5, 49 KB at k = 6, 69 KB at k = 7), geometry loads in
  * the G pass */
 constexpr int WPE_Q2[8] = {0, 2, 3, 4, 4, 3, 2, 2};
-#define MFCG_WPE_MIN_Q(K, QX) ((QX) ? WPE_Q2[(K) < 8 ? (K) : 0] : MFCG_WPE_MIN(K))
+/* the quadratic-geometry variants hold the cell's contracted geometry (27
+ * values per line) through the G pass: at k = 5 they ask for as many
+ * waves as their register use allows, at k = 2 as their LDS allows */
+constexpr int WPE_QG[9] = {0, 2, 3, 4, 4, 2, 2, 2, 2};
+#define MFCG_WPE_MIN_Q(K, QX, OPV)                                                                                   \
+    ((QX) ? WPE_Q2[(K) < 8 ? (K) : 0] : ((OPV) == OPV_LAPLACE_QGEOM ? WPE_QG[(K) < 9 ? (K) : 0] : MFCG_WPE_MIN(K)))
 /* the batch kernel holds more uniform values (its arguments come from
  * memory): it asks for at most two workgroups per CU to avoid spills */
 #define MFCG_WPE_MIN_BATCH(K) (((MFCG_OCC_OF(K) < 2 ? MFCG_OCC_OF(K) : 2) * Cfg<K>::WG / 64 + 3) / 4)
@@ -161,10 +166,13 @@ __device__ __forceinline__ T gload(const T *p)
 
 /* Operator variants of the fused kernel: the Laplacian on the Gauss points
  * (default), the Laplacian with quadrature on the GLL nodes (collocation:
- * the interpolation passes are the identity and are skipped), and the mass
+ * the interpolation passes are the identity and are skipped), the mass
  * operator on the Gauss points (no derivative passes; component 0 of the
- * stored tensor holds a_e w_q det J_q). */
-enum OpVariant : int { OPV_LAPLACE = 0, OPV_LAPLACE_GLL = 1, OPV_MASS = 2 };
+ * stored tensor holds a_e w_q det J_q), and the Laplacian with quadratic
+ * geometry (Sec. 2.2): the tensor a_e w_q det J_q J_q^{-1} J_q^{-T} is
+ * computed at each Gauss point from the cell's 27 interpolation points
+ * instead of being loaded. */
+enum OpVariant : int { OPV_LAPLACE = 0, OPV_LAPLACE_GLL = 1, OPV_MASS = 2, OPV_LAPLACE_QGEOM = 3 };
 
 /* One tile of one problem: the pre / cell / sum / post passes over the
  * tile's cell layers (called by one whole workgroup).  QX = 1: k + 2
@@ -174,10 +182,10 @@ enum OpVariant : int { OPV_LAPLACE = 0, OPV_LAPLACE_GLL = 1, OPV_MASS = 2 };
 template <int K, typename T, int MODE, int OPV = OPV_LAPLACE, bool NTG = true, int QX = 0>
 __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t tile)
 {
-    constexpr bool GLLQ = OPV == OPV_LAPLACE_GLL, MASS = OPV == OPV_MASS;
-    static_assert(QX == 0 || (QX == 1 && !GLLQ && K <= 7), "k+2 points: Gauss rules up to k = 7");
+    constexpr bool GLLQ = OPV == OPV_LAPLACE_GLL, MASS = OPV == OPV_MASS, QGEOM = OPV == OPV_LAPLACE_QGEOM;
+    static_assert(QX == 0 || (QX == 1 && !GLLQ && !QGEOM && K <= 7), "k+2 points: Gauss rules up to k = 7");
     constexpr int NG = MASS ? 1 : 6; /* tensor components read */
-    constexpr int GPF = QX ? 0 : MFCG_GPREF_OF(K); /* when the geometry loads are issued */
+    constexpr int GPF = (QX || QGEOM) ? 0 : MFCG_GPREF_OF(K); /* when the geometry loads are issued */
     constexpr int n = K + 1, n2 = n * n;
     /* nq points per direction; the cell scratch holds nq^3 values with the
      * strides (1, nq, nq^2) in every stage (fewer entries used where a
@@ -202,6 +210,8 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
     __shared__ T TA[NLC * CS];
     __shared__ T TB[NLC * CS];
     __shared__ T cv[2 * PNM];
+    /* quadratic geometry of the current layer's cells */
+    __shared__ T XS[QGEOM ? NLC * QGEOM_STRIDE : 1];
     __shared__ T red[8 * (WG / 64)];
     __shared__ EntityRef ent[27];
     /* per node of the tile's xy plane: x = entity class in x,y (dx + 3 dy)
@@ -360,6 +370,12 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         const int s0 = (L * K) % (K + 1);
         asm volatile("" : "+v"(tid)); /* see above */
         const T *Gl = a.G + td.gbase + (int64_t)L * 6 * gcomp;
+        if (QGEOM) {
+            /* this layer's cells: the previous layer's last reads of XS
+             * were followed by barriers */
+            const T *Xl = a.G + td.gbase / (6 * CS) * QGEOM_STRIDE + (int64_t)L * TXa * TYa * QGEOM_STRIDE;
+            for (int e = tid; e < TXa * TYa * QGEOM_STRIDE; e += WG) XS[e] = Xl[e];
+        }
         T gp[R][6][nq];
         if (GPF == 2) {
             /* G of this layer issued first: its latency overlaps the pre loads */
@@ -547,7 +563,93 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
             }
         }
 #pragma unroll
-        for (int rr = 0; rr < R && !MASS; ++rr) {
+        for (int rr = 0; rr < R && QGEOM; ++rr) {
+            const int l = tid + WG * rr;
+            if (l < nlines) {
+                const int c = l / q2, rem = l % q2, i = rem % nq, z = rem / nq;
+                const int base = c * CS + i + q2 * z;
+                /* this line's Gauss coordinates and weights in x and z */
+                T tx = 0, tz = 0, wx = 0, wz = 0;
+#pragma unroll
+                for (int m = 0; m < n; ++m) {
+                    tx = i == m ? (T)TT.xq[m] : tx;
+                    wx = i == m ? (T)TT.wq[m] : wx;
+                    tz = z == m ? (T)TT.xq[m] : tz;
+                    wz = z == m ? (T)TT.wq[m] : wz;
+                }
+                /* quadratic Lagrange basis on {0, 1/2, 1} and its derivative */
+                const T Nx[3] = {(2 * tx - 1) * (tx - 1), 4 * tx * (1 - tx), tx * (2 * tx - 1)};
+                const T dNx[3] = {4 * tx - 3, 4 - 8 * tx, 4 * tx - 1};
+                const T Nz[3] = {(2 * tz - 1) * (tz - 1), 4 * tz * (1 - tz), tz * (2 * tz - 1)};
+                const T dNz[3] = {4 * tz - 3, 4 - 8 * tz, 4 * tz - 1};
+                /* the geometry contracted in x and z for this line:
+                 * V = sum N_a N_d x, Vx = sum N_a' N_d x, Vz = sum N_a N_d' x,
+                 * per component and y point b */
+                const T *Xc = XS + c * QGEOM_STRIDE;
+                T V[3][3], Vx[3][3], Vz[3][3];
+#pragma unroll
+                for (int co = 0; co < 3; ++co)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        T v = 0, vx = 0, vz = 0;
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            const T x0 = Xc[co * 27 + 9 * d + 3 * b], x1 = Xc[co * 27 + 9 * d + 3 * b + 1],
+                                    x2 = Xc[co * 27 + 9 * d + 3 * b + 2];
+                            const T sv = Nx[0] * x0 + Nx[1] * x1 + Nx[2] * x2;
+                            const T sx = dNx[0] * x0 + dNx[1] * x1 + dNx[2] * x2;
+                            v += Nz[d] * sv;
+                            vz += dNz[d] * sv;
+                            vx += Nz[d] * sx;
+                        }
+                        V[co][b] = v;
+                        Vx[co][b] = vx;
+                        Vz[co][b] = vz;
+                    }
+                const T aw = Xc[81] * wx * wz;
+                T fy[nq];
+#pragma unroll
+                for (int j = 0; j < nq; ++j) {
+                    const T ty = (T)TT.xq[j];
+                    const T Ny[3] = {(2 * ty - 1) * (ty - 1), 4 * ty * (1 - ty), ty * (2 * ty - 1)};
+                    const T dNy[3] = {4 * ty - 3, 4 - 8 * ty, 4 * ty - 1};
+                    T J[3][3];
+#pragma unroll
+                    for (int co = 0; co < 3; ++co) {
+                        J[co][0] = Vx[co][0] * Ny[0] + Vx[co][1] * Ny[1] + Vx[co][2] * Ny[2];
+                        J[co][1] = V[co][0] * dNy[0] + V[co][1] * dNy[1] + V[co][2] * dNy[2];
+                        J[co][2] = Vz[co][0] * Ny[0] + Vz[co][1] * Ny[1] + Vz[co][2] * Ny[2];
+                    }
+                    /* adjugate (det J times J^{-1}) and determinant */
+                    const T A00 = J[1][1] * J[2][2] - J[1][2] * J[2][1], A01 = J[0][2] * J[2][1] - J[0][1] * J[2][2],
+                            A02 = J[0][1] * J[1][2] - J[0][2] * J[1][1], A10 = J[1][2] * J[2][0] - J[1][0] * J[2][2],
+                            A11 = J[0][0] * J[2][2] - J[0][2] * J[2][0], A12 = J[0][2] * J[1][0] - J[0][0] * J[1][2],
+                            A20 = J[1][0] * J[2][1] - J[1][1] * J[2][0], A21 = J[0][1] * J[2][0] - J[0][0] * J[2][1],
+                            A22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+                    const T det = J[0][0] * A00 + J[0][1] * A10 + J[0][2] * A20;
+                    /* a_e w_q det J J^{-1} J^{-T} = a_e w_q / det (A A^T) */
+                    const T sc = aw * (T)TT.wq[j] / det;
+                    const T g00 = sc * (A00 * A00 + A01 * A01 + A02 * A02), g11 = sc * (A10 * A10 + A11 * A11 + A12 * A12),
+                            g22 = sc * (A20 * A20 + A21 * A21 + A22 * A22), g01 = sc * (A00 * A10 + A01 * A11 + A02 * A12),
+                            g02 = sc * (A00 * A20 + A01 * A21 + A02 * A22), g12 = sc * (A10 * A20 + A11 * A21 + A12 * A22);
+                    const T ux = TB[base + nq * j], uy = gy[rr][j], uz = TA[base + nq * j];
+                    const T fx = g00 * ux + g01 * uy + g02 * uz;
+                    fy[j] = g01 * ux + g11 * uy + g12 * uz;
+                    const T fz = g02 * ux + g12 * uy + g22 * uz;
+                    TB[base + nq * j] = fx;
+                    TA[base + nq * j] = fz;
+                }
+#pragma unroll
+                for (int m = 0; m < nq; ++m) {
+                    T t = 0;
+#pragma unroll
+                    for (int q = 0; q < nq; ++q) t = fma(cD(q, m), fy[q], t);
+                    wy[rr][m] = t;
+                }
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < R && !MASS && !QGEOM; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlines) {
                 const int c = l / q2, rem = l % q2, i = rem % nq, z = rem / nq;
@@ -735,7 +837,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
 
 template <int K, typename T, int MODE, int OPV = OPV_LAPLACE, int QX = 0>
 __global__ __launch_bounds__(Cfg<K>::WG)
-__attribute__((amdgpu_waves_per_eu(MFCG_WPE_MIN_Q(K, QX), 8)))
+__attribute__((amdgpu_waves_per_eu(MFCG_WPE_MIN_Q(K, QX, OPV), 8)))
 void fused_tile_kernel(const IterArgs<T> a)
 {
     if (mode_is_cg(MODE) && a.st->flag != FLAG_RUN) return;
@@ -750,7 +852,7 @@ void fused_tile_kernel(const IterArgs<T> a)
  * partial sums at c*pstride and its inner-product records at c*dstride. */
 template <int K, int MODE, int OPV, int QX = 0>
 __global__ __launch_bounds__(Cfg<K>::WG)
-__attribute__((amdgpu_waves_per_eu(MFCG_WPE_MIN_Q(K, QX), 8)))
+__attribute__((amdgpu_waves_per_eu(MFCG_WPE_MIN_Q(K, QX, OPV), 8)))
 void fused_tile_vec_kernel(const IterArgs<double> a, int64_t nstride, int64_t pstride, int64_t dstride)
 {
     if (a.st->flag != FLAG_RUN) return;
@@ -947,15 +1049,18 @@ template <int K, typename T>
 static hipError_t launch_fused_k(int mode, const IterArgs<T> &a, hipStream_t s)
 {
     dim3 grid((unsigned)a.L.ntiles), block(Cfg<K>::WG);
-    if (mode & (MODE_GLL | MODE_MASS | MODE_Q2)) {
+    if (mode & (MODE_GLL | MODE_MASS | MODE_Q2 | MODE_QGEOM)) {
         if constexpr (!std::is_same<T, double>::value) {
             return hipErrorInvalidValue; /* FP64 only */
         } else {
-            const bool mass = mode & MODE_MASS, gll = mode & MODE_GLL, q2 = mode & MODE_Q2;
+            const bool mass = mode & MODE_MASS, gll = mode & MODE_GLL, q2 = mode & MODE_Q2, qg = mode & MODE_QGEOM;
             if (gll && (mass || q2)) return hipErrorInvalidValue;
-            mode &= ~(MODE_GLL | MODE_MASS | MODE_Q2);
+            if (qg && (gll || mass || q2)) return hipErrorInvalidValue;
+            mode &= ~(MODE_GLL | MODE_MASS | MODE_Q2 | MODE_QGEOM);
             if (mode != MODE_CG && mode != MODE_CG_NOPREC && mode != MODE_VMULT) return hipErrorInvalidValue;
-            if (q2) {
+            if (qg) {
+                launch_fused_variant<K, OPV_LAPLACE_QGEOM, 0>(mode, grid, block, a, s);
+            } else if (q2) {
                 if constexpr (K <= 7) {
                     if (mass) launch_fused_variant<K, OPV_MASS, 1>(mode, grid, block, a, s);
                     else launch_fused_variant<K, OPV_LAPLACE, 1>(mode, grid, block, a, s);

@@ -53,11 +53,47 @@ __device__ inline void map_eval(int kind, double A, const double X[3], double x[
     }
 }
 
-/* Reference point xi of cell c -> mapped point x, J = dx/dxi, det J. */
+__device__ inline int64_t x_offset(const LayoutView &L, int K, const int c[3]);
+
+/* Reference point xi of cell c -> mapped point x, J = dx/dxi, det J (of
+ * the quadratic interpolant when g.X holds the quadratic geometry). */
 __device__ inline double cell_jacobian(const GeomArgs &g, const int c[3], const double xi[3], double x[3],
                                        double J[3][3])
 {
     double X[3], DF[3][3];
+    if (g.X) {
+        const double *Xc = g.X + x_offset(g.L, g.K, c);
+        double N[3][3], dN[3][3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double t = xi[d];
+            N[d][0] = (2.0 * t - 1.0) * (t - 1.0);
+            N[d][1] = 4.0 * t * (1.0 - t);
+            N[d][2] = t * (2.0 * t - 1.0);
+            dN[d][0] = 4.0 * t - 3.0;
+            dN[d][1] = 4.0 - 8.0 * t;
+            dN[d][2] = 4.0 * t - 1.0;
+        }
+        for (int i = 0; i < 3; ++i) {
+            x[i] = 0.0;
+            for (int j = 0; j < 3; ++j) J[i][j] = 0.0;
+        }
+        for (int p = 0; p < 27; ++p) {
+            const int a = p % 3, b = (p / 3) % 3, d = p / 9;
+            const double v = N[0][a] * N[1][b] * N[2][d];
+            const double gx = dN[0][a] * N[1][b] * N[2][d], gy = N[0][a] * dN[1][b] * N[2][d],
+                         gz = N[0][a] * N[1][b] * dN[2][d];
+            for (int i = 0; i < 3; ++i) {
+                const double xn = Xc[i * 27 + p];
+                x[i] += xn * v;
+                J[i][0] += xn * gx;
+                J[i][1] += xn * gy;
+                J[i][2] += xn * gz;
+            }
+        }
+        return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+               J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    }
 #pragma unroll
     for (int d = 0; d < 3; ++d) X[d] = (c[d] + xi[d]) / g.L.d[d].ncells;
     map_eval(g.map_kind, g.amp, X, x, DF);
@@ -88,6 +124,50 @@ __device__ inline int64_t g_offset(const LayoutView &L, int nq, const int c[3], 
     const int line = (cl[0] + td.nc[0] * cl[1]) * n2 + qx + n * qz;
     cstride = (int64_t)nlc * n3;
     return td.gbase + (int64_t)cl[2] * 6 * nlc * n3 + (int64_t)qy * nlc * n2 + line;
+}
+
+/* Offset of cell c's block in the quadratic geometry array: the cells in
+ * the order of the geometry tensor (tile, then layer, then x fastest). */
+__device__ inline int64_t x_offset(const LayoutView &L, int K, const int c[3])
+{
+    const int n3 = (K + 1) * (K + 1) * (K + 1);
+    int t[3], cl[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) t[d] = c[d] / L.d[d].T;
+    const int64_t tid = t[0] + (int64_t)L.d[0].ntiles * (t[1] + (int64_t)L.d[1].ntiles * t[2]);
+    const TileDesc td = L.tiles[tid];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) cl[d] = c[d] - td.c0[d];
+    const int64_t first = td.gbase / (6 * n3); /* cells of the earlier tiles */
+    return (first + cl[0] + (int64_t)td.nc[0] * (cl[1] + (int64_t)td.nc[1] * cl[2])) * QGEOM_STRIDE;
+}
+
+__global__ __launch_bounds__(SETUP_WG) void qgeom_nodes_kernel(const GeomArgs g, double *X)
+{
+    const int64_t ncell = (int64_t)g.L.d[0].ncells * g.L.d[1].ncells * g.L.d[2].ncells;
+    const int64_t t = (int64_t)blockIdx.x * SETUP_WG + threadIdx.x;
+    if (t >= ncell * 27) return;
+    const int64_t cell = t / 27;
+    const int p = (int)(t % 27), a = p % 3, b = (p / 3) % 3, d = p / 9;
+    const int c[3] = {(int)(cell % g.L.d[0].ncells), (int)((cell / g.L.d[0].ncells) % g.L.d[1].ncells),
+                      (int)(cell / ((int64_t)g.L.d[0].ncells * g.L.d[1].ncells))};
+    const int ab[3] = {a, b, d};
+    double Xp[3], x[3], DF[3][3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) Xp[e] = (c[e] + 0.5 * ab[e]) / g.L.d[e].ncells;
+    map_eval(g.map_kind, g.amp, Xp, x, DF);
+    const int64_t o = x_offset(g.L, g.K, c);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) X[o + i * 27 + p] = x[i];
+    if (p == 0) X[o + 81] = g.coeff ? g.coeff[cell] : 1.0;
+}
+
+hipError_t launch_qgeom_nodes(const GeomArgs &g, double *X, hipStream_t s)
+{
+    const int64_t tot = (int64_t)g.L.d[0].ncells * g.L.d[1].ncells * g.L.d[2].ncells * 27;
+    const int64_t nb = (tot + SETUP_WG - 1) / SETUP_WG;
+    hipLaunchKernelGGL(qgeom_nodes_kernel, dim3((unsigned)nb), dim3(SETUP_WG), 0, s, g, X);
+    return hipGetLastError();
 }
 
 __global__ __launch_bounds__(SETUP_WG) void geometry_kernel(const GeomArgs g, double *G)

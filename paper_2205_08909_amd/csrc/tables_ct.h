@@ -61,6 +61,7 @@ struct Tab {
     double S[NP * NP];
     double D[NP * NP];
     double xq[NP];
+    double wq[NP]; /* Gauss weights on [0,1] (Gauss tables only) */
     double gll[NP];
 };
 
@@ -83,6 +84,9 @@ constexpr Tab<NP> make_tab()
             if (cabs(dx) < 1e-17) break;
         }
         t.xq[i] = 0.5 * (1.0 + x);
+        double p = 0, dp = 0;
+        legendre(n, x, p, dp);
+        t.wq[i] = 1.0 / ((1.0 - x * x) * dp * dp); /* 2 / ((1 - x^2) P_n'(x)^2), halved for [0,1] */
     }
     /* GLL points on [0,1] */
     t.gll[0] = 0.0;

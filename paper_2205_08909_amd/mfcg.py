@@ -21,6 +21,7 @@ SOLVER_FUSED, SOLVER_ALG5_SPLIT, SOLVER_PCG_BASIC, SOLVER_PIPELINED, SOLVER_SSTE
 PRECOND_JACOBI, PRECOND_NONE = 0, 1
 QUAD_GAUSS, QUAD_GLL = 0, 1
 OP_LAPLACE, OP_MASS = 0, 1
+GEOM_STORED, GEOM_QUADRATIC = 0, 1
 
 EXPORTED = [
     "mfcg_setup", "mfcg_n_dofs", "mfcg_vmult", "mfcg_diagonal", "mfcg_assemble_rhs", "mfcg_solve",
@@ -45,7 +46,8 @@ class Mesh(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("n_q_1d", ctypes.c_int32), ("tile", ctypes.c_int32 * 3), ("check_every", ctypes.c_int32),
-                ("fp32", ctypes.c_int32), ("quad_rule", ctypes.c_int32), ("op", ctypes.c_int32)]
+                ("fp32", ctypes.c_int32), ("quad_rule", ctypes.c_int32), ("op", ctypes.c_int32),
+                ("geometry", ctypes.c_int32)]
 
 
 _lib = None
@@ -122,9 +124,10 @@ def make_mesh(cells, map_kind=MAP_AFFINE, amplitude=0.0, bc=BC_DIRICHLET0):
     return m
 
 
-def make_options(tile=None, check_every=0, fp32=0, quad=QUAD_GAUSS, op=OP_LAPLACE, n_q_1d=0):
+def make_options(tile=None, check_every=0, fp32=0, quad=QUAD_GAUSS, op=OP_LAPLACE, n_q_1d=0, geometry=GEOM_STORED):
     o = Options()
     o.n_q_1d = int(n_q_1d)
+    o.geometry = int(geometry)
     for d in range(3):
         o.tile[d] = 0 if tile is None else int(tile[d])
     o.check_every = int(check_every)
@@ -176,10 +179,10 @@ class Problem:
     """mfcg_setup on a mesh + degree + per-cell coefficient."""
 
     def __init__(self, cells, degree, coeff=None, map_kind=MAP_AFFINE, amplitude=0.0, bc=BC_DIRICHLET0, tile=None,
-                 check_every=0, stream=None, quad=QUAD_GAUSS, op=OP_LAPLACE, n_q_1d=0):
+                 check_every=0, stream=None, quad=QUAD_GAUSS, op=OP_LAPLACE, n_q_1d=0, geometry=GEOM_STORED):
         self.mesh = make_mesh(cells, map_kind, amplitude, bc)
         self.degree = int(degree)
-        self.opt = make_options(tile, check_every, quad=quad, op=op, n_q_1d=n_q_1d)
+        self.opt = make_options(tile, check_every, quad=quad, op=op, n_q_1d=n_q_1d, geometry=geometry)
         self.h = ctypes.c_void_p()
         self._coeff = None
         if coeff is not None:
