@@ -102,9 +102,11 @@ int fused_block_size(int K)
  * the G pass */
 constexpr int WPE_Q2[8] = {0, 2, 3, 4, 4, 3, 2, 2};
 /* the quadratic-geometry variants hold the cell's contracted geometry (27
- * values per line) through the G pass: at k = 5 they ask for as many
- * waves as their register use allows, at k = 2 as their LDS allows */
-constexpr int WPE_QG[9] = {0, 2, 3, 4, 4, 2, 2, 2, 2};
+ * values per line) through the G pass: they ask for as many waves as their
+ * register use allows without heavy spills (k = 3: 3 waves per SIMD was 4%
+ * faster than 4, k = 4: 4 was 3% faster than 3), at k = 2 as their LDS
+ * allows */
+constexpr int WPE_QG[9] = {0, 2, 3, 3, 4, 2, 2, 2, 2};
 #define MFCG_WPE_MIN_Q(K, QX, OPV)                                                                                   \
     ((QX) ? WPE_Q2[(K) < 8 ? (K) : 0] : ((OPV) == OPV_LAPLACE_QGEOM ? WPE_QG[(K) < 9 ? (K) : 0] : MFCG_WPE_MIN(K)))
 /* the batch kernel holds more uniform values (its arguments come from
