@@ -334,7 +334,9 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
             if (MODE == MODE_VMULT) {
                 a.dst[idx] = v;
             } else {
-                const bool use = Cfg<K>::CARRY && reg;
+                /* the quadratic-geometry G pass needs the registers at k <= 4
+                 * (k = 4: 0.90 instead of 1.01 ms per iteration): re-read */
+                const bool use = Cfg<K>::CARRY && !(QGEOM && K <= 4) && reg;
                 const T rn = use ? rk : a.r[idx];
                 const T dv = MODE == MODE_CG_NOPREC ? (T)1 : (use ? dk : a.dinv[idx]);
                 const T pn = win[slot * PNM + node];
@@ -629,15 +631,15 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
                             A20 = J[1][0] * J[2][1] - J[1][1] * J[2][0], A21 = J[0][1] * J[2][0] - J[0][0] * J[2][1],
                             A22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
                     const T det = J[0][0] * A00 + J[0][1] * A10 + J[0][2] * A20;
-                    /* a_e w_q det J J^{-1} J^{-T} = a_e w_q / det (A A^T) */
+                    /* flux a_e w_q det J J^{-1} J^{-T} grad u = sc A (A^T grad u)
+                     * with sc = a_e w_q / det J, without forming the tensor */
                     const T sc = aw * (T)TT.wq[j] / det;
-                    const T g00 = sc * (A00 * A00 + A01 * A01 + A02 * A02), g11 = sc * (A10 * A10 + A11 * A11 + A12 * A12),
-                            g22 = sc * (A20 * A20 + A21 * A21 + A22 * A22), g01 = sc * (A00 * A10 + A01 * A11 + A02 * A12),
-                            g02 = sc * (A00 * A20 + A01 * A21 + A02 * A22), g12 = sc * (A10 * A20 + A11 * A21 + A12 * A22);
                     const T ux = TB[base + nq * j], uy = gy[rr][j], uz = TA[base + nq * j];
-                    const T fx = g00 * ux + g01 * uy + g02 * uz;
-                    fy[j] = g01 * ux + g11 * uy + g12 * uz;
-                    const T fz = g02 * ux + g12 * uy + g22 * uz;
+                    const T t0 = A00 * ux + A10 * uy + A20 * uz, t1 = A01 * ux + A11 * uy + A21 * uz,
+                            t2 = A02 * ux + A12 * uy + A22 * uz;
+                    const T fx = sc * (A00 * t0 + A01 * t1 + A02 * t2);
+                    fy[j] = sc * (A10 * t0 + A11 * t1 + A12 * t2);
+                    const T fz = sc * (A20 * t0 + A21 * t1 + A22 * t2);
                     TB[base + nq * j] = fx;
                     TA[base + nq * j] = fz;
                 }
