@@ -406,7 +406,7 @@ def main():
                     ("mass_bp1_ms", {"op": mfcg.OP_MASS}, "mass_bp2_vector_ms"),
                     ("kplus2_bp3_ms", {"n_q_1d": k + 2}, "kplus2_bp4_vector_ms"),
                     ("kplus2_mass_bp1_ms", {"op": mfcg.OP_MASS, "n_q_1d": k + 2}, "kplus2_mass_bp2_vector_ms"),
-                    ("quadratic_geometry_ms", {"geometry": mfcg.GEOM_QUADRATIC}, None))
+                    ("quadratic_geometry_ms", {"geometry": mfcg.GEOM_QUADRATIC}, "quadratic_geometry_bp4_vector_ms"))
         for name, extra, vname in variants:
             if extra.get("n_q_1d", 0) > 9:  # k + 2 points up to k = 7
                 continue

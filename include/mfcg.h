@@ -116,8 +116,8 @@ enum {
                              * evaluates J_q of their quadratic interpolant at each Gauss point and forms
                              * G_q on the fly.  The operator is that of the interpolated map (diagonal and
                              * load vector too).  Laplacian on k+1 Gauss points, FP64: not with n_q_1d =
-                             * k+2, GLL, the mass operator, fp32 / mfcg_solve_ir, mfcg_solve_vector or a
-                             * batch */
+                             * k+2, GLL, the mass operator, fp32 / mfcg_solve_ir or a batch; the vector
+                             * solve evaluates the geometry once per component */
 };
 
 /* Options.  Zero-initialised fields select the defaults. */

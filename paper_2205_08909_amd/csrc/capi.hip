@@ -924,7 +924,6 @@ int mfcg_solve_vector(mfcg_handle h, const double *b, double *x, double tol, int
     if (!h || !b || !x || !iters) return fail(h, MFCG_EINVAL, "null argument");
     if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(h, MFCG_EINVAL, "tol must be finite and >= 0");
     if (maxit < 1) return fail(h, MFCG_EINVAL, "maxit must be >= 1");
-    if (h->qgeom) return fail(h, MFCG_EINVAL, "the vector solve runs on the stored tensor only");
     hipStream_t s = (hipStream_t)hip_stream;
     const int64_t n = h->hl.n;
     const int64_t nrec = h->hl.ntiles + h->nshared_blocks; /* records per component */

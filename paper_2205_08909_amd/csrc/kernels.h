@@ -73,8 +73,8 @@ hipError_t launch_shared(int mode, const IterArgs<T> &a, hipStream_t s);
  * over nparts records starting at a.dots (all components' records). */
 hipError_t launch_shared_nofinish(const IterArgs<double> &a, hipStream_t s);
 /* The fused tile kernel over all three components of a vector problem in
- * one launch (mode: MODE_CG, optionally with MODE_GLL or MODE_MASS, and
- * MODE_Q2 without MODE_GLL); the
+ * one launch (mode: MODE_CG, optionally with MODE_GLL, MODE_MASS or
+ * MODE_QGEOM, and MODE_Q2 without MODE_GLL); the
  * vectors, shared partial sums and records of component c sit at c times
  * the given strides (elements). */
 hipError_t launch_fused_vec(int K, int mode, const IterArgs<double> &a, int64_t nstride, int64_t pstride,

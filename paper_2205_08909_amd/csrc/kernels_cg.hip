@@ -1152,6 +1152,9 @@ static hipError_t launch_fused_vec_k(int mode, const IterArgs<double> &a, int64_
     else if (mode == (MODE_CG | MODE_MASS))
         hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_MASS>), grid, block, 0, s, a, nstride, pstride,
                            dstride);
+    else if (mode == (MODE_CG | MODE_QGEOM))
+        hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_LAPLACE_QGEOM>), grid, block, 0, s, a, nstride,
+                           pstride, dstride);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
