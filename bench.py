@@ -422,6 +422,22 @@ def main():
             ablation[name] = round((time.perf_counter() - t0) * 1e3 / K, 5)
             code_g, its_g, _ = Pg.cg_end(xg)
             assert its_g == W + K, (name, code_g, its_g)
+            if "geometry" in extra:
+                # the comparison solvers on the same handle: with the geometry computed in the
+                # kernel the vector traffic is most of the iteration's bytes
+                for solver, sname in ((mfcg.SOLVER_ALG5_SPLIT, "quadratic_geometry_alg5_3pass_ms"),
+                                      (mfcg.SOLVER_PCG_BASIC, "quadratic_geometry_basic_pcg_ms")):
+                    Pg.set_solver(solver)
+                    Pg.cg_begin(bg, None, tol=0.0, maxit=W + K)
+                    Pg.cg_iterate(W)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    Pg.cg_iterate(K)
+                    torch.cuda.synchronize()
+                    ablation[sname] = round((time.perf_counter() - t0) * 1e3 / K, 5)
+                    code_s, its_s, _ = Pg.cg_end(xg)
+                    assert its_s == W + K, (sname, code_s, its_s)
+                Pg.set_solver(mfcg.SOLVER_FUSED)
             if vname is not None:
                 b3 = torch.cat([bg, bg, bg])
                 x3 = torch.zeros_like(b3)
