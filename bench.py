@@ -402,11 +402,14 @@ def main():
         # components through the vector solve), and both operators on k+2 Gauss points per
         # direction (the BP1-BP4 rule: BP3 scalar / BP4 vector Laplacian, BP1 / BP2 mass), and the
         # Laplacian with quadratic geometry evaluated in the kernel instead of the stored tensor
+        # (also on k+2 points: the paper's BP4 base case)
         variants = (("gll_collocation_ms", {"quad": mfcg.QUAD_GLL}, None),
                     ("mass_bp1_ms", {"op": mfcg.OP_MASS}, "mass_bp2_vector_ms"),
                     ("kplus2_bp3_ms", {"n_q_1d": k + 2}, "kplus2_bp4_vector_ms"),
                     ("kplus2_mass_bp1_ms", {"op": mfcg.OP_MASS, "n_q_1d": k + 2}, "kplus2_mass_bp2_vector_ms"),
-                    ("quadratic_geometry_ms", {"geometry": mfcg.GEOM_QUADRATIC}, "quadratic_geometry_bp4_vector_ms"))
+                    ("quadratic_geometry_ms", {"geometry": mfcg.GEOM_QUADRATIC}, "quadratic_geometry_bp4_vector_ms"),
+                    ("quadratic_geometry_kplus2_bp3_ms", {"geometry": mfcg.GEOM_QUADRATIC, "n_q_1d": k + 2},
+                     "quadratic_geometry_kplus2_bp4_vector_ms"))
         for name, extra, vname in variants:
             if extra.get("n_q_1d", 0) > 9:  # k + 2 points up to k = 7
                 continue
@@ -422,7 +425,7 @@ def main():
             ablation[name] = round((time.perf_counter() - t0) * 1e3 / K, 5)
             code_g, its_g, _ = Pg.cg_end(xg)
             assert its_g == W + K, (name, code_g, its_g)
-            if "geometry" in extra:
+            if "geometry" in extra and "n_q_1d" not in extra:
                 # the comparison solvers on the same handle: with the geometry computed in the
                 # kernel the vector traffic is most of the iteration's bytes
                 for solver, sname in ((mfcg.SOLVER_ALG5_SPLIT, "quadratic_geometry_alg5_3pass_ms"),

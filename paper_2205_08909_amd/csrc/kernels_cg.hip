@@ -107,8 +107,12 @@ constexpr int WPE_Q2[8] = {0, 2, 3, 4, 4, 3, 2, 2};
  * faster than 4, k = 4: 4 was 3% faster than 3), at k = 2 as their LDS
  * allows */
 constexpr int WPE_QG[9] = {0, 2, 3, 3, 4, 2, 2, 2, 2};
+/* both: the k+2 cell buffers plus the staged geometry fit one workgroup per
+ * CU at k = 3 and 4 */
+constexpr int WPE_QGQ2[8] = {0, 2, 3, 2, 2, 3, 2, 2};
 #define MFCG_WPE_MIN_Q(K, QX, OPV)                                                                                   \
-    ((QX) ? WPE_Q2[(K) < 8 ? (K) : 0] : ((OPV) == OPV_LAPLACE_QGEOM ? WPE_QG[(K) < 9 ? (K) : 0] : MFCG_WPE_MIN(K)))
+    ((QX) ? ((OPV) == OPV_LAPLACE_QGEOM ? WPE_QGQ2[(K) < 8 ? (K) : 0] : WPE_Q2[(K) < 8 ? (K) : 0])                    \
+          : ((OPV) == OPV_LAPLACE_QGEOM ? WPE_QG[(K) < 9 ? (K) : 0] : MFCG_WPE_MIN(K)))
 /* the batch kernel holds more uniform values (its arguments come from
  * memory): it asks for at most two workgroups per CU to avoid spills */
 #define MFCG_WPE_MIN_BATCH(K) (((MFCG_OCC_OF(K) < 2 ? MFCG_OCC_OF(K) : 2) * Cfg<K>::WG / 64 + 3) / 4)
@@ -185,7 +189,7 @@ template <int K, typename T, int MODE, int OPV = OPV_LAPLACE, bool NTG = true, i
 __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t tile)
 {
     constexpr bool GLLQ = OPV == OPV_LAPLACE_GLL, MASS = OPV == OPV_MASS, QGEOM = OPV == OPV_LAPLACE_QGEOM;
-    static_assert(QX == 0 || (QX == 1 && !GLLQ && !QGEOM && K <= 7), "k+2 points: Gauss rules up to k = 7");
+    static_assert(QX == 0 || (QX == 1 && !GLLQ && K <= 7), "k+2 points: Gauss rules up to k = 7");
     constexpr int NG = MASS ? 1 : 6; /* tensor components read */
     constexpr int GPF = (QX || QGEOM) ? 0 : MFCG_GPREF_OF(K); /* when the geometry loads are issued */
     constexpr int n = K + 1, n2 = n * n;
@@ -207,6 +211,9 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
     constexpr ct::Tab2<n, nq> TQ = QX ? ct::make_tab2<n, nq>() : ct::Tab2<n, nq>{};
     constexpr auto cS = [](int q, int i) { return QX ? (T)TQ.S[q * n + i] : (T)TT.S[q * n + i]; };
     constexpr auto cD = [](int q, int m) { return QX ? (T)TQ.D[q * nq + m] : (T)TT.D[q * n + m]; };
+    /* Gauss points and weights on [0,1] */
+    constexpr auto cxq = [](int q) { return QX ? (T)TQ.xq[q] : (T)TT.xq[q]; };
+    constexpr auto cwq = [](int q) { return QX ? (T)TQ.wq[q] : (T)TT.wq[q]; };
 
     __shared__ T win[(K + 1) * PNM];
     __shared__ T TA[NLC * CS];
@@ -582,11 +589,11 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
                 /* this line's Gauss coordinates and weights in x and z */
                 T tx = 0, tz = 0, wx = 0, wz = 0;
 #pragma unroll
-                for (int m = 0; m < n; ++m) {
-                    tx = i == m ? (T)TT.xq[m] : tx;
-                    wx = i == m ? (T)TT.wq[m] : wx;
-                    tz = z == m ? (T)TT.xq[m] : tz;
-                    wz = z == m ? (T)TT.wq[m] : wz;
+                for (int m = 0; m < nq; ++m) {
+                    tx = i == m ? cxq(m) : tx;
+                    wx = i == m ? cwq(m) : wx;
+                    tz = z == m ? cxq(m) : tz;
+                    wz = z == m ? cwq(m) : wz;
                 }
                 /* quadratic Lagrange basis on {0, 1/2, 1} and its derivative */
                 const T Nx[3] = {(2 * tx - 1) * (tx - 1), 4 * tx * (1 - tx), tx * (2 * tx - 1)};
@@ -621,7 +628,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
                 T fy[nq];
 #pragma unroll
                 for (int j = 0; j < nq; ++j) {
-                    const T ty = (T)TT.xq[j];
+                    const T ty = cxq(j);
                     const T Ny[3] = {(2 * ty - 1) * (ty - 1), 4 * ty * (1 - ty), ty * (2 * ty - 1)};
                     const T dNy[3] = {4 * ty - 3, 4 - 8 * ty, 4 * ty - 1};
                     T J[3][3];
@@ -640,7 +647,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
                     const T det = J[0][0] * A00 + J[0][1] * A10 + J[0][2] * A20;
                     /* flux a_e w_q det J J^{-1} J^{-T} grad u = sc A (A^T grad u)
                      * with sc = a_e w_q / det J, without forming the tensor */
-                    const T sc = aw * (T)TT.wq[j] / det;
+                    const T sc = aw * cwq(j) / det;
                     const T ux = TB[base + nq * j], uy = gy[rr][j], uz = TA[base + nq * j];
                     const T t0 = A00 * ux + A10 * uy + A20 * uz, t1 = A01 * ux + A11 * uy + A21 * uz,
                             t2 = A02 * ux + A12 * uy + A22 * uz;
@@ -1087,10 +1094,13 @@ static hipError_t launch_fused_k(int mode, const IterArgs<T> &a, hipStream_t s)
         } else {
             const bool mass = mode & MODE_MASS, gll = mode & MODE_GLL, q2 = mode & MODE_Q2, qg = mode & MODE_QGEOM;
             if (gll && (mass || q2)) return hipErrorInvalidValue;
-            if (qg && (gll || mass || q2)) return hipErrorInvalidValue;
+            if (qg && (gll || mass)) return hipErrorInvalidValue;
             mode &= ~(MODE_GLL | MODE_MASS | MODE_Q2 | MODE_QGEOM);
             if (mode != MODE_CG && mode != MODE_CG_NOPREC && mode != MODE_VMULT) return hipErrorInvalidValue;
-            if (qg) {
+            if (qg && q2) {
+                if constexpr (K <= 7) launch_fused_variant<K, OPV_LAPLACE_QGEOM, 1>(mode, grid, block, a, s);
+                else return hipErrorInvalidValue;
+            } else if (qg) {
                 launch_fused_variant<K, OPV_LAPLACE_QGEOM, 0>(mode, grid, block, a, s);
             } else if (q2) {
                 if constexpr (K <= 7) {
@@ -1158,9 +1168,12 @@ static hipError_t launch_fused_vec_k(int mode, const IterArgs<double> &a, int64_
                                      int64_t dstride, hipStream_t s)
 {
     dim3 grid((unsigned)(3 * a.L.ntiles)), block(Cfg<K>::WG);
-    if (mode == (MODE_CG | MODE_Q2) || mode == (MODE_CG | MODE_MASS | MODE_Q2)) {
+    if (mode == (MODE_CG | MODE_Q2) || mode == (MODE_CG | MODE_MASS | MODE_Q2) || mode == (MODE_CG | MODE_QGEOM | MODE_Q2)) {
         if constexpr (K <= 7) {
-            if (mode & MODE_MASS)
+            if (mode & MODE_QGEOM)
+                hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_LAPLACE_QGEOM, 1>), grid, block, 0, s, a,
+                                   nstride, pstride, dstride);
+            else if (mode & MODE_MASS)
                 hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_MASS, 1>), grid, block, 0, s, a, nstride,
                                    pstride, dstride);
             else

@@ -53,7 +53,7 @@ __device__ inline void map_eval(int kind, double A, const double X[3], double x[
     }
 }
 
-__device__ inline int64_t x_offset(const LayoutView &L, int K, const int c[3]);
+__device__ inline int64_t x_offset(const LayoutView &L, int nq, const int c[3]);
 
 /* Reference point xi of cell c -> mapped point x, J = dx/dxi, det J (of
  * the quadratic interpolant when g.X holds the quadratic geometry). */
@@ -62,7 +62,7 @@ __device__ inline double cell_jacobian(const GeomArgs &g, const int c[3], const 
 {
     double X[3], DF[3][3];
     if (g.X) {
-        const double *Xc = g.X + x_offset(g.L, g.K, c);
+        const double *Xc = g.X + x_offset(g.L, g.nq, c);
         double N[3][3], dN[3][3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -128,9 +128,9 @@ __device__ inline int64_t g_offset(const LayoutView &L, int nq, const int c[3], 
 
 /* Offset of cell c's block in the quadratic geometry array: the cells in
  * the order of the geometry tensor (tile, then layer, then x fastest). */
-__device__ inline int64_t x_offset(const LayoutView &L, int K, const int c[3])
+__device__ inline int64_t x_offset(const LayoutView &L, int nq, const int c[3])
 {
-    const int n3 = (K + 1) * (K + 1) * (K + 1);
+    const int n3 = nq * nq * nq; /* quadratic geometry of the geometry tensor's nq^3-point layout */
     int t[3], cl[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) t[d] = c[d] / L.d[d].T;
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(SETUP_WG) void qgeom_nodes_kernel(const GeomArgs g,
 #pragma unroll
     for (int e = 0; e < 3; ++e) Xp[e] = (c[e] + 0.5 * ab[e]) / g.L.d[e].ncells;
     map_eval(g.map_kind, g.amp, Xp, x, DF);
-    const int64_t o = x_offset(g.L, g.K, c);
+    const int64_t o = x_offset(g.L, g.nq, c);
 #pragma unroll
     for (int i = 0; i < 3; ++i) X[o + i * 27 + p] = x[i];
     if (p == 0) X[o + 81] = g.coeff ? g.coeff[cell] : 1.0;

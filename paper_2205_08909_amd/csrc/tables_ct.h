@@ -140,6 +140,7 @@ struct Tab2 {
     double S[NQ * NP];
     double D[NQ * NQ];
     double xq[NQ];
+    double wq[NQ]; /* Gauss weights on [0,1] */
     double gll[NP];
 };
 
@@ -158,6 +159,9 @@ constexpr Tab2<NP, NQ> make_tab2()
             if (cabs(dx) < 1e-17) break;
         }
         t.xq[i] = 0.5 * (1.0 + x);
+        double p = 0, dp = 0;
+        legendre(NQ, x, p, dp);
+        t.wq[i] = 1.0 / ((1.0 - x * x) * dp * dp);
     }
     t.gll[0] = 0.0;
     t.gll[k] = 1.0;

@@ -1,6 +1,7 @@
 """Quadratic geometry evaluated in the operator kernel (Sec. 2.2: per cell
 the map at 27 interpolation points instead of the stored tensor G_q)
-against the oracle's quadratic-geometry operator.
+against the oracle's quadratic-geometry operator, on k+1 and on k+2 Gauss
+points per direction.
 
 Checked: the GPU operator equals the oracle's CSR matrix (1e-12 relative,
 componentwise within 1e-13 (|A| |u|)) on curved meshes with a rough
@@ -38,21 +39,33 @@ def _ids(c):
     return "x".join(map(str, c[0])) + f"-k{c[1]}-map{c[2]}-bc{c[3]}-t{c[4]}"
 
 
-def _setup(case, oracle_mod, coeff_seed=23, amp=0.08):
+# with k+2 Gauss points per direction (the BP4 base case of the paper:
+# quadratic geometry and (k+2)^3 points)
+CASES_Q2 = [
+    ((6, 5, 4), 2, 1, 0, (5, 3, 2)),
+    ((10, 10, 10), 4, 1, 0, None),
+    ((3, 4, 3), 5, 2, 1, (2, 3, 2)),
+    ((3, 2, 3), 7, 1, 0, (2, 1, 2)),
+]
+
+
+def _setup(case, oracle_mod, coeff_seed=23, amp=0.08, kplus2=False):
     from paper_2205_08909_amd import mfcg
     cells, k, kind, bc, tile = case
     coeff = inputs.grf_coefficient(cells, 0.3, 1.0, seed=coeff_seed)
-    m = oracle_mod.Mesh(cells, k, map_kind=kind, amp=amp, bc=bc, coeff=coeff, geometry="quadratic")
+    nq1 = k + 2 if kplus2 else None
+    m = oracle_mod.Mesh(cells, k, nq1=nq1, map_kind=kind, amp=amp, bc=bc, coeff=coeff, geometry="quadratic")
     P = mfcg.Problem(cells, k, coeff=coeff, map_kind=kind, amplitude=amp, bc=bc, tile=tile,
-                     geometry=mfcg.GEOM_QUADRATIC)
+                     geometry=mfcg.GEOM_QUADRATIC, n_q_1d=nq1 or 0)
     return m, P
 
 
-@pytest.mark.parametrize("case", CASES, ids=_ids)
-def test_vmult_and_diagonal_match_oracle(case, oracle_mod, torch_cuda):
+@pytest.mark.parametrize("case,kplus2", [(c, False) for c in CASES] + [(c, True) for c in CASES_Q2],
+                         ids=[_ids(c) for c in CASES] + [_ids(c) + "-kplus2" for c in CASES_Q2])
+def test_vmult_and_diagonal_match_oracle(case, kplus2, oracle_mod, torch_cuda):
     torch = torch_cuda
-    print("case", _ids(case), flush=True)
-    m, P = _setup(case, oracle_mod)
+    print("case", _ids(case), "k+2" if kplus2 else "", flush=True)
+    m, P = _setup(case, oracle_mod, kplus2=kplus2)
     A = oracle_mod.assemble(m)
     assert P.n == A.n
     u = inputs.random_vector(A.n, seed=9)
@@ -139,14 +152,16 @@ def test_coefficient_update(oracle_mod, torch_cuda):
     P.close()
 
 
-def test_vector_solve_matches_oracle(oracle_mod, torch_cuda):
-    """BP4 with quadratic geometry (the paper's base case): three components,
-    one CG, against the block-diagonal oracle."""
+@pytest.mark.parametrize("kplus2", [False, True], ids=["k+1", "k+2"])
+def test_vector_solve_matches_oracle(kplus2, oracle_mod, torch_cuda):
+    """The vector Laplacian with quadratic geometry, on k+1 and on k+2 Gauss
+    points per direction (BP4 as the paper runs it): three components, one
+    CG, against the block-diagonal oracle."""
     torch = torch_cuda
     from paper_2205_08909_amd import mfcg
     from tests.test_gpu_vector import _block3
     case = CASES[3]
-    m, P = _setup(case, oracle_mod)
+    m, P = _setup(case, oracle_mod, kplus2=kplus2)
     A = oracle_mod.assemble(m)
     cells, k = case[0], case[1]
     A3 = _block3(A)
@@ -168,7 +183,7 @@ def test_unsupported_combinations_rejected(torch_cuda):
     torch = torch_cuda
     from paper_2205_08909_amd import mfcg
     G = mfcg.GEOM_QUADRATIC
-    for kw in (dict(quad=mfcg.QUAD_GLL), dict(op=mfcg.OP_MASS), dict(n_q_1d=5)):
+    for kw in (dict(quad=mfcg.QUAD_GLL), dict(op=mfcg.OP_MASS), dict(n_q_1d=6)):
         with pytest.raises(mfcg.MfcgError):
             mfcg.Problem((4, 4, 4), 3, geometry=G, **kw)
     with pytest.raises(mfcg.MfcgError):
