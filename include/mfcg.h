@@ -219,8 +219,9 @@ int mfcg_solve(mfcg_handle h, const double *b, double *x, double tol, int32_t ma
  * so the geometry tensor they share is read from HBM about once -- the
  * shared-node kernel per component and one finish over all components'
  * inner-product records.  The operator is the handle's: the Laplacian on
- * (k+1)^3 Gauss points (BP4 with the configured quadrature), GLL
- * collocation, or the mass operator (BP2).
+ * (k+1)^3 or (k+2)^3 Gauss points (BP4), with the stored tensor or the
+ * quadratic geometry (evaluated once per component), GLL collocation, or
+ * the mass operator (BP2).
  *   b, x   device vectors of 3n doubles, component-blocked: entries
  *          [c*n, (c+1)*n) hold component c in lexicographic node order;
  *          x holds x_0 on entry and the solution on return

@@ -187,7 +187,7 @@ static int validate_mesh(const mfcg_mesh *mesh, int32_t degree, const int32_t *t
 
 /* vmult on internal vectors: dst = A src */
 /* operator-variant flags for launch_fused */
-static int gll_flag(const mfcg_ctx *h)
+static int op_flags(const mfcg_ctx *h)
 {
     return (h->gll ? MODE_GLL : 0) | (h->mass ? MODE_MASS : 0) | (h->q2 ? MODE_Q2 : 0) | (h->qgeom ? MODE_QGEOM : 0);
 }
@@ -209,7 +209,7 @@ static int vmult_internal(mfcg_ctx *h, const double *src, double *dst, hipStream
     a.st = h->st;
     a.hist = h->hist;
     a.nshared_blocks = h->nshared_blocks;
-    HIPCHK(h, launch_fused<double>(h->K, MODE_VMULT | gll_flag(h), a, s));
+    HIPCHK(h, launch_fused<double>(h->K, MODE_VMULT | op_flags(h), a, s));
     HIPCHK(h, launch_shared<double>(MODE_VMULT, a, s));
     return MFCG_OK;
 }
@@ -836,7 +836,7 @@ int mfcg_cg_iterate(mfcg_handle h, int32_t n_it, void *hip_stream)
             IterArgs<double> m = a;
             m.src = h->p;
             m.dst = h->v;
-            HIPCHK(h, launch_fused<double>(h->K, MODE_VMULT | gll_flag(h), m, s));
+            HIPCHK(h, launch_fused<double>(h->K, MODE_VMULT | op_flags(h), m, s));
             HIPCHK(h, launch_shared<double>(MODE_VMULT, m, s));
             HIPCHK(h, launch_alg5_post(a, n, h->prec_active, s));
             continue;
@@ -846,7 +846,7 @@ int mfcg_cg_iterate(mfcg_handle h, int32_t n_it, void *hip_stream)
             IterArgs<double> m = a;
             m.src = h->p;
             m.dst = h->v;
-            HIPCHK(h, launch_fused<double>(h->K, MODE_VMULT | gll_flag(h), m, s));
+            HIPCHK(h, launch_fused<double>(h->K, MODE_VMULT | op_flags(h), m, s));
             HIPCHK(h, launch_shared<double>(MODE_VMULT, m, s));
             HIPCHK(h, launch_pcg_update(a, n, s));
             continue;
@@ -860,7 +860,7 @@ int mfcg_cg_iterate(mfcg_handle h, int32_t n_it, void *hip_stream)
             HIPCHK(h, hipEventRecord(e1.a, s));
         }
         const int mode = h->prec_active ? MODE_CG : MODE_CG_NOPREC;
-        HIPCHK(h, launch_fused<double>(h->K, mode | gll_flag(h), a, s));
+        HIPCHK(h, launch_fused<double>(h->K, mode | op_flags(h), a, s));
         if (h->timing) {
             HIPCHK(h, hipEventRecord(e1.b, s));
             HIPCHK(h, hipEventRecord(e2.a, s));
@@ -1001,7 +1001,7 @@ int mfcg_solve_vector(mfcg_handle h, const double *b, double *x, double tol, int
         const int chunk = std::min(h->check_every, maxit - launched);
         for (int it = 0; it < chunk; ++it) {
             /* the three components' tiles in one launch (geometry shared in L2) */
-            HIPCHK(h, launch_fused_vec(h->K, MODE_CG | gll_flag(h), ac[0], n, std::max<int64_t>(1, h->hl.npart),
+            HIPCHK(h, launch_fused_vec(h->K, MODE_CG | op_flags(h), ac[0], n, std::max<int64_t>(1, h->hl.npart),
                                        8 * nrec, s));
             for (int c = 0; c < 3; ++c) HIPCHK(h, launch_shared_nofinish(ac[c], s));
             HIPCHK(h, launch_finish_parts(ac[0], 3 * nrec, s));
