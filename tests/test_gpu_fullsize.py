@@ -1,6 +1,7 @@
 """Parity at the benchmark's full size, in the configuration bench.py times
 (Q4, 64^3 cells of the sine-shear mesh, 16,974,593 DoFs, default tiles),
-and the GLL-collocation operator at the same size.
+and the GLL-collocation, k+2-point and quadratic-geometry operators at the
+same size.
 
 The oracle cannot assemble this matrix in a test (3.7e9 nonzeros), so it
 evaluates sampled rows of A u cell by cell (oracle_apply_rows): random rows
@@ -95,3 +96,27 @@ def test_fullsize_collocation_operator(oracle_mod):
     assert err <= 1e-12
     P.close()
 
+
+
+@pytest.mark.parametrize("variant", ["kplus2", "quadratic", "quadratic_kplus2"])
+def test_fullsize_operator_variants(variant, oracle_mod):
+    """k+2 Gauss points per direction, the quadratic geometry evaluated in the
+    kernel, and both together (BP4's scalar operator as the paper runs it) at
+    the same full size: sampled operator rows against the oracle's rows of
+    the same rule."""
+    import torch
+    from paper_2205_08909_amd import mfcg
+    nq = K + 2 if "kplus2" in variant else 0
+    quad = variant.startswith("quadratic")
+    P = mfcg.Problem(N, K, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05, n_q_1d=nq,
+                     geometry=mfcg.GEOM_QUADRATIC if quad else mfcg.GEOM_STORED)
+    m = oracle_mod.Mesh(N, K, nq1=nq or None, map_kind=oracle_mod.MAP_SINE_SHEAR, amp=0.05,
+                        geometry="quadratic" if quad else "exact")
+    rows = _rows(P, nsample=1500, seed=2)
+    u = inputs.random_vector(P.n, seed=23)
+    v = P.vmult(P.empty(), torch.from_numpy(u).cuda()).cpu().numpy()
+    ref = oracle_mod.apply_rows(m, u, rows)
+    err = np.max(np.abs(v[rows] - ref)) / np.max(np.abs(ref))
+    print(variant, "sampled rows", rows.size, "operator max rel err", err)
+    assert err <= 1e-12
+    P.close()
