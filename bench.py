@@ -409,7 +409,10 @@ def main():
                     ("kplus2_mass_bp1_ms", {"op": mfcg.OP_MASS, "n_q_1d": k + 2}, "kplus2_mass_bp2_vector_ms"),
                     ("quadratic_geometry_ms", {"geometry": mfcg.GEOM_QUADRATIC}, "quadratic_geometry_bp4_vector_ms"),
                     ("quadratic_geometry_kplus2_bp3_ms", {"geometry": mfcg.GEOM_QUADRATIC, "n_q_1d": k + 2},
-                     "quadratic_geometry_kplus2_bp4_vector_ms"))
+                     "quadratic_geometry_kplus2_bp4_vector_ms"),
+                    ("quadratic_geometry_kplus2_mass_bp1_ms",
+                     {"geometry": mfcg.GEOM_QUADRATIC, "n_q_1d": k + 2, "op": mfcg.OP_MASS},
+                     "quadratic_geometry_kplus2_mass_bp2_vector_ms"))
         for name, extra, vname in variants:
             if extra.get("n_q_1d", 0) > 9:  # k + 2 points up to k = 7
                 continue

@@ -115,8 +115,8 @@ enum {
                              * (c + (a, b, d) / 2) / n and a_e are stored (82 doubles); the mat-vec
                              * evaluates J_q of their quadratic interpolant at each Gauss point and forms
                              * G_q on the fly.  The operator is that of the interpolated map (diagonal and
-                             * load vector too).  Laplacian on k+1 or k+2 Gauss points, FP64: not with GLL,
-                             * the mass operator, fp32 / mfcg_solve_ir or a batch; the vector solve
+                             * load vector too).  Laplacian or mass operator on k+1 or k+2 Gauss points,
+                             * FP64: not with GLL, fp32 / mfcg_solve_ir or a batch; the vector solve
                              * evaluates the geometry once per component */
 };
 

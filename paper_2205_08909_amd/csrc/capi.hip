@@ -323,8 +323,8 @@ int mfcg_setup(const mfcg_mesh *mesh, int32_t degree, const double *cell_coeff, 
     if (opt && opt->geometry != MFCG_GEOM_STORED && opt->geometry != MFCG_GEOM_QUADRATIC)
         return fail(nullptr, MFCG_EINVAL, "unknown geometry");
     const bool qgeom = opt && opt->geometry == MFCG_GEOM_QUADRATIC;
-    if (qgeom && (opt->quad_rule != MFCG_QUAD_GAUSS || opt->op != MFCG_OP_LAPLACE || opt->fp32))
-        return fail(nullptr, MFCG_EINVAL, "quadratic geometry: Laplacian on Gauss points, FP64 only");
+    if (qgeom && (opt->quad_rule != MFCG_QUAD_GAUSS || opt->fp32))
+        return fail(nullptr, MFCG_EINVAL, "quadratic geometry: Gauss points, FP64 only");
     if (opt && opt->check_every < 0) return fail(nullptr, MFCG_EINVAL, "check_every must be >= 0");
     if (opt && opt->quad_rule != MFCG_QUAD_GAUSS && opt->quad_rule != MFCG_QUAD_GLL)
         return fail(nullptr, MFCG_EINVAL, "unknown quad_rule");

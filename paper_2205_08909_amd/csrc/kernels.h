@@ -20,9 +20,9 @@ constexpr int MODE_MASS = 16;
 /* or-ed likewise: k + 2 Gauss points per direction instead of k + 1
  * (k <= 7, Laplacian or mass; FP64 only) */
 constexpr int MODE_Q2 = 32;
-/* or-ed likewise: quadratic geometry evaluated in the kernel (Laplacian on
- * k+1 Gauss points, FP64): the geometry argument is the per-cell node array
- * below instead of the stored tensor */
+/* or-ed likewise: quadratic geometry evaluated in the kernel (Laplacian or
+ * mass operator, Gauss points, FP64): the geometry argument is the per-cell
+ * node array below instead of the stored tensor */
 constexpr int MODE_QGEOM = 64;
 /* doubles per cell of the quadratic geometry array: the 27 interpolation
  * points' coordinates (x, y and z blocks of 27, point a + 3 b + 9 d at

@@ -107,12 +107,16 @@ constexpr int WPE_Q2[8] = {0, 2, 3, 4, 4, 3, 2, 2};
  * faster than 4, k = 4: 4 was 3% faster than 3), at k = 2 as their LDS
  * allows */
 constexpr int WPE_QG[9] = {0, 2, 3, 3, 4, 2, 2, 2, 2};
+/* the mass operator with quadratic geometry (no derivative passes) */
+constexpr int WPE_QGM[9] = {0, 2, 3, 4, 4, 3, 2, 2, 2};
 /* both: the k+2 cell buffers plus the staged geometry fit one workgroup per
  * CU at k = 3 and 4 */
 constexpr int WPE_QGQ2[8] = {0, 2, 3, 2, 2, 3, 2, 2};
 #define MFCG_WPE_MIN_Q(K, QX, OPV)                                                                                   \
-    ((QX) ? ((OPV) == OPV_LAPLACE_QGEOM ? WPE_QGQ2[(K) < 8 ? (K) : 0] : WPE_Q2[(K) < 8 ? (K) : 0])                    \
-          : ((OPV) == OPV_LAPLACE_QGEOM ? WPE_QG[(K) < 9 ? (K) : 0] : MFCG_WPE_MIN(K)))
+    ((QX) ? (((OPV) == OPV_LAPLACE_QGEOM || (OPV) == OPV_MASS_QGEOM) ? WPE_QGQ2[(K) < 8 ? (K) : 0]                   \
+                                                                      : WPE_Q2[(K) < 8 ? (K) : 0])                   \
+          : ((OPV) == OPV_LAPLACE_QGEOM ? WPE_QG[(K) < 9 ? (K) : 0]                                                 \
+                                        : ((OPV) == OPV_MASS_QGEOM ? WPE_QGM[(K) < 9 ? (K) : 0] : MFCG_WPE_MIN(K))))
 /* the batch kernel holds more uniform values (its arguments come from
  * memory): it asks for at most two workgroups per CU to avoid spills */
 #define MFCG_WPE_MIN_BATCH(K) (((MFCG_OCC_OF(K) < 2 ? MFCG_OCC_OF(K) : 2) * Cfg<K>::WG / 64 + 3) / 4)
@@ -177,8 +181,9 @@ __device__ __forceinline__ T gload(const T *p)
  * stored tensor holds a_e w_q det J_q), and the Laplacian with quadratic
  * geometry (Sec. 2.2): the tensor a_e w_q det J_q J_q^{-1} J_q^{-T} is
  * computed at each Gauss point from the cell's 27 interpolation points
- * instead of being loaded. */
-enum OpVariant : int { OPV_LAPLACE = 0, OPV_LAPLACE_GLL = 1, OPV_MASS = 2, OPV_LAPLACE_QGEOM = 3 };
+ * instead of being loaded; likewise a_e w_q det J_q for the mass operator
+ * with quadratic geometry. */
+enum OpVariant : int { OPV_LAPLACE = 0, OPV_LAPLACE_GLL = 1, OPV_MASS = 2, OPV_LAPLACE_QGEOM = 3, OPV_MASS_QGEOM = 4 };
 
 /* One tile of one problem: the pre / cell / sum / post passes over the
  * tile's cell layers (called by one whole workgroup).  QX = 1: k + 2
@@ -188,7 +193,8 @@ enum OpVariant : int { OPV_LAPLACE = 0, OPV_LAPLACE_GLL = 1, OPV_MASS = 2, OPV_L
 template <int K, typename T, int MODE, int OPV = OPV_LAPLACE, bool NTG = true, int QX = 0>
 __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t tile)
 {
-    constexpr bool GLLQ = OPV == OPV_LAPLACE_GLL, MASS = OPV == OPV_MASS, QGEOM = OPV == OPV_LAPLACE_QGEOM;
+    constexpr bool GLLQ = OPV == OPV_LAPLACE_GLL, MASS = OPV == OPV_MASS || OPV == OPV_MASS_QGEOM,
+                   QGEOM = OPV == OPV_LAPLACE_QGEOM || OPV == OPV_MASS_QGEOM;
     static_assert(QX == 0 || (QX == 1 && !GLLQ && K <= 7), "k+2 points: Gauss rules up to k = 7");
     constexpr int NG = MASS ? 1 : 6; /* tensor components read */
     constexpr int GPF = (QX || QGEOM) ? 0 : MFCG_GPREF_OF(K); /* when the geometry loads are issued */
@@ -225,7 +231,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
      * layer, one slot per wave, so that the accumulators are not held through
      * the geometry evaluation (0.79 instead of 0.90 ms per iteration; at the
      * other degrees, which do not spill, the flush costs more than it saves) */
-    constexpr bool FLUSH = QGEOM && mode_is_cg(MODE) && K == 4;
+    constexpr bool FLUSH = OPV == OPV_LAPLACE_QGEOM && mode_is_cg(MODE) && K == 4;
     __shared__ T wacc[FLUSH ? 8 * (WG / 64) : 1];
     __shared__ T red[8 * (WG / 64)];
     __shared__ EntityRef ent[27];
@@ -350,7 +356,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
             } else {
                 /* the quadratic-geometry G pass needs the registers at k <= 4
                  * (k = 4: 0.90 instead of 1.01 ms per iteration): re-read */
-                const bool use = Cfg<K>::CARRY && !(QGEOM && K <= 4) && reg;
+                const bool use = Cfg<K>::CARRY && !(OPV == OPV_LAPLACE_QGEOM && K <= 4) && reg;
                 const T rn = use ? rk : a.r[idx];
                 const T dv = MODE == MODE_CG_NOPREC ? (T)1 : (use ? dk : a.dinv[idx]);
                 const T pn = win[slot * PNM + node];
@@ -568,7 +574,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
          * of the transposed derivative in registers.  Mass operator: the
          * values scaled by a_e w_q det J_q, into TB. */
 #pragma unroll
-        for (int rr = 0; rr < R && MASS; ++rr) {
+        for (int rr = 0; rr < R && MASS && !QGEOM; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlines) {
                 const int c = l / q2, rem = l % q2, i = rem % nq, z = rem / nq;
@@ -638,6 +644,14 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
                         J[co][1] = V[co][0] * dNy[0] + V[co][1] * dNy[1] + V[co][2] * dNy[2];
                         J[co][2] = Vz[co][0] * Ny[0] + Vz[co][1] * Ny[1] + Vz[co][2] * Ny[2];
                     }
+                    if (MASS) {
+                        /* a_e w_q det J_q times the value at the point */
+                        const T det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) +
+                                      J[0][1] * (J[1][2] * J[2][0] - J[1][0] * J[2][2]) +
+                                      J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+                        TB[base + nq * j] = aw * cwq(j) * det * TA[base + nq * j];
+                        continue;
+                    }
                     /* adjugate (det J times J^{-1}) and determinant */
                     const T A00 = J[1][1] * J[2][2] - J[1][2] * J[2][1], A01 = J[0][2] * J[2][1] - J[0][1] * J[2][2],
                             A02 = J[0][1] * J[1][2] - J[0][2] * J[1][1], A10 = J[1][2] * J[2][0] - J[1][0] * J[2][2],
@@ -658,7 +672,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
                     TA[base + nq * j] = fz;
                 }
 #pragma unroll
-                for (int m = 0; m < nq; ++m) {
+                for (int m = 0; m < nq && !MASS; ++m) {
                     T t = 0;
 #pragma unroll
                     for (int q = 0; q < nq; ++q) t = fma(cD(q, m), fy[q], t);
@@ -1094,14 +1108,19 @@ static hipError_t launch_fused_k(int mode, const IterArgs<T> &a, hipStream_t s)
         } else {
             const bool mass = mode & MODE_MASS, gll = mode & MODE_GLL, q2 = mode & MODE_Q2, qg = mode & MODE_QGEOM;
             if (gll && (mass || q2)) return hipErrorInvalidValue;
-            if (qg && (gll || mass)) return hipErrorInvalidValue;
+            if (qg && gll) return hipErrorInvalidValue;
             mode &= ~(MODE_GLL | MODE_MASS | MODE_Q2 | MODE_QGEOM);
             if (mode != MODE_CG && mode != MODE_CG_NOPREC && mode != MODE_VMULT) return hipErrorInvalidValue;
             if (qg && q2) {
-                if constexpr (K <= 7) launch_fused_variant<K, OPV_LAPLACE_QGEOM, 1>(mode, grid, block, a, s);
-                else return hipErrorInvalidValue;
+                if constexpr (K <= 7) {
+                    if (mass) launch_fused_variant<K, OPV_MASS_QGEOM, 1>(mode, grid, block, a, s);
+                    else launch_fused_variant<K, OPV_LAPLACE_QGEOM, 1>(mode, grid, block, a, s);
+                } else {
+                    return hipErrorInvalidValue;
+                }
             } else if (qg) {
-                launch_fused_variant<K, OPV_LAPLACE_QGEOM, 0>(mode, grid, block, a, s);
+                if (mass) launch_fused_variant<K, OPV_MASS_QGEOM, 0>(mode, grid, block, a, s);
+                else launch_fused_variant<K, OPV_LAPLACE_QGEOM, 0>(mode, grid, block, a, s);
             } else if (q2) {
                 if constexpr (K <= 7) {
                     if (mass) launch_fused_variant<K, OPV_MASS, 1>(mode, grid, block, a, s);
@@ -1168,9 +1187,13 @@ static hipError_t launch_fused_vec_k(int mode, const IterArgs<double> &a, int64_
                                      int64_t dstride, hipStream_t s)
 {
     dim3 grid((unsigned)(3 * a.L.ntiles)), block(Cfg<K>::WG);
-    if (mode == (MODE_CG | MODE_Q2) || mode == (MODE_CG | MODE_MASS | MODE_Q2) || mode == (MODE_CG | MODE_QGEOM | MODE_Q2)) {
+    if (mode == (MODE_CG | MODE_Q2) || mode == (MODE_CG | MODE_MASS | MODE_Q2) || mode == (MODE_CG | MODE_QGEOM | MODE_Q2) ||
+        mode == (MODE_CG | MODE_QGEOM | MODE_MASS | MODE_Q2)) {
         if constexpr (K <= 7) {
-            if (mode & MODE_QGEOM)
+            if ((mode & MODE_QGEOM) && (mode & MODE_MASS))
+                hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_MASS_QGEOM, 1>), grid, block, 0, s, a,
+                                   nstride, pstride, dstride);
+            else if (mode & MODE_QGEOM)
                 hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_LAPLACE_QGEOM, 1>), grid, block, 0, s, a,
                                    nstride, pstride, dstride);
             else if (mode & MODE_MASS)
@@ -1193,6 +1216,9 @@ static hipError_t launch_fused_vec_k(int mode, const IterArgs<double> &a, int64_
     else if (mode == (MODE_CG | MODE_MASS))
         hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_MASS>), grid, block, 0, s, a, nstride, pstride,
                            dstride);
+    else if (mode == (MODE_CG | MODE_QGEOM | MODE_MASS))
+        hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_MASS_QGEOM>), grid, block, 0, s, a, nstride,
+                           pstride, dstride);
     else if (mode == (MODE_CG | MODE_QGEOM))
         hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_LAPLACE_QGEOM>), grid, block, 0, s, a, nstride,
                            pstride, dstride);

@@ -1,7 +1,7 @@
 """Quadratic geometry evaluated in the operator kernel (Sec. 2.2: per cell
 the map at 27 interpolation points instead of the stored tensor G_q)
 against the oracle's quadratic-geometry operator, on k+1 and on k+2 Gauss
-points per direction.
+points per direction, for the Laplacian and the mass operator.
 
 Checked: the GPU operator equals the oracle's CSR matrix (1e-12 relative,
 componentwise within 1e-13 (|A| |u|)) on curved meshes with a rough
@@ -10,8 +10,8 @@ without boundary condition; it differs from the exact-map operator; the
 diagonal and the load vector; the fused Jacobi-CG solve, scalar and
 vector (three components, BP4), against the oracle's Algorithm 1 (iteration
 count within the oracle's summation-order range +-2, x within 1e-10); the
-comparison solvers reach the same solution;
-a coefficient update re-writes the per-cell values; combinations the
+comparison solvers reach the same solution; the mass operator's BP1 and
+BP2 solves; a coefficient update re-writes the per-cell values; combinations the
 library does not offer are rejected.
 """
 import numpy as np
@@ -49,23 +49,30 @@ CASES_Q2 = [
 ]
 
 
-def _setup(case, oracle_mod, coeff_seed=23, amp=0.08, kplus2=False):
+def _setup(case, oracle_mod, coeff_seed=23, amp=0.08, kplus2=False, mass=False):
     from paper_2205_08909_amd import mfcg
     cells, k, kind, bc, tile = case
     coeff = inputs.grf_coefficient(cells, 0.3, 1.0, seed=coeff_seed)
     nq1 = k + 2 if kplus2 else None
-    m = oracle_mod.Mesh(cells, k, nq1=nq1, map_kind=kind, amp=amp, bc=bc, coeff=coeff, geometry="quadratic")
+    m = oracle_mod.Mesh(cells, k, nq1=nq1, map_kind=kind, amp=amp, bc=bc, coeff=coeff, geometry="quadratic",
+                        op="mass" if mass else "laplace")
     P = mfcg.Problem(cells, k, coeff=coeff, map_kind=kind, amplitude=amp, bc=bc, tile=tile,
-                     geometry=mfcg.GEOM_QUADRATIC, n_q_1d=nq1 or 0)
+                     geometry=mfcg.GEOM_QUADRATIC, n_q_1d=nq1 or 0, op=mfcg.OP_MASS if mass else mfcg.OP_LAPLACE)
     return m, P
 
 
-@pytest.mark.parametrize("case,kplus2", [(c, False) for c in CASES] + [(c, True) for c in CASES_Q2],
-                         ids=[_ids(c) for c in CASES] + [_ids(c) + "-kplus2" for c in CASES_Q2])
-def test_vmult_and_diagonal_match_oracle(case, kplus2, oracle_mod, torch_cuda):
+MASS_CASES = [(CASES[2], False), (CASES[4], False), (CASES_Q2[0], True), (CASES_Q2[2], True)]
+
+
+@pytest.mark.parametrize("case,kplus2,mass",
+                         [(c, False, False) for c in CASES] + [(c, True, False) for c in CASES_Q2] +
+                         [(c, q, True) for c, q in MASS_CASES],
+                         ids=[_ids(c) for c in CASES] + [_ids(c) + "-kplus2" for c in CASES_Q2] +
+                         [_ids(c) + ("-kplus2" if q else "") + "-mass" for c, q in MASS_CASES])
+def test_vmult_and_diagonal_match_oracle(case, kplus2, mass, oracle_mod, torch_cuda):
     torch = torch_cuda
-    print("case", _ids(case), "k+2" if kplus2 else "", flush=True)
-    m, P = _setup(case, oracle_mod, kplus2=kplus2)
+    print("case", _ids(case), "k+2" if kplus2 else "", "mass" if mass else "", flush=True)
+    m, P = _setup(case, oracle_mod, kplus2=kplus2, mass=mass)
     A = oracle_mod.assemble(m)
     assert P.n == A.n
     u = inputs.random_vector(A.n, seed=9)
@@ -179,11 +186,44 @@ def test_vector_solve_matches_oracle(kplus2, oracle_mod, torch_cuda):
     P.close()
 
 
+@pytest.mark.parametrize("kplus2", [False, True], ids=["k+1", "k+2"])
+def test_mass_solves_match_oracle(kplus2, oracle_mod, torch_cuda):
+    """BP1 (scalar) and BP2 (three components) with quadratic geometry."""
+    torch = torch_cuda
+    from paper_2205_08909_amd import mfcg
+    from tests.test_gpu_vector import _block3
+    case = CASES_Q2[0]
+    m, P = _setup(case, oracle_mod, kplus2=kplus2, mass=True)
+    A = oracle_mod.assemble(m)
+    cells, k = case[0], case[1]
+    b = inputs.random_rhs(cells, k, seed=97)
+    xo, its_o, _, rc_o = oracle_mod.pcg(A, A.diagonal(), b, tol=1e-10, maxit=2000)
+    lo, hi, _ = oracle_noise(oracle_mod, A, b, nperm=2)
+    bt = torch.from_numpy(b).cuda()
+    xt = torch.zeros_like(bt)
+    code, its, _, tr = P.solve(bt, xt, tol=1e-10, maxit=2000, want_true_res=True)
+    print("BP1 its", its, "oracle", its_o, (lo, hi), "true res", tr)
+    assert rc_o == 0 and code == mfcg.OK and lo - 2 <= its <= hi + 2
+    assert np.linalg.norm(xt.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo) and tr <= 2e-10
+    A3 = _block3(A)
+    d3 = np.tile(A.diagonal(), 3)
+    b3 = np.concatenate([inputs.random_rhs(cells, k, seed=98 + c) for c in range(3)])
+    xo3, its_o3, _, rc_o3 = oracle_mod.pcg(A3, d3, b3, tol=1e-10, maxit=2000)
+    lo3, hi3, _ = oracle_noise(oracle_mod, A3, b3, nperm=2, diag=d3)
+    bt3 = torch.from_numpy(b3).cuda()
+    xt3 = torch.zeros_like(bt3)
+    code3, its3, _, tr3 = P.solve_vector(bt3, xt3, tol=1e-10, maxit=2000, want_true_res=True)
+    print("BP2 its", its3, "oracle", its_o3, (lo3, hi3), "true res", tr3)
+    assert rc_o3 == 0 and code3 == mfcg.OK and lo3 - 2 <= its3 <= hi3 + 2
+    assert np.linalg.norm(xt3.cpu().numpy() - xo3) <= 1e-10 * np.linalg.norm(xo3) and tr3 <= 2e-10
+    P.close()
+
+
 def test_unsupported_combinations_rejected(torch_cuda):
     torch = torch_cuda
     from paper_2205_08909_amd import mfcg
     G = mfcg.GEOM_QUADRATIC
-    for kw in (dict(quad=mfcg.QUAD_GLL), dict(op=mfcg.OP_MASS), dict(n_q_1d=6)):
+    for kw in (dict(quad=mfcg.QUAD_GLL), dict(n_q_1d=6)):
         with pytest.raises(mfcg.MfcgError):
             mfcg.Problem((4, 4, 4), 3, geometry=G, **kw)
     with pytest.raises(mfcg.MfcgError):

@@ -1,8 +1,9 @@
 """Operator parity over a seeded random sample of shapes: cells per
 direction, degree, tile (ragged in any direction, one-cell tiles), map,
 boundary condition, coefficient and operator variant (Laplacian on Gauss
-points, GLL collocation, mass; a second sample: k+2 Gauss points for the
-Laplacian and the mass operator, quadratic geometry), each against the
+points, GLL collocation, mass; a second sample: k+2 Gauss points and the
+quadratic geometry, each for the Laplacian and the mass operator), each
+against the
 oracle's brute-force CSR
 matrix (1e-12 relative; componentwise within 1e-13 (|A| |u|)), and, where
 the operator is definite, five fused iterations against the oracle's fifth
@@ -72,7 +73,7 @@ def test_random_shape_parity(i, oracle_mod):
 
 def _draw_variant(i):
     rng = np.random.default_rng(2000 + i)
-    variant = ["kplus2", "kplus2_mass", "qgeom"][i % 3]
+    variant = ["kplus2", "kplus2_mass", "qgeom", "qgeom_mass"][i % 4]
     kmax = 7 if variant.startswith("kplus2") else 8
     k = int(rng.integers(1, kmax + 1))
     cmax = max(2, 9 - k)
@@ -87,7 +88,7 @@ def _draw_variant(i):
     return cells, k, tile, kind, bc, variant, coeff_seed
 
 
-@pytest.mark.parametrize("i", range(18))
+@pytest.mark.parametrize("i", range(24))
 def test_random_shape_parity_kplus2_and_quadratic_geometry(i, oracle_mod):
     """The same check for k+2 Gauss points per direction (Laplacian and
     mass) and for the quadratic geometry evaluated in the kernel."""
@@ -96,13 +97,13 @@ def test_random_shape_parity_kplus2_and_quadratic_geometry(i, oracle_mod):
     cells, k, tile, kind, bc, variant, coeff_seed = _draw_variant(i)
     print("case", i, cells, k, tile, kind, bc, variant, coeff_seed, flush=True)
     coeff = inputs.grf_coefficient(cells, 0.3, 1.0, seed=coeff_seed) if coeff_seed is not None else None
-    op = "mass" if variant == "kplus2_mass" else "laplace"
+    op = "mass" if variant.endswith("mass") else "laplace"
     nq1 = k + 2 if variant.startswith("kplus2") else None
-    geometry = "quadratic" if variant == "qgeom" else "exact"
+    geometry = "quadratic" if variant.startswith("qgeom") else "exact"
     m = oracle_mod.Mesh(cells, k, nq1=nq1, map_kind=kind, amp=0.05, bc=bc, coeff=coeff, op=op, geometry=geometry)
     P = mfcg.Problem(cells, k, coeff=coeff, map_kind=kind, amplitude=0.05, bc=bc, tile=tile,
                      op=mfcg.OP_MASS if op == "mass" else mfcg.OP_LAPLACE, n_q_1d=nq1 or 0,
-                     geometry=mfcg.GEOM_QUADRATIC if variant == "qgeom" else mfcg.GEOM_STORED)
+                     geometry=mfcg.GEOM_QUADRATIC if variant.startswith("qgeom") else mfcg.GEOM_STORED)
     A = oracle_mod.assemble(m)
     assert P.n == A.n
     u = inputs.random_vector(A.n, seed=i)
