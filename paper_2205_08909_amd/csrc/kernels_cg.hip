@@ -42,899 +42,12 @@
 
 #include <type_traits>
 
-#include "cg_common.h"
-#include "kernels.h"
-#include "tables_ct.h"
+#include "fused_tile.h"
 
 namespace mfcg {
 
-/* ------------------------------------------------------------------ */
-/* Per-degree configuration (compile time)                             */
-/* ------------------------------------------------------------------ */
-
-/* TX, TY: compiled maximum tile extent in x and y (cells); WG: workgroup
- * size; GPREF: where a layer's geometry tensor is loaded (0: in the pass
- * that applies it, 1: before the x and z derivative passes, held in
- * registers across them); OCC: workgroups per CU the register allocator
- * aims for; CARRY: r_k and D^{-1} of a node kept in registers from its pre
- * to its post (1) or re-read there (0).  Chosen per degree by timing on
- * MI355X. */
-template <int K>
-struct Cfg;
-template <> struct Cfg<1> { static constexpr int TX = 8, TY = 8, WG = 256, GPREF = 0, OCC = 2, CARRY = 0; };
-template <> struct Cfg<2> { static constexpr int TX = 8, TY = 8, WG = 576, GPREF = 0, OCC = 2, CARRY = 0; };
-template <> struct Cfg<3> { static constexpr int TX = 5, TY = 5, WG = 448, GPREF = 0, OCC = 2, CARRY = 1; };
-template <> struct Cfg<4> { static constexpr int TX = 4, TY = 4, WG = 448, GPREF = 0, OCC = 2, CARRY = 1; };
-template <> struct Cfg<5> { static constexpr int TX = 3, TY = 3, WG = 384, GPREF = 0, OCC = 3, CARRY = 1; };
-template <> struct Cfg<6> { static constexpr int TX = 2, TY = 2, WG = 256, GPREF = 0, OCC = 2, CARRY = 1; };
-template <> struct Cfg<7> { static constexpr int TX = 2, TY = 2, WG = 256, GPREF = 1, OCC = 2, CARRY = 1; };
-template <> struct Cfg<8> { static constexpr int TX = 2, TY = 2, WG = 384, GPREF = 0, OCC = 1, CARRY = 0; };
-
-void tile_limits(int K, int *tx, int *ty)
-{
-    static const int t[9] = {0, 8, 8, 5, 4, 3, 2, 2, 2};
-    *tx = *ty = (K >= 1 && K <= 8) ? t[K] : 0;
-}
-
-int fused_block_size(int K)
-{
-    static const int w[9] = {0, 256, 576, 448, 448, 384, 256, 256, 384};
-    return (K >= 1 && K <= 8) ? w[K] : 0;
-}
-
-/* minimum waves per SIMD requested from the register allocator */
-/* build-time overrides of the per-degree choices (timing experiments) */
-#ifdef MFCG_OCC
-#define MFCG_OCC_OF(K) (MFCG_OCC)
-#else
-#define MFCG_OCC_OF(K) (Cfg<K>::OCC)
-#endif
-/* geometry loads issued before the derivative passes (1) or in the G pass (0) */
-#ifdef MFCG_GPREF
-#define MFCG_GPREF_OF(K) (MFCG_GPREF)
-#else
-#define MFCG_GPREF_OF(K) (Cfg<K>::GPREF)
-#endif
-#define MFCG_WPE_MIN(K) ((MFCG_OCC_OF(K) * Cfg<K>::WG / 64 + 3) / 4)
-/* the k+2-point variants: no more waves than their larger cell scratch
- * lets fit per CU (LDS per workgroup 32 KB at k = 1, 83 KB at k = 2,
- * 67-77 KB at k = 3..5, 49 KB at k = 6, 69 KB at k = 7), geometry loads in
- * the G pass */
-constexpr int WPE_Q2[8] = {0, 2, 3, 4, 4, 3, 2, 2};
-/* the quadratic-geometry variants hold the cell's contracted geometry (27
- * values per line) through the G pass: they ask for as many waves as their
- * register use allows without heavy spills (k = 3: 3 waves per SIMD was 4%
- * faster than 4, k = 4: 4 was 3% faster than 3), at k = 2 as their LDS
- * allows */
-constexpr int WPE_QG[9] = {0, 2, 3, 3, 4, 2, 2, 2, 2};
-/* the mass operator with quadratic geometry (no derivative passes) */
-constexpr int WPE_QGM[9] = {0, 2, 3, 4, 4, 3, 2, 2, 2};
-/* both: the k+2 cell buffers plus the staged geometry fit one workgroup per
- * CU at k = 3 and 4 */
-constexpr int WPE_QGQ2[8] = {0, 2, 3, 2, 2, 3, 2, 2};
-#define MFCG_WPE_MIN_Q(K, QX, OPV)                                                                                   \
-    ((QX) ? (((OPV) == OPV_LAPLACE_QGEOM || (OPV) == OPV_MASS_QGEOM) ? WPE_QGQ2[(K) < 8 ? (K) : 0]                   \
-                                                                      : WPE_Q2[(K) < 8 ? (K) : 0])                   \
-          : ((OPV) == OPV_LAPLACE_QGEOM ? WPE_QG[(K) < 9 ? (K) : 0]                                                 \
-                                        : ((OPV) == OPV_MASS_QGEOM ? WPE_QGM[(K) < 9 ? (K) : 0] : MFCG_WPE_MIN(K))))
-/* the batch kernel holds more uniform values (its arguments come from
- * memory): it asks for at most two workgroups per CU to avoid spills */
-#define MFCG_WPE_MIN_BATCH(K) (((MFCG_OCC_OF(K) < 2 ? MFCG_OCC_OF(K) : 2) * Cfg<K>::WG / 64 + 3) / 4)
-
-/* ------------------------------------------------------------------ */
-/* Helpers                                                             */
-/* ------------------------------------------------------------------ */
-
-/* Workgroups are dispatched round-robin over the 8 XCDs (separate L2s).
- * Map consecutive blocks of one XCD to consecutive tiles so that tiles
- * sharing faces mostly run under the same L2. */
-__device__ inline int64_t xcd_remap(int64_t b, int64_t nb)
-{
-    const int64_t X = 8;
-    const int64_t q = nb / X, r = nb % X;
-    const int64_t x = b % X, i = b / X;
-    return x * q + (x < r ? x : r) + i;
-}
-
-/* The batch's per-problem arguments live in device memory that no kernel
- * writes during a launch: read them through the constant address space
- * (scalar loads). */
-template <typename A>
-__device__ __forceinline__ const A *const_view(const A *p)
-{
-    return (const A *)(const __attribute__((address_space(4))) A *)p;
-}
-
-/* Division by a divisor fixed for a workgroup, for dividends below 2^16:
- * q = floor(n * ceil(2^32 / d) / 2^32) is exact when n, d < 2^16. */
-struct FastDiv {
-    uint32_t d, m;
-    __device__ __forceinline__ explicit FastDiv(uint32_t dd)
-        : d(dd), m(dd > 1 ? (uint32_t)((0x100000000ull + dd - 1) / dd) : 0u) {}
-    __device__ __forceinline__ int div(int n) const { return d > 1 ? (int)__umulhi((uint32_t)n, m) : n; }
-    __device__ __forceinline__ int mod(int n) const { return n - div(n) * (int)d; }
-};
-
-/* The geometry tensor is streamed once per iteration: its loads carry the
- * non-temporal hint so that they do not displace the vector lines that are
- * reused within the iteration (measured: 1.5-2% off the fused kernel at
- * Q4, 64^3, and 0.045 GB less HBM traffic per launch).  The vector kernel,
- * whose three components read each tensor line in turn, keeps plain loads
- * so that L2 holds the lines for the second and third reads. */
-template <bool NT, typename T>
-__device__ __forceinline__ T gload(const T *p)
-{
-    if constexpr (NT)
-        return __builtin_nontemporal_load(p);
-    else
-        return *p;
-}
-
-/* ------------------------------------------------------------------ */
-/* Fused tile kernel                                                   */
-/* ------------------------------------------------------------------ */
-
-/* Operator variants of the fused kernel: the Laplacian on the Gauss points
- * (default), the Laplacian with quadrature on the GLL nodes (collocation:
- * the interpolation passes are the identity and are skipped), the mass
- * operator on the Gauss points (no derivative passes; component 0 of the
- * stored tensor holds a_e w_q det J_q), and the Laplacian with quadratic
- * geometry (Sec. 2.2): the tensor a_e w_q det J_q J_q^{-1} J_q^{-T} is
- * computed at each Gauss point from the cell's 27 interpolation points
- * instead of being loaded; likewise a_e w_q det J_q for the mass operator
- * with quadratic geometry. */
-enum OpVariant : int { OPV_LAPLACE = 0, OPV_LAPLACE_GLL = 1, OPV_MASS = 2, OPV_LAPLACE_QGEOM = 3, OPV_MASS_QGEOM = 4 };
-
-/* One tile of one problem: the pre / cell / sum / post passes over the
- * tile's cell layers (called by one whole workgroup).  QX = 1: k + 2
- * Gauss points per direction instead of k + 1 (Gauss variants only); the
- * passes on the quadrature grid then run over (k + 2)^2 lines per cell and
- * the interpolation passes map k + 1 values to k + 2 and back. */
-template <int K, typename T, int MODE, int OPV = OPV_LAPLACE, bool NTG = true, int QX = 0>
-__device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t tile)
-{
-    constexpr bool GLLQ = OPV == OPV_LAPLACE_GLL, MASS = OPV == OPV_MASS || OPV == OPV_MASS_QGEOM,
-                   QGEOM = OPV == OPV_LAPLACE_QGEOM || OPV == OPV_MASS_QGEOM;
-    static_assert(QX == 0 || (QX == 1 && !GLLQ && K <= 7), "k+2 points: Gauss rules up to k = 7");
-    constexpr int NG = MASS ? 1 : 6; /* tensor components read */
-    constexpr int GPF = (QX || QGEOM) ? 0 : MFCG_GPREF_OF(K); /* when the geometry loads are issued */
-    constexpr int n = K + 1, n2 = n * n;
-    /* nq points per direction; the cell scratch holds nq^3 values with the
-     * strides (1, nq, nq^2) in every stage (fewer entries used where a
-     * direction still has n values) */
-    constexpr int nq = n + QX, q2 = nq * nq, CS = nq * nq * nq, nnq = n * nq;
-    constexpr int WG = Cfg<K>::WG;
-    constexpr int NLC = Cfg<K>::TX * Cfg<K>::TY;
-    constexpr int RA = (NLC * n2 + WG - 1) / WG;  /* lines of the F1 and B7 passes */
-    constexpr int RB = (NLC * nnq + WG - 1) / WG; /* F2 and B6 */
-    constexpr int R = (NLC * q2 + WG - 1) / WG;   /* passes on the quadrature grid */
-    constexpr int PNM = (Cfg<K>::TX * K + 1) * (Cfg<K>::TY * K + 1);
-    constexpr int NS = (K * PNM + WG - 1) / WG;
-    constexpr int NC = (PNM + WG - 1) / WG;
-    /* compile-time 1D tables: S (GLL basis at Gauss points, nq x n), D
-     * (collocation derivative on the Gauss points, nq x nq) */
-    constexpr ct::Tab<n> TT = ct::make_tab<n, GLLQ>();
-    constexpr ct::Tab2<n, nq> TQ = QX ? ct::make_tab2<n, nq>() : ct::Tab2<n, nq>{};
-    constexpr auto cS = [](int q, int i) { return QX ? (T)TQ.S[q * n + i] : (T)TT.S[q * n + i]; };
-    constexpr auto cD = [](int q, int m) { return QX ? (T)TQ.D[q * nq + m] : (T)TT.D[q * n + m]; };
-    /* Gauss points and weights on [0,1] */
-    constexpr auto cxq = [](int q) { return QX ? (T)TQ.xq[q] : (T)TT.xq[q]; };
-    constexpr auto cwq = [](int q) { return QX ? (T)TQ.wq[q] : (T)TT.wq[q]; };
-
-    __shared__ T win[(K + 1) * PNM];
-    __shared__ T TA[NLC * CS];
-    __shared__ T TB[NLC * CS];
-    __shared__ T cv[2 * PNM];
-    /* quadratic geometry of the current layer's cells */
-    __shared__ T XS[QGEOM ? NLC * QGEOM_STRIDE : 1];
-    /* quadratic geometry, CG modes at k = 4: the inner products flushed per
-     * layer, one slot per wave, so that the accumulators are not held through
-     * the geometry evaluation (0.79 instead of 0.90 ms per iteration; at the
-     * other degrees, which do not spill, the flush costs more than it saves) */
-    constexpr bool FLUSH = OPV == OPV_LAPLACE_QGEOM && mode_is_cg(MODE) && K == 4;
-    __shared__ T wacc[FLUSH ? 8 * (WG / 64) : 1];
-    __shared__ T red[8 * (WG / 64)];
-    __shared__ EntityRef ent[27];
-    /* per node of the tile's xy plane: x = entity class in x,y (dx + 3 dy)
-     * | stride of the entity's z index << 8, y = offset of (x,y) inside the
-     * entity, z/w = offsets into the cell scratch of the (up to) 4 cells
-     * around the node (16 bits each, 0xffff: no such cell), cell order
-     * (-x,-y), (+x,-y), (-x,+y), (+x,+y) */
-    __shared__ int4 desc[PNM];
-
-    const int tid0 = threadIdx.x;
-    const TileDesc td = a.L.tiles[tile];
-    if (tid0 < 27) ent[tid0] = a.L.tile_ent[tile * 27 + tid0];
-    /* The thread index is re-made opaque to the compiler at every phase of
-     * the layer loop: all per-thread index arithmetic is then recomputed
-     * where it is used instead of being hoisted out of the loop and held in
-     * registers across all layers (which doubles the register footprint
-     * and halves the number of resident workgroups). */
-    int tid = tid0;
-
-    T alpha = 0, beta = 0, ratio = 0;
-    bool xupd = false;
-    if (mode_is_cg(MODE)) {
-        alpha = (T)a.st->alpha;
-        beta = (T)a.st->beta;
-        ratio = (T)a.st->ratio;
-        const int kk = a.st->k + 1;
-        xupd = (kk > 1) && (kk & 1);
-    }
-
-    const int TXa = td.nc[0], TYa = td.nc[1], TZa = td.nc[2];
-    const int EX = TXa * K, EY = TYa * K, EZ = TZa * K;
-    const int PW = EX + 1;
-    const int PN = (EX + 1) * (EY + 1);
-    const int nlines = TXa * TYa * q2;
-    const int nlA = QX ? TXa * TYa * n2 : nlines, nlB = QX ? TXa * TYa * nnq : nlines;
-    const int gcomp = CS * TXa * TYa; /* stride between components of G in a layer */
-    const int gq = TXa * TYa * q2;    /* stride of the y-index of G in a component */
-    const FastDiv dPW(PW), dPN(PN), dTX(TXa);
-    for (int node = tid0; node < PN; node += WG) {
-        const int by = dPW.div(node), ax = node - by * PW;
-        const int dx = ax == 0 ? 0 : (ax == EX ? 2 : 1);
-        const int dy = by == 0 ? 0 : (by == EY ? 2 : 1);
-        const int sx = dx == 1 ? EX - 1 : 1, sy = dy == 1 ? EY - 1 : 1;
-        const int lx = dx == 1 ? ax - 1 : 0, ly = dy == 1 ? by - 1 : 0;
-        const int cx1 = ax / K, cy1 = by / K;
-        const bool xl = (ax % K) == 0 && cx1 > 0, xr = cx1 < TXa;
-        const bool yl = (by % K) == 0 && cy1 > 0, yr = cy1 < TYa;
-        auto off = [&](int cx, int cy) { return (cx + TXa * cy) * CS + (ax - cx * K) + nq * (by - cy * K); };
-        const int o00 = (xl && yl) ? off(cx1 - 1, cy1 - 1) : 0xffff;
-        const int o01 = (xr && yl) ? off(cx1, cy1 - 1) : 0xffff;
-        const int o10 = (xl && yr) ? off(cx1 - 1, cy1) : 0xffff;
-        const int o11 = (xr && yr) ? off(cx1, cy1) : 0xffff;
-        desc[node] = make_int4((dx + 3 * dy) | ((sx * sy) << 8), lx + sx * ly, o00 | (o01 << 16), o10 | (o11 << 16));
-    }
-    if (FLUSH && tid0 < 8 * (WG / 64)) wacc[tid0] = 0;
-    __syncthreads();
-
-    T acc[7];
-#pragma unroll
-    for (int c = 0; c < 7; ++c) acc[c] = 0;
-
-    /* element offset, kind and partial-sum offset of the node with xy
-     * descriptor dsc on tile plane zz; vectors and partial arrays hold fewer
-     * than 2^31 entries */
-    auto locate = [&](const int4 &dsc, int zz, int &idx, int &kind, int &pidx) {
-        const int dz = zz == 0 ? 0 : (zz == EZ ? 2 : 1);
-        const int lz = dz == 1 ? zz - 1 : 0;
-        const EntityRef &e = ent[(dsc.x & 0xff) + 9 * dz];
-        const int loc = dsc.y + (dsc.x >> 8) * lz;
-        idx = (int)e.vbase + loc;
-        kind = e.kind;
-        pidx = (int)e.pbase + loc;
-    };
-
-    /* Algorithm 5's pre on one node; interior nodes are written back,
-     * shared nodes only recomputed; returns p_k (0 on Dirichlet nodes) and
-     * r_k, D^{-1} in rk, dk (kept in registers for the post of the node) */
-    auto pre_node = [&](int node, int zz, T &rk, T &dk) -> T {
-        int idx, kind, pidx;
-        locate(desc[node], zz, idx, kind, pidx);
-        if (kind == KIND_C) return (T)0;
-        if (MODE == MODE_VMULT) return a.src[idx];
-        const T r0 = a.r[idx], v0 = a.v[idx], p0 = a.p[idx];
-        const T dv = MODE == MODE_CG_NOPREC ? (T)1 : a.dinv[idx];
-        T rn, pn;
-        pre_update(r0, v0, p0, dv, alpha, beta, rn, pn);
-        rk = rn;
-        dk = dv;
-        if (kind == KIND_I) {
-            a.r[idx] = rn;
-            a.p[idx] = pn;
-            if (xupd) a.x[idx] = x_update(a.x[idx], r0, p0, dv, alpha, ratio);
-        }
-        return pn;
-    };
-
-    /* v of a layer node summed over the cells around it, fixed order */
-    auto sum_cells = [&](const int4 &dsc, int zl) -> T {
-        const int o00 = dsc.z & 0xffff, o01 = (int)((unsigned)dsc.z >> 16);
-        const int o10 = dsc.w & 0xffff, o11 = (int)((unsigned)dsc.w >> 16);
-        const int zo = q2 * zl;
-        const T v00 = o00 != 0xffff ? TB[o00 + zo] : (T)0;
-        const T v01 = o01 != 0xffff ? TB[o01 + zo] : (T)0;
-        const T v10 = o10 != 0xffff ? TB[o10 + zo] : (T)0;
-        const T v11 = o11 != 0xffff ? TB[o11 + zo] : (T)0;
-        return ((v00 + v01) + v10) + v11;
-    };
-
-    /* post on one node: r_k and D^{-1} from the registers of this thread's
-     * pre of the node (reg = true) or re-read (the tile's layer-top plane,
-     * whose pre ran in the layer below under another thread mapping), p_k
-     * from the window */
-    auto post_node = [&](const int4 &dsc, int node, int zz, int slot, T v, bool reg, T rk, T dk) {
-        int idx, kind, pidx;
-        locate(dsc, zz, idx, kind, pidx);
-        if (kind == KIND_S) {
-            a.part[pidx] = v;
-        } else if (kind == KIND_I) {
-            if (MODE == MODE_VMULT) {
-                a.dst[idx] = v;
-            } else {
-                /* the quadratic-geometry G pass needs the registers at k <= 4
-                 * (k = 4: 0.90 instead of 1.01 ms per iteration): re-read */
-                const bool use = Cfg<K>::CARRY && !(OPV == OPV_LAPLACE_QGEOM && K <= 4) && reg;
-                const T rn = use ? rk : a.r[idx];
-                const T dv = MODE == MODE_CG_NOPREC ? (T)1 : (use ? dk : a.dinv[idx]);
-                const T pn = win[slot * PNM + node];
-                const T zr = dv * rn, zv = dv * v;
-                acc[0] += rn * rn;
-                acc[1] += pn * v;
-                acc[2] += rn * v;
-                acc[3] += v * v;
-                acc[4] += rn * zr;
-                acc[5] += rn * zv;
-                acc[6] += v * zv;
-                a.v[idx] = v;
-            }
-        }
-    };
-
-    /* r_k and D^{-1} of the nodes this thread pre-processes, held until
-     * their post: the tile's bottom plane (kb*) and the planes 1..K of the
-     * current layer (kr, kd) */
-    T kbr[NC], kbd[NC], kr[NS], kd[NS];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) kbr[c] = kbd[c] = 0;
-#pragma unroll
-    for (int s = 0; s < NS; ++s) kr[s] = kd[s] = 0;
-
-    /* bottom plane of the tile into the window */
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        const int node = tid + WG * c;
-        if (node < PN) win[node] = pre_node(node, 0, kbr[c], kbd[c]);
-    }
-
-#pragma unroll 1
-    for (int L = 0; L < TZa; ++L) {
-        const int s0 = (L * K) % (K + 1);
-        asm volatile("" : "+v"(tid)); /* see above */
-        const T *Gl = a.G + td.gbase + (int64_t)L * 6 * gcomp;
-        if (QGEOM) {
-            /* this layer's cells: the previous layer's last reads of XS
-             * were followed by barriers */
-            const T *Xl = a.G + td.gbase / (6 * CS) * QGEOM_STRIDE + (int64_t)L * TXa * TYa * QGEOM_STRIDE;
-            for (int e = tid; e < TXa * TYa * QGEOM_STRIDE; e += WG) XS[e] = Xl[e];
-        }
-        T gp[R][6][nq];
-        if (GPF == 2) {
-            /* G of this layer issued first: its latency overlaps the pre loads */
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr) {
-                const int l = tid + WG * rr;
-#pragma unroll
-                for (int j = 0; j < nq; ++j)
-#pragma unroll
-                    for (int c = 0; c < NG; ++c) gp[rr][c][j] = (l < nlines) ? gload<NTG>(&Gl[c * gcomp + j * gq + l]) : (T)0;
-            }
-        }
-        /* ---- pre on the planes this layer touches first ---- */
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int f = tid + WG * s;
-            if (f < K * PN) {
-                const int zq = dPN.div(f), zl = 1 + zq, node = f - zq * PN;
-                int slot = s0 + zl;
-                if (slot > K) slot -= K + 1;
-                win[slot * PNM + node] = pre_node(node, L * K + zl, kr[s], kd[s]);
-            }
-        }
-        __syncthreads();
-        asm volatile("" : "+v"(tid)); /* see above */
-        asm volatile("" : "+v"(tid));
-
-        T gy[R][nq], wy[R][nq], wz[R][nq];
-
-        /* F1 [z-lines (i, j)]: gather p from the window, interpolate along z
-         * -> TA at i + n j + n^2 qz */
-#pragma unroll
-        for (int rr = 0; rr < RA; ++rr) {
-            const int l = tid + WG * rr;
-            if (l < nlA) {
-                const int c = l / n2, rem = l % n2, i = rem % n, j = rem / n;
-                const int cy = dTX.div(c), cx = c - cy * TXa;
-                const int nodexy = cx * K + i + PW * (cy * K + j);
-                T u[n];
-#pragma unroll
-                for (int z = 0; z < n; ++z) {
-                    int slot = s0 + z;
-                    if (slot > K) slot -= K + 1;
-                    u[z] = win[slot * PNM + nodexy];
-                }
-#pragma unroll
-                for (int q = 0; q < nq; ++q) {
-                    T t = 0;
-                    if (GLLQ) {
-                        t = u[q];
-                    } else {
-#pragma unroll
-                        for (int z = 0; z < n; ++z) t = fma(cS(q, z), u[z], t);
-                    }
-                    TA[c * CS + rem + n2 * q] = t;
-                }
-            }
-        }
-        __syncthreads();
-        asm volatile("" : "+v"(tid));
-        /* F2 [x-lines (j, qz)]: interpolate along x -> TB at qx + nq j + nq n qz */
-#pragma unroll
-        for (int rr = 0; rr < RB && !GLLQ; ++rr) {
-            const int l = tid + WG * rr;
-            if (l < nlB) {
-                const int c = l / nnq, rem = l % nnq;
-                const int base = c * CS + n * rem, bout = QX ? c * CS + nq * rem : base;
-                T u[n];
-#pragma unroll
-                for (int i = 0; i < n; ++i) u[i] = TA[base + i];
-#pragma unroll
-                for (int q = 0; q < nq; ++q) {
-                    T t = 0;
-#pragma unroll
-                    for (int i = 0; i < n; ++i) t = fma(cS(q, i), u[i], t);
-                    TB[bout + q] = t;
-                }
-            }
-        }
-        __syncthreads();
-        asm volatile("" : "+v"(tid));
-        /* F3 [y-lines (qx, qz)]: interpolate along y -> values at the Gauss
-         * points in TA at qx + nq qy + nq^2 qz, y derivative kept in registers */
-#pragma unroll
-        for (int rr = 0; rr < R; ++rr) {
-            const int l = tid + WG * rr;
-            if (l < nlines) {
-                const int c = l / q2, rem = l % q2, i = rem % nq, z = rem / nq;
-                const int base = c * CS + i + q2 * z;
-                const int bin = QX ? c * CS + i + nnq * z : base;
-                T u[n], uq[nq];
-#pragma unroll
-                for (int j = 0; j < n; ++j) u[j] = GLLQ ? TA[base + nq * j] : TB[bin + nq * j];
-#pragma unroll
-                for (int q = 0; q < nq; ++q) {
-                    if (GLLQ) {
-                        uq[q] = u[q]; /* values already in TA */
-                    } else {
-                        T t = 0;
-#pragma unroll
-                        for (int j = 0; j < n; ++j) t = fma(cS(q, j), u[j], t);
-                        uq[q] = t;
-                        TA[base + nq * q] = t;
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < nq && !MASS; ++q) {
-                    T t = 0;
-#pragma unroll
-                    for (int m = 0; m < nq; ++m) t = fma(cD(q, m), uq[m], t);
-                    gy[rr][q] = t;
-                }
-            }
-        }
-        __syncthreads();
-        asm volatile("" : "+v"(tid));
-        /* G of this layer: loads issued here, consumed after the x and z
-         * derivative passes */
-        if (GPF == 1) {
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr) {
-                const int l = tid + WG * rr;
-#pragma unroll
-                for (int j = 0; j < nq; ++j)
-#pragma unroll
-                    for (int c = 0; c < NG; ++c) gp[rr][c][j] = (l < nlines) ? gload<NTG>(&Gl[c * gcomp + j * gq + l]) : (T)0;
-            }
-        }
-        /* F4 [x-lines (qy, qz)]: x derivative */
-#pragma unroll
-        for (int rr = 0; rr < R && !MASS; ++rr) {
-            const int l = tid + WG * rr;
-            if (l < nlines) {
-                const int c = l / q2, rem = l % q2;
-                const int base = c * CS + nq * rem;
-                T u[nq];
-#pragma unroll
-                for (int i = 0; i < nq; ++i) u[i] = TA[base + i];
-#pragma unroll
-                for (int q = 0; q < nq; ++q) {
-                    T t = 0;
-#pragma unroll
-                    for (int m = 0; m < nq; ++m) t = fma(cD(q, m), u[m], t);
-                    TB[base + q] = t;
-                }
-            }
-        }
-        __syncthreads();
-        asm volatile("" : "+v"(tid));
-        /* F5 [z-lines (qx, qy)]: z derivative, in place */
-#pragma unroll
-        for (int rr = 0; rr < R && !MASS; ++rr) {
-            const int l = tid + WG * rr;
-            if (l < nlines) {
-                const int c = l / q2, rem = l % q2;
-                const int base = c * CS + rem;
-                T u[nq];
-#pragma unroll
-                for (int z = 0; z < nq; ++z) u[z] = TA[base + q2 * z];
-#pragma unroll
-                for (int q = 0; q < nq; ++q) {
-                    T t = 0;
-#pragma unroll
-                    for (int m = 0; m < nq; ++m) t = fma(cD(q, m), u[m], t);
-                    TA[base + q2 * q] = t;
-                }
-            }
-        }
-        __syncthreads();
-        asm volatile("" : "+v"(tid));
-        /* G [y-lines (qx, qz)]: flux = G_q grad u at each Gauss point; y part
-         * of the transposed derivative in registers.  Mass operator: the
-         * values scaled by a_e w_q det J_q, into TB. */
-#pragma unroll
-        for (int rr = 0; rr < R && MASS && !QGEOM; ++rr) {
-            const int l = tid + WG * rr;
-            if (l < nlines) {
-                const int c = l / q2, rem = l % q2, i = rem % nq, z = rem / nq;
-                const int base = c * CS + i + q2 * z;
-#pragma unroll
-                for (int j = 0; j < nq; ++j) {
-                    if (!GPF) gp[rr][0][j] = gload<NTG>(&Gl[j * gq + l]);
-                    TB[base + nq * j] = gp[rr][0][j] * TA[base + nq * j];
-                }
-            }
-        }
-#pragma unroll
-        for (int rr = 0; rr < R && QGEOM; ++rr) {
-            const int l = tid + WG * rr;
-            if (l < nlines) {
-                const int c = l / q2, rem = l % q2, i = rem % nq, z = rem / nq;
-                const int base = c * CS + i + q2 * z;
-                /* this line's Gauss coordinates and weights in x and z */
-                T tx = 0, tz = 0, wx = 0, wz = 0;
-#pragma unroll
-                for (int m = 0; m < nq; ++m) {
-                    tx = i == m ? cxq(m) : tx;
-                    wx = i == m ? cwq(m) : wx;
-                    tz = z == m ? cxq(m) : tz;
-                    wz = z == m ? cwq(m) : wz;
-                }
-                /* quadratic Lagrange basis on {0, 1/2, 1} and its derivative */
-                const T Nx[3] = {(2 * tx - 1) * (tx - 1), 4 * tx * (1 - tx), tx * (2 * tx - 1)};
-                const T dNx[3] = {4 * tx - 3, 4 - 8 * tx, 4 * tx - 1};
-                const T Nz[3] = {(2 * tz - 1) * (tz - 1), 4 * tz * (1 - tz), tz * (2 * tz - 1)};
-                const T dNz[3] = {4 * tz - 3, 4 - 8 * tz, 4 * tz - 1};
-                /* the geometry contracted in x and z for this line:
-                 * V = sum N_a N_d x, Vx = sum N_a' N_d x, Vz = sum N_a N_d' x,
-                 * per component and y point b */
-                const T *Xc = XS + c * QGEOM_STRIDE;
-                T V[3][3], Vx[3][3], Vz[3][3];
-#pragma unroll
-                for (int co = 0; co < 3; ++co)
-#pragma unroll
-                    for (int b = 0; b < 3; ++b) {
-                        T v = 0, vx = 0, vz = 0;
-#pragma unroll
-                        for (int d = 0; d < 3; ++d) {
-                            const T x0 = Xc[co * 27 + 9 * d + 3 * b], x1 = Xc[co * 27 + 9 * d + 3 * b + 1],
-                                    x2 = Xc[co * 27 + 9 * d + 3 * b + 2];
-                            const T sv = Nx[0] * x0 + Nx[1] * x1 + Nx[2] * x2;
-                            const T sx = dNx[0] * x0 + dNx[1] * x1 + dNx[2] * x2;
-                            v += Nz[d] * sv;
-                            vz += dNz[d] * sv;
-                            vx += Nz[d] * sx;
-                        }
-                        V[co][b] = v;
-                        Vx[co][b] = vx;
-                        Vz[co][b] = vz;
-                    }
-                const T aw = Xc[81] * wx * wz;
-                T fy[nq];
-#pragma unroll
-                for (int j = 0; j < nq; ++j) {
-                    const T ty = cxq(j);
-                    const T Ny[3] = {(2 * ty - 1) * (ty - 1), 4 * ty * (1 - ty), ty * (2 * ty - 1)};
-                    const T dNy[3] = {4 * ty - 3, 4 - 8 * ty, 4 * ty - 1};
-                    T J[3][3];
-#pragma unroll
-                    for (int co = 0; co < 3; ++co) {
-                        J[co][0] = Vx[co][0] * Ny[0] + Vx[co][1] * Ny[1] + Vx[co][2] * Ny[2];
-                        J[co][1] = V[co][0] * dNy[0] + V[co][1] * dNy[1] + V[co][2] * dNy[2];
-                        J[co][2] = Vz[co][0] * Ny[0] + Vz[co][1] * Ny[1] + Vz[co][2] * Ny[2];
-                    }
-                    if (MASS) {
-                        /* a_e w_q det J_q times the value at the point */
-                        const T det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) +
-                                      J[0][1] * (J[1][2] * J[2][0] - J[1][0] * J[2][2]) +
-                                      J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
-                        TB[base + nq * j] = aw * cwq(j) * det * TA[base + nq * j];
-                        continue;
-                    }
-                    /* adjugate (det J times J^{-1}) and determinant */
-                    const T A00 = J[1][1] * J[2][2] - J[1][2] * J[2][1], A01 = J[0][2] * J[2][1] - J[0][1] * J[2][2],
-                            A02 = J[0][1] * J[1][2] - J[0][2] * J[1][1], A10 = J[1][2] * J[2][0] - J[1][0] * J[2][2],
-                            A11 = J[0][0] * J[2][2] - J[0][2] * J[2][0], A12 = J[0][2] * J[1][0] - J[0][0] * J[1][2],
-                            A20 = J[1][0] * J[2][1] - J[1][1] * J[2][0], A21 = J[0][1] * J[2][0] - J[0][0] * J[2][1],
-                            A22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-                    const T det = J[0][0] * A00 + J[0][1] * A10 + J[0][2] * A20;
-                    /* flux a_e w_q det J J^{-1} J^{-T} grad u = sc A (A^T grad u)
-                     * with sc = a_e w_q / det J, without forming the tensor */
-                    const T sc = aw * cwq(j) / det;
-                    const T ux = TB[base + nq * j], uy = gy[rr][j], uz = TA[base + nq * j];
-                    const T t0 = A00 * ux + A10 * uy + A20 * uz, t1 = A01 * ux + A11 * uy + A21 * uz,
-                            t2 = A02 * ux + A12 * uy + A22 * uz;
-                    const T fx = sc * (A00 * t0 + A01 * t1 + A02 * t2);
-                    fy[j] = sc * (A10 * t0 + A11 * t1 + A12 * t2);
-                    const T fz = sc * (A20 * t0 + A21 * t1 + A22 * t2);
-                    TB[base + nq * j] = fx;
-                    TA[base + nq * j] = fz;
-                }
-#pragma unroll
-                for (int m = 0; m < nq && !MASS; ++m) {
-                    T t = 0;
-#pragma unroll
-                    for (int q = 0; q < nq; ++q) t = fma(cD(q, m), fy[q], t);
-                    wy[rr][m] = t;
-                }
-            }
-        }
-#pragma unroll
-        for (int rr = 0; rr < R && !MASS && !QGEOM; ++rr) {
-            const int l = tid + WG * rr;
-            if (l < nlines) {
-                const int c = l / q2, rem = l % q2, i = rem % nq, z = rem / nq;
-                const int base = c * CS + i + q2 * z;
-                T fy[nq];
-#pragma unroll
-                for (int j = 0; j < nq; ++j) {
-                    if (!GPF) {
-#pragma unroll
-                        for (int c2 = 0; c2 < 6; ++c2) gp[rr][c2][j] = gload<NTG>(&Gl[c2 * gcomp + j * gq + l]);
-                    }
-                    const T ux = TB[base + nq * j], uy = gy[rr][j], uz = TA[base + nq * j];
-                    const T fx = gp[rr][0][j] * ux + gp[rr][3][j] * uy + gp[rr][4][j] * uz;
-                    fy[j] = gp[rr][3][j] * ux + gp[rr][1][j] * uy + gp[rr][5][j] * uz;
-                    const T fz = gp[rr][4][j] * ux + gp[rr][5][j] * uy + gp[rr][2][j] * uz;
-                    TB[base + nq * j] = fx;
-                    TA[base + nq * j] = fz;
-                }
-#pragma unroll
-                for (int m = 0; m < nq; ++m) {
-                    T t = 0;
-#pragma unroll
-                    for (int q = 0; q < nq; ++q) t = fma(cD(q, m), fy[q], t);
-                    wy[rr][m] = t;
-                }
-            }
-        }
-        __syncthreads();
-        asm volatile("" : "+v"(tid));
-        /* B2 [x-lines (qy, qz)]: transposed x derivative, in place; B3
-         * [z-lines (qx, qy)]: transposed z derivative into registers */
-#pragma unroll
-        for (int rr = 0; rr < R && !MASS; ++rr) {
-            const int l = tid + WG * rr;
-            if (l < nlines) {
-                const int c = l / q2, rem = l % q2;
-                {
-                    const int base = c * CS + nq * rem;
-                    T f[nq];
-#pragma unroll
-                    for (int q = 0; q < nq; ++q) f[q] = TB[base + q];
-#pragma unroll
-                    for (int m = 0; m < nq; ++m) {
-                        T t = 0;
-#pragma unroll
-                        for (int q = 0; q < nq; ++q) t = fma(cD(q, m), f[q], t);
-                        TB[base + m] = t;
-                    }
-                }
-                {
-                    const int base = c * CS + rem;
-                    T f[nq];
-#pragma unroll
-                    for (int q = 0; q < nq; ++q) f[q] = TA[base + q2 * q];
-#pragma unroll
-                    for (int m = 0; m < nq; ++m) {
-                        T t = 0;
-#pragma unroll
-                        for (int q = 0; q < nq; ++q) t = fma(cD(q, m), f[q], t);
-                        wz[rr][m] = t;
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        asm volatile("" : "+v"(tid));
-        /* B4 [y-lines (qx, qz)]: add the y part */
-#pragma unroll
-        for (int rr = 0; rr < R && !MASS; ++rr) {
-            const int l = tid + WG * rr;
-            if (l < nlines) {
-                const int c = l / q2, rem = l % q2, i = rem % nq, z = rem / nq;
-                const int base = c * CS + i + q2 * z;
-#pragma unroll
-                for (int j = 0; j < nq; ++j) TB[base + nq * j] += wy[rr][j];
-            }
-        }
-        __syncthreads();
-        asm volatile("" : "+v"(tid));
-        /* B5 [z-lines (qx, qy)]: add the z part, transposed interpolation
-         * along z -> qx + nq qy + nq^2 z */
-#pragma unroll
-        for (int rr = 0; rr < R; ++rr) {
-            const int l = tid + WG * rr;
-            if (l < nlines) {
-                const int c = l / q2, rem = l % q2;
-                const int base = c * CS + rem;
-                T w[nq];
-#pragma unroll
-                for (int q = 0; q < nq; ++q) w[q] = MASS ? TB[base + q2 * q] : TB[base + q2 * q] + wz[rr][q];
-#pragma unroll
-                for (int z = 0; z < n; ++z) {
-                    T t = 0;
-                    if (GLLQ) {
-                        t = w[z];
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < nq; ++q) t = fma(cS(q, z), w[q], t);
-                    }
-                    TB[base + q2 * z] = t;
-                }
-            }
-        }
-        __syncthreads();
-        asm volatile("" : "+v"(tid));
-        /* B6 [x-lines (qy, z)]: transposed interpolation along x -> i + nq qy + nq^2 z */
-#pragma unroll
-        for (int rr = 0; rr < RB && !GLLQ; ++rr) {
-            const int l = tid + WG * rr;
-            if (l < nlB) {
-                const int c = l / nnq, rem = l % nnq;
-                const int base = c * CS + nq * rem;
-                T w[nq];
-#pragma unroll
-                for (int q = 0; q < nq; ++q) w[q] = TB[base + q];
-#pragma unroll
-                for (int i = 0; i < n; ++i) {
-                    T t = 0;
-#pragma unroll
-                    for (int q = 0; q < nq; ++q) t = fma(cS(q, i), w[q], t);
-                    TB[base + i] = t;
-                }
-            }
-        }
-        __syncthreads();
-        asm volatile("" : "+v"(tid));
-        /* B7 [y-lines (i, z)]: transposed interpolation along y -> cell
-         * vectors at i + nq j + nq^2 z */
-#pragma unroll
-        for (int rr = 0; rr < RA && !GLLQ; ++rr) {
-            const int l = tid + WG * rr;
-            if (l < nlA) {
-                const int c = l / n2, rem = l % n2, i = rem % n, z = rem / n;
-                const int base = c * CS + i + q2 * z;
-                T w[nq];
-#pragma unroll
-                for (int q = 0; q < nq; ++q) w[q] = TB[base + nq * q];
-#pragma unroll
-                for (int j = 0; j < n; ++j) {
-                    T t = 0;
-#pragma unroll
-                    for (int q = 0; q < nq; ++q) t = fma(cS(q, j), w[q], t);
-                    TB[base + nq * j] = t;
-                }
-            }
-        }
-        __syncthreads();
-        asm volatile("" : "+v"(tid));
-
-        /* ---- sum over cells and post ---- */
-        /* plane z = 0 of the layer, completing the carry of the layer below */
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const int node = tid + WG * c;
-            if (node < PN) {
-                const int4 dsc = desc[node];
-                T v = sum_cells(dsc, 0);
-                if (L > 0) v = cv[(L & 1) * PNM + node] + v;
-                post_node(dsc, node, L * K, s0, v, L == 0, kbr[c], kbd[c]);
-            }
-        }
-        /* planes z = 1..K; the top plane is carried unless it is the tile's last */
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int f = tid + WG * s;
-            if (f < K * PN) {
-                const int zq = dPN.div(f), zl = 1 + zq, node = f - zq * PN;
-                const int4 dsc = desc[node];
-                const T v = sum_cells(dsc, zl);
-                if (zl == K && L + 1 < TZa) {
-                    cv[((L + 1) & 1) * PNM + node] = v;
-                } else {
-                    int slot = s0 + zl;
-                    if (slot > K) slot -= K + 1;
-                    post_node(dsc, node, L * K + zl, slot, v, true, kr[s], kd[s]);
-                }
-            }
-        }
-        if (FLUSH) {
-            /* fixed order: shuffle tree in the wave, then the wave's slot in
-             * layer order */
-            const int lane = tid0 & 63, wave = tid0 >> 6;
-#pragma unroll
-            for (int c = 0; c < 7; ++c) {
-                T sv = acc[c];
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) sv += __shfl_xor(sv, off, 64);
-                if (lane == 0) wacc[wave * 8 + c] += sv;
-                acc[c] = 0;
-            }
-        }
-        __syncthreads();
-        asm volatile("" : "+v"(tid));
-    }
-
-    if (FLUSH) {
-        if (tid0 < 7) {
-            T sv = 0;
-            for (int w = 0; w < WG / 64; ++w) sv += wacc[w * 8 + tid0];
-            a.dots[tile * 8 + tid0] = sv;
-        }
-    } else if (mode_is_cg(MODE)) {
-        block_reduce<T, 7, WG>(acc, red, a.dots + tile * 8);
-    }
-}
-
-template <int K, typename T, int MODE, int OPV = OPV_LAPLACE, int QX = 0>
-__global__ __launch_bounds__(Cfg<K>::WG)
-__attribute__((amdgpu_waves_per_eu(MFCG_WPE_MIN_Q(K, QX, OPV), 8)))
-void fused_tile_kernel(const IterArgs<T> a)
-{
-    if (mode_is_cg(MODE) && a.st->flag != FLAG_RUN) return;
-    fused_tile<K, T, MODE, OPV, true, QX>(a, xcd_remap(blockIdx.x, gridDim.x));
-}
-
-/* Vector problems: one launch over (tile, component) pairs, the component
- * fastest, so the workgroups of one tile's three components are
- * dispatched together on one XCD and the geometry tensor they all apply is
- * fetched from HBM about once and then served from that XCD's L2.
- * Component c works on the vectors at offset c*nstride, its shared-node
- * partial sums at c*pstride and its inner-product records at c*dstride. */
-template <int K, int MODE, int OPV, int QX = 0>
-__global__ __launch_bounds__(Cfg<K>::WG)
-__attribute__((amdgpu_waves_per_eu(MFCG_WPE_MIN_Q(K, QX, OPV), 8)))
-void fused_tile_vec_kernel(const IterArgs<double> a, int64_t nstride, int64_t pstride, int64_t dstride)
-{
-    if (a.st->flag != FLAG_RUN) return;
-    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int c = (int)(lb % 3);
-    IterArgs<double> b = a;
-    b.r += c * nstride;
-    b.p += c * nstride;
-    b.v += c * nstride;
-    b.x += c * nstride;
-    b.part += c * pstride;
-    b.dots += c * dstride;
-    fused_tile<K, double, MODE, OPV, false, QX>(b, lb / 3);
-}
-
-/* Batch of problems of degree K: one workgroup per (problem, tile) item of
- * the work list; problems that have left the running state are skipped. */
-template <int K, typename T>
-__global__ __launch_bounds__(Cfg<K>::WG)
-__attribute__((amdgpu_waves_per_eu(MFCG_WPE_MIN_BATCH(K), 8)))
-void fused_batch_kernel(const IterArgs<T> *__restrict__ probs, const int2 *__restrict__ items, int nitems)
-{
-    const int2 it = items[xcd_remap(blockIdx.x, nitems)];
-    const int p = __builtin_amdgcn_readfirstlane(it.x);
-    const int64_t tile = __builtin_amdgcn_readfirstlane(it.y);
-    const IterArgs<T> &a = *const_view(probs + p);
-    if (a.st->flag != FLAG_RUN) return;
-    fused_tile<K, T, MODE_CG>(a, tile);
-}
+void tile_limits(int K, int *tx, int *ty) { tile_limits_impl(K, tx, ty); }
+int fused_block_size(int K) { return fused_block_size_impl(K); }
 
 /* ------------------------------------------------------------------ */
 /* Shared-node kernel with the single-pass finish                      */
@@ -1086,79 +199,24 @@ __global__ __launch_bounds__(SHARED_WG) void finish_batch_kernel(const IterArgs<
 /* Launch wrappers                                                     */
 /* ------------------------------------------------------------------ */
 
-/* one operator variant in one of the three modes */
-template <int K, int OPV, int QX>
-static void launch_fused_variant(int mode, dim3 grid, dim3 block, const IterArgs<double> &a, hipStream_t s)
-{
-    if (mode == MODE_CG)
-        hipLaunchKernelGGL((fused_tile_kernel<K, double, MODE_CG, OPV, QX>), grid, block, 0, s, a);
-    else if (mode == MODE_CG_NOPREC)
-        hipLaunchKernelGGL((fused_tile_kernel<K, double, MODE_CG_NOPREC, OPV, QX>), grid, block, 0, s, a);
-    else
-        hipLaunchKernelGGL((fused_tile_kernel<K, double, MODE_VMULT, OPV, QX>), grid, block, 0, s, a);
-}
-
-template <int K, typename T>
-static hipError_t launch_fused_k(int mode, const IterArgs<T> &a, hipStream_t s)
-{
-    dim3 grid((unsigned)a.L.ntiles), block(Cfg<K>::WG);
-    if (mode & (MODE_GLL | MODE_MASS | MODE_Q2 | MODE_QGEOM)) {
-        if constexpr (!std::is_same<T, double>::value) {
-            return hipErrorInvalidValue; /* FP64 only */
-        } else {
-            const bool mass = mode & MODE_MASS, gll = mode & MODE_GLL, q2 = mode & MODE_Q2, qg = mode & MODE_QGEOM;
-            if (gll && (mass || q2)) return hipErrorInvalidValue;
-            if (qg && gll) return hipErrorInvalidValue;
-            mode &= ~(MODE_GLL | MODE_MASS | MODE_Q2 | MODE_QGEOM);
-            if (mode != MODE_CG && mode != MODE_CG_NOPREC && mode != MODE_VMULT) return hipErrorInvalidValue;
-            if (qg && q2) {
-                if constexpr (K <= 7) {
-                    if (mass) launch_fused_variant<K, OPV_MASS_QGEOM, 1>(mode, grid, block, a, s);
-                    else launch_fused_variant<K, OPV_LAPLACE_QGEOM, 1>(mode, grid, block, a, s);
-                } else {
-                    return hipErrorInvalidValue;
-                }
-            } else if (qg) {
-                if (mass) launch_fused_variant<K, OPV_MASS_QGEOM, 0>(mode, grid, block, a, s);
-                else launch_fused_variant<K, OPV_LAPLACE_QGEOM, 0>(mode, grid, block, a, s);
-            } else if (q2) {
-                if constexpr (K <= 7) {
-                    if (mass) launch_fused_variant<K, OPV_MASS, 1>(mode, grid, block, a, s);
-                    else launch_fused_variant<K, OPV_LAPLACE, 1>(mode, grid, block, a, s);
-                } else {
-                    return hipErrorInvalidValue;
-                }
-            } else if (mass) {
-                launch_fused_variant<K, OPV_MASS, 0>(mode, grid, block, a, s);
-            } else {
-                launch_fused_variant<K, OPV_LAPLACE_GLL, 0>(mode, grid, block, a, s);
-            }
-            return hipGetLastError();
-        }
-    }
-    if (mode == MODE_CG) {
-        hipLaunchKernelGGL((fused_tile_kernel<K, T, MODE_CG>), grid, block, 0, s, a);
-    } else if (mode == MODE_CG_NOPREC) {
-        if constexpr (!std::is_same<T, double>::value) return hipErrorInvalidValue; /* FP64 only */
-        else hipLaunchKernelGGL((fused_tile_kernel<K, T, MODE_CG_NOPREC>), grid, block, 0, s, a);
-    } else {
-        hipLaunchKernelGGL((fused_tile_kernel<K, T, MODE_VMULT>), grid, block, 0, s, a);
-    }
-    return hipGetLastError();
-}
-
 template <typename T>
 hipError_t launch_fused(int K, int mode, const IterArgs<T> &a, hipStream_t s)
 {
+    constexpr bool D = std::is_same<T, double>::value;
+    auto pick = [&](auto deg) -> hipError_t {
+        using F = decltype(deg);
+        if constexpr (D) return F::fused64(mode, a, s);
+        else return F::fused32(mode, a, s);
+    };
     switch (K) {
-    case 1: return launch_fused_k<1, T>(mode, a, s);
-    case 2: return launch_fused_k<2, T>(mode, a, s);
-    case 3: return launch_fused_k<3, T>(mode, a, s);
-    case 4: return launch_fused_k<4, T>(mode, a, s);
-    case 5: return launch_fused_k<5, T>(mode, a, s);
-    case 6: return launch_fused_k<6, T>(mode, a, s);
-    case 7: return launch_fused_k<7, T>(mode, a, s);
-    case 8: return launch_fused_k<8, T>(mode, a, s);
+    case 1: return pick(FusedDeg<1>{});
+    case 2: return pick(FusedDeg<2>{});
+    case 3: return pick(FusedDeg<3>{});
+    case 4: return pick(FusedDeg<4>{});
+    case 5: return pick(FusedDeg<5>{});
+    case 6: return pick(FusedDeg<6>{});
+    case 7: return pick(FusedDeg<7>{});
+    case 8: return pick(FusedDeg<8>{});
     default: return hipErrorInvalidValue;
     }
 }
@@ -1182,63 +240,18 @@ hipError_t launch_shared(int mode, const IterArgs<T> &a, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int K>
-static hipError_t launch_fused_vec_k(int mode, const IterArgs<double> &a, int64_t nstride, int64_t pstride,
-                                     int64_t dstride, hipStream_t s)
-{
-    dim3 grid((unsigned)(3 * a.L.ntiles)), block(Cfg<K>::WG);
-    if (mode == (MODE_CG | MODE_Q2) || mode == (MODE_CG | MODE_MASS | MODE_Q2) || mode == (MODE_CG | MODE_QGEOM | MODE_Q2) ||
-        mode == (MODE_CG | MODE_QGEOM | MODE_MASS | MODE_Q2)) {
-        if constexpr (K <= 7) {
-            if ((mode & MODE_QGEOM) && (mode & MODE_MASS))
-                hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_MASS_QGEOM, 1>), grid, block, 0, s, a,
-                                   nstride, pstride, dstride);
-            else if (mode & MODE_QGEOM)
-                hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_LAPLACE_QGEOM, 1>), grid, block, 0, s, a,
-                                   nstride, pstride, dstride);
-            else if (mode & MODE_MASS)
-                hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_MASS, 1>), grid, block, 0, s, a, nstride,
-                                   pstride, dstride);
-            else
-                hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_LAPLACE, 1>), grid, block, 0, s, a, nstride,
-                                   pstride, dstride);
-            return hipGetLastError();
-        } else {
-            return hipErrorInvalidValue;
-        }
-    }
-    if (mode == MODE_CG)
-        hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_LAPLACE>), grid, block, 0, s, a, nstride, pstride,
-                           dstride);
-    else if (mode == (MODE_CG | MODE_GLL))
-        hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_LAPLACE_GLL>), grid, block, 0, s, a, nstride, pstride,
-                           dstride);
-    else if (mode == (MODE_CG | MODE_MASS))
-        hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_MASS>), grid, block, 0, s, a, nstride, pstride,
-                           dstride);
-    else if (mode == (MODE_CG | MODE_QGEOM | MODE_MASS))
-        hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_MASS_QGEOM>), grid, block, 0, s, a, nstride,
-                           pstride, dstride);
-    else if (mode == (MODE_CG | MODE_QGEOM))
-        hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_LAPLACE_QGEOM>), grid, block, 0, s, a, nstride,
-                           pstride, dstride);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
-}
-
 hipError_t launch_fused_vec(int K, int mode, const IterArgs<double> &a, int64_t nstride, int64_t pstride,
                             int64_t dstride, hipStream_t s)
 {
     switch (K) {
-    case 1: return launch_fused_vec_k<1>(mode, a, nstride, pstride, dstride, s);
-    case 2: return launch_fused_vec_k<2>(mode, a, nstride, pstride, dstride, s);
-    case 3: return launch_fused_vec_k<3>(mode, a, nstride, pstride, dstride, s);
-    case 4: return launch_fused_vec_k<4>(mode, a, nstride, pstride, dstride, s);
-    case 5: return launch_fused_vec_k<5>(mode, a, nstride, pstride, dstride, s);
-    case 6: return launch_fused_vec_k<6>(mode, a, nstride, pstride, dstride, s);
-    case 7: return launch_fused_vec_k<7>(mode, a, nstride, pstride, dstride, s);
-    case 8: return launch_fused_vec_k<8>(mode, a, nstride, pstride, dstride, s);
+    case 1: return FusedDeg<1>::vec(mode, a, nstride, pstride, dstride, s);
+    case 2: return FusedDeg<2>::vec(mode, a, nstride, pstride, dstride, s);
+    case 3: return FusedDeg<3>::vec(mode, a, nstride, pstride, dstride, s);
+    case 4: return FusedDeg<4>::vec(mode, a, nstride, pstride, dstride, s);
+    case 5: return FusedDeg<5>::vec(mode, a, nstride, pstride, dstride, s);
+    case 6: return FusedDeg<6>::vec(mode, a, nstride, pstride, dstride, s);
+    case 7: return FusedDeg<7>::vec(mode, a, nstride, pstride, dstride, s);
+    case 8: return FusedDeg<8>::vec(mode, a, nstride, pstride, dstride, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1261,16 +274,15 @@ hipError_t launch_batch_iteration(const BatchLaunch &b, hipStream_t s)
     for (int K = 1; K <= 8; ++K) {
         const int ni = b.nitems[K];
         if (ni == 0) continue;
-        const dim3 grid((unsigned)ni);
         switch (K) {
-        case 1: hipLaunchKernelGGL((fused_batch_kernel<1, double>), grid, dim3(Cfg<1>::WG), 0, s, b.probs, b.items[K], ni); break;
-        case 2: hipLaunchKernelGGL((fused_batch_kernel<2, double>), grid, dim3(Cfg<2>::WG), 0, s, b.probs, b.items[K], ni); break;
-        case 3: hipLaunchKernelGGL((fused_batch_kernel<3, double>), grid, dim3(Cfg<3>::WG), 0, s, b.probs, b.items[K], ni); break;
-        case 4: hipLaunchKernelGGL((fused_batch_kernel<4, double>), grid, dim3(Cfg<4>::WG), 0, s, b.probs, b.items[K], ni); break;
-        case 5: hipLaunchKernelGGL((fused_batch_kernel<5, double>), grid, dim3(Cfg<5>::WG), 0, s, b.probs, b.items[K], ni); break;
-        case 6: hipLaunchKernelGGL((fused_batch_kernel<6, double>), grid, dim3(Cfg<6>::WG), 0, s, b.probs, b.items[K], ni); break;
-        case 7: hipLaunchKernelGGL((fused_batch_kernel<7, double>), grid, dim3(Cfg<7>::WG), 0, s, b.probs, b.items[K], ni); break;
-        case 8: hipLaunchKernelGGL((fused_batch_kernel<8, double>), grid, dim3(Cfg<8>::WG), 0, s, b.probs, b.items[K], ni); break;
+        case 1: FusedDeg<1>::batch(b.probs, b.items[K], ni, s); break;
+        case 2: FusedDeg<2>::batch(b.probs, b.items[K], ni, s); break;
+        case 3: FusedDeg<3>::batch(b.probs, b.items[K], ni, s); break;
+        case 4: FusedDeg<4>::batch(b.probs, b.items[K], ni, s); break;
+        case 5: FusedDeg<5>::batch(b.probs, b.items[K], ni, s); break;
+        case 6: FusedDeg<6>::batch(b.probs, b.items[K], ni, s); break;
+        case 7: FusedDeg<7>::batch(b.probs, b.items[K], ni, s); break;
+        case 8: FusedDeg<8>::batch(b.probs, b.items[K], ni, s); break;
         }
     }
     if (b.nshared_items > 0)
