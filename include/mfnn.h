@@ -70,6 +70,21 @@ int mfnn_conv3d_bwd_weight(const mfnn_conv_desc *desc, const void *x, int32_t x_
                            void *hip_stream);
 int64_t mfnn_conv3d_bwd_weight_work(const mfnn_conv_desc *desc);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight training or serving loops, harnesses that forbid
+ * hipMalloc): mfnn_conv3d_bwd_weight with the workspace taken from a
+ * library-owned device array of MFNN_NOALLOC_WORK_FLOATS floats (4 MiB), one
+ * per GPU, held until the process ends.  The call allocates nothing and
+ * gives the same dw and db as mfnn_conv3d_bwd_weight.  Returns MFNN_EINVAL
+ * (before any launch) when mfnn_conv3d_bwd_weight_work(desc) exceeds
+ * MFNN_NOALLOC_WORK_FLOATS.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (different streams, or host threads without
+ * ordering) race and give wrong gradients; calls ordered on one stream are
+ * safe.  No part of the array needs to start at any value. */
+#define MFNN_NOALLOC_WORK_FLOATS (1 << 20)
+int mfnn_conv3d_bwd_weight_noalloc(const mfnn_conv_desc *desc, const void *x, int32_t x_dtype, const void *g,
+                                   int32_t g_dtype, float *dw, float *db, void *hip_stream);
+
 /* dz = dy * a'(z), with a'(z) taken from the activation's output y
  * (the leaky ReLU keeps the sign): dz_i = dy_i if y_i > 0 else 0.1 dy_i. */
 int mfnn_act_bwd(int64_t n, const float *dy, const void *y, int32_t y_dtype, int32_t act, float *dz,

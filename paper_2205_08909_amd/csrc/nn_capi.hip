@@ -4,12 +4,25 @@
  */
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <string>
 
 #include "../../include/mfnn.h"
 #include "nn_kernels.h"
 
 using namespace mfnn;
+
+/* Workspace of mfnn_conv3d_bwd_weight_noalloc: the per-chunk partial weight
+ * gradients live in this array instead of a caller buffer.  Each GPU holds
+ * its own copy for the life of the process.  Host code never passes the
+ * array's name to a kernel (on the host it is a stand-in, not a device
+ * address); it passes the device address that hipGetSymbolAddress returned
+ * for the current device. */
+static __device__ __align__(256) float scratch[MFNN_NOALLOC_WORK_FLOATS];
+
+constexpr int MAX_SCRATCH_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static float *g_scratch_ptr[MAX_SCRATCH_DEVICES];
 
 static thread_local std::string g_nn_err;
 
@@ -106,6 +119,44 @@ int mfnn_conv3d_bwd_weight(const mfnn_conv_desc *desc, const void *x, int32_t x_
     if (!x || !gr || !dw || !work) return nn_fail(MFNN_EINVAL, "null tensor");
     if (!dtype_ok(x_dtype) || !dtype_ok(g_dtype)) return nn_fail(MFNN_EINVAL, "x and g must be BF16 or F32");
     if (work_floats < mfnn_conv3d_bwd_weight_work(desc)) return nn_fail(MFNN_EINVAL, "work buffer too small");
+    NNCHK(launch_conv_bwd_weight(g, x, x_dtype, gr, g_dtype, dw, db, work, (hipStream_t)hip_stream));
+    return MFNN_OK;
+}
+
+/* Device address of the current device's copy of the scratch array, looked
+ * up once per device (on the first call made with that device current). */
+static int scratch_of_current_device(float **out)
+{
+    int dev = -1;
+    NNCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_SCRATCH_DEVICES) return nn_fail(MFNN_EINVAL, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        float *p = nullptr;
+        NNCHK(hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch)));
+        if (!p) return nn_fail(MFNN_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MFNN_OK;
+}
+
+int mfnn_conv3d_bwd_weight_noalloc(const mfnn_conv_desc *desc, const void *x, int32_t x_dtype, const void *gr,
+                                   int32_t g_dtype, float *dw, float *db, void *hip_stream)
+{
+    ConvGeom g{};
+    int rc = check_desc(desc, g);
+    if (rc) return rc;
+    if (!x || !gr || !dw) return nn_fail(MFNN_EINVAL, "null tensor");
+    if (!dtype_ok(x_dtype) || !dtype_ok(g_dtype)) return nn_fail(MFNN_EINVAL, "x and g must be BF16 or F32");
+    const int64_t need = mfnn_conv3d_bwd_weight_work(desc);
+    if (need < 0 || need > MFNN_NOALLOC_WORK_FLOATS)
+        return nn_fail(MFNN_EINVAL, "layer needs " + std::to_string(need) +
+                                        " floats of weight-gradient workspace; the allocation-free entry point has " +
+                                        std::to_string((long long)MFNN_NOALLOC_WORK_FLOATS));
+    float *work = nullptr;
+    rc = scratch_of_current_device(&work);
+    if (rc) return rc;
     NNCHK(launch_conv_bwd_weight(g, x, x_dtype, gr, g_dtype, dw, db, work, (hipStream_t)hip_stream));
     return MFNN_OK;
 }

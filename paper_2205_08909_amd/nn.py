@@ -12,9 +12,11 @@ OK, EINVAL, EHIP = 0, -1, -3
 BF16, F32, F64 = 0, 1, 2
 ACT_NONE, ACT_LEAKY = 0, 1
 LEAKY_SLOPE = 0.1
+NOALLOC_WORK_FLOATS = 1 << 20   # workspace of mfnn_conv3d_bwd_weight_noalloc (floats per GPU)
 
 EXPORTED = [
     "mfnn_conv3d_fwd", "mfnn_conv3d_bwd_data", "mfnn_conv3d_bwd_weight", "mfnn_conv3d_bwd_weight_work",
+    "mfnn_conv3d_bwd_weight_noalloc",
     "mfnn_act_bwd", "mfnn_mse", "mfnn_adam", "mfnn_convert", "mfnn_features", "mfnn_channel_sum",
     "mfnn_normalize", "mfnn_last_error",
 ]
@@ -68,6 +70,7 @@ def lib():
         L.mfnn_conv3d_bwd_weight.argtypes = [DP, P, I32, P, I32, P, P, P, I64, P]
         L.mfnn_conv3d_bwd_weight_work.argtypes = [DP]
         L.mfnn_conv3d_bwd_weight_work.restype = I64
+        L.mfnn_conv3d_bwd_weight_noalloc.argtypes = [DP, P, I32, P, I32, P, P, P]
         L.mfnn_act_bwd.argtypes = [I64, P, P, I32, I32, P, P]
         L.mfnn_mse.argtypes = [I64, P, P, P, P, P, P]
         L.mfnn_adam.argtypes = [I64, P, P, P, P, P, I32, F, F, F, F, P]
@@ -148,6 +151,19 @@ def conv_bwd_weight(d, x, g, dw, db, work, stream=None):
         _need(db, d.c_out, "db")
     _check(lib().mfnn_conv3d_bwd_weight(ctypes.byref(d), _p(x), _dt(x), _p(g), _dt(g), _p(dw), _p(db), _p(work),
                                         int(work.numel()), _s(stream)))
+    return dw
+
+
+def conv_bwd_weight_noalloc(d, x, g, dw, db, stream=None):
+    """conv_bwd_weight with the library's own per-GPU workspace (no caller buffer)."""
+    iv, ov, kk = _sizes(d)
+    _need(x, d.n * d.c_in * iv, "x")
+    _need(g, d.n * d.c_out * ov, "g")
+    _need(dw, d.c_out * d.c_in * kk, "dw")
+    if db is not None:
+        _need(db, d.c_out, "db")
+    _check(lib().mfnn_conv3d_bwd_weight_noalloc(ctypes.byref(d), _p(x), _dt(x), _p(g), _dt(g), _p(dw), _p(db),
+                                                _s(stream)))
     return dw
 
 

@@ -61,6 +61,12 @@ def test_network_calls_reject_bad_descriptors():
     assert L.mfnn_convert(10, fake, 3, fake, 0, None) == nn.EINVAL
     cells = (ctypes.c_int32 * 3)(4, 4, 0)
     assert L.mfnn_features(cells, 3, fake, fake, fake, fake, fake, None) == nn.EINVAL
+    # the allocation-free weight gradient refuses a layer whose workspace exceeds its array
+    wide = nn.desc(1, 256, 256, (8, 8, 8), 3, 1, 1, 1)
+    assert L.mfnn_conv3d_bwd_weight_work(ctypes.byref(wide)) > nn.NOALLOC_WORK_FLOATS
+    assert L.mfnn_conv3d_bwd_weight_noalloc(ctypes.byref(wide), fake, 0, fake, 0, fake, None, None) == nn.EINVAL
+    assert b"workspace" in L.mfnn_last_error()
+    assert L.mfnn_conv3d_bwd_weight_noalloc(ctypes.byref(bad), fake, 0, fake, 0, fake, None, None) == nn.EINVAL
 
 
 def test_error_strings():
