@@ -150,3 +150,60 @@ def test_l2_convergence_rate(oracle_mod, kind, k, Ns):
         errs.append(O.l2_error(m, x))
     rate = np.log2(errs[0] / errs[1]) / np.log2(Ns[1] / Ns[0])
     assert abs(rate - (k + 1)) < 0.35, (errs, rate)
+
+
+def _bump_moments(params):
+    """Closed forms of int f and int f x_d over the unit cube for
+    f = sum_m A_m exp(-|x - c_m|^2 / (2 s_m^2)): per direction,
+    int_0^1 exp(-(t-c)^2/(2s^2)) dt = s sqrt(pi/2) [erf((1-c)/(s sqrt2)) + erf(c/(s sqrt2))]
+    and int_0^1 t exp(-(t-c)^2/(2s^2)) dt = c I0 + s^2 [exp(-c^2/(2s^2)) - exp(-(1-c)^2/(2s^2))]."""
+    from math import erf, exp, pi, sqrt
+    nb = int(params[0])
+    m0, m1 = 0.0, np.zeros(3)
+    for b in range(nb):
+        A, cx, cy, cz, s = params[1 + 5 * b: 6 + 5 * b]
+        i0, i1 = [], []
+        for c in (cx, cy, cz):
+            z = s * sqrt(2.0)
+            I0 = s * sqrt(pi / 2.0) * (erf((1.0 - c) / z) + erf(c / z))
+            I1 = c * I0 + s * s * (exp(-c * c / (2 * s * s)) - exp(-(1.0 - c) ** 2 / (2 * s * s)))
+            i0.append(I0)
+            i1.append(I1)
+        m0 += A * i0[0] * i0[1] * i0[2]
+        m1 += A * np.array([i1[0] * i0[1] * i0[2], i0[0] * i1[1] * i0[2], i0[0] * i0[1] * i1[2]])
+    return m0, m1
+
+
+@pytest.mark.parametrize("k,N", [(3, 12), (4, 10)])
+def test_rhs_bumps_closed_form(oracle_mod, k, N):
+    """Gaussian-bump forcing (the warm-start workload's load vector): with no
+    boundary condition on the affine unit cube, sum_i b_i = int f (partition
+    of unity) and sum_i x_d(node i) b_i = int f x_d (the Q_k basis reproduces
+    linear functions), against the closed-form integrals, to Gauss-quadrature
+    accuracy.  A wrong width factor, centre, amplitude or sign fails."""
+    O = oracle_mod
+    rng = np.random.default_rng(5)
+    nb = 4
+    params = [nb]
+    for _ in range(nb):
+        params += [rng.normal(), *rng.uniform(0.25, 0.75, 3), rng.uniform(0.08, 0.12)]
+    params = np.array(params)
+    m = O.Mesh(N, k, map_kind=O.MAP_AFFINE, amp=0.0, bc=O.BC_NONE)
+    b = O.rhs(m, O.F_BUMPS, params)
+    m0, m1 = _bump_moments(params)
+    nn = N * k + 1
+    # node coordinates of the lexicographic order (GLL nodes in each cell)
+    g = np.asarray(O.gll(k))
+    x1 = np.concatenate([(c + g[:-1]) / N for c in range(N)] + [np.array([1.0])])
+    assert x1.size == nn
+    X = x1[np.arange(b.size) % nn]
+    Y = x1[(np.arange(b.size) // nn) % nn]
+    Z = x1[np.arange(b.size) // (nn * nn)]
+    scale = np.abs(params[1::5]).sum() * 0.01  # size of the bumps' integrals
+    assert abs(b.sum() - m0) <= 1e-8 * scale, (b.sum(), m0)
+    for d, C in enumerate((X, Y, Z)):
+        assert abs((C * b).sum() - m1[d]) <= 1e-8 * scale, (d, (C * b).sum(), m1[d])
+    # the same bumps with a width 1/sqrt(2) too small give a clearly different integral
+    wrong = params.copy()
+    wrong[5::5] /= np.sqrt(2.0)
+    assert abs(_bump_moments(wrong)[0] - m0) > 1e-3 * scale
