@@ -17,7 +17,10 @@
  *                 + alpha_{k-2}/beta_{k-2} (p_{k-1} - D^{-1} r_{k-1})  (odd k > 1),
  *           written back for tile-interior nodes; recomputed (not written)
  *           for nodes shared with other tiles; p_k staged in an LDS window
- *           of k+1 node planes.
+ *           of k+1 node planes.  Nodes of the tile's interior entity (one
+ *           contiguous run per node plane) take a branch-free path with
+ *           uniform base pointers; the other nodes go through the entity
+ *           table.
  *     cell  Eq. 5 by sum factorisation: gather from the window, 1D
  *           interpolations to the Gauss points and collocation derivatives
  *           (Sec. 2, sum factorisation), G_q = a w det J J^{-1} J^{-T}
@@ -99,6 +102,12 @@ inline int fused_block_size_impl(int K)
 #define MFCG_GPREF_OF(K) (Cfg<K>::GPREF)
 #endif
 #define MFCG_WPE_MIN(K) ((MFCG_OCC_OF(K) * Cfg<K>::WG / 64 + 3) / 4)
+/* r_k and D^{-1} kept in registers from a node's pre to its post */
+#ifdef MFCG_CARRY
+#define MFCG_CARRY_OF(K) (MFCG_CARRY)
+#else
+#define MFCG_CARRY_OF(K) (Cfg<K>::CARRY)
+#endif
 /* the k+2-point variants: no more waves than their larger cell scratch
  * lets fit per CU (LDS per workgroup 32 KB at k = 1, 83 KB at k = 2,
  * 67-77 KB at k = 3..5, 49 KB at k = 6, 69 KB at k = 7), geometry loads in
@@ -158,6 +167,14 @@ struct FastDiv {
     __device__ __forceinline__ int mod(int n) const { return n - div(n) * (int)d; }
 };
 
+/* A value known to be equal in all lanes, moved to scalar registers. */
+__device__ __forceinline__ int64_t uniform64(int64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 /* The geometry tensor is streamed once per iteration: its loads carry the
  * non-temporal hint so that they do not displace the vector lines that are
  * reused within the iteration (measured: 1.5-2% off the fused kernel at
@@ -171,6 +188,43 @@ __device__ __forceinline__ T gload(const T *p)
         return __builtin_nontemporal_load(p);
     else
         return *p;
+}
+
+/* t = sum_j M(q, j) u[j] (row q of a 1D table M given by coef) and
+ * t = sum_q M(q, m) w[q] (column m), unrolled with the table entries as
+ * compile-time constants: exactly-zero entries are skipped and unit
+ * entries added, which changes no result (with k + 1 Gauss points and even
+ * k, the centre Gauss point is the centre GLL node, so one row of the
+ * interpolation matrix is a unit row, and the centre entry of the
+ * collocation derivative is zero). */
+template <typename T, int N, typename F>
+__device__ __forceinline__ T row_dot(F coef, int q, const T (&u)[N])
+{
+    T t = 0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const T c = coef(q, j);
+        if (c == (T)1)
+            t += u[j];
+        else if (c != (T)0)
+            t = fma(c, u[j], t);
+    }
+    return t;
+}
+
+template <typename T, int N, typename F>
+__device__ __forceinline__ T col_dot(F coef, int m, const T (&w)[N])
+{
+    T t = 0;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        const T c = coef(q, m);
+        if (c == (T)1)
+            t += w[q];
+        else if (c != (T)0)
+            t = fma(c, w[q], t);
+    }
+    return t;
 }
 
 /* ------------------------------------------------------------------ */
@@ -200,7 +254,13 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
                    QGEOM = OPV == OPV_LAPLACE_QGEOM || OPV == OPV_MASS_QGEOM;
     static_assert(QX == 0 || (QX == 1 && !GLLQ && K <= 7), "k+2 points: Gauss rules up to k = 7");
     constexpr int NG = MASS ? 1 : 6; /* tensor components read */
-    constexpr int GPF = (QX || QGEOM) ? 0 : MFCG_GPREF_OF(K); /* when the geometry loads are issued */
+    /* when the geometry loads are issued: 0 in the G pass, 1 before the
+     * derivative passes, 2 before the pre pass (measured on MI355X with the
+     * present kernel at k = 4: holding a whole layer's tensor in registers,
+     * whether issued one layer ahead or all at once in the G pass, costs
+     * more in occupancy than it saves in latency: 0.60-0.77 ms against
+     * 0.584 ms per launch) */
+    constexpr int GPF = (QX || QGEOM) ? 0 : MFCG_GPREF_OF(K);
     constexpr int n = K + 1, n2 = n * n;
     /* nq points per direction; the cell scratch holds nq^3 values with the
      * strides (1, nq, nq^2) in every stage (fewer entries used where a
@@ -226,7 +286,9 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
 
     __shared__ T win[(K + 1) * PNM];
     __shared__ T TA[NLC * CS];
-    __shared__ T TB[NLC * CS];
+    /* cell scratch; TB[NLC * CS] stays 0: the sum over the cells around a
+     * node reads it for the cells that do not exist */
+    __shared__ T TB[NLC * CS + 1];
     __shared__ T cv[2 * PNM];
     /* quadratic geometry of the current layer's cells */
     __shared__ T XS[QGEOM ? NLC * QGEOM_STRIDE : 1];
@@ -244,6 +306,11 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
      * around the node (16 bits each, 0xffff: no such cell), cell order
      * (-x,-y), (+x,-y), (-x,+y), (+x,+y) */
     __shared__ int4 desc[PNM];
+    /* the nodes of a tile node plane that lie on the tile's side faces (the
+     * "ring": every node of the plane outside the interior entity), in the
+     * order bottom row, top row, left column, right column */
+    constexpr int RINGM = 2 * (Cfg<K>::TX + Cfg<K>::TY) * K;
+    __shared__ int16_t ring[RINGM];
 
     const int tid0 = threadIdx.x;
     const TileDesc td = a.L.tiles[tile];
@@ -290,8 +357,55 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         const int o11 = (xr && yr) ? off(cx1, cy1) : 0xffff;
         desc[node] = make_int4((dx + 3 * dy) | ((sx * sy) << 8), lx + sx * ly, o00 | (o01 << 16), o10 | (o11 << 16));
     }
+    /* LDS offsets of the lines this thread owns in every pass (k + 1 points
+     * per direction: all passes split a layer's cells into the same
+     * (cell, 2D index) lines): z-lines oZ = c CS + rem, x-lines oX =
+     * c CS + nq rem, y-lines oY = c CS + i + nq^2 z, and the window position
+     * oW of the line's node column for the gather; computed once per tile
+     * instead of in every pass */
+    int oZ[R], oX[R], oY[R], oW[R];
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+        const int l = tid0 + WG * rr;
+        const int c = l / q2, rem = l - c * q2, i = rem % nq, z = rem / nq;
+        const int cy = dTX.div(c), cx = c - cy * TXa;
+        oZ[rr] = c * CS + rem;
+        oX[rr] = c * CS + nq * rem;
+        oY[rr] = c * CS + i + q2 * z;
+        oW[rr] = cx * K + i + PW * (cy * K + z);
+    }
+    for (int r = tid0; r < 2 * (EX + EY); r += WG) {
+        int node;
+        if (r <= EX)
+            node = r;
+        else if (r < 2 * (EX + 1))
+            node = (r - (EX + 1)) + PW * EY;
+        else if (r < 2 * (EX + 1) + EY - 1)
+            node = PW * (1 + r - 2 * (EX + 1));
+        else
+            node = EX + PW * (2 + r - 2 * (EX + 1) - EY);
+        ring[r] = (int16_t)node;
+    }
+    if (tid0 == 0) TB[NLC * CS] = 0;
     if (FLUSH && tid0 < 8 * (WG / 64)) wacc[tid0] = 0;
     __syncthreads();
+
+    /* Tile-interior nodes (the interior entity, always of kind I) take a
+     * branch-free path: its nodes of interior node planes zz = 1..EZ-1 are
+     * one contiguous run per plane, (EX-1)(EY-1) nodes, x fastest, so the
+     * f-th interior node from plane zz0 on lies at vector index
+     * vbase + (zz0 - 1) SXY + f; the other nodes of a plane (the ring) and the
+     * tile's bottom and top planes take the general path through the entity
+     * table.  Base pointers are uniform (scalar registers) and offsets 32-bit. */
+    const int SXI = EX - 1, SXY = SXI * (EY - 1), NRING = 2 * (EX + EY);
+    const int64_t vb13 = uniform64(ent[13].vbase);
+    const bool fast = __builtin_amdgcn_readfirstlane(ent[13].kind) == KIND_I && SXY > 0;
+    const FastDiv dSXY(SXY > 0 ? SXY : 1), dSXI(SXI > 0 ? SXI : 1), dRING(NRING);
+    /* window position of interior node rem of a plane: (lx + 1) + PW (ly + 1) */
+    auto inode = [&](int rem) {
+        const int ly = dSXI.div(rem);
+        return rem + 2 * ly + PW + 1;
+    };
 
     T acc[7];
 #pragma unroll
@@ -310,24 +424,44 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         pidx = (int)e.pbase + loc;
     };
 
-    /* Algorithm 5's pre on one node; interior nodes are written back,
-     * shared nodes only recomputed; returns p_k (0 on Dirichlet nodes) and
-     * r_k, D^{-1} in rk, dk (kept in registers for the post of the node) */
-    auto pre_node = [&](int node, int zz, T &rk, T &dk) -> T {
-        int idx, kind, pidx;
-        locate(desc[node], zz, idx, kind, pidx);
-        if (kind == KIND_C) return (T)0;
-        if (MODE == MODE_VMULT) return a.src[idx];
-        const T r0 = a.r[idx], v0 = a.v[idx], p0 = a.p[idx];
-        const T dv = MODE == MODE_CG_NOPREC ? (T)1 : a.dinv[idx];
+    /* Algorithm 5's pre, split in two so that a thread issues the loads of
+     * all its nodes of a pass before it waits for any of them (one memory
+     * round trip per pass instead of one per node): pre_load reads the old
+     * r, v, p, D^{-1} (and x on the iterations that update it), pre_apply
+     * computes r_k and p_k, writes them back for tile-interior nodes (shared
+     * nodes are only recomputed) and returns p_k (0 on Dirichlet nodes);
+     * r_k and D^{-1} go to rk, dk (kept in registers for the node's post) */
+    struct PreIn {
+        T r0, v0, p0, dv, x0;
+        int idx, kind;
+    };
+    auto pre_load = [&](int node, int zz, PreIn &in) {
+        int pidx;
+        locate(desc[node], zz, in.idx, in.kind, pidx);
+        in.r0 = in.v0 = in.p0 = in.x0 = 0;
+        in.dv = 1;
+        if (in.kind == KIND_C) return;
+        if (MODE == MODE_VMULT) {
+            in.p0 = a.src[in.idx];
+            return;
+        }
+        in.r0 = a.r[in.idx];
+        in.v0 = a.v[in.idx];
+        in.p0 = a.p[in.idx];
+        if (MODE != MODE_CG_NOPREC) in.dv = a.dinv[in.idx];
+        if (xupd && in.kind == KIND_I) in.x0 = a.x[in.idx];
+    };
+    auto pre_apply = [&](const PreIn &in, T &rk, T &dk) -> T {
+        if (in.kind == KIND_C) return (T)0;
+        if (MODE == MODE_VMULT) return in.p0;
         T rn, pn;
-        pre_update(r0, v0, p0, dv, alpha, beta, rn, pn);
+        pre_update(in.r0, in.v0, in.p0, in.dv, alpha, beta, rn, pn);
         rk = rn;
-        dk = dv;
-        if (kind == KIND_I) {
-            a.r[idx] = rn;
-            a.p[idx] = pn;
-            if (xupd) a.x[idx] = x_update(a.x[idx], r0, p0, dv, alpha, ratio);
+        dk = in.dv;
+        if (in.kind == KIND_I) {
+            a.r[in.idx] = rn;
+            a.p[in.idx] = pn;
+            if (xupd) a.x[in.idx] = x_update(in.x0, in.r0, in.p0, in.dv, alpha, ratio);
         }
         return pn;
     };
@@ -337,10 +471,10 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         const int o00 = dsc.z & 0xffff, o01 = (int)((unsigned)dsc.z >> 16);
         const int o10 = dsc.w & 0xffff, o11 = (int)((unsigned)dsc.w >> 16);
         const int zo = q2 * zl;
-        const T v00 = o00 != 0xffff ? TB[o00 + zo] : (T)0;
-        const T v01 = o01 != 0xffff ? TB[o01 + zo] : (T)0;
-        const T v10 = o10 != 0xffff ? TB[o10 + zo] : (T)0;
-        const T v11 = o11 != 0xffff ? TB[o11 + zo] : (T)0;
+        const T v00 = TB[o00 != 0xffff ? o00 + zo : NLC * CS];
+        const T v01 = TB[o01 != 0xffff ? o01 + zo : NLC * CS];
+        const T v10 = TB[o10 != 0xffff ? o10 + zo : NLC * CS];
+        const T v11 = TB[o11 != 0xffff ? o11 + zo : NLC * CS];
         return ((v00 + v01) + v10) + v11;
     };
 
@@ -359,7 +493,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
             } else {
                 /* the quadratic-geometry G pass needs the registers at k <= 4
                  * (k = 4: 0.90 instead of 1.01 ms per iteration): re-read */
-                const bool use = Cfg<K>::CARRY && !(OPV == OPV_LAPLACE_QGEOM && K <= 4) && reg;
+                const bool use = MFCG_CARRY_OF(K) && !(OPV == OPV_LAPLACE_QGEOM && K <= 4) && reg;
                 const T rn = use ? rk : a.r[idx];
                 const T dv = MODE == MODE_CG_NOPREC ? (T)1 : (use ? dk : a.dinv[idx]);
                 const T pn = win[slot * PNM + node];
@@ -376,22 +510,36 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         }
     };
 
-    /* r_k and D^{-1} of the nodes this thread pre-processes, held until
-     * their post: the tile's bottom plane (kb*) and the planes 1..K of the
-     * current layer (kr, kd) */
-    T kbr[NC], kbd[NC], kr[NS], kd[NS];
+    /* fast-path nodes per thread: of a layer's interior planes (pre and
+     * post) and of one interior plane (the post of a layer's bottom plane) */
+    constexpr int SXYM = (Cfg<K>::TX * K - 1) * (Cfg<K>::TY * K - 1);
+    constexpr int NFI = (K * SXYM + WG - 1) / WG;
+    constexpr int NF0 = (SXYM + WG - 1) / WG;
+    /* r_k and D^{-1} of the fast-path nodes this thread pre-processes, held
+     * until their post (except where the G pass needs the registers) */
+    constexpr bool CARRYF = MFCG_CARRY_OF(K) && !(OPV == OPV_LAPLACE_QGEOM && K <= 4);
+    T kr[NFI], kd[NFI];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) kbr[c] = kbd[c] = 0;
-#pragma unroll
-    for (int s = 0; s < NS; ++s) kr[s] = kd[s] = 0;
+    for (int s = 0; s < NFI; ++s) kr[s] = kd[s] = 0;
+    T rdummy, ddummy;
 
-    /* bottom plane of the tile into the window */
+    /* bottom plane of the tile into the window (general path) */
+    {
+        PreIn in[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        const int node = tid + WG * c;
-        if (node < PN) win[node] = pre_node(node, 0, kbr[c], kbd[c]);
+        for (int c = 0; c < NC; ++c) {
+            const int node = tid + WG * c;
+            in[c].kind = KIND_C;
+            if (node < PN) pre_load(node, 0, in[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int node = tid + WG * c;
+            if (node < PN) win[node] = pre_apply(in[c], rdummy, ddummy);
+        }
     }
 
+    T gp[R][6][nq];
 #pragma unroll 1
     for (int L = 0; L < TZa; ++L) {
         const int s0 = (L * K) % (K + 1);
@@ -403,7 +551,6 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
             const T *Xl = a.G + td.gbase / (6 * CS) * QGEOM_STRIDE + (int64_t)L * TXa * TYa * QGEOM_STRIDE;
             for (int e = tid; e < TXa * TYa * QGEOM_STRIDE; e += WG) XS[e] = Xl[e];
         }
-        T gp[R][6][nq];
         if (GPF == 2) {
             /* G of this layer issued first: its latency overlaps the pre loads */
 #pragma unroll
@@ -416,14 +563,86 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
             }
         }
         /* ---- pre on the planes this layer touches first ---- */
+        /* interior planes among L K + 1 .. L K + K (K - 1 in the last layer) */
+        const int nzi = min(K, EZ - 1 - L * K);
+        const int nf = fast ? nzi * SXY : 0;
+        /* vector index of the first interior node of plane L K + 1 */
+        const int64_t fb = vb13 + (int64_t)(L * K) * SXY;
+        /* general-path nodes of the layer: the rings of the interior planes,
+         * then whole planes (the tile's top plane) */
+        const int NR = fast ? nzi * NRING + (K - nzi) * PN : K * PN;
+        auto gdecode = [&](int f, int &zl, int &node) {
+            if (fast && f < nzi * NRING) {
+                const int zq = dRING.div(f);
+                zl = 1 + zq;
+                node = ring[f - zq * NRING];
+            } else {
+                const int f2 = f - (fast ? nzi * NRING : 0);
+                const int zq = dPN.div(f2);
+                zl = 1 + (fast ? nzi : 0) + zq;
+                node = f2 - zq * PN;
+            }
+        };
+        {
+            /* fast path: all loads of the thread's nodes, then the updates */
+            T r0[NFI], v0[NFI], p0[NFI], d0[NFI], x0[NFI];
+            const uint32_t ob = (uint32_t)sizeof(T);
+            auto at = [&](const T *base, int f) -> const T & {
+                return *(const T *)((const char *)(base + fb) + (uint32_t)f * ob);
+            };
+            auto atw = [&](T *base, int f) -> T & { return *(T *)((char *)(base + fb) + (uint32_t)f * ob); };
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int f = tid + WG * s;
-            if (f < K * PN) {
-                const int zq = dPN.div(f), zl = 1 + zq, node = f - zq * PN;
-                int slot = s0 + zl;
-                if (slot > K) slot -= K + 1;
-                win[slot * PNM + node] = pre_node(node, L * K + zl, kr[s], kd[s]);
+            for (int s = 0; s < NFI; ++s) {
+                const int f = tid + WG * s;
+                r0[s] = v0[s] = p0[s] = x0[s] = 0;
+                d0[s] = 1;
+                if (f < nf) {
+                    if (MODE == MODE_VMULT) {
+                        p0[s] = at(a.src, f);
+                    } else {
+                        r0[s] = at(a.r, f);
+                        v0[s] = at(a.v, f);
+                        p0[s] = at(a.p, f);
+                        if (MODE != MODE_CG_NOPREC) d0[s] = at(a.dinv, f);
+                        if (xupd) x0[s] = at(a.x, f);
+                    }
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < NFI; ++s) {
+                const int f = tid + WG * s;
+                if (f < nf) {
+                    T pn = p0[s];
+                    if (MODE != MODE_VMULT) {
+                        T rn;
+                        pre_update(r0[s], v0[s], p0[s], d0[s], alpha, beta, rn, pn);
+                        kr[s] = rn;
+                        kd[s] = d0[s];
+                        atw(a.r, f) = rn;
+                        atw(a.p, f) = pn;
+                        if (xupd) atw(a.x, f) = x_update(x0[s], r0[s], p0[s], d0[s], alpha, ratio);
+                    }
+                    const int zq = dSXY.div(f);
+                    int slot = s0 + 1 + zq;
+                    if (slot > K) slot -= K + 1;
+                    win[slot * PNM + inode(f - zq * SXY)] = pn;
+                }
+            }
+        }
+        {
+            /* general path (one node at a time) */
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const int f = tid + WG * s;
+                if (f < NR) {
+                    int zl, node;
+                    gdecode(f, zl, node);
+                    PreIn in;
+                    pre_load(node, L * K + zl, in);
+                    int slot = s0 + zl;
+                    if (slot > K) slot -= K + 1;
+                    win[slot * PNM + node] = pre_apply(in, rdummy, ddummy);
+                }
             }
         }
         __syncthreads();
@@ -438,9 +657,16 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         for (int rr = 0; rr < RA; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlA) {
-                const int c = l / n2, rem = l % n2, i = rem % n, j = rem / n;
-                const int cy = dTX.div(c), cx = c - cy * TXa;
-                const int nodexy = cx * K + i + PW * (cy * K + j);
+                int nodexy, oz1;
+                if constexpr (QX) {
+                    const int c = l / n2, rem = l % n2, i = rem % n, j = rem / n;
+                    const int cy = dTX.div(c), cx = c - cy * TXa;
+                    nodexy = cx * K + i + PW * (cy * K + j);
+                    oz1 = c * CS + rem;
+                } else {
+                    nodexy = oW[rr];
+                    oz1 = oZ[rr];
+                }
                 T u[n];
 #pragma unroll
                 for (int z = 0; z < n; ++z) {
@@ -449,16 +675,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
                     u[z] = win[slot * PNM + nodexy];
                 }
 #pragma unroll
-                for (int q = 0; q < nq; ++q) {
-                    T t = 0;
-                    if (GLLQ) {
-                        t = u[q];
-                    } else {
-#pragma unroll
-                        for (int z = 0; z < n; ++z) t = fma(cS(q, z), u[z], t);
-                    }
-                    TA[c * CS + rem + n2 * q] = t;
-                }
+                for (int q = 0; q < nq; ++q) TA[oz1 + n2 * q] = GLLQ ? u[q] : row_dot(cS, q, u);
             }
         }
         __syncthreads();
@@ -468,18 +685,19 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         for (int rr = 0; rr < RB && !GLLQ; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlB) {
-                const int c = l / nnq, rem = l % nnq;
-                const int base = c * CS + n * rem, bout = QX ? c * CS + nq * rem : base;
+                int base, bout;
+                if constexpr (QX) {
+                    const int c = l / nnq, rem = l % nnq;
+                    base = c * CS + n * rem;
+                    bout = c * CS + nq * rem;
+                } else {
+                    base = bout = oX[rr];
+                }
                 T u[n];
 #pragma unroll
                 for (int i = 0; i < n; ++i) u[i] = TA[base + i];
 #pragma unroll
-                for (int q = 0; q < nq; ++q) {
-                    T t = 0;
-#pragma unroll
-                    for (int i = 0; i < n; ++i) t = fma(cS(q, i), u[i], t);
-                    TB[bout + q] = t;
-                }
+                for (int q = 0; q < nq; ++q) TB[bout + q] = row_dot(cS, q, u);
             }
         }
         __syncthreads();
@@ -490,9 +708,14 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         for (int rr = 0; rr < R; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlines) {
-                const int c = l / q2, rem = l % q2, i = rem % nq, z = rem / nq;
-                const int base = c * CS + i + q2 * z;
-                const int bin = QX ? c * CS + i + nnq * z : base;
+                int base, bin;
+                if constexpr (QX) {
+                    const int c = l / q2, rem = l % q2, i = rem % nq, z = rem / nq;
+                    base = c * CS + i + q2 * z;
+                    bin = c * CS + i + nnq * z;
+                } else {
+                    base = bin = oY[rr];
+                }
                 T u[n], uq[nq];
 #pragma unroll
                 for (int j = 0; j < n; ++j) u[j] = GLLQ ? TA[base + nq * j] : TB[bin + nq * j];
@@ -501,20 +724,12 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
                     if (GLLQ) {
                         uq[q] = u[q]; /* values already in TA */
                     } else {
-                        T t = 0;
-#pragma unroll
-                        for (int j = 0; j < n; ++j) t = fma(cS(q, j), u[j], t);
-                        uq[q] = t;
-                        TA[base + nq * q] = t;
+                        uq[q] = row_dot(cS, q, u);
+                        TA[base + nq * q] = uq[q];
                     }
                 }
 #pragma unroll
-                for (int q = 0; q < nq && !MASS; ++q) {
-                    T t = 0;
-#pragma unroll
-                    for (int m = 0; m < nq; ++m) t = fma(cD(q, m), uq[m], t);
-                    gy[rr][q] = t;
-                }
+                for (int q = 0; q < nq && !MASS; ++q) gy[rr][q] = row_dot(cD, q, uq);
             }
         }
         __syncthreads();
@@ -536,18 +751,12 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         for (int rr = 0; rr < R && !MASS; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlines) {
-                const int c = l / q2, rem = l % q2;
-                const int base = c * CS + nq * rem;
+                const int base = QX ? (l / q2) * CS + nq * (l % q2) : oX[rr];
                 T u[nq];
 #pragma unroll
                 for (int i = 0; i < nq; ++i) u[i] = TA[base + i];
 #pragma unroll
-                for (int q = 0; q < nq; ++q) {
-                    T t = 0;
-#pragma unroll
-                    for (int m = 0; m < nq; ++m) t = fma(cD(q, m), u[m], t);
-                    TB[base + q] = t;
-                }
+                for (int q = 0; q < nq; ++q) TB[base + q] = row_dot(cD, q, u);
             }
         }
         __syncthreads();
@@ -557,18 +766,12 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         for (int rr = 0; rr < R && !MASS; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlines) {
-                const int c = l / q2, rem = l % q2;
-                const int base = c * CS + rem;
+                const int base = QX ? (l / q2) * CS + (l % q2) : oZ[rr];
                 T u[nq];
 #pragma unroll
                 for (int z = 0; z < nq; ++z) u[z] = TA[base + q2 * z];
 #pragma unroll
-                for (int q = 0; q < nq; ++q) {
-                    T t = 0;
-#pragma unroll
-                    for (int m = 0; m < nq; ++m) t = fma(cD(q, m), u[m], t);
-                    TA[base + q2 * q] = t;
-                }
+                for (int q = 0; q < nq; ++q) TA[base + q2 * q] = row_dot(cD, q, u);
             }
         }
         __syncthreads();
@@ -580,13 +783,15 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         for (int rr = 0; rr < R && MASS && !QGEOM; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlines) {
-                const int c = l / q2, rem = l % q2, i = rem % nq, z = rem / nq;
-                const int base = c * CS + i + q2 * z;
+                const int base = QX ? (l / q2) * CS + (l % q2) % nq + q2 * ((l % q2) / nq) : oY[rr];
+                if (!GPF) {
 #pragma unroll
-                for (int j = 0; j < nq; ++j) {
-                    if (!GPF) gp[rr][0][j] = gload<NTG>(&Gl[j * gq + l]);
-                    TB[base + nq * j] = gp[rr][0][j] * TA[base + nq * j];
+                    for (int j = 0; j < nq; ++j) gp[rr][0][j] = gload<NTG>(&Gl[j * gq + l]);
+                    /* every load of the line is issued before the first use */
+                    asm volatile("" ::: "memory");
                 }
+#pragma unroll
+                for (int j = 0; j < nq; ++j) TB[base + nq * j] = gp[rr][0][j] * TA[base + nq * j];
             }
         }
 #pragma unroll
@@ -675,20 +880,14 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
                     TA[base + nq * j] = fz;
                 }
 #pragma unroll
-                for (int m = 0; m < nq && !MASS; ++m) {
-                    T t = 0;
-#pragma unroll
-                    for (int q = 0; q < nq; ++q) t = fma(cD(q, m), fy[q], t);
-                    wy[rr][m] = t;
-                }
+                for (int m = 0; m < nq && !MASS; ++m) wy[rr][m] = col_dot(cD, m, fy);
             }
         }
 #pragma unroll
         for (int rr = 0; rr < R && !MASS && !QGEOM; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlines) {
-                const int c = l / q2, rem = l % q2, i = rem % nq, z = rem / nq;
-                const int base = c * CS + i + q2 * z;
+                const int base = QX ? (l / q2) * CS + (l % q2) % nq + q2 * ((l % q2) / nq) : oY[rr];
                 T fy[nq];
 #pragma unroll
                 for (int j = 0; j < nq; ++j) {
@@ -704,12 +903,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
                     TA[base + nq * j] = fz;
                 }
 #pragma unroll
-                for (int m = 0; m < nq; ++m) {
-                    T t = 0;
-#pragma unroll
-                    for (int q = 0; q < nq; ++q) t = fma(cD(q, m), fy[q], t);
-                    wy[rr][m] = t;
-                }
+                for (int m = 0; m < nq; ++m) wy[rr][m] = col_dot(cD, m, fy);
             }
         }
         __syncthreads();
@@ -720,32 +914,21 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         for (int rr = 0; rr < R && !MASS; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlines) {
-                const int c = l / q2, rem = l % q2;
                 {
-                    const int base = c * CS + nq * rem;
+                    const int base = QX ? (l / q2) * CS + nq * (l % q2) : oX[rr];
                     T f[nq];
 #pragma unroll
                     for (int q = 0; q < nq; ++q) f[q] = TB[base + q];
 #pragma unroll
-                    for (int m = 0; m < nq; ++m) {
-                        T t = 0;
-#pragma unroll
-                        for (int q = 0; q < nq; ++q) t = fma(cD(q, m), f[q], t);
-                        TB[base + m] = t;
-                    }
+                    for (int m = 0; m < nq; ++m) TB[base + m] = col_dot(cD, m, f);
                 }
                 {
-                    const int base = c * CS + rem;
+                    const int base = QX ? (l / q2) * CS + (l % q2) : oZ[rr];
                     T f[nq];
 #pragma unroll
                     for (int q = 0; q < nq; ++q) f[q] = TA[base + q2 * q];
 #pragma unroll
-                    for (int m = 0; m < nq; ++m) {
-                        T t = 0;
-#pragma unroll
-                        for (int q = 0; q < nq; ++q) t = fma(cD(q, m), f[q], t);
-                        wz[rr][m] = t;
-                    }
+                    for (int m = 0; m < nq; ++m) wz[rr][m] = col_dot(cD, m, f);
                 }
             }
         }
@@ -756,8 +939,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         for (int rr = 0; rr < R && !MASS; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlines) {
-                const int c = l / q2, rem = l % q2, i = rem % nq, z = rem / nq;
-                const int base = c * CS + i + q2 * z;
+                const int base = QX ? (l / q2) * CS + (l % q2) % nq + q2 * ((l % q2) / nq) : oY[rr];
 #pragma unroll
                 for (int j = 0; j < nq; ++j) TB[base + nq * j] += wy[rr][j];
             }
@@ -770,22 +952,12 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         for (int rr = 0; rr < R; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlines) {
-                const int c = l / q2, rem = l % q2;
-                const int base = c * CS + rem;
+                const int base = QX ? (l / q2) * CS + (l % q2) : oZ[rr];
                 T w[nq];
 #pragma unroll
                 for (int q = 0; q < nq; ++q) w[q] = MASS ? TB[base + q2 * q] : TB[base + q2 * q] + wz[rr][q];
 #pragma unroll
-                for (int z = 0; z < n; ++z) {
-                    T t = 0;
-                    if (GLLQ) {
-                        t = w[z];
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < nq; ++q) t = fma(cS(q, z), w[q], t);
-                    }
-                    TB[base + q2 * z] = t;
-                }
+                for (int z = 0; z < n; ++z) TB[base + q2 * z] = GLLQ ? w[z] : col_dot(cS, z, w);
             }
         }
         __syncthreads();
@@ -795,18 +967,12 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         for (int rr = 0; rr < RB && !GLLQ; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlB) {
-                const int c = l / nnq, rem = l % nnq;
-                const int base = c * CS + nq * rem;
+                const int base = QX ? (l / nnq) * CS + nq * (l % nnq) : oX[rr];
                 T w[nq];
 #pragma unroll
                 for (int q = 0; q < nq; ++q) w[q] = TB[base + q];
 #pragma unroll
-                for (int i = 0; i < n; ++i) {
-                    T t = 0;
-#pragma unroll
-                    for (int q = 0; q < nq; ++q) t = fma(cS(q, i), w[q], t);
-                    TB[base + i] = t;
-                }
+                for (int i = 0; i < n; ++i) TB[base + i] = col_dot(cS, i, w);
             }
         }
         __syncthreads();
@@ -817,41 +983,92 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
         for (int rr = 0; rr < RA && !GLLQ; ++rr) {
             const int l = tid + WG * rr;
             if (l < nlA) {
-                const int c = l / n2, rem = l % n2, i = rem % n, z = rem / n;
-                const int base = c * CS + i + q2 * z;
+                const int base = QX ? (l / n2) * CS + (l % n2) % n + q2 * ((l % n2) / n) : oY[rr];
                 T w[nq];
 #pragma unroll
                 for (int q = 0; q < nq; ++q) w[q] = TB[base + nq * q];
 #pragma unroll
-                for (int j = 0; j < n; ++j) {
-                    T t = 0;
-#pragma unroll
-                    for (int q = 0; q < nq; ++q) t = fma(cS(q, j), w[q], t);
-                    TB[base + nq * j] = t;
-                }
+                for (int j = 0; j < n; ++j) TB[base + nq * j] = col_dot(cS, j, w);
             }
         }
         __syncthreads();
         asm volatile("" : "+v"(tid));
 
         /* ---- sum over cells and post ---- */
-        /* plane z = 0 of the layer, completing the carry of the layer below */
+        /* the CG post of a tile-interior node at vector index i (fast path) */
+        auto post_fast = [&](int64_t i, int node, int slot, T v, bool reg, T rk, T dk) {
+            if (MODE == MODE_VMULT) {
+                a.dst[i] = v;
+            } else {
+                const T rn = reg ? rk : a.r[i];
+                const T dv = MODE == MODE_CG_NOPREC ? (T)1 : (reg ? dk : a.dinv[i]);
+                const T pn = win[slot * PNM + node];
+                const T zr = dv * rn, zv = dv * v;
+                acc[0] += rn * rn;
+                acc[1] += pn * v;
+                acc[2] += rn * v;
+                acc[3] += v * v;
+                acc[4] += rn * zr;
+                acc[5] += rn * zv;
+                acc[6] += v * zv;
+                a.v[i] = v;
+            }
+        };
+        /* plane z = 0 of the layer (plane L K), completing the carry of the
+         * layer below: interior nodes (fast path, L > 0; their pre ran in
+         * the layer below, so r and D^{-1} are re-read) */
+        if (L > 0 && fast) {
+            const int64_t fb0 = vb13 + (int64_t)(L * K - 1) * SXY;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const int node = tid + WG * c;
-            if (node < PN) {
-                const int4 dsc = desc[node];
-                T v = sum_cells(dsc, 0);
-                if (L > 0) v = cv[(L & 1) * PNM + node] + v;
-                post_node(dsc, node, L * K, s0, v, L == 0, kbr[c], kbd[c]);
+            for (int c = 0; c < NF0; ++c) {
+                const int f = tid + WG * c;
+                if (f < SXY) {
+                    const int node = inode(f);
+                    const T v = cv[(L & 1) * PNM + node] + sum_cells(desc[node], 0);
+                    post_fast(fb0 + f, node, s0, v, false, (T)0, (T)0);
+                }
             }
         }
-        /* planes z = 1..K; the top plane is carried unless it is the tile's last */
+        /* plane z = 0, general path: the whole plane in the first layer (the
+         * tile's bottom plane), else its ring */
+        {
+            const bool whole = L == 0 || !fast;
+            const int N0 = whole ? PN : NRING;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const int f = tid + WG * c;
+                if (f < N0) {
+                    const int node = whole ? f : ring[f];
+                    const int4 dsc = desc[node];
+                    T v = sum_cells(dsc, 0);
+                    if (L > 0) v = cv[(L & 1) * PNM + node] + v;
+                    post_node(dsc, node, L * K, s0, v, false, (T)0, (T)0);
+                }
+            }
+        }
+        /* planes z = 1..K; the top plane is carried unless it is the tile's
+         * last.  Fast path in the thread mapping of its pre. */
+#pragma unroll
+        for (int s = 0; s < NFI; ++s) {
+            const int f = tid + WG * s;
+            if (f < nf) {
+                const int zq = dSXY.div(f), node = inode(f - zq * SXY), zl = 1 + zq;
+                const T v = sum_cells(desc[node], zl);
+                if (zl == K && L + 1 < TZa) {
+                    cv[((L + 1) & 1) * PNM + node] = v;
+                } else {
+                    int slot = s0 + zl;
+                    if (slot > K) slot -= K + 1;
+                    post_fast(fb + f, node, slot, v, CARRYF, kr[s], kd[s]);
+                }
+            }
+        }
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const int f = tid + WG * s;
-            if (f < K * PN) {
-                const int zq = dPN.div(f), zl = 1 + zq, node = f - zq * PN;
+            if (f < NR) {
+                int zl, node;
+                gdecode(f, zl, node);
                 const int4 dsc = desc[node];
                 const T v = sum_cells(dsc, zl);
                 if (zl == K && L + 1 < TZa) {
@@ -859,7 +1076,7 @@ __device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t t
                 } else {
                     int slot = s0 + zl;
                     if (slot > K) slot -= K + 1;
-                    post_node(dsc, node, L * K + zl, slot, v, true, kr[s], kd[s]);
+                    post_node(dsc, node, L * K + zl, slot, v, false, (T)0, (T)0);
                 }
             }
         }
