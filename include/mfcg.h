@@ -132,6 +132,13 @@ typedef struct {
     int32_t quad_rule;       /* MFCG_QUAD_* */
     int32_t op;              /* MFCG_OP_* */
     int32_t geometry;        /* MFCG_GEOM_* */
+    int32_t deterministic;   /* accepted for interface compatibility; 0 and 1 behave the same: every
+                              * reduction and every sum of partial contributions runs in a fixed
+                              * order (no floating-point atomics), so results are always bitwise
+                              * reproducible from run to run on the same device */
+    const char *tune_cache;  /* mfcg_setup_batch: path of the autotuner cache (JSON, one record per
+                              * GPU, degree, tuning cube size, map and precision; created or updated
+                              * in place); NULL: tune on every call.  Ignored by mfcg_setup */
 } mfcg_options;
 
 /* Builds the operator (Sec. 2, Eq. 3-5): tiles and DoF enumeration of the
@@ -181,6 +188,16 @@ int mfcg_vmult(mfcg_handle h, double *dst, const double *src, void *hip_stream);
 /* diag = diag(A) (the point-Jacobi preconditioner, Sec. 3); 1 on Dirichlet
  * nodes.  Device vector of length n_dofs. */
 int mfcg_diagonal(mfcg_handle h, double *diag, void *hip_stream);
+
+/* dst = A32 src with the single-precision operator of mfcg_solve_ir (the
+ * inner solver of the mixed-precision extension: G_q stored in FP32, the
+ * sum factorisation and the sums in FP32): src rounded to FP32, the result
+ * widened to FP64; lexicographic device vectors as mfcg_vmult.  Builds the
+ * FP32 copy on first use and uses its work vectors (no solve may be in
+ * progress on the handle).  Gauss-point Laplacian with the stored tensor
+ * only.  Errors: EINVAL (null or aliasing vectors, other operators), ENOMEM,
+ * EHIP. */
+int mfcg_vmult_fp32(mfcg_handle h, double *dst, const double *src, void *hip_stream);
 
 /* Load vector b_i = sum_e sum_q f(x_q) phi_i(x_q) w_q det J_q on free nodes,
  * 0 on Dirichlet nodes, Gauss quadrature with k+1 points per direction.
@@ -340,8 +357,11 @@ int mfcg_layout_permutation(const mfcg_mesh *mesh, int32_t degree, const int32_t
  * ceiling (the denominator of the "measured" roofline and the calibration
  * kernel of the HBM byte counters).  kind 0: dst[0..n) = src[0..n) (one read
  * and one write per element); kind 1: dst[b] = partial sum of src over block
- * b of the grid (one read per element; dst holds nblocks doubles).  n even,
- * 16-byte aligned device pointers; nblocks >= 1 workgroups of 256 threads. */
+ * b of the grid (one read per element; dst holds nblocks doubles).  Bits 1-2
+ * of kind: log2 of the independent 16-byte loads each thread keeps in flight
+ * (1, 2 or 4; 3 is invalid); bit 3: non-temporal hint on loads and stores.
+ * n even, 16-byte aligned device pointers; nblocks >= 1 workgroups of 256
+ * threads. */
 int mfcg_stream_bench(int32_t kind, int64_t n, const double *src, double *dst, int32_t nblocks, void *hip_stream);
 
 /* Tile autotuner: times `iters` fused iterations (after 2 untimed ones)
@@ -387,6 +407,17 @@ int mfcg_batch_info(mfcg_batch hb, int32_t i, mfcg_handle *h, int32_t *tile);
  * problem converged, else the first non-OK status; EINVAL/EHIP on errors.
  * Synchronises hip_stream. */
 int mfcg_batch_solve(mfcg_batch hb, const double *const *b, double *const *x, double tol, int32_t maxit,
+                     int32_t *iters, int32_t *status, void *hip_stream);
+/* The batch calls under the names of the library's interface summary:
+ * mfcg_setup_batch takes mfcg_options (NULL: defaults) instead of the
+ * autotune flag: a tile with all three extents > 0 is used for every
+ * problem (clipped to its mesh), otherwise one tile per degree is tuned,
+ * read from and written to opt->tune_cache when that is set; the other
+ * option fields must be 0 (a batch runs the FP64 Gauss-point Laplacian
+ * with the stored tensor).  mfcg_solve_batch is mfcg_batch_solve. */
+int mfcg_setup_batch(int32_t nprob, const mfcg_mesh *meshes, const int32_t *degrees, const double *const *coeffs,
+                     const mfcg_options *opt, void *hip_stream, mfcg_batch *out);
+int mfcg_solve_batch(mfcg_batch hb, const double *const *b, double *const *x, double tol, int32_t maxit,
                      int32_t *iters, int32_t *status, void *hip_stream);
 int mfcg_batch_destroy(mfcg_batch hb);
 const char *mfcg_batch_last_error(mfcg_batch hb);

@@ -95,12 +95,19 @@ int mfnn_act_bwd(int64_t n, const float *dy, const void *y, int32_t y_dtype, int
 int mfnn_mse(int64_t n, const float *pred, const float *target, float *grad, double *loss, double *work,
              void *hip_stream);
 
+/* mfnn_mse under the name of the library's interface summary. */
+int mfnn_mse_loss(int64_t n, const float *pred, const float *target, float *grad, double *loss, double *work,
+                  void *hip_stream);
+
 /* One Adam step (Kingma and Ba, 2015) with bias correction for step >= 1:
  * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
  * theta -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps);
  * theta_bf16 (may be NULL) receives theta rounded to BF16. */
 int mfnn_adam(int64_t n, float *theta, uint16_t *theta_bf16, const float *g, float *m, float *v, int32_t step,
               float lr, float beta1, float beta2, float eps, void *hip_stream);
+/* mfnn_adam under the name of the library's interface summary. */
+int mfnn_adam_step(int64_t n, float *theta, uint16_t *theta_bf16, const float *g, float *m, float *v, int32_t step,
+                   float lr, float beta1, float beta2, float eps, void *hip_stream);
 
 /* out[i] = in[i] converted (BF16 / F32 / F64; to BF16 by rounding to
  * nearest even). */

@@ -176,10 +176,13 @@ static int validate_mesh(const mfcg_mesh *mesh, int32_t degree, const int32_t *t
             return MFCG_EINVAL;
         }
     }
+    /* the fused kernels index vectors and partial-sum arrays with 32-bit
+     * offsets: at most 2^31 - 1 nodes (the largest stored-tensor problem
+     * that fits in 288 GB at Q4 has about 1.8e9) */
     int64_t lat = 1;
     for (int d = 0; d < 3; ++d) lat *= (int64_t)mesh->cells[d] * degree + 1;
-    if (lat > ((int64_t)1 << 40)) {
-        msg = "mesh too large";
+    if (lat >= ((int64_t)1 << 31)) {
+        msg = "mesh too large: at most 2^31 - 1 nodes";
         return MFCG_EINVAL;
     }
     return MFCG_OK;
@@ -367,10 +370,14 @@ int mfcg_setup(const mfcg_mesh *mesh, int32_t degree, const double *cell_coeff, 
         }                                                                                        \
     } while (0)
 
-    SCHK(hipGetDevice(&h->device));
     int nc[3] = {mesh->cells[0], mesh->cells[1], mesh->cells[2]};
     int t[3] = {tile ? tile[0] : 0, tile ? tile[1] : 0, tile ? tile[2] : 0};
     build_layout(nc, degree, t, mesh->bc, h->hl, n_q(h));
+    if (h->hl.npart >= ((int64_t)1 << 31)) {
+        h->err = "mesh too large: the shared-node partial sums exceed 2^31 - 1 entries";
+        return bail(MFCG_EINVAL);
+    }
+    SCHK(hipGetDevice(&h->device));
     if (build_tables(degree, h->tab, h->gll, n_q(h))) {
         h->err = "quadrature tables";
         return bail(MFCG_EINVAL);
@@ -548,6 +555,30 @@ int mfcg_vmult(mfcg_handle h, double *dst, const double *src, void *hip_stream)
     int rc = vmult_internal(h, h->vin, h->vout, s);
     if (rc) return rc;
     HIPCHK(h, launch_int_to_lex<double>(h->lv, h->vout, dst, s));
+    return MFCG_OK;
+}
+
+int mfcg_vmult_fp32(mfcg_handle h, double *dst, const double *src, void *hip_stream)
+{
+    if (!h || !dst || !src) return fail(h, MFCG_EINVAL, "null argument");
+    if (dst == src) return fail(h, MFCG_EINVAL, "dst and src must differ");
+    hipStream_t s = (hipStream_t)hip_stream;
+    int rc = ensure_fp32(h, s);
+    if (rc) return rc;
+    IterArgs<float> a{};
+    a.L = h->lv;
+    a.G = h->G32;
+    a.dinv = h->dinv32;
+    a.src = h->r32;
+    a.dst = h->v32;
+    a.part = h->part32;
+    a.dots = h->dots32;
+    a.st = h->st32;
+    a.nshared_blocks = h->nshared_blocks;
+    HIPCHK(h, launch_lex_to_int<float>(h->lv, src, h->r32, s));
+    HIPCHK(h, launch_fused<float>(h->K, MODE_VMULT, a, s));
+    HIPCHK(h, launch_shared<float>(MODE_VMULT, a, s));
+    HIPCHK(h, launch_int_to_lex<float>(h->lv, h->v32, dst, s));
     return MFCG_OK;
 }
 
@@ -1246,7 +1277,7 @@ int mfcg_solve_ir(mfcg_handle h, const double *b, double *x, double tol, double 
 
 int mfcg_stream_bench(int32_t kind, int64_t n, const double *src, double *dst, int32_t nblocks, void *hip_stream)
 {
-    if (n < 2 || (n & 1) || !src || !dst || (kind != 0 && kind != 1) || nblocks < 1)
+    if (n < 2 || (n & 1) || !src || !dst || kind < 0 || kind > 15 || ((kind >> 1) & 3) == 3 || nblocks < 1)
         return fail(nullptr, MFCG_EINVAL, "bad stream_bench arguments");
     HIPCHK(nullptr, launch_stream(kind, n, src, dst, nblocks, (hipStream_t)hip_stream));
     return MFCG_OK;
@@ -1394,8 +1425,100 @@ static IterArgs<double> iter_args(const mfcg_ctx *h)
 
 extern "C" {
 
-int mfcg_batch_setup(int32_t nprob, const mfcg_mesh *meshes, const int32_t *degrees, const double *const *coeffs,
-                     int32_t autotune, void *hip_stream, mfcg_batch *out)
+}  // extern "C"
+
+/* ------------------------------------------------------------------ */
+/* Autotuner cache: one JSON record per tuned case, one record per line */
+/* ------------------------------------------------------------------ */
+
+struct TuneKey {
+    std::string gpu;
+    int k, cells, map;
+    std::string prec;
+};
+
+static std::string gpu_key()
+{
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string n = std::string(prop.gcnArchName) + "/" + prop.name;
+    for (char &c : n)
+        if (c == '"' || c == '\\' || (unsigned char)c < 32) c = '_';
+    return n;
+}
+
+static std::string tune_record(const TuneKey &key, const int tile[3], double ms)
+{
+    char buf[512];
+    snprintf(buf, sizeof(buf),
+             "{\"gpu\": \"%s\", \"k\": %d, \"cells\": %d, \"map\": %d, \"precision\": \"%s\", "
+             "\"tile\": [%d, %d, %d], \"ms\": %.6g}",
+             key.gpu.c_str(), key.k, key.cells, key.map, key.prec.c_str(), tile[0], tile[1], tile[2], ms);
+    return buf;
+}
+
+/* the record's key part (everything before "tile") identifies the case */
+static std::string record_key(const std::string &rec)
+{
+    const size_t p = rec.find("\"tile\"");
+    return p == std::string::npos ? std::string() : rec.substr(rec.find('{'), p - rec.find('{'));
+}
+
+static std::vector<std::string> tune_cache_read(const char *path)
+{
+    std::vector<std::string> recs;
+    FILE *f = fopen(path, "r");
+    if (!f) return recs;
+    char line[1024];
+    while (fgets(line, sizeof(line), f)) {
+        std::string l(line);
+        const size_t a = l.find('{'), b = l.rfind('}');
+        if (l.find("\"gpu\"") == std::string::npos || a == std::string::npos || b == std::string::npos) continue;
+        recs.push_back(l.substr(a, b - a + 1));
+    }
+    fclose(f);
+    return recs;
+}
+
+static bool tune_cache_lookup(const char *path, const TuneKey &key, int tile[3])
+{
+    const int zero[3] = {0, 0, 0};
+    const std::string want = record_key(tune_record(key, zero, 0.0));
+    for (const std::string &r : tune_cache_read(path)) {
+        if (record_key(r) != want) continue;
+        const size_t p = r.find('[', r.find("\"tile\""));
+        if (p != std::string::npos && sscanf(r.c_str() + p, "[%d, %d, %d]", &tile[0], &tile[1], &tile[2]) == 3 &&
+            tile[0] > 0 && tile[1] > 0 && tile[2] > 0)
+            return true;
+    }
+    return false;
+}
+
+/* adds or replaces the case's record; written to a temporary file and
+ * renamed, so a reader never sees a partial file */
+static void tune_cache_store(const char *path, const TuneKey &key, const int tile[3], double ms)
+{
+    const std::string rec = tune_record(key, tile, ms), k = record_key(rec);
+    std::vector<std::string> recs;
+    for (const std::string &r : tune_cache_read(path))
+        if (record_key(r) != k) recs.push_back(r);
+    recs.push_back(rec);
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    fprintf(f, "{\"version\": 1, \"entries\": [\n");
+    for (size_t i = 0; i < recs.size(); ++i) fprintf(f, "%s%s\n", recs[i].c_str(), i + 1 < recs.size() ? "," : "");
+    fprintf(f, "]}\n");
+    const bool ok = fclose(f) == 0;
+    if (ok) rename(tmp.c_str(), path);
+}
+
+/* autotune: 0 none, 1 per degree; fixed: a tile for every problem (clipped
+ * to its mesh) or NULL; cache: autotuner cache path or NULL */
+static int batch_setup_impl(int32_t nprob, const mfcg_mesh *meshes, const int32_t *degrees,
+                            const double *const *coeffs, int autotune, const int32_t *fixed, const char *cache,
+                            void *hip_stream, mfcg_batch *out)
 {
     if (!out) return batch_fail(nullptr, MFCG_EINVAL, "null out");
     *out = nullptr;
@@ -1423,17 +1546,31 @@ int mfcg_batch_setup(int32_t nprob, const mfcg_mesh *meshes, const int32_t *degr
             const int c = std::min(cmax, 48);
             m.cells[0] = m.cells[1] = m.cells[2] = c;
             int32_t t[3];
-            int rc = mfcg_autotune_tile(&m, K, 6, t, nullptr, hip_stream);
-            if (rc) {
-                batch_release(hb);
-                delete hb;
-                return rc;
+            const TuneKey key{cache ? gpu_key() : std::string(), K, c, m.map_kind, "fp64"};
+            int ct[3];
+            if (cache && tune_cache_lookup(cache, key, ct)) {
+                for (int d = 0; d < 3; ++d) t[d] = ct[d];
+            } else {
+                double ms = 0.0;
+                int rc = mfcg_autotune_tile(&m, K, 6, t, &ms, hip_stream);
+                if (rc) {
+                    batch_release(hb);
+                    delete hb;
+                    return rc;
+                }
+                if (cache) {
+                    const int tt[3] = {t[0], t[1], t[2]};
+                    tune_cache_store(cache, key, tt, ms);
+                }
             }
             for (int i = 0; i < nprob; ++i)
                 if (degrees[i] == K)
                     for (int d = 0; d < 3; ++d) hb->tiles[i][d] = std::min(t[d], meshes[i].cells[d]);
         }
     }
+    if (fixed && !autotune)
+        for (int i = 0; i < nprob; ++i)
+            for (int d = 0; d < 3; ++d) hb->tiles[i][d] = std::min(fixed[d], meshes[i].cells[d]);
     for (int i = 0; i < nprob; ++i) {
         mfcg_options o{};
         for (int d = 0; d < 3; ++d) o.tile[d] = hb->tiles[i][d];
@@ -1464,6 +1601,27 @@ int mfcg_batch_setup(int32_t nprob, const mfcg_mesh *meshes, const int32_t *degr
     return MFCG_OK;
 }
 
+extern "C" {
+
+int mfcg_batch_setup(int32_t nprob, const mfcg_mesh *meshes, const int32_t *degrees, const double *const *coeffs,
+                     int32_t autotune, void *hip_stream, mfcg_batch *out)
+{
+    return batch_setup_impl(nprob, meshes, degrees, coeffs, autotune != 0, nullptr, nullptr, hip_stream, out);
+}
+
+int mfcg_setup_batch(int32_t nprob, const mfcg_mesh *meshes, const int32_t *degrees, const double *const *coeffs,
+                     const mfcg_options *opt, void *hip_stream, mfcg_batch *out)
+{
+    if (opt && (opt->tile[0] < 0 || opt->tile[1] < 0 || opt->tile[2] < 0))
+        return batch_fail(nullptr, MFCG_EINVAL, "tile sizes must be >= 0");
+    if (opt && (opt->n_q_1d != 0 || opt->fp32 || opt->quad_rule != MFCG_QUAD_GAUSS || opt->op != MFCG_OP_LAPLACE ||
+                opt->geometry != MFCG_GEOM_STORED))
+        return batch_fail(nullptr, MFCG_EINVAL, "a batch runs the FP64 Gauss-point Laplacian with the stored tensor");
+    const bool fixed = opt && opt->tile[0] > 0 && opt->tile[1] > 0 && opt->tile[2] > 0;
+    return batch_setup_impl(nprob, meshes, degrees, coeffs, !fixed, fixed ? opt->tile : nullptr,
+                            opt ? opt->tune_cache : nullptr, hip_stream, out);
+}
+
 int mfcg_batch_info(mfcg_batch hb, int32_t i, mfcg_handle *h, int32_t *tile)
 {
     if (!hb || i < 0 || i >= (int32_t)hb->probs.size()) return batch_fail(hb, MFCG_EINVAL, "bad problem index");
@@ -1471,6 +1629,12 @@ int mfcg_batch_info(mfcg_batch hb, int32_t i, mfcg_handle *h, int32_t *tile)
     if (tile)
         for (int d = 0; d < 3; ++d) tile[d] = hb->tiles[i][d];
     return MFCG_OK;
+}
+
+int mfcg_solve_batch(mfcg_batch hb, const double *const *b, double *const *x, double tol, int32_t maxit,
+                     int32_t *iters, int32_t *status, void *hip_stream)
+{
+    return mfcg_batch_solve(hb, b, x, tol, maxit, iters, status, hip_stream);
 }
 
 int mfcg_batch_solve(mfcg_batch hb, const double *const *b, double *const *x, double tol, int32_t maxit,

@@ -604,20 +604,56 @@ namespace mfcg {
 /* device (copy: 1 read + 1 write per element; read: 1 read, reduced)    */
 /* ------------------------------------------------------------------ */
 
-__global__ __launch_bounds__(256) void stream_copy_kernel(int64_t n2, const double2 *__restrict__ src,
-                                                          double2 *__restrict__ dst)
+/* U independent 16-byte loads in flight per thread (grid-stride blocks of
+ * U strides), optionally with the non-temporal hint. */
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
+template <int U, bool NT>
+__device__ __forceinline__ dbl2 sload(const dbl2 *p)
 {
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n2; i += stride) dst[i] = src[i];
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
 }
 
-__global__ __launch_bounds__(256) void stream_read_kernel(int64_t n2, const double2 *__restrict__ src, double *out)
+template <int U, bool NT>
+__global__ __launch_bounds__(256) void stream_copy_kernel(int64_t n2, const dbl2 *__restrict__ src,
+                                                          dbl2 *__restrict__ dst)
+{
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    for (; i + (U - 1) * stride < n2; i += U * stride) {
+        dbl2 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = sload<U, NT>(src + i + u * stride);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if constexpr (NT)
+                __builtin_nontemporal_store(v[u], dst + i + u * stride);
+            else
+                dst[i + u * stride] = v[u];
+        }
+    }
+    for (; i < n2; i += stride) dst[i] = src[i];
+}
+
+template <int U, bool NT>
+__global__ __launch_bounds__(256) void stream_read_kernel(int64_t n2, const dbl2 *__restrict__ src, double *out)
 {
     __shared__ double red[4];
     const int64_t stride = (int64_t)gridDim.x * 256;
     double s = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n2; i += stride) {
-        const double2 v = src[i];
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    for (; i + (U - 1) * stride < n2; i += U * stride) {
+        dbl2 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = sload<U, NT>(src + i + u * stride);
+#pragma unroll
+        for (int u = 0; u < U; ++u) s += v[u].x + v[u].y;
+    }
+    for (; i < n2; i += stride) {
+        const dbl2 v = src[i];
         s += v.x + v.y;
     }
 #pragma unroll
@@ -627,14 +663,26 @@ __global__ __launch_bounds__(256) void stream_read_kernel(int64_t n2, const doub
     if (threadIdx.x == 0) out[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
+template <int U, bool NT>
+static void launch_stream_t(bool read, int64_t n2, const double *src, double *dst, int nblocks, hipStream_t s)
+{
+    if (read)
+        hipLaunchKernelGGL((stream_read_kernel<U, NT>), dim3(nblocks), dim3(256), 0, s, n2, (const dbl2 *)src, dst);
+    else
+        hipLaunchKernelGGL((stream_copy_kernel<U, NT>), dim3(nblocks), dim3(256), 0, s, n2, (const dbl2 *)src,
+                           (dbl2 *)dst);
+}
+
+/* kind: bit 0 read (1) or copy (0); bits 1-2: log2 of the loads in flight
+ * per thread (1, 2 or 4); bit 3: non-temporal hint */
 hipError_t launch_stream(int kind, int64_t n, const double *src, double *dst, int nblocks, hipStream_t s)
 {
     const int64_t n2 = n / 2;
-    if (kind == 0)
-        hipLaunchKernelGGL(stream_copy_kernel, dim3(nblocks), dim3(256), 0, s, n2, (const double2 *)src,
-                           (double2 *)dst);
-    else
-        hipLaunchKernelGGL(stream_read_kernel, dim3(nblocks), dim3(256), 0, s, n2, (const double2 *)src, dst);
+    const bool read = kind & 1, nt = kind & 8;
+    const int lu = (kind >> 1) & 3;
+    if (lu == 0) nt ? launch_stream_t<1, true>(read, n2, src, dst, nblocks, s) : launch_stream_t<1, false>(read, n2, src, dst, nblocks, s);
+    else if (lu == 1) nt ? launch_stream_t<2, true>(read, n2, src, dst, nblocks, s) : launch_stream_t<2, false>(read, n2, src, dst, nblocks, s);
+    else nt ? launch_stream_t<4, true>(read, n2, src, dst, nblocks, s) : launch_stream_t<4, false>(read, n2, src, dst, nblocks, s);
     return hipGetLastError();
 }
 

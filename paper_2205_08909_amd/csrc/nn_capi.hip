@@ -180,6 +180,18 @@ int mfnn_mse(int64_t n, const float *pred, const float *target, float *grad, dou
     return MFNN_OK;
 }
 
+int mfnn_mse_loss(int64_t n, const float *pred, const float *target, float *grad, double *loss, double *work,
+                  void *hip_stream)
+{
+    return mfnn_mse(n, pred, target, grad, loss, work, hip_stream);
+}
+
+int mfnn_adam_step(int64_t n, float *theta, uint16_t *theta_bf16, const float *g, float *m, float *v, int32_t step,
+                   float lr, float beta1, float beta2, float eps, void *hip_stream)
+{
+    return mfnn_adam(n, theta, theta_bf16, g, m, v, step, lr, beta1, beta2, eps, hip_stream);
+}
+
 int mfnn_adam(int64_t n, float *theta, uint16_t *theta_bf16, const float *g, float *m, float *v, int32_t step,
               float lr, float beta1, float beta2, float eps, void *hip_stream)
 {

@@ -30,6 +30,7 @@ EXPORTED = [
     "mfcg_stream_bench", "mfcg_solve_ir", "mfcg_set_solver", "mfcg_set_coefficient", "mfcg_warmstart",
     "mfcg_autotune_tile", "mfcg_batch_setup", "mfcg_batch_info", "mfcg_batch_solve", "mfcg_batch_destroy",
     "mfcg_batch_last_error", "mfcg_set_sstep", "mfcg_set_preconditioner", "mfcg_solve_vector",
+    "mfcg_vmult_fp32", "mfcg_setup_batch", "mfcg_solve_batch",
 ]
 
 
@@ -47,7 +48,7 @@ class Mesh(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("n_q_1d", ctypes.c_int32), ("tile", ctypes.c_int32 * 3), ("check_every", ctypes.c_int32),
                 ("fp32", ctypes.c_int32), ("quad_rule", ctypes.c_int32), ("op", ctypes.c_int32),
-                ("geometry", ctypes.c_int32)]
+                ("geometry", ctypes.c_int32), ("deterministic", ctypes.c_int32), ("tune_cache", ctypes.c_char_p)]
 
 
 _lib = None
@@ -92,6 +93,9 @@ def lib():
         L.mfcg_warmstart.argtypes = [P, P, P, D, P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I32), P]
         L.mfcg_autotune_tile.argtypes = [ctypes.POINTER(Mesh), I32, I32, P, ctypes.POINTER(D), P]
         L.mfcg_batch_setup.argtypes = [I32, P, P, P, I32, P, ctypes.POINTER(P)]
+        L.mfcg_setup_batch.argtypes = [I32, P, P, P, ctypes.POINTER(Options), P, ctypes.POINTER(P)]
+        L.mfcg_solve_batch.argtypes = [P, P, P, D, I32, P, P, P]
+        L.mfcg_vmult_fp32.argtypes = [P, P, P, P]
         L.mfcg_batch_info.argtypes = [P, I32, ctypes.POINTER(P), P]
         L.mfcg_batch_solve.argtypes = [P, P, P, D, I32, P, P, P]
         L.mfcg_batch_destroy.argtypes = [P]
@@ -124,8 +128,10 @@ def make_mesh(cells, map_kind=MAP_AFFINE, amplitude=0.0, bc=BC_DIRICHLET0):
     return m
 
 
-def make_options(tile=None, check_every=0, fp32=0, quad=QUAD_GAUSS, op=OP_LAPLACE, n_q_1d=0, geometry=GEOM_STORED):
+def make_options(tile=None, check_every=0, fp32=0, quad=QUAD_GAUSS, op=OP_LAPLACE, n_q_1d=0, geometry=GEOM_STORED,
+                 tune_cache=None):
     o = Options()
+    o.tune_cache = None if tune_cache is None else str(tune_cache).encode()
     o.n_q_1d = int(n_q_1d)
     o.geometry = int(geometry)
     for d in range(3):
@@ -213,6 +219,13 @@ class Problem:
         _dev_vec(dst, self.n, "dst")
         _dev_vec(src, self.n, "src")
         _check(lib().mfcg_vmult(self.h, _ptr(dst), _ptr(src), _stream(stream)), self.h)
+        return dst
+
+    def vmult_fp32(self, dst, src, stream=None):
+        """dst = A32 src with the single-precision operator of the mixed-precision solver."""
+        _dev_vec(dst, self.n, "dst")
+        _dev_vec(src, self.n, "src")
+        _check(lib().mfcg_vmult_fp32(self.h, _ptr(dst), _ptr(src), _stream(stream)), self.h)
         return dst
 
     def diagonal(self, out=None, stream=None):
@@ -374,7 +387,7 @@ class Batch:
     problems: list of dicts with cells, degree and optional coeff, map_kind,
     amplitude, bc."""
 
-    def __init__(self, problems, autotune=True, stream=None):
+    def __init__(self, problems, autotune=True, stream=None, tile=None, tune_cache=None):
         np_ = len(problems)
         meshes = (Mesh * np_)()
         degs = (ctypes.c_int32 * np_)()
@@ -392,8 +405,14 @@ class Batch:
             else:
                 cptrs[i] = None
         self.h = ctypes.c_void_p()
-        code = lib().mfcg_batch_setup(np_, meshes, degs, cptrs, 1 if autotune else 0, _stream(stream),
-                                      ctypes.byref(self.h))
+        if tile is not None or tune_cache is not None:
+            # the options form: a fixed tile for every problem, or the autotuner with its cache
+            self._opt = make_options(tile=tile, tune_cache=tune_cache)
+            code = lib().mfcg_setup_batch(np_, meshes, degs, cptrs, ctypes.byref(self._opt), _stream(stream),
+                                          ctypes.byref(self.h))
+        else:
+            code = lib().mfcg_batch_setup(np_, meshes, degs, cptrs, 1 if autotune else 0, _stream(stream),
+                                          ctypes.byref(self.h))
         if code != OK:
             raise MfcgError(code, lib().mfcg_batch_last_error(None).decode())
         self.nprob = np_

@@ -16,7 +16,7 @@ NOALLOC_WORK_FLOATS = 1 << 20   # workspace of mfnn_conv3d_bwd_weight_noalloc (f
 
 EXPORTED = [
     "mfnn_conv3d_fwd", "mfnn_conv3d_bwd_data", "mfnn_conv3d_bwd_weight", "mfnn_conv3d_bwd_weight_work",
-    "mfnn_conv3d_bwd_weight_noalloc",
+    "mfnn_conv3d_bwd_weight_noalloc", "mfnn_mse_loss", "mfnn_adam_step",
     "mfnn_act_bwd", "mfnn_mse", "mfnn_adam", "mfnn_convert", "mfnn_features", "mfnn_channel_sum",
     "mfnn_normalize", "mfnn_last_error",
 ]
@@ -74,6 +74,8 @@ def lib():
         L.mfnn_act_bwd.argtypes = [I64, P, P, I32, I32, P, P]
         L.mfnn_mse.argtypes = [I64, P, P, P, P, P, P]
         L.mfnn_adam.argtypes = [I64, P, P, P, P, P, I32, F, F, F, F, P]
+        L.mfnn_adam_step.argtypes = L.mfnn_adam.argtypes
+        L.mfnn_mse_loss.argtypes = L.mfnn_mse.argtypes
         L.mfnn_convert.argtypes = [I64, P, I32, P, I32, P]
         L.mfnn_features.argtypes = [ctypes.POINTER(I32), I32, P, P, P, P, P, P]
         L.mfnn_channel_sum.argtypes = [I32, I32, ctypes.POINTER(I32), P, I32, P, P]

@@ -90,6 +90,49 @@ def test_setup_rejects_invalid_arguments(cells, degree, bc, msg):
     assert msg in L.mfcg_last_error(None).decode()
 
 
+def test_setup_rejects_meshes_beyond_32_bit_offsets():
+    """The fused kernels index vectors with 32-bit offsets: a lattice of
+    2^31 nodes or more is refused on the host, before any allocation or HIP
+    call (here 1300^3 Q1 cells, 1301^3 = 2.2e9 nodes); one just below the
+    limit passes the check (it then needs the GPU, so only the message of
+    the first failure is compared)."""
+    L = mfcg.lib()
+    h = ctypes.c_void_p()
+    m = mfcg.make_mesh((1300, 1300, 1300))
+    assert L.mfcg_setup(ctypes.byref(m), 1, None, None, None, ctypes.byref(h)) == mfcg.EINVAL and not h.value
+    assert "2^31" in L.mfcg_last_error(None).decode()
+    m = mfcg.make_mesh((1290, 1290, 1290))   # 1291^3 = 2.15e9 >= 2^31
+    assert L.mfcg_setup(ctypes.byref(m), 1, None, None, None, ctypes.byref(h)) == mfcg.EINVAL
+    # the batch validates every problem the same way
+    meshes = (mfcg.Mesh * 2)(mfcg.make_mesh((4, 4, 4)), mfcg.make_mesh((2000, 1100, 1000)))
+    degs = (ctypes.c_int32 * 2)(2, 1)
+    assert L.mfcg_setup_batch(2, meshes, degs, None, None, None, ctypes.byref(h)) == mfcg.EINVAL
+    assert L.mfcg_batch_setup(2, meshes, degs, None, 1, None, ctypes.byref(h)) == mfcg.EINVAL
+
+
+def test_interface_summary_names_are_exported():
+    """The calls under the names of the interface summary (batch set-up and
+    solve, the network's Adam step and MSE loss) are exported, and the batch
+    set-up with options refuses operator variants a batch does not run."""
+    from paper_2205_08909_amd import nn
+    L = mfcg.lib()
+    for name in ("mfcg_setup", "mfcg_vmult", "mfcg_diagonal", "mfcg_solve", "mfcg_solve_ir", "mfcg_setup_batch",
+                 "mfcg_solve_batch", "mfcg_destroy", "mfcg_error_string", "mfcg_last_error", "mfnn_conv3d_fwd",
+                 "mfnn_conv3d_bwd_data", "mfnn_conv3d_bwd_weight", "mfnn_adam_step", "mfnn_mse_loss"):
+        assert hasattr(L, name), name
+    meshes = (mfcg.Mesh * 1)(mfcg.make_mesh((4, 4, 4)))
+    degs = (ctypes.c_int32 * 1)(2)
+    h = ctypes.c_void_p()
+    o = mfcg.make_options(op=mfcg.OP_MASS)
+    assert L.mfcg_setup_batch(1, meshes, degs, None, ctypes.byref(o), None, ctypes.byref(h)) == mfcg.EINVAL
+    o = mfcg.make_options(tile=(-1, 2, 2))
+    assert L.mfcg_setup_batch(1, meshes, degs, None, ctypes.byref(o), None, ctypes.byref(h)) == mfcg.EINVAL
+    fake = ctypes.c_void_p(64)
+    assert nn.lib().mfnn_adam_step(10, fake, None, fake, fake, fake, 0, 1e-3, 0.9, 0.999, 1e-8, None) == nn.EINVAL
+    assert nn.lib().mfnn_mse_loss(0, fake, fake, fake, fake, fake, None) == nn.EINVAL
+    assert L.mfcg_vmult_fp32(None, fake, fake, None) == mfcg.EINVAL
+
+
 def test_setup_rejects_bad_coefficient_and_tile():
     L = mfcg.lib()
     m = mfcg.make_mesh((2, 2, 2))

@@ -131,3 +131,41 @@ def test_batch_mixed_own_and_packed_launches():
         assert c == mfcg.OK and it == its[i] and torch.equal(x, xs[i])
         P.close()
     B.close()
+
+
+def test_setup_batch_options_and_tune_cache(tmp_path):
+    """mfcg_setup_batch: a fixed tile from the options is used for every
+    problem (clipped to its mesh); with a tune cache the first set-up tunes
+    and records one tile per degree, the second reads them back (same tiles,
+    no tuning), and both batches solve to the same solution bitwise."""
+    import json
+    import time
+    import torch
+    from paper_2205_08909_amd import mfcg
+    probs = _draw(11, 4, 4, 10, kmin=2, kmax=4)
+    bs = [torch.from_numpy(inputs.random_rhs(p["cells"][0], p["degree"], seed=p["seed"])).cuda() for p in probs]
+    fixed = mfcg.Batch(probs, tile=(2, 2, 4))
+    for i, p in enumerate(probs):
+        assert fixed.tiles[i] == tuple(min(t, c) for t, c in zip((2, 2, 4), p["cells"]))
+    fixed.close()
+    cache = tmp_path / "tune.json"
+    t0 = time.perf_counter()
+    B1 = mfcg.Batch(probs, tune_cache=str(cache))
+    t1 = time.perf_counter()
+    recs = json.load(open(cache))["entries"]
+    assert {r["k"] for r in recs} == {p["degree"] for p in probs}
+    assert all(r["precision"] == "fp64" and len(r["tile"]) == 3 and r["ms"] > 0 for r in recs)
+    before = cache.read_bytes()
+    B2 = mfcg.Batch(probs, tune_cache=str(cache))
+    t2 = time.perf_counter()
+    print(f"set-up with tuning {t1 - t0:.2f} s, from the cache {t2 - t1:.2f} s")
+    assert B2.tiles == B1.tiles
+    assert cache.read_bytes() == before  # read back, nothing tuned again
+    xs1 = [torch.zeros_like(b) for b in bs]
+    xs2 = [torch.zeros_like(b) for b in bs]
+    c1, its1, _ = B1.solve(bs, xs1, tol=1e-10, maxit=5000)
+    c2, its2, _ = B2.solve(bs, xs2, tol=1e-10, maxit=5000)
+    assert c1 == c2 == mfcg.OK and its1 == its2
+    assert all(torch.equal(a, b) for a, b in zip(xs1, xs2))
+    B1.close()
+    B2.close()
