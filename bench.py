@@ -48,7 +48,8 @@ def source_hash():
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2205_08909_amd", "csrc")
-    for f in ("kernels_cg.hip", "kernels.h", "tables_ct.h", "mfcg_internal.h", "setup_host.cpp"):
+    for f in ("fused_tile.h", "fused_k4.hip", "cg_common.h", "kernels_cg.hip", "kernels.h", "tables_ct.h",
+              "mfcg_internal.h", "setup_host.cpp"):
         h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -248,6 +249,88 @@ def batch_experiment(args):
     B.close()
 
 
+def sweep_block(args, torch, mfcg):
+    """Degree sweep of the default run: k = 1..8 at about 1e7 DoFs
+    (N = round(216 / k)), the per-degree default tiles, curved mesh, a = 1,
+    random-normal right-hand side, tol = 0: time per iteration without
+    per-launch events and the fraction of 8 TB/s by the per-DoF bytes of the
+    fused method (4.5 + 3.5 vector entries plus the stored G)."""
+    from paper_2205_08909_amd import inputs
+    rows = []
+    S, W = args.extra_steps, 3
+    for k in range(1, 9):
+        N = round(216 / k)
+        P = mfcg.Problem(N, k, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05)
+        n = P.n
+        b = torch.from_numpy(inputs.random_rhs(N, k, seed=7)).cuda()
+        P.cg_begin(b, None, tol=0.0, maxit=W + S)
+        P.cg_iterate(W)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.cg_iterate(S)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        x = torch.empty_like(b)
+        code, its, _ = P.cg_end(x)
+        assert its == W + S, (k, code, its)
+        it_bytes = 64 * n + 8 * 6 * (k + 1) ** 3 * N ** 3
+        row = {"k": k, "cells": N, "n_dofs": n, "tile": list(P.layout_info()["tile"]),
+               "ms_per_iter": round(wall * 1e3 / S, 4), "GDoF_it_s": round(n * S / wall / 1e9, 3),
+               "bytes_per_dof": round(it_bytes / n, 2),
+               "frac_8TBs": round(it_bytes * S / wall / 1e9 / HBM_PEAK_GBS, 4)}
+        print(f"[bench] sweep {row}", file=sys.stderr, flush=True)
+        rows.append(row)
+        del b, x
+        P.close()
+        torch.cuda.empty_cache()
+    return {"workload": "fused FP64 CG iteration, curved mesh (sine shear 0.05), a = 1, about 1e7 DoFs per "
+                        "degree, default tiles", "steps": S, "rows": rows}
+
+
+def batch_block(args, torch, mfcg):
+    """The batched workload (32 problems, side N ~ U{16..96}, degree
+    k ~ U{2..6}, draw seed 0, random-field coefficients, random-normal
+    right-hand sides): a fixed number of iterations of all problems in one
+    batch (one set of launches per iteration) against the same iterations of
+    the problems solved one after another, per-degree default tiles."""
+    from paper_2205_08909_amd import inputs
+    draw = inputs.batch_draw(0, 32, 16, 96)
+    probs = [{"cells": (d["N"],) * 3, "degree": d["k"], "map_kind": mfcg.MAP_SINE_SHEAR, "amplitude": 0.05,
+              "coeff": inputs.grf_coefficient(d["N"], 0.1, 1.0, seed=d["seed"]), "seed": d["seed"]} for d in draw]
+    t0 = time.perf_counter()
+    B = mfcg.Batch(probs, autotune=False)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    bs = [torch.from_numpy(inputs.random_rhs(d["N"], d["k"], seed=d["seed"])).cuda() for d in draw]
+    xs = [torch.zeros_like(b) for b in bs]
+    ns = [P.n for P in B.problems]
+    S = args.extra_steps
+    B.solve(bs, xs, tol=0.0, maxit=2)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    code, its, st = B.solve(bs, xs, tol=0.0, maxit=S)
+    torch.cuda.synchronize()
+    batch_s = time.perf_counter() - t0
+    assert all(i == S for i in its), its
+    t0 = time.perf_counter()
+    for P, b, x in zip(B.problems, bs, xs):
+        x.zero_()
+        P.solve(b, x, tol=0.0, maxit=S, want_hist=False, raise_on=False)
+    torch.cuda.synchronize()
+    seq_s = time.perf_counter() - t0
+    work = sum(ns) * S
+    out = {"workload": "32 problems, N ~ U{16..96}, k ~ U{2..6} (draw seed 0), curved mesh, a = exp(GRF l=0.1), "
+                       "random-normal b, FP64", "total_dofs": sum(ns), "iterations": S, "setup_s": round(setup_s, 2),
+           "batched_s": round(batch_s, 4), "sequential_s": round(seq_s, 4),
+           "batched_GDoF_it_s": round(work / batch_s / 1e9, 3), "sequential_GDoF_it_s": round(work / seq_s / 1e9, 3),
+           "speedup_vs_sequential": round(seq_s / batch_s, 3)}
+    print(f"[bench] batch {out}", file=sys.stderr, flush=True)
+    B.close()
+    del bs, xs
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -273,6 +356,9 @@ def main():
     ap.add_argument("--batch-nmax", type=int, default=96)
     ap.add_argument("--batch-maxit", type=int, default=30000)
     ap.add_argument("--batch-compare", action="store_true", help="also solve the problems one after another")
+    ap.add_argument("--precision-seeds", default="0,1,2,3,4", help="random-field seeds of the precision block")
+    ap.add_argument("--no-extra", action="store_true", help="skip the degree-sweep and batch blocks")
+    ap.add_argument("--extra-steps", type=int, default=20, help="iterations timed per case in those blocks")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this benchmark runs on one GPU only (the path is single-GPU); "
@@ -306,12 +392,11 @@ def main():
           flush=True)
 
     # ---- timed region: K fused iterations, inputs resident in HBM ----
-    P.cg_begin(b, None, tol=0.0, maxit=W + K)
+    # no per-launch events here: the K steps run back to back as a user's
+    # solve would; stream events split them into (up to) 5 blocks for min / median
+    P.cg_begin(b, None, tol=0.0, maxit=W + 2 * K)
     P.cg_iterate(W)
     torch.cuda.synchronize()
-    P.set_timing(True)
-    torch.cuda.synchronize()
-    # the K steps run back to back; stream events split them into (up to) 5 blocks for min / median
     nblk = min(5, K)
     sizes = [K // nblk + (1 if i < K % nblk else 0) for i in range(nblk)]
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(nblk + 1)]
@@ -323,14 +408,24 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     blk_ms = sorted(evs[i].elapsed_time(evs[i + 1]) / sizes[i] for i in range(nblk))
+    # second timed region, same K steps continued: HIP events recorded by the
+    # library on its launch stream around every fused and shared-node launch
+    # give the per-kernel durations of the roofline
+    P.set_timing(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    P.cg_iterate(K)
+    torch.cuda.synchronize()
+    wall_ev = time.perf_counter() - t1
     tm = P.get_timing()
     P.set_timing(False)
     code, its, _ = P.cg_end(x)
-    assert its == W + K, (code, its)
+    assert its == W + 2 * K, (code, its)
     ms_per_step = wall * 1e3 / K
     value = n * K / wall / 1e9
     print(f"[bench] {K} iterations in {wall * 1e3:.2f} ms: {ms_per_step:.4f} ms/it, {value:.3f} GDoF*it/s; "
-          f"fused {tm['fused_ms'] / K:.4f} ms, shared {tm['shared_ms'] / K:.4f} ms", file=sys.stderr, flush=True)
+          f"with per-launch events {wall_ev * 1e3 / K:.4f} ms/it: fused {tm['fused_ms'] / K:.4f} ms, "
+          f"shared + finish {tm['shared_ms'] / K:.4f} ms", file=sys.stderr, flush=True)
 
     # ---- comparison solvers on the same problem: what the fusion saves ----
     ablation = None
@@ -469,10 +564,14 @@ def main():
     ncell = N ** 3
     g_bytes = 8 * 6 * nq * ncell
     nI, nS, nC = info["n_interior"], info["n_shared"], info["n_dirichlet"]
-    it_bytes = 8 * 8 * n + g_bytes                      # 4.5 reads + 3.5 writes per vector entry, plus G
-    fused_bytes = g_bytes + 64 * nI + 32 * nS + 8 * nS  # G, interior nodes once, shared nodes read once + handed over once
+    # algorithmic bytes of one iteration (the per-DoF figure of the fused
+    # method: 4.5 reads + 3.5 writes per vector entry plus the stored G,
+    # 156.66 B/DoF at Q4 64^3) times the DoFs one fused launch processes
+    it_bytes = 8 * 8 * n + g_bytes
+    fused_bytes = g_bytes + 64 * nI + 32 * nS + 8 * nS  # what the fused launch itself reads and writes
     fused_avg_ms = tm["fused_ms"] / max(1, tm["fused_launches"])
-    achieved = fused_bytes / (fused_avg_ms * 1e-3) / 1e9
+    shared_avg_ms = tm["shared_ms"] / max(1, tm["shared_launches"])
+    achieved = it_bytes / (fused_avg_ms * 1e-3) / 1e9
     traffic = counter_traffic("fused_tile_kernel")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
@@ -481,16 +580,27 @@ def main():
     nb = 256 * 1024 * 1024  # 2 GiB per buffer
     a_ = torch.ones(nb, dtype=torch.float64, device="cuda")
     c_ = torch.empty_like(a_)
-    part = torch.empty(1024, dtype=torch.float64, device="cuda")
-    ceil = {}
-    for kind, name, dst, by in ((0, "copy", c_, 16 * nb), (1, "read", part, 8 * nb)):
-        mfcg.stream_bench(kind, a_, dst, 1024)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(5):
-            mfcg.stream_bench(kind, a_, dst, 1024)
-        torch.cuda.synchronize()
-        ceil[name] = by * 5 / (time.perf_counter() - t0) / 1e9
+    part = torch.empty(4096, dtype=torch.float64, device="cuda")
+    ceil, ceil_cfg = {}, {}
+    # best over grid size, loads in flight per thread and the non-temporal hint
+    for base, name, dst, by in ((0, "copy", c_, 16 * nb), (1, "read", part, 8 * nb)):
+        best = 0.0
+        for nblocks in (1024, 2048, 4096):
+            for lu in (0, 1):
+                for nt in (0, 8):
+                    kind = base | (lu << 1) | nt
+                    mfcg.stream_bench(kind, a_, dst, nblocks)
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    for _ in range(5):
+                        mfcg.stream_bench(kind, a_, dst, nblocks)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    gbs = by * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+                    if gbs > best:
+                        best = gbs
+                        ceil_cfg[name] = {"blocks": nblocks, "loads_per_thread": 1 << lu, "nontemporal": bool(nt)}
+        ceil[name] = best
     del a_, c_, part
     copy_gbs = ceil["copy"]
 
@@ -506,30 +616,40 @@ def main():
     precision = None
     if not args.no_solve:
         from paper_2205_08909_amd import inputs
-        coeff = inputs.grf_coefficient(N, 0.1, 1.0, seed=0)
-        P2 = mfcg.Problem(N, k, coeff=coeff, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05, tile=args.tile)
-        P2.solve_ir(P2.rhs(), torch.zeros(P2.n, dtype=torch.float64, device="cuda"), tol=1e-10)  # builds the FP32 copy
-        b2 = P2.rhs(mfcg.RHS_SINE)
-        plain = time_solve(P2, b2, torch)
-        x_plain = plain.pop("_x")
-        precision = {"workload": f"{N}^3 cells Q{k} curved, a = exp(GRF l=0.1 var=1, seed 0)",
-                     "plain_fp64": plain}
-        for keep, itol, name in ((False, 1e-4, "fp32_inner_ir"), (True, 1e-1, "fp32_residual_replacement")):
-            x2 = torch.zeros_like(b2)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            code, outer, inner, hist, tr = P2.solve_ir(b2, x2, tol=1e-10, inner_tol=itol, keep_direction=keep,
-                                                       max_outer=100)
-            torch.cuda.synchronize()
-            t_ir = time.perf_counter() - t0
-            diff = (torch.linalg.norm(x2 - x_plain) / torch.linalg.norm(x_plain)).item()
-            precision[name] = {"inner_tol": itol, "seconds": round(t_ir, 4), "outer": outer, "inner_iters": inner,
-                               "status": int(code),
-                               "true_rel_res": float(f"{tr:.3e}"),
-                               "rel_diff_vs_plain_fp64_solution": float(f"{diff:.3e}"),
-                               "speedup": round(plain["seconds"] / t_ir, 3)}
-        print(f"[bench] precision: {precision}", file=sys.stderr, flush=True)
-        P2.close()
+        seeds = [int(v) for v in args.precision_seeds.split(",") if v != ""]
+        precision = {"workload": f"{N}^3 cells Q{k} curved, a = exp(GRF l=0.1 var=1), f = 3 pi^2 prod sin, "
+                                 f"solve to 1e-10 from x0 = 0", "seeds": []}
+        for seed in seeds:
+            coeff = inputs.grf_coefficient(N, 0.1, 1.0, seed=seed)
+            P2 = mfcg.Problem(N, k, coeff=coeff, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05, tile=args.tile,
+                              fp32=1)
+            b2 = P2.rhs(mfcg.RHS_SINE)
+            plain = time_solve(P2, b2, torch)
+            x_plain = plain.pop("_x")
+            row = {"seed": seed, "plain_fp64": plain}
+            for keep, itol, name in ((False, 1e-4, "fp32_inner_ir"), (True, 1e-1, "fp32_residual_replacement")):
+                x2 = torch.zeros_like(b2)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                code, outer, inner, hist, tr = P2.solve_ir(b2, x2, tol=1e-10, inner_tol=itol, keep_direction=keep,
+                                                           max_outer=100)
+                torch.cuda.synchronize()
+                t_ir = time.perf_counter() - t0
+                diff = (torch.linalg.norm(x2 - x_plain) / torch.linalg.norm(x_plain)).item()
+                row[name] = {"inner_tol": itol, "seconds": round(t_ir, 4), "outer": outer, "inner_iters": inner,
+                             "status": int(code), "true_rel_res": float(f"{tr:.3e}"),
+                             "rel_diff_vs_plain_fp64_solution": float(f"{diff:.3e}"),
+                             "speedup": round(plain["seconds"] / t_ir, 3)}
+            precision["seeds"].append(row)
+            print(f"[bench] precision seed {seed}: {row}", file=sys.stderr, flush=True)
+            del b2, x_plain
+            P2.close()
+        for name in ("fp32_inner_ir", "fp32_residual_replacement"):
+            sp = [r[name]["speedup"] for r in precision["seeds"]]
+            precision[name + "_speedup_mean"] = round(sum(sp) / len(sp), 3) if sp else None
+
+    sweep = None if args.no_extra else sweep_block(args, torch, mfcg)
+    batch = None if args.no_extra else batch_block(args, torch, mfcg)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -559,12 +679,18 @@ def main():
         "iteration_roofline": {"bytes_per_dof": round(it_bytes / n, 2),
                                "achieved_GBs": round(it_bytes / (ms_per_step * 1e-3) / 1e9, 1),
                                "frac": round(it_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
-        "kernel_ms": {"fused": round(fused_avg_ms, 5), "shared": round(tm["shared_ms"] / max(1, tm["shared_launches"]), 5)},
+        "kernel_ms": {"fused": round(fused_avg_ms, 5), "shared_plus_finish": round(shared_avg_ms, 5),
+                      "iteration_with_launch_events": round(wall_ev * 1e3 / K, 5)},
+        "fused_kernel_own_bytes_GBs": round(fused_bytes / (fused_avg_ms * 1e-3) / 1e9, 1),
         "measured_ceiling_GBs": {k_: round(v_, 1) for k_, v_ in ceil.items()},
+        "measured_ceiling_config": ceil_cfg,
+        "fused_kernel_frac_of_measured_copy": round(achieved / copy_gbs, 4),
         "iteration_frac_of_measured_copy": round(it_bytes / (ms_per_step * 1e-3) / 1e9 / copy_gbs, 4),
         "ablation_ms_per_iter": ablation,
         "time_to_1e-10": solve,
         "precision": precision,
+        "sweep": sweep,
+        "batch": batch,
         "setup_s": round(setup_s, 3),
     }
     print(json.dumps(line), flush=True)

@@ -185,10 +185,10 @@ class Problem:
     """mfcg_setup on a mesh + degree + per-cell coefficient."""
 
     def __init__(self, cells, degree, coeff=None, map_kind=MAP_AFFINE, amplitude=0.0, bc=BC_DIRICHLET0, tile=None,
-                 check_every=0, stream=None, quad=QUAD_GAUSS, op=OP_LAPLACE, n_q_1d=0, geometry=GEOM_STORED):
+                 check_every=0, stream=None, quad=QUAD_GAUSS, op=OP_LAPLACE, n_q_1d=0, geometry=GEOM_STORED, fp32=0):
         self.mesh = make_mesh(cells, map_kind, amplitude, bc)
         self.degree = int(degree)
-        self.opt = make_options(tile, check_every, quad=quad, op=op, n_q_1d=n_q_1d, geometry=geometry)
+        self.opt = make_options(tile, check_every, fp32=fp32, quad=quad, op=op, n_q_1d=n_q_1d, geometry=geometry)
         self.h = ctypes.c_void_p()
         self._coeff = None
         if coeff is not None:
