@@ -287,65 +287,124 @@ __device__ inline void cell_range(const Dim1 &d, int64_t gd, int &lo, int &hi)
 }
 
 /* ------------------------------------------------------------------ */
+/* Cell-by-cell assembly of node vectors                               */
+/* ------------------------------------------------------------------ */
+
+/* The cells whose coordinates have the parities of `colour` (bit d: odd in
+ * direction d) share no node, so the cells of one colour class add their
+ * element contributions into a node vector without atomics; the 8 classes
+ * run one after another, so every node's sum has a fixed order. */
+constexpr int CELL_WG = 256;
+constexpr int MAXQ3 = 9 * 9 * 9; /* up to 9 quadrature points per direction */
+
+__device__ inline bool colour_cell(const LayoutView &L, int colour, int64_t b, int c[3])
+{
+    int64_t nc[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) nc[d] = (L.d[d].ncells - ((colour >> d) & 1) + 1) / 2;
+    if (b >= nc[0] * nc[1] * nc[2]) return false;
+    c[0] = (int)(2 * (b % nc[0]) + (colour & 1));
+    c[1] = (int)(2 * ((b / nc[0]) % nc[1]) + ((colour >> 1) & 1));
+    c[2] = (int)(2 * (b / (nc[0] * nc[1])) + ((colour >> 2) & 1));
+    return true;
+}
+
+/* v[0..n) = 0 (a kernel rather than a memset node, so that a caller may
+ * capture the assembly in a graph) */
+__global__ __launch_bounds__(SETUP_WG) void zero_kernel(int64_t n, double *v)
+{
+    const int64_t t = (int64_t)blockIdx.x * SETUP_WG + threadIdx.x;
+    if (t < n) v[t] = 0.0;
+}
+
+static void launch_zero(int64_t n, double *v, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((n + SETUP_WG - 1) / SETUP_WG)), dim3(SETUP_WG), 0, s, n, v);
+}
+
+/* lexicographic index of local node (ix, iy, iz) of cell c */
+__device__ inline int64_t cell_node_lex(const LayoutView &L, int K, const int c[3], int ix, int iy, int iz)
+{
+    const int64_t l0 = (int64_t)L.d[0].ncells * K + 1, l1 = (int64_t)L.d[1].ncells * K + 1;
+    return ((int64_t)c[0] * K + ix) + l0 * (((int64_t)c[1] * K + iy) + l1 * ((int64_t)c[2] * K + iz));
+}
+
+/* ------------------------------------------------------------------ */
 /* Diagonal (Sec. 3: point Jacobi)                                     */
 /* ------------------------------------------------------------------ */
 
-__global__ __launch_bounds__(SETUP_WG) void diagonal_kernel(const GeomArgs g, const double *G, double *diag_lex,
-                                                            double *dinv_int)
+/* One cell of colour class `colour` per workgroup: the cell's tensor G_q
+ * staged in LDS, then every local node i adds
+ * sum_q (grad phi_i)^T G_q grad phi_i (Laplacian) or sum_q G_q phi_i^2
+ * (mass: component 0 holds a_e w_q det J_q) into diag_lex. */
+__global__ __launch_bounds__(CELL_WG) void diagonal_cells_kernel(const GeomArgs g, const double *G, int colour,
+                                                                 double *diag_lex)
+{
+    __shared__ double gs[6 * MAXQ3];
+    const LayoutView &L = g.L;
+    const int K = g.K, n = K + 1, nq = g.nq, nq3 = nq * nq * nq;
+    int c[3];
+    if (!colour_cell(L, colour, blockIdx.x, c)) return;
+    const int ncomp = g.op == 1 ? 1 : 6;
+    for (int q = threadIdx.x; q < nq3; q += CELL_WG) {
+        const int qx = q % nq, qy = (q / nq) % nq, qz = q / (nq * nq);
+        int64_t cs;
+        const int64_t o = g_offset(L, nq, c, qx, qy, qz, cs);
+        for (int comp = 0; comp < ncomp; ++comp) gs[comp * nq3 + q] = G[o + comp * cs];
+    }
+    __syncthreads();
+    for (int li = threadIdx.x; li < n * n * n; li += CELL_WG) {
+        const int ix = li % n, iy = (li / n) % n, iz = li / (n * n);
+        double dsum = 0.0;
+        for (int qz = 0; qz < nq; ++qz)
+            for (int qy = 0; qy < nq; ++qy)
+                for (int qx = 0; qx < nq; ++qx) {
+                    const int q = qx + nq * (qy + nq * qz);
+                    const double sx = g.tab.S[qx * n + ix], sy = g.tab.S[qy * n + iy], sz = g.tab.S[qz * n + iz];
+                    if (g.op == 1) {
+                        const double phi = sx * sy * sz;
+                        dsum += gs[q] * phi * phi;
+                        continue;
+                    }
+                    const double gx = g.tab.Sd[qx * n + ix] * sy * sz;
+                    const double gy = sx * g.tab.Sd[qy * n + iy] * sz;
+                    const double gz = sx * sy * g.tab.Sd[qz * n + iz];
+                    dsum += gs[q] * gx * gx + gs[nq3 + q] * gy * gy + gs[2 * nq3 + q] * gz * gz +
+                            2.0 * (gs[3 * nq3 + q] * gx * gy + gs[4 * nq3 + q] * gx * gz + gs[5 * nq3 + q] * gy * gz);
+                }
+        diag_lex[cell_node_lex(L, K, c, ix, iy, iz)] += dsum;
+    }
+}
+
+/* Dirichlet rows (identity: diagonal 1) and the inverse in internal order. */
+__global__ __launch_bounds__(SETUP_WG) void diagonal_finish_kernel(const GeomArgs g, double *diag_lex,
+                                                                   double *dinv_int)
 {
     const LayoutView &L = g.L;
-    const int K = g.K, n = K + 1, nq = g.nq;
     const int64_t t = (int64_t)blockIdx.x * SETUP_WG + threadIdx.x;
     if (t >= L.n) return;
     int64_t gc[3];
     lex_coords(L, t, gc);
-    double dsum = 0.0;
+    double d = diag_lex[t];
     if (g.bc == 0 && on_boundary(L, gc)) {
-        dsum = 1.0;
-    } else {
-        int lo[3], hi[3];
-        for (int d = 0; d < 3; ++d) cell_range(L.d[d], gc[d], lo[d], hi[d]);
-        for (int cz = lo[2]; cz <= hi[2]; ++cz)
-            for (int cy = lo[1]; cy <= hi[1]; ++cy)
-                for (int cx = lo[0]; cx <= hi[0]; ++cx) {
-                    const int c[3] = {cx, cy, cz};
-                    const int ix = (int)(gc[0] - (int64_t)cx * K), iy = (int)(gc[1] - (int64_t)cy * K),
-                              iz = (int)(gc[2] - (int64_t)cz * K);
-                    if (g.op == 1) { /* mass: sum_q a_e w_q det J_q phi_i^2 */
-                        for (int qz = 0; qz < nq; ++qz)
-                            for (int qy = 0; qy < nq; ++qy)
-                                for (int qx = 0; qx < nq; ++qx) {
-                                    int64_t cs;
-                                    const int64_t o = g_offset(L, nq, c, qx, qy, qz, cs);
-                                    const double phi =
-                                        g.tab.S[qx * n + ix] * g.tab.S[qy * n + iy] * g.tab.S[qz * n + iz];
-                                    dsum += G[o] * phi * phi;
-                                }
-                        continue;
-                    }
-                    for (int qz = 0; qz < nq; ++qz)
-                        for (int qy = 0; qy < nq; ++qy)
-                            for (int qx = 0; qx < nq; ++qx) {
-                                const double gx = g.tab.Sd[qx * n + ix] * g.tab.S[qy * n + iy] * g.tab.S[qz * n + iz];
-                                const double gy = g.tab.S[qx * n + ix] * g.tab.Sd[qy * n + iy] * g.tab.S[qz * n + iz];
-                                const double gz = g.tab.S[qx * n + ix] * g.tab.S[qy * n + iy] * g.tab.Sd[qz * n + iz];
-                                int64_t cs;
-                                const int64_t o = g_offset(L, nq, c, qx, qy, qz, cs);
-                                const double g00 = G[o], g11 = G[o + cs], g22 = G[o + 2 * cs], g01 = G[o + 3 * cs],
-                                             g02 = G[o + 4 * cs], g12 = G[o + 5 * cs];
-                                dsum += g00 * gx * gx + g11 * gy * gy + g22 * gz * gz +
-                                        2.0 * (g01 * gx * gy + g02 * gx * gz + g12 * gy * gz);
-                            }
-                }
+        d = 1.0;
+        diag_lex[t] = d;
     }
-    if (diag_lex) diag_lex[t] = dsum;
-    if (dinv_int) dinv_int[internal_index(L, gc)] = 1.0 / dsum;
+    if (dinv_int) dinv_int[internal_index(L, gc)] = 1.0 / d;
 }
 
 hipError_t launch_diagonal(const GeomArgs &g, const double *G, double *diag_lex, double *dinv_int, hipStream_t s)
 {
+    if (g.nq * g.nq * g.nq > MAXQ3) return hipErrorInvalidValue;
+    launch_zero(g.L.n, diag_lex, s);
+    for (int colour = 0; colour < 8; ++colour) {
+        int64_t m = 1;
+        for (int d = 0; d < 3; ++d) m *= (g.L.d[d].ncells - ((colour >> d) & 1) + 1) / 2;
+        if (m == 0) continue;
+        hipLaunchKernelGGL(diagonal_cells_kernel, dim3((unsigned)m), dim3(CELL_WG), 0, s, g, G, colour, diag_lex);
+    }
     const int64_t nb = (g.L.n + SETUP_WG - 1) / SETUP_WG;
-    hipLaunchKernelGGL(diagonal_kernel, dim3((unsigned)nb), dim3(SETUP_WG), 0, s, g, G, diag_lex, dinv_int);
+    hipLaunchKernelGGL(diagonal_finish_kernel, dim3((unsigned)nb), dim3(SETUP_WG), 0, s, g, diag_lex, dinv_int);
     return hipGetLastError();
 }
 
@@ -371,36 +430,37 @@ __device__ inline double forcing(const RhsParams &f, const double x[3])
     return s;
 }
 
-__global__ __launch_bounds__(SETUP_WG) void rhs_kernel(const GeomArgs g, const RhsParams f, double *b)
+/* One cell of colour class `colour` per workgroup: f(x_q) w_q det J_q at
+ * the cell's quadrature points, staged in LDS, then every local node i
+ * that is not a Dirichlet node adds sum_q phi_i(x_q) f(x_q) w_q det J_q
+ * into b. */
+__global__ __launch_bounds__(CELL_WG) void rhs_cells_kernel(const GeomArgs g, const RhsParams f, int colour, double *b)
 {
+    __shared__ double fq[MAXQ3];
     const LayoutView &L = g.L;
-    const int K = g.K, n = K + 1, nq = g.nq;
-    const int64_t t = (int64_t)blockIdx.x * SETUP_WG + threadIdx.x;
-    if (t >= L.n) return;
-    int64_t gc[3];
-    lex_coords(L, t, gc);
-    double acc = 0.0;
-    if (!(g.bc == 0 && on_boundary(L, gc))) {
-        int lo[3], hi[3];
-        for (int d = 0; d < 3; ++d) cell_range(L.d[d], gc[d], lo[d], hi[d]);
-        for (int cz = lo[2]; cz <= hi[2]; ++cz)
-            for (int cy = lo[1]; cy <= hi[1]; ++cy)
-                for (int cx = lo[0]; cx <= hi[0]; ++cx) {
-                    const int c[3] = {cx, cy, cz};
-                    const int ix = (int)(gc[0] - (int64_t)cx * K), iy = (int)(gc[1] - (int64_t)cy * K),
-                              iz = (int)(gc[2] - (int64_t)cz * K);
-                    for (int qz = 0; qz < nq; ++qz)
-                        for (int qy = 0; qy < nq; ++qy)
-                            for (int qx = 0; qx < nq; ++qx) {
-                                const double xi[3] = {g.tab.xq[qx], g.tab.xq[qy], g.tab.xq[qz]};
-                                double x[3], J[3][3];
-                                const double det = cell_jacobian(g, c, xi, x, J);
-                                const double phi = g.tab.S[qx * n + ix] * g.tab.S[qy * n + iy] * g.tab.S[qz * n + iz];
-                                acc += forcing(f, x) * phi * g.tab.wq[qx] * g.tab.wq[qy] * g.tab.wq[qz] * det;
-                            }
-                }
+    const int K = g.K, n = K + 1, nq = g.nq, nq3 = nq * nq * nq;
+    int c[3];
+    if (!colour_cell(L, colour, blockIdx.x, c)) return;
+    for (int q = threadIdx.x; q < nq3; q += CELL_WG) {
+        const int qx = q % nq, qy = (q / nq) % nq, qz = q / (nq * nq);
+        const double xi[3] = {g.tab.xq[qx], g.tab.xq[qy], g.tab.xq[qz]};
+        double x[3], J[3][3];
+        const double det = cell_jacobian(g, c, xi, x, J);
+        fq[q] = forcing(f, x) * g.tab.wq[qx] * g.tab.wq[qy] * g.tab.wq[qz] * det;
     }
-    b[t] = acc;
+    __syncthreads();
+    for (int li = threadIdx.x; li < n * n * n; li += CELL_WG) {
+        const int ix = li % n, iy = (li / n) % n, iz = li / (n * n);
+        const int64_t gc[3] = {(int64_t)c[0] * K + ix, (int64_t)c[1] * K + iy, (int64_t)c[2] * K + iz};
+        if (g.bc == 0 && on_boundary(L, gc)) continue;
+        double acc = 0.0;
+        for (int qz = 0; qz < nq; ++qz)
+            for (int qy = 0; qy < nq; ++qy) {
+                const double syz = g.tab.S[qy * n + iy] * g.tab.S[qz * n + iz];
+                for (int qx = 0; qx < nq; ++qx) acc += fq[qx + nq * (qy + nq * qz)] * g.tab.S[qx * n + ix] * syz;
+            }
+        b[cell_node_lex(L, K, c, ix, iy, iz)] += acc;
+    }
 }
 
 hipError_t launch_rhs(const GeomArgs &g, int kind, const double *params, int nparams, double *b_lex, hipStream_t s)
@@ -413,8 +473,14 @@ hipError_t launch_rhs(const GeomArgs &g, int kind, const double *params, int npa
         if (f.nbumps < 0 || f.nbumps > 16 || nparams < 1 + 5 * f.nbumps) return hipErrorInvalidValue;
         for (int i = 0; i < 5 * f.nbumps; ++i) f.p[i] = params[1 + i];
     }
-    const int64_t nb = (g.L.n + SETUP_WG - 1) / SETUP_WG;
-    hipLaunchKernelGGL(rhs_kernel, dim3((unsigned)nb), dim3(SETUP_WG), 0, s, g, f, b_lex);
+    if (g.nq * g.nq * g.nq > MAXQ3) return hipErrorInvalidValue;
+    launch_zero(g.L.n, b_lex, s);
+    for (int colour = 0; colour < 8; ++colour) {
+        int64_t m = 1;
+        for (int d = 0; d < 3; ++d) m *= (g.L.d[d].ncells - ((colour >> d) & 1) + 1) / 2;
+        if (m == 0) continue;
+        hipLaunchKernelGGL(rhs_cells_kernel, dim3((unsigned)m), dim3(CELL_WG), 0, s, g, f, colour, b_lex);
+    }
     return hipGetLastError();
 }
 
