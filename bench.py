@@ -386,6 +386,7 @@ def main():
     setup_s = time.perf_counter() - t0
     info = P.layout_info()
     n = P.n
+    g_bytes_stored = 8 * 6 * (k + 1) ** 3 * N ** 3
     b = P.rhs(mfcg.RHS_SINE)
     x = torch.zeros_like(b)
     print(f"[bench] setup {setup_s:.2f} s, n={n}, tiles={info['n_tiles']} tile={info['tile']}", file=sys.stderr,
@@ -604,6 +605,39 @@ def main():
     del a_, c_, part
     copy_gbs = ceil["copy"]
 
+    # ---- many right-hand sides on the same operator: one fused launch per
+    # iteration over (tile, right-hand side) pairs, G_q read about once for
+    # all m; per-iteration time from two solves with tol = 0 that differ by K
+    # iterations (the set-up cancels) ----
+    multi = None
+    if not args.no_extra:
+        multi = {"workload": f"m right-hand sides (random normal, seeds 0..m-1) on the {N}^3 Q{k} operator",
+                 "single_rhs_ms": round(ms_per_step, 5), "m": []}
+        from paper_2205_08909_amd import inputs
+        for m in (2, 4, 8):
+            bs = [torch.from_numpy(inputs.random_rhs(N, k, seed=c)).cuda() for c in range(m)]
+            xs = [torch.zeros_like(bs[0]) for _ in range(m)]
+            tv = []
+            for its_m in (W, W + K):
+                for x_ in xs:
+                    x_.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, got, _, _ = P.solve_multi(bs, xs, tol=0.0, maxit=its_m, raise_on=False)
+                torch.cuda.synchronize()
+                tv.append(time.perf_counter() - t0)
+                assert got == [its_m] * m, got
+            mms = (tv[1] - tv[0]) * 1e3 / K
+            mbytes = m * 64 * n + g_bytes_stored
+            row = {"m": m, "ms_per_iteration": round(mms, 5), "GDoF_it_s": round(m * n / mms / 1e6, 3),
+                   "bytes_per_dof_per_rhs": round(mbytes / (m * n), 2),
+                   "achieved_GBs": round(mbytes / (mms * 1e-3) / 1e9, 1),
+                   "speedup_vs_single_solves": round(m * ms_per_step / mms, 3)}
+            multi["m"].append(row)
+            print(f"[bench] multi-rhs {row}", file=sys.stderr, flush=True)
+            del bs, xs
+        torch.cuda.empty_cache()
+
     # ---- time to 1e-10 with the plain fused FP64 solver ----
     solve = None
     if not args.no_solve:
@@ -691,6 +725,7 @@ def main():
         "precision": precision,
         "sweep": sweep,
         "batch": batch,
+        "multi_rhs": multi,
         "setup_s": round(setup_s, 3),
     }
     print(json.dumps(line), flush=True)

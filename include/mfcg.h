@@ -251,6 +251,32 @@ int mfcg_solve(mfcg_handle h, const double *b, double *x, double tol, int32_t ma
 int mfcg_solve_vector(mfcg_handle h, const double *b, double *x, double tol, int32_t maxit, int32_t *iters,
                       double *res_hist, double *true_rel_res, void *hip_stream);
 
+/* Many right-hand sides on one operator (an extension of Algorithm 5, Sec.
+ * 4.2): m independent solves A x_c = b_c, c = 0..m-1, each with its own CG
+ * scalars and its own stopping test ||r_c||_2 < tol ||b_c||_2.  One fused
+ * launch per iteration covers every (tile, right-hand side) pair, the
+ * right-hand side index fastest, so a tile's geometry tensor G_q is read
+ * from HBM about once per iteration for all m; a right-hand side that has
+ * stopped drops out while the others go on.
+ *   m         1 <= m <= MFCG_MULTI_MAX
+ *   b, x      host arrays of m device pointers, each a vector of n doubles
+ *             in lexicographic node order; x[c] holds x_0 on entry and the
+ *             solution on return.  A zero b[c] gives x[c] = 0, 0 iterations.
+ *   iters     host, m: iterations taken by each
+ *   status    host, m: MFCG_OK, MFCG_ENOTCONV or MFCG_EBREAKDOWN
+ *   true_rel_res  host, m doubles or NULL: ||b_c - A x_c|| / ||b_c||
+ * Each right-hand side follows exactly the iteration of mfcg_solve with the
+ * Jacobi preconditioner on this handle's operator variant.  Allocates 4 m n
+ * doubles of work vectors at the first call with this m or a larger one
+ * (kept by the handle).  Ends a stepping-interface solve in progress.
+ * Returns MFCG_OK when every right-hand side converged, else the first
+ * non-OK status (ENOTCONV or EBREAKDOWN; the per-right-hand-side results
+ * are filled in either case); EINVAL for bad arguments; ENOMEM, EHIP.
+ * Synchronises hip_stream. */
+#define MFCG_MULTI_MAX 64
+int mfcg_solve_multi(mfcg_handle h, int32_t m, const double *const *b, double *const *x, double tol, int32_t maxit,
+                     int32_t *iters, int32_t *status, double *true_rel_res, void *hip_stream);
+
 /* Mixed precision: FP64 iterative refinement around the fused solver run
  * in FP32 (operator with an FP32 copy of G_q and D^{-1}, vector updates and
  * inner products in FP32).  Outer loop in FP64 on the GPU:

@@ -66,6 +66,11 @@ struct mfcg_ctx {
     KrylovState *ks = nullptr;
     /* three-component work vectors of the vector Laplacian (component-blocked) */
     double *r3 = nullptr, *p3 = nullptr, *v3 = nullptr, *x3 = nullptr, *dots3 = nullptr, *part3 = nullptr;
+    /* independent right-hand sides (mfcg_solve_multi): m blocks of each */
+    double *rM = nullptr, *pM = nullptr, *vM = nullptr, *xM = nullptr, *dotsM = nullptr, *partM = nullptr;
+    double *histM = nullptr;
+    CGState *stM = nullptr;
+    int mcap = 0, histM_cap = 0;
     int nshared_blocks = 1;
     int nsum_blocks = 1;
     /* solve bookkeeping */
@@ -119,7 +124,8 @@ static void release(mfcg_ctx *h)
                     h->dots,       h->sums,       h->hist,    h->st,      h->G32,   h->dinv32, h->r32,
                     h->p32,        h->v32,        h->x32,     h->part32,  h->dots32, h->st32,  h->hist32,
                     h->kvec,       h->kpart,      h->ks,      h->r3,      h->p3,    h->v3,     h->x3,
-                    h->dots3,      h->part3,      h->Xq};
+                    h->dots3,      h->part3,      h->Xq,      h->rM,      h->pM,    h->vM,     h->xM,
+                    h->dotsM,      h->partM,      h->histM,   h->stM};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (auto &e : h->ev_pool) {
@@ -944,6 +950,151 @@ int mfcg_cg_end(mfcg_handle h, double *x, int32_t *iters, double *res_hist, void
     return fail(h, MFCG_ENOTCONV, "maxit reached");
 }
 
+/* Independent right-hand sides on one operator (Algorithm 5 for each,
+ * with its own scalars and stopping test): every iteration runs one fused
+ * launch over (tile, right-hand side) pairs, so a tile's geometry tensor is
+ * fetched once and served from L2 to the other right-hand sides, then the
+ * shared-node kernel over (block, right-hand side) and one finish block per
+ * right-hand side.  A right-hand side that has converged or broken down
+ * drops out (its workgroups return at once) while the others continue. */
+int mfcg_solve_multi(mfcg_handle h, int32_t m, const double *const *b, double *const *x, double tol, int32_t maxit,
+                     int32_t *iters, int32_t *status, double *true_rel_res, void *hip_stream)
+{
+    if (!h || !b || !x || !iters || !status) return fail(h, MFCG_EINVAL, "null argument");
+    if (m < 1 || m > MFCG_MULTI_MAX) return fail(h, MFCG_EINVAL, "m must be in 1..MFCG_MULTI_MAX");
+    for (int c = 0; c < m; ++c)
+        if (!b[c] || !x[c]) return fail(h, MFCG_EINVAL, "null vector of right-hand side " + std::to_string(c));
+    if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(h, MFCG_EINVAL, "tol must be finite and >= 0");
+    if (maxit < 1) return fail(h, MFCG_EINVAL, "maxit must be >= 1");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int64_t n = h->hl.n;
+    const int64_t nrec = h->hl.ntiles + h->nshared_blocks; /* records per right-hand side */
+    const int64_t ps = std::max<int64_t>(1, h->hl.npart);
+    /* the device CG state of a scalar solve is not touched, but its work
+     * vectors are: a stepping solve in progress ends here */
+    h->maxit = 0;
+    h->launched = 0;
+    if (m > h->mcap) {
+        HIPCHK(h, hipStreamSynchronize(s));
+        double *bufs[] = {h->rM, h->pM, h->vM, h->xM, h->dotsM, h->partM};
+        for (double *q : bufs)
+            if (q) HIPCHK(h, hipFree(q));
+        if (h->stM) HIPCHK(h, hipFree(h->stM));
+        h->rM = h->pM = h->vM = h->xM = h->dotsM = h->partM = nullptr;
+        h->stM = nullptr;
+        h->mcap = 0;
+        HIPCHK(h, dalloc(&h->rM, (size_t)(m * n)));
+        HIPCHK(h, dalloc(&h->pM, (size_t)(m * n)));
+        HIPCHK(h, dalloc(&h->vM, (size_t)(m * n)));
+        HIPCHK(h, dalloc(&h->xM, (size_t)(m * n)));
+        HIPCHK(h, dalloc(&h->dotsM, (size_t)(8 * m * nrec)));
+        HIPCHK(h, dalloc(&h->partM, (size_t)(m * ps)));
+        HIPCHK(h, dalloc(&h->stM, (size_t)m));
+        HIPCHK(h, hipMemsetAsync(h->partM, 0, sizeof(double) * m * ps, s));
+        h->mcap = m;
+    }
+    if ((int64_t)m * (maxit + 1) > (int64_t)h->histM_cap) {
+        HIPCHK(h, hipStreamSynchronize(s));
+        if (h->histM) HIPCHK(h, hipFree(h->histM));
+        h->histM = nullptr;
+        HIPCHK(h, dalloc(&h->histM, (size_t)m * (maxit + 1)));
+        h->histM_cap = m * (maxit + 1);
+    }
+    const int64_t hs = (int64_t)maxit + 1;
+    std::vector<CGState> st(m);
+    std::vector<char> zero(m, 0);
+    for (int c = 0; c < m; ++c) {
+        double *rc_ = h->rM + c * n, *pc = h->pM + c * n, *vc = h->vM + c * n, *xc = h->xM + c * n;
+        HIPCHK(h, launch_lex_to_int<double>(h->lv, b[c], rc_, s));
+        double bb = 0.0;
+        int rc = host_sumsq(h, rc_, nullptr, n, &bb, s);
+        if (rc) return rc;
+        st[c] = CGState{};
+        st[c].maxit = maxit;
+        if (bb == 0.0) { /* x = 0 exactly, no iteration */
+            zero[c] = 1;
+            st[c].flag = FLAG_CONV;
+            HIPCHK(h, hipMemcpyAsync(h->histM + c * hs, &st[c].r0norm, sizeof(double), hipMemcpyHostToDevice, s));
+            continue;
+        }
+        HIPCHK(h, launch_lex_to_int<double>(h->lv, x[c], xc, s));
+        rc = vmult_internal(h, xc, vc, s);
+        if (rc) return rc;
+        HIPCHK(h, launch_init_cg(n, rc_, pc, vc, 1, s)); /* r = b - A x0, p = v = 0 */
+        double rr = 0.0;
+        rc = host_sumsq(h, rc_, nullptr, n, &rr, s);
+        if (rc) return rc;
+        st[c].bnorm = std::sqrt(bb);
+        st[c].eps = tol * st[c].bnorm;
+        st[c].r0norm = std::sqrt(rr);
+        st[c].flag = st[c].r0norm < st[c].eps ? FLAG_CONV : FLAG_RUN;
+        HIPCHK(h, hipMemcpyAsync(h->histM + c * hs, &st[c].r0norm, sizeof(double), hipMemcpyHostToDevice, s));
+    }
+    HIPCHK(h, hipMemcpyAsync(h->stM, st.data(), sizeof(CGState) * m, hipMemcpyHostToDevice, s));
+    IterArgs<double> a{};
+    a.L = h->lv;
+    a.G = op_geometry(h);
+    a.dinv = h->dinv;
+    a.r = h->rM;
+    a.p = h->pM;
+    a.v = h->vM;
+    a.x = h->xM;
+    a.part = h->partM;
+    a.dots = h->dotsM;
+    a.st = h->stM;
+    a.hist = h->histM;
+    a.nshared_blocks = h->nshared_blocks;
+    auto running = [&]() {
+        for (int c = 0; c < m; ++c)
+            if (st[c].flag == FLAG_RUN) return true;
+        return false;
+    };
+    int launched = 0;
+    while (running() && launched < maxit) {
+        const int chunk = std::min(h->check_every, maxit - launched);
+        for (int it = 0; it < chunk; ++it) {
+            HIPCHK(h, launch_fused_vec(h->K, MODE_CG | op_flags(h), a, m, n, ps, 8 * nrec, 1, s));
+            HIPCHK(h, launch_shared_finish_multi(a, m, n, ps, 8 * nrec, hs, s));
+        }
+        launched += chunk;
+        HIPCHK(h, hipMemcpyAsync(st.data(), h->stM, sizeof(CGState) * m, hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+    }
+    int first = MFCG_OK;
+    for (int c = 0; c < m; ++c) {
+        if (zero[c]) {
+            HIPCHK(h, hipMemsetAsync(x[c], 0, sizeof(double) * n, s));
+        } else {
+            HIPCHK(h, launch_reconstruct<double>(n, h->xM + c * n, h->pM + c * n, h->rM + c * n, h->dinv, h->stM + c,
+                                                 s));
+            HIPCHK(h, launch_int_to_lex<double>(h->lv, h->xM + c * n, x[c], s));
+        }
+        iters[c] = zero[c] ? 0 : st[c].k;
+        status[c] = st[c].flag == FLAG_CONV ? MFCG_OK : (st[c].flag == FLAG_BREAK ? MFCG_EBREAKDOWN : MFCG_ENOTCONV);
+        if (first == MFCG_OK && status[c] != MFCG_OK) first = status[c];
+    }
+    HIPCHK(h, hipStreamSynchronize(s));
+    if (true_rel_res) {
+        for (int c = 0; c < m; ++c) {
+            if (zero[c]) {
+                true_rel_res[c] = 0.0;
+                continue;
+            }
+            HIPCHK(h, launch_lex_to_int<double>(h->lv, x[c], h->vin, s));
+            int rc = vmult_internal(h, h->vin, h->vout, s);
+            if (rc) return rc;
+            HIPCHK(h, launch_int_to_lex<double>(h->lv, h->vout, h->vin, s));
+            double rr = 0.0;
+            rc = host_sumsq(h, b[c], h->vin, n, &rr, s);
+            if (rc) return rc;
+            true_rel_res[c] = std::sqrt(rr) / st[c].bnorm;
+        }
+    }
+    if (first == MFCG_EBREAKDOWN) return fail(h, first, "breakdown in at least one right-hand side");
+    if (first == MFCG_ENOTCONV) return fail(h, first, "maxit reached for at least one right-hand side");
+    return MFCG_OK;
+}
+
 /* Vector problem (three uncoupled components sharing the operator, the
  * diagonal and the CG scalars): each iteration runs one fused launch over
  * (tile, component) pairs and the shared-node kernel per component, each
@@ -1032,8 +1183,8 @@ int mfcg_solve_vector(mfcg_handle h, const double *b, double *x, double tol, int
         const int chunk = std::min(h->check_every, maxit - launched);
         for (int it = 0; it < chunk; ++it) {
             /* the three components' tiles in one launch (geometry shared in L2) */
-            HIPCHK(h, launch_fused_vec(h->K, MODE_CG | op_flags(h), ac[0], n, std::max<int64_t>(1, h->hl.npart),
-                                       8 * nrec, s));
+            HIPCHK(h, launch_fused_vec(h->K, MODE_CG | op_flags(h), ac[0], 3, n, std::max<int64_t>(1, h->hl.npart),
+                                       8 * nrec, 0, s));
             for (int c = 0; c < 3; ++c) HIPCHK(h, launch_shared_nofinish(ac[c], s));
             HIPCHK(h, launch_finish_parts(ac[0], 3 * nrec, s));
         }

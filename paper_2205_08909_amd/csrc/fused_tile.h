@@ -1117,28 +1117,33 @@ void fused_tile_kernel(const IterArgs<T> a)
     fused_tile<K, T, MODE, OPV, true, QX>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
-/* Vector problems: one launch over (tile, component) pairs, the component
- * fastest, so the workgroups of one tile's three components are
- * dispatched together on one XCD and the geometry tensor they all apply is
- * fetched from HBM about once and then served from that XCD's L2.
- * Component c works on the vectors at offset c*nstride, its shared-node
- * partial sums at c*pstride and its inner-product records at c*dstride. */
+/* Several vectors on one operator: one launch over (tile, component)
+ * pairs, the component fastest, so the workgroups of one tile's m
+ * components are dispatched together on one XCD and the geometry tensor
+ * they all apply is fetched from HBM about once and then served from that
+ * XCD's L2.  Component c works on the vectors at offset c*nstride, its
+ * shared-node partial sums at c*pstride, its inner-product records at
+ * c*dstride and the CG state at a.st + c*sstride: sstride = 0 for the
+ * vector problem (three components, one CG), 1 for independent right-hand
+ * sides (one CG each; a component whose CG has stopped is skipped). */
 template <int K, int MODE, int OPV, int QX = 0>
 __global__ __launch_bounds__(Cfg<K>::WG)
 __attribute__((amdgpu_waves_per_eu(MFCG_WPE_MIN_Q(K, QX, OPV), 8)))
-void fused_tile_vec_kernel(const IterArgs<double> a, int64_t nstride, int64_t pstride, int64_t dstride)
+void fused_tile_vec_kernel(const IterArgs<double> a, int m, int64_t nstride, int64_t pstride, int64_t dstride,
+                           int sstride)
 {
-    if (a.st->flag != FLAG_RUN) return;
     const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int c = (int)(lb % 3);
+    const int c = (int)(lb % m);
+    if (a.st[c * sstride].flag != FLAG_RUN) return;
     IterArgs<double> b = a;
+    b.st += c * sstride;
     b.r += c * nstride;
     b.p += c * nstride;
     b.v += c * nstride;
     b.x += c * nstride;
     b.part += c * pstride;
     b.dots += c * dstride;
-    fused_tile<K, double, MODE, OPV, false, QX>(b, lb / 3);
+    fused_tile<K, double, MODE, OPV, false, QX>(b, lb / m);
 }
 
 /* Batch of problems of degree K: one workgroup per (problem, tile) item of
@@ -1221,45 +1226,45 @@ static inline hipError_t launch_fused_k(int mode, const IterArgs<T> &a, hipStrea
 }
 
 template <int K>
-static inline hipError_t launch_fused_vec_k(int mode, const IterArgs<double> &a, int64_t nstride, int64_t pstride,
-                                     int64_t dstride, hipStream_t s)
+static inline hipError_t launch_fused_vec_k(int mode, const IterArgs<double> &a, int m, int64_t nstride,
+                                            int64_t pstride, int64_t dstride, int sstride, hipStream_t s)
 {
-    dim3 grid((unsigned)(3 * a.L.ntiles)), block(Cfg<K>::WG);
+    dim3 grid((unsigned)(m * a.L.ntiles)), block(Cfg<K>::WG);
     if (mode == (MODE_CG | MODE_Q2) || mode == (MODE_CG | MODE_MASS | MODE_Q2) || mode == (MODE_CG | MODE_QGEOM | MODE_Q2) ||
         mode == (MODE_CG | MODE_QGEOM | MODE_MASS | MODE_Q2)) {
         if constexpr (K <= 7) {
             if ((mode & MODE_QGEOM) && (mode & MODE_MASS))
-                hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_MASS_QGEOM, 1>), grid, block, 0, s, a,
-                                   nstride, pstride, dstride);
+                hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_MASS_QGEOM, 1>), grid, block, 0, s, a, m,
+                                   nstride, pstride, dstride, sstride);
             else if (mode & MODE_QGEOM)
-                hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_LAPLACE_QGEOM, 1>), grid, block, 0, s, a,
-                                   nstride, pstride, dstride);
+                hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_LAPLACE_QGEOM, 1>), grid, block, 0, s, a, m,
+                                   nstride, pstride, dstride, sstride);
             else if (mode & MODE_MASS)
-                hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_MASS, 1>), grid, block, 0, s, a, nstride,
-                                   pstride, dstride);
+                hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_MASS, 1>), grid, block, 0, s, a, m, nstride,
+                                   pstride, dstride, sstride);
             else
-                hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_LAPLACE, 1>), grid, block, 0, s, a, nstride,
-                                   pstride, dstride);
+                hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_LAPLACE, 1>), grid, block, 0, s, a, m, nstride,
+                                   pstride, dstride, sstride);
             return hipGetLastError();
         } else {
             return hipErrorInvalidValue;
         }
     }
     if (mode == MODE_CG)
-        hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_LAPLACE>), grid, block, 0, s, a, nstride, pstride,
-                           dstride);
+        hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_LAPLACE>), grid, block, 0, s, a, m, nstride, pstride,
+                           dstride, sstride);
     else if (mode == (MODE_CG | MODE_GLL))
-        hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_LAPLACE_GLL>), grid, block, 0, s, a, nstride, pstride,
-                           dstride);
+        hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_LAPLACE_GLL>), grid, block, 0, s, a, m, nstride, pstride,
+                           dstride, sstride);
     else if (mode == (MODE_CG | MODE_MASS))
-        hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_MASS>), grid, block, 0, s, a, nstride, pstride,
-                           dstride);
+        hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_MASS>), grid, block, 0, s, a, m, nstride, pstride,
+                           dstride, sstride);
     else if (mode == (MODE_CG | MODE_QGEOM | MODE_MASS))
-        hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_MASS_QGEOM>), grid, block, 0, s, a, nstride,
-                           pstride, dstride);
+        hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_MASS_QGEOM>), grid, block, 0, s, a, m, nstride,
+                           pstride, dstride, sstride);
     else if (mode == (MODE_CG | MODE_QGEOM))
-        hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_LAPLACE_QGEOM>), grid, block, 0, s, a, nstride,
-                           pstride, dstride);
+        hipLaunchKernelGGL((fused_tile_vec_kernel<K, MODE_CG, OPV_LAPLACE_QGEOM>), grid, block, 0, s, a, m, nstride,
+                           pstride, dstride, sstride);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -1274,8 +1279,8 @@ template <int K>
 struct FusedDeg {
     static hipError_t fused64(int mode, const IterArgs<double> &a, hipStream_t s);
     static hipError_t fused32(int mode, const IterArgs<float> &a, hipStream_t s);
-    static hipError_t vec(int mode, const IterArgs<double> &a, int64_t nstride, int64_t pstride, int64_t dstride,
-                          hipStream_t s);
+    static hipError_t vec(int mode, const IterArgs<double> &a, int m, int64_t nstride, int64_t pstride,
+                          int64_t dstride, int sstride, hipStream_t s);
     static void batch(const IterArgs<double> *probs, const int2 *items, int nitems, hipStream_t s);
 };
 
@@ -1293,10 +1298,10 @@ struct FusedDeg {
         return launch_fused_k<K, float>(mode, a, s);                                                                  \
     }                                                                                                                 \
     template <>                                                                                                       \
-    hipError_t FusedDeg<K>::vec(int mode, const IterArgs<double> &a, int64_t nstride, int64_t pstride,                \
-                                int64_t dstride, hipStream_t s)                                                       \
+    hipError_t FusedDeg<K>::vec(int mode, const IterArgs<double> &a, int m, int64_t nstride, int64_t pstride,         \
+                                int64_t dstride, int sstride, hipStream_t s)                                          \
     {                                                                                                                 \
-        return launch_fused_vec_k<K>(mode, a, nstride, pstride, dstride, s);                                          \
+        return launch_fused_vec_k<K>(mode, a, m, nstride, pstride, dstride, sstride, s);                              \
     }                                                                                                                 \
     template <>                                                                                                       \
     void FusedDeg<K>::batch(const IterArgs<double> *probs, const int2 *items, int nitems, hipStream_t s)              \

@@ -72,13 +72,19 @@ hipError_t launch_shared(int mode, const IterArgs<T> &a, hipStream_t s);
  * shared-node kernel of one component without the finish, and the finish
  * over nparts records starting at a.dots (all components' records). */
 hipError_t launch_shared_nofinish(const IterArgs<double> &a, hipStream_t s);
+/* Independent right-hand sides c = 0..m-1 on one operator (vectors at
+ * c*nstride, partial sums at c*pstride, records at c*dstride, state a.st + c,
+ * history at c*hstride): the shared-node kernel over (block, c) and one
+ * finish block per c; a right-hand side whose CG has stopped is skipped. */
+hipError_t launch_shared_finish_multi(const IterArgs<double> &a, int m, int64_t nstride, int64_t pstride,
+                                      int64_t dstride, int64_t hstride, hipStream_t s);
 /* The fused tile kernel over all three components of a vector problem in
  * one launch (mode: MODE_CG, optionally with MODE_GLL, MODE_MASS or
  * MODE_QGEOM, and MODE_Q2 without MODE_GLL); the
  * vectors, shared partial sums and records of component c sit at c times
  * the given strides (elements). */
-hipError_t launch_fused_vec(int K, int mode, const IterArgs<double> &a, int64_t nstride, int64_t pstride,
-                            int64_t dstride, hipStream_t s);
+hipError_t launch_fused_vec(int K, int mode, const IterArgs<double> &a, int m, int64_t nstride, int64_t pstride,
+                            int64_t dstride, int sstride, hipStream_t s);
 hipError_t launch_finish_parts(const IterArgs<double> &a, int64_t nparts, hipStream_t s);
 
 /* Setup kernels (FP64). */

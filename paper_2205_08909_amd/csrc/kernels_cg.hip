@@ -184,6 +184,41 @@ __global__ __launch_bounds__(SHARED_WG) void finish_parts_kernel(const IterArgs<
     finish_iteration<double>(a, nparts, red);
 }
 
+/* Independent right-hand sides on one operator: blockIdx.y is the
+ * right-hand side c, whose vectors, shared-node partial sums, records and
+ * CG state sit at c*nstride, c*pstride, c*dstride and a.st + c. */
+__global__ __launch_bounds__(SHARED_WG) void shared_node_multi_kernel(const IterArgs<double> a, int64_t nstride,
+                                                                      int64_t pstride, int64_t dstride)
+{
+    __shared__ double red[8 * (SHARED_WG / 64)];
+    const int c = blockIdx.y;
+    if (a.st[c].flag != FLAG_RUN) return;
+    IterArgs<double> b = a;
+    b.r += c * nstride;
+    b.p += c * nstride;
+    b.v += c * nstride;
+    b.x += c * nstride;
+    b.part += c * pstride;
+    b.dots += c * dstride;
+    b.st += c;
+    shared_nodes<double, MODE_CG>(b, blockIdx.x, gridDim.x, red);
+}
+
+/* One block per right-hand side: its records, its scalars, its history
+ * (c*hstride). */
+__global__ __launch_bounds__(SHARED_WG) void finish_multi_kernel(const IterArgs<double> a, int64_t dstride,
+                                                                 int64_t hstride)
+{
+    __shared__ double red[8 * (SHARED_WG / 64)];
+    const int c = blockIdx.x;
+    if (a.st[c].flag != FLAG_RUN) return;
+    IterArgs<double> b = a;
+    b.dots += c * dstride;
+    b.st += c;
+    b.hist += c * hstride;
+    finish_iteration<double>(b, a.L.ntiles + a.nshared_blocks, red);
+}
+
 /* Batch: one block per listed problem. */
 template <typename T>
 __global__ __launch_bounds__(SHARED_WG) void finish_batch_kernel(const IterArgs<T> *__restrict__ probs,
@@ -240,18 +275,18 @@ hipError_t launch_shared(int mode, const IterArgs<T> &a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_fused_vec(int K, int mode, const IterArgs<double> &a, int64_t nstride, int64_t pstride,
-                            int64_t dstride, hipStream_t s)
+hipError_t launch_fused_vec(int K, int mode, const IterArgs<double> &a, int m, int64_t nstride, int64_t pstride,
+                            int64_t dstride, int sstride, hipStream_t s)
 {
     switch (K) {
-    case 1: return FusedDeg<1>::vec(mode, a, nstride, pstride, dstride, s);
-    case 2: return FusedDeg<2>::vec(mode, a, nstride, pstride, dstride, s);
-    case 3: return FusedDeg<3>::vec(mode, a, nstride, pstride, dstride, s);
-    case 4: return FusedDeg<4>::vec(mode, a, nstride, pstride, dstride, s);
-    case 5: return FusedDeg<5>::vec(mode, a, nstride, pstride, dstride, s);
-    case 6: return FusedDeg<6>::vec(mode, a, nstride, pstride, dstride, s);
-    case 7: return FusedDeg<7>::vec(mode, a, nstride, pstride, dstride, s);
-    case 8: return FusedDeg<8>::vec(mode, a, nstride, pstride, dstride, s);
+    case 1: return FusedDeg<1>::vec(mode, a, m, nstride, pstride, dstride, sstride, s);
+    case 2: return FusedDeg<2>::vec(mode, a, m, nstride, pstride, dstride, sstride, s);
+    case 3: return FusedDeg<3>::vec(mode, a, m, nstride, pstride, dstride, sstride, s);
+    case 4: return FusedDeg<4>::vec(mode, a, m, nstride, pstride, dstride, sstride, s);
+    case 5: return FusedDeg<5>::vec(mode, a, m, nstride, pstride, dstride, sstride, s);
+    case 6: return FusedDeg<6>::vec(mode, a, m, nstride, pstride, dstride, sstride, s);
+    case 7: return FusedDeg<7>::vec(mode, a, m, nstride, pstride, dstride, sstride, s);
+    case 8: return FusedDeg<8>::vec(mode, a, m, nstride, pstride, dstride, sstride, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -260,6 +295,15 @@ hipError_t launch_shared_nofinish(const IterArgs<double> &a, hipStream_t s)
 {
     hipLaunchKernelGGL((shared_node_kernel<double, MODE_CG>), dim3((unsigned)a.nshared_blocks), dim3(SHARED_WG), 0, s,
                        a);
+    return hipGetLastError();
+}
+
+hipError_t launch_shared_finish_multi(const IterArgs<double> &a, int m, int64_t nstride, int64_t pstride,
+                                      int64_t dstride, int64_t hstride, hipStream_t s)
+{
+    hipLaunchKernelGGL(shared_node_multi_kernel, dim3((unsigned)a.nshared_blocks, (unsigned)m), dim3(SHARED_WG), 0,
+                       s, a, nstride, pstride, dstride);
+    hipLaunchKernelGGL(finish_multi_kernel, dim3((unsigned)m), dim3(SHARED_WG), 0, s, a, dstride, hstride);
     return hipGetLastError();
 }
 

@@ -30,8 +30,9 @@ EXPORTED = [
     "mfcg_stream_bench", "mfcg_solve_ir", "mfcg_set_solver", "mfcg_set_coefficient", "mfcg_warmstart",
     "mfcg_autotune_tile", "mfcg_batch_setup", "mfcg_batch_info", "mfcg_batch_solve", "mfcg_batch_destroy",
     "mfcg_batch_last_error", "mfcg_set_sstep", "mfcg_set_preconditioner", "mfcg_solve_vector",
-    "mfcg_vmult_fp32", "mfcg_setup_batch", "mfcg_solve_batch",
+    "mfcg_vmult_fp32", "mfcg_setup_batch", "mfcg_solve_batch", "mfcg_solve_multi",
 ]
+MULTI_MAX = 64
 
 
 class MfcgError(RuntimeError):
@@ -89,6 +90,7 @@ def lib():
         L.mfcg_set_sstep.argtypes = [P, I32]
         L.mfcg_set_preconditioner.argtypes = [P, I32]
         L.mfcg_solve_vector.argtypes = [P, P, P, D, I32, ctypes.POINTER(I32), P, P, P]
+        L.mfcg_solve_multi.argtypes = [P, I32, P, P, D, I32, P, P, P, P]
         L.mfcg_set_coefficient.argtypes = [P, P, P]
         L.mfcg_warmstart.argtypes = [P, P, P, D, P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I32), P]
         L.mfcg_autotune_tile.argtypes = [ctypes.POINTER(Mesh), I32, I32, P, ctypes.POINTER(D), P]
@@ -274,6 +276,28 @@ class Problem:
             _check(code, self.h)
         h = hist[: its.value + 1].copy() if want_hist else None
         return code, its.value, h, tr.value
+
+    def solve_multi(self, bs, xs, tol=1e-10, maxit=10000, want_true_res=False, stream=None, raise_on=True):
+        """m independent right-hand sides on this operator, advanced together
+        (one fused launch per iteration over all (tile, right-hand side)
+        pairs).  xs hold the initial guesses and are overwritten.  Returns
+        (code, iters[], status[], true_rel_res[] or None)."""
+        m = len(bs)
+        if m != len(xs) or not 1 <= m <= MULTI_MAX:
+            raise ValueError(f"need 1..{MULTI_MAX} right-hand sides and as many solution vectors")
+        for i, (b, x) in enumerate(zip(bs, xs)):
+            _dev_vec(b, self.n, f"b[{i}]")
+            _dev_vec(x, self.n, f"x[{i}]")
+        bp = (ctypes.c_void_p * m)(*[b.data_ptr() for b in bs])
+        xp = (ctypes.c_void_p * m)(*[x.data_ptr() for x in xs])
+        its = (ctypes.c_int32 * m)()
+        st = (ctypes.c_int32 * m)()
+        tr = (ctypes.c_double * m)(*([float("nan")] * m))
+        code = lib().mfcg_solve_multi(self.h, m, bp, xp, float(tol), int(maxit), its, st,
+                                      tr if want_true_res else None, _stream(stream))
+        if raise_on and code not in (OK, ENOTCONV, EBREAKDOWN):
+            _check(code, self.h)
+        return code, list(its), list(st), (list(tr) if want_true_res else None)
 
     def solve_ir(self, b, x, tol=1e-10, inner_tol=1e-4, max_outer=20, max_inner=10000, keep_direction=False,
                  stream=None, raise_on=True):

@@ -173,6 +173,8 @@ def test_null_handle_calls():
     assert L.mfcg_batch_destroy(None) == mfcg.OK
     assert L.mfcg_batch_solve(None, None, None, 1e-10, 10, None, None, None) == mfcg.EINVAL
     assert L.mfcg_batch_info(None, 0, None, None) == mfcg.EINVAL
+    its, st = (ctypes.c_int32 * 2)(), (ctypes.c_int32 * 2)()
+    assert L.mfcg_solve_multi(None, 2, None, None, 1e-10, 10, its, st, None, None) == mfcg.EINVAL
 
 
 def test_batch_and_autotune_reject_bad_arguments_on_the_host():
