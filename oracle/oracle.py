@@ -19,7 +19,10 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# MFCG_ORACLE_LIBRARY selects another build of the same source (the
+# host-sanitizer build of the CPU tests)
+_DEFAULT_LIB = os.path.join(_HERE, "liboracle.so")
+LIB_PATH = os.environ.get("MFCG_ORACLE_LIBRARY") or _DEFAULT_LIB
 SOURCE = os.path.join(_HERE, "mfcg_oracle.c")
 
 MAP_AFFINE, MAP_SINE_SHEAR, MAP_SINE_PRODUCT = 0, 1, 2
@@ -32,11 +35,11 @@ _lib = None
 def build(verbose=False):
     """Compile liboracle.so with gcc + OpenMP."""
     import subprocess
-    cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11", "-o", LIB_PATH + ".tmp", SOURCE, "-lm"]
+    cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11", "-o", _DEFAULT_LIB + ".tmp", SOURCE, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
-    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    os.replace(_DEFAULT_LIB + ".tmp", _DEFAULT_LIB)
 
 
 def lib():

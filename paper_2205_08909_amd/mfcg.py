@@ -11,7 +11,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmfcg.so")
+# MFCG_LIBRARY selects another build of the same library (the host-sanitizer
+# build of the CPU tests)
+LIB_PATH = os.environ.get("MFCG_LIBRARY") or os.path.join(HERE, "libmfcg.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENOTCONV, EBREAKDOWN, ESTAGNATION = 0, -1, -2, -3, -4, -5, -6
 MAP_AFFINE, MAP_SINE_SHEAR, MAP_SINE_PRODUCT = 0, 1, 2
