@@ -9,7 +9,59 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
+
 #include "kernels.h"
+
+namespace mfcg {
+
+/* The batch kernels read each problem's arguments from device memory.
+ * Pointers loaded from memory are generic to the compiler, which then
+ * emits flat loads and stores: those count against the LDS wait counter
+ * too, so every LDS wait also waits for them, and they cannot be scalar.
+ * Read through these layout-identical views, whose pointers are declared
+ * in the global address space, the same code compiles to global and scalar
+ * memory instructions as it does for kernel arguments. */
+/* (the host pass, which compiles no kernel code, sees plain pointers) */
+#ifdef __HIP_DEVICE_COMPILE__
+#define MFCG_GLOBAL __attribute__((address_space(1)))
+#else
+#define MFCG_GLOBAL
+#endif
+struct LayoutViewG {
+    Dim1 d[3];
+    int64_t n;
+    int64_t nI, nF, nE, nV, nC;
+    int64_t offF, offE, offV, offC;
+    int64_t partF, partE, partV;
+    int64_t ntiles;
+    const MFCG_GLOBAL int64_t *ent_base;
+    const MFCG_GLOBAL EntityRef *tile_ent;
+    const MFCG_GLOBAL TileDesc *tiles;
+};
+template <typename T>
+struct IterArgsG {
+    LayoutViewG L;
+    const MFCG_GLOBAL T *G;
+    const MFCG_GLOBAL T *dinv;
+    MFCG_GLOBAL T *r, *p, *v, *x;
+    const MFCG_GLOBAL T *src;
+    MFCG_GLOBAL T *dst;
+    MFCG_GLOBAL T *part;
+    MFCG_GLOBAL T *dots;
+    MFCG_GLOBAL CGState *st;
+    MFCG_GLOBAL double *hist;
+    int32_t nshared_blocks;
+};
+static_assert(sizeof(LayoutViewG) == sizeof(LayoutView) && offsetof(LayoutViewG, tiles) == offsetof(LayoutView, tiles),
+              "global view of LayoutView");
+static_assert(sizeof(IterArgsG<double>) == sizeof(IterArgs<double>) &&
+                  offsetof(IterArgsG<double>, G) == offsetof(IterArgs<double>, G) &&
+                  offsetof(IterArgsG<double>, dots) == offsetof(IterArgs<double>, dots) &&
+                  offsetof(IterArgsG<double>, nshared_blocks) == offsetof(IterArgs<double>, nshared_blocks),
+              "global view of IterArgs");
+
+}  // namespace mfcg
 
 namespace mfcg {
 
@@ -54,8 +106,8 @@ __device__ __forceinline__ void block_reduce(T (&acc)[NV], T *red, T *out)
 /* Fixed-order sums of the seven inner products over nparts per-block
  * partial records (8 doubles each, 7 used), then the scalar update of
  * Algorithm 5 into the device state.  Called by one block. */
-template <typename T>
-__device__ void finish_iteration(const IterArgs<T> &a, int64_t nparts, T *red)
+template <typename T, typename ARGS>
+__device__ void finish_iteration(const ARGS &a, int64_t nparts, T *red)
 {
     /* fixed-order sums of the 7 inner products over all per-block partials;
      * every thread owns a fixed strided subset, loads issued 4 records at a time */

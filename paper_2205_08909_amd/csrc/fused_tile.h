@@ -247,8 +247,8 @@ enum OpVariant : int { OPV_LAPLACE = 0, OPV_LAPLACE_GLL = 1, OPV_MASS = 2, OPV_L
  * Gauss points per direction instead of k + 1 (Gauss variants only); the
  * passes on the quadrature grid then run over (k + 2)^2 lines per cell and
  * the interpolation passes map k + 1 values to k + 2 and back. */
-template <int K, typename T, int MODE, int OPV = OPV_LAPLACE, bool NTG = true, int QX = 0>
-__device__ __forceinline__ void fused_tile(const IterArgs<T> &a, const int64_t tile)
+template <int K, typename T, int MODE, int OPV = OPV_LAPLACE, bool NTG = true, int QX = 0, typename ARGS>
+__device__ __forceinline__ void fused_tile(const ARGS &a, const int64_t tile)
 {
     constexpr bool GLLQ = OPV == OPV_LAPLACE_GLL, MASS = OPV == OPV_MASS || OPV == OPV_MASS_QGEOM,
                    QGEOM = OPV == OPV_LAPLACE_QGEOM || OPV == OPV_MASS_QGEOM;
@@ -1156,7 +1156,7 @@ void fused_batch_kernel(const IterArgs<T> *__restrict__ probs, const int2 *__res
     const int2 it = items[xcd_remap(blockIdx.x, nitems)];
     const int p = __builtin_amdgcn_readfirstlane(it.x);
     const int64_t tile = __builtin_amdgcn_readfirstlane(it.y);
-    const IterArgs<T> &a = *const_view(probs + p);
+    const IterArgsG<T> &a = *(const IterArgsG<T> *)(probs + p);
     if (a.st->flag != FLAG_RUN) return;
     fused_tile<K, T, MODE_CG>(a, tile);
 }

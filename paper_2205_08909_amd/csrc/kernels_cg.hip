@@ -58,10 +58,10 @@ int fused_block_size(int K) { return fused_block_size_impl(K); }
 constexpr int SH_UNROLL = 4;
 
 /* Block blk of nblk of one problem's shared-node pass. */
-template <typename T, int MODE>
-__device__ __forceinline__ void shared_nodes(const IterArgs<T> &a, const int blk, const int nblk, T *red)
+template <typename T, int MODE, typename ARGS>
+__device__ __forceinline__ void shared_nodes(const ARGS &a, const int blk, const int nblk, T *red)
 {
-    const LayoutView &L = a.L;
+    const auto &L = a.L;
 
     T alpha = 0, beta = 0, ratio = 0;
     bool xupd = false;
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(SHARED_WG) void shared_batch_kernel(const IterArgs<
     __shared__ T red[8 * (SHARED_WG / 64)];
     const int2 it = items[blockIdx.x];
     const int p = __builtin_amdgcn_readfirstlane(it.x);
-    const IterArgs<T> &a = *const_view(probs + p);
+    const IterArgsG<T> &a = *(const IterArgsG<T> *)(probs + p);
     if (a.st->flag != FLAG_RUN) return;
     shared_nodes<T, MODE_CG>(a, __builtin_amdgcn_readfirstlane(it.y), a.nshared_blocks, red);
 }
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(SHARED_WG) void finish_batch_kernel(const IterArgs<
                                                                  const int *__restrict__ plist)
 {
     __shared__ T red[8 * (SHARED_WG / 64)];
-    const IterArgs<T> &a = *const_view(probs + __builtin_amdgcn_readfirstlane(plist[blockIdx.x]));
+    const IterArgsG<T> &a = *(const IterArgsG<T> *)(probs + __builtin_amdgcn_readfirstlane(plist[blockIdx.x]));
     if (a.st->flag != FLAG_RUN) return;
     finish_iteration<T>(a, a.L.ntiles + a.nshared_blocks, red);
 }
