@@ -1515,10 +1515,6 @@ int mfcg_autotune_tile(const mfcg_mesh *mesh, int32_t degree, int32_t iters, int
 
 }  // extern "C"
 
-/* a batch problem with at least this many tiles (two per compute unit)
- * runs its own kernel launches in each batch iteration */
-constexpr int64_t BATCH_OWN_LAUNCH_TILES = 512;
-
 struct mfcg_batch_ctx {
     std::vector<mfcg_ctx *> probs;
     std::vector<std::array<int32_t, 3>> tiles;
@@ -1526,6 +1522,8 @@ struct mfcg_batch_ctx {
     int2 *d_items = nullptr;   /* all fused-kernel items, grouped by degree */
     int2 *d_shared = nullptr;  /* shared-node items */
     int *d_active = nullptr;
+    CGState *d_states = nullptr; /* gathered solver states of all problems */
+    CGState *h_states = nullptr; /* pinned host copy */
     int64_t max_items = 0, max_shared = 0;
     int check_every = 16;
     std::string err;
@@ -1539,6 +1537,8 @@ static void batch_release(mfcg_batch_ctx *hb)
     (void)hipFree(hb->d_items);
     (void)hipFree(hb->d_shared);
     (void)hipFree(hb->d_active);
+    (void)hipFree(hb->d_states);
+    if (hb->h_states) (void)hipHostFree(hb->h_states);
 }
 
 static int batch_fail(mfcg_batch_ctx *hb, int code, const std::string &msg)
@@ -1748,6 +1748,9 @@ static int batch_setup_impl(int32_t nprob, const mfcg_mesh *meshes, const int32_
     if ((e = dalloc(&hb->d_items, hb->max_items)) != hipSuccess) return bail(e);
     if ((e = dalloc(&hb->d_shared, hb->max_shared)) != hipSuccess) return bail(e);
     if ((e = dalloc(&hb->d_active, nprob)) != hipSuccess) return bail(e);
+    if ((e = dalloc(&hb->d_states, nprob)) != hipSuccess) return bail(e);
+    if ((e = hipHostMalloc((void **)&hb->h_states, sizeof(CGState) * nprob, hipHostMallocDefault)) != hipSuccess)
+        return bail(e);
     *out = hb;
     return MFCG_OK;
 }
@@ -1809,10 +1812,12 @@ int mfcg_batch_solve(mfcg_batch hb, const double *const *b, double *const *x, do
     std::vector<IterArgs<double>> args(np);
     for (int i = 0; i < np; ++i) args[i] = iter_args(hb->probs[i]);
     BCHK(hb, hipMemcpyAsync(hb->d_args, args.data(), sizeof(IterArgs<double>) * np, hipMemcpyHostToDevice, s));
-    std::vector<CGState> st(np);
+    /* the host reads every problem's state with one gather launch and one
+     * copy into pinned memory */
+    const CGState *st = hb->h_states;
     auto poll = [&]() -> int {
-        for (int i = 0; i < np; ++i)
-            BCHK(hb, hipMemcpyAsync(&st[i], hb->probs[i]->st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+        BCHK(hb, launch_gather_states(hb->d_args, np, hb->d_states, s));
+        BCHK(hb, hipMemcpyAsync(hb->h_states, hb->d_states, sizeof(CGState) * np, hipMemcpyDeviceToHost, s));
         BCHK(hb, hipStreamSynchronize(s));
         return MFCG_OK;
     };
@@ -1829,28 +1834,20 @@ int mfcg_batch_solve(mfcg_batch hb, const double *const *b, double *const *x, do
         shared.clear();
         active.clear();
         int off[10] = {0};
-        /* problems with enough tiles to fill the device run their own
-         * launches (kernel arguments, no register spills); the others are
-         * packed into the work lists */
-        std::vector<int> own;
         for (int K = 1; K <= 8; ++K) {
             off[K] = (int)items.size();
             for (int i = 0; i < np; ++i) {
                 if (hb->probs[i]->K != K || st[i].flag != FLAG_RUN) continue;
-                if (hb->probs[i]->hl.ntiles >= BATCH_OWN_LAUNCH_TILES) {
-                    if (std::find(own.begin(), own.end(), i) == own.end()) own.push_back(i);
-                    continue;
-                }
                 for (int64_t t = 0; t < hb->probs[i]->hl.ntiles; ++t) items.push_back(make_int2(i, (int)t));
             }
             bl.nitems[K] = (int)items.size() - off[K];
         }
         for (int i = 0; i < np; ++i)
-            if (st[i].flag == FLAG_RUN && std::find(own.begin(), own.end(), i) == own.end()) {
+            if (st[i].flag == FLAG_RUN) {
                 active.push_back(i);
                 for (int q = 0; q < hb->probs[i]->nshared_blocks; ++q) shared.push_back(make_int2(i, q));
             }
-        if (active.empty() && own.empty()) break;
+        if (active.empty()) break;
         if (!items.empty())
             BCHK(hb, hipMemcpyAsync(hb->d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, s));
         if (!shared.empty())
@@ -1863,13 +1860,7 @@ int mfcg_batch_solve(mfcg_batch hb, const double *const *b, double *const *x, do
         bl.active = hb->d_active;
         bl.nactive = (int)active.size();
         const int chunk = std::min(hb->check_every, maxit - launched);
-        for (int it = 0; it < chunk; ++it) {
-            for (int i : own) {
-                BCHK(hb, launch_fused<double>(hb->probs[i]->K, MODE_CG, args[i], s));
-                BCHK(hb, launch_shared<double>(MODE_CG, args[i], s));
-            }
-            if (!active.empty()) BCHK(hb, launch_batch_iteration(bl, s));
-        }
+        for (int it = 0; it < chunk; ++it) BCHK(hb, launch_batch_iteration(bl, s));
         launched += chunk;
         rc = poll();
         if (rc) return rc;

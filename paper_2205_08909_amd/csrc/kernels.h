@@ -59,6 +59,8 @@ struct BatchLaunch {
     int nactive;
 };
 hipError_t launch_batch_iteration(const BatchLaunch &b, hipStream_t s);
+/* out[i] = *probs[i].st, i < np (one launch instead of np small copies) */
+hipError_t launch_gather_states(const IterArgs<double> *probs, int np, CGState *out, hipStream_t s);
 
 /* Maximum tile extent in x and y (cells) compiled for degree K. */
 void tile_limits(int K, int *tx, int *ty);

@@ -307,6 +307,18 @@ hipError_t launch_shared_finish_multi(const IterArgs<double> &a, int m, int64_t 
     return hipGetLastError();
 }
 
+__global__ void gather_states_kernel(const IterArgs<double> *__restrict__ probs, int np, CGState *__restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < np) out[i] = *probs[i].st;
+}
+
+hipError_t launch_gather_states(const IterArgs<double> *probs, int np, CGState *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(gather_states_kernel, dim3((unsigned)((np + 63) / 64)), dim3(64), 0, s, probs, np, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_finish_parts(const IterArgs<double> &a, int64_t nparts, hipStream_t s)
 {
     hipLaunchKernelGGL(finish_parts_kernel, dim3(1), dim3(SHARED_WG), 0, s, a, nparts);
