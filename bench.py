@@ -157,9 +157,9 @@ def warmstart_experiment(args):
     from paper_2205_08909_amd import mfcg, warmstart
     cells, k = args.ws_cells, 3
     log = lambda m: print(f"[warmstart] {m}", file=sys.stderr, flush=True)
-    P = mfcg.Problem(cells, k, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05)
+    P = mfcg.Problem(cells, k, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05, fp32=1)
     nodes = (cells * k + 1,) * 3
-    X, T, gen = warmstart.generate(P, cells, k, list(range(args.ws_train)), tol=1e-4, log=log)
+    X, T, gen = warmstart.generate(P, cells, k, list(range(args.ws_train)), tol=args.ws_data_tol, log=log)
     log(f"data: {gen}")
     net = warmstart.Net(nodes, channels=32, seed=0)
     torch.cuda.synchronize()
@@ -179,8 +179,11 @@ def warmstart_experiment(args):
         warmstart.predict_x0(net, P, cells, k, b, diag, logc, ws)
     torch.cuda.synchronize()
     infer_ms = (time.perf_counter() - t0) * 100
-    rows = warmstart.evaluate(net, P, cells, k, list(range(10000, 10000 + args.ws_eval)), tol=1e-10, log=log)
+    coarse = warmstart.CoarseLevel(cells, mfcg.MAP_SINE_SHEAR, 0.05, tol=1e-2)
+    rows = warmstart.evaluate(net, P, cells, k, list(range(10000, 10000 + args.ws_eval)), tol=1e-10, log=log,
+                              coarse=coarse, ir=True)
     summ = warmstart.summarize(rows)
+    coarse.close()
     out = {"experiment": "learned warm start", "workload": f"Q3, {cells}^3 cells curved (sine shear 0.05), "
            f"{P.n} DoFs, a = exp(GRF, l ~ U[0.05,0.2], var 1), f = 8 Gaussian bumps",
            "train_samples": args.ws_train, "epochs": args.ws_epochs, "params": net.nparam,
@@ -382,6 +385,7 @@ def main():
     ap.add_argument("--ws-train", type=int, default=2000)
     ap.add_argument("--ws-eval", type=int, default=200)
     ap.add_argument("--ws-epochs", type=int, default=10)
+    ap.add_argument("--ws-data-tol", type=float, default=1e-8, help="tolerance of the training solutions")
     ap.add_argument("--batch", action="store_true", help="batched-solve experiment instead of the main line")
     ap.add_argument("--batch-n", type=int, default=32)
     ap.add_argument("--batch-nmin", type=int, default=16)

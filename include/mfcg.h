@@ -178,6 +178,42 @@ int mfcg_set_coefficient(mfcg_handle h, const double *cell_coeff, void *hip_stre
 int mfcg_warmstart(mfcg_handle h, const double *b, const double *u, double max_rel_res, double *x0, double *scale,
                    double *rel_res, int32_t *used, void *hip_stream);
 
+/* The same guarantee over a span (Sec. 3, CG minimises the A-norm of the
+ * error): x0 = sum_i c_i u_i', the u_i' being the m vectors u_i with their
+ * Dirichlet entries set to 0, with the coefficients that minimise
+ * ||x - x0||_A over their span (the Galerkin system G c = g, G_ij =
+ * u_i'^T A u_j', g_i = u_i'^T b, solved by Cholesky in the given order; a
+ * vector whose pivot is not above 1e-12 u_i'^T A u_i' -- zero, or in the
+ * span of the earlier ones -- gets c_i = 0).  So x0 is never worse in the
+ * A-norm than the best Galerkin-scaled single u_i, nor than x0 = 0.  With
+ * m = 1 it is mfcg_warmstart.
+ *   m        1 <= m <= MFCG_SPAN_MAX
+ *   u        host array of m device vectors (lexicographic, length n)
+ *   coef     host out or NULL: m coefficients (all 0 when x0 = 0)
+ *   other arguments and the fall-back to x0 = 0 as for mfcg_warmstart.
+ * Allocates 2 m n doubles of work vectors the first time m grows (kept by
+ * the handle).  Must not be called between mfcg_cg_begin and mfcg_cg_end.
+ * Synchronises hip_stream.  Errors: EINVAL (null pointers, m out of range,
+ * max_rel_res NaN), ENOMEM, EHIP. */
+#define MFCG_SPAN_MAX 8
+int mfcg_warmstart_span(mfcg_handle h, const double *b, int32_t m, const double *const *u, double max_rel_res,
+                        double *x0, double *coef, double *rel_res, int32_t *used, void *hip_stream);
+
+/* Interpolation between two handles on the same cells (Sec. 2: the
+ * continuous Q_k space with its nodes at the Gauss-Lobatto points of every
+ * cell): dst = the Q_{k_from} finite-element function with nodal values
+ * src, evaluated at the nodes of the Q_{k_to} space of handle `to`.  For
+ * k_from <= k_to the spaces are nested and this is their exact embedding
+ * (e.g. a Q1 solution as a Q3 vector, the coarse level of a two-level
+ * initial guess).  The evaluation is per cell in reference coordinates, so
+ * it does not depend on the mesh map; nodes on cell faces take the value
+ * both sides share.
+ *   src  device, lexicographic nodal values of `from` (its n)
+ *   dst  device out, lexicographic, the n of `to`; may not alias src
+ * Synchronises hip_stream.  Errors: EINVAL (null pointers, different cell
+ * counts, src == dst), EHIP. */
+int mfcg_interpolate(mfcg_handle from, const double *src, mfcg_handle to, double *dst, void *hip_stream);
+
 /* Number of nodes (vector length), Dirichlet nodes included. */
 int mfcg_n_dofs(mfcg_handle h, int64_t *n);
 

@@ -266,5 +266,33 @@ def pcg(A, diag, b, x0=None, tol=1e-10, maxit=10000):
     return x, it.value, hist[: it.value + 1].copy(), rc
 
 
+def interpolate(cells, k_from, k_to, src):
+    """The Q_{k_from} finite-element function with lexicographic nodal
+    values src (x fastest), evaluated at the nodes of the Q_{k_to} space on
+    the same cells (Sec. 2: continuous Q_k, nodes at the Gauss-Lobatto
+    points of every cell).  The function is a tensor product of 1D
+    piecewise Lagrange interpolants, so its values at the destination
+    nodes are (P_z (x) P_y (x) P_x) src with the 1D matrices P_d[g, j] = the
+    Lagrange polynomial of source node j of the cell holding destination
+    node g (the last cell for the right end), at g's reference position."""
+    cells = tuple(int(c) for c in cells)
+    xf, xt = gll(k_from), gll(k_to)
+    P = []
+    for N in cells:
+        M = np.zeros((N * k_to + 1, N * k_from + 1))
+        for g in range(N * k_to + 1):
+            e = min(g // k_to, N - 1)
+            t = xt[g - k_to * e]
+            for j in range(k_from + 1):
+                M[g, k_from * e + j] = lagrange(xf, j, t)
+        P.append(M)
+    U = np.asarray(src, dtype=np.float64).reshape(cells[2] * k_from + 1, cells[1] * k_from + 1,
+                                                  cells[0] * k_from + 1)
+    U = np.einsum("zyx,ax->zya", U, P[0])
+    U = np.einsum("zya,by->zba", U, P[1])
+    U = np.einsum("zba,cz->cba", U, P[2])
+    return U.reshape(-1).copy()
+
+
 def max_threads():
     return int(lib().oracle_max_threads())

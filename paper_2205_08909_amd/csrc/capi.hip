@@ -66,6 +66,9 @@ struct mfcg_ctx {
     KrylovState *ks = nullptr;
     /* three-component work vectors of the vector Laplacian (component-blocked) */
     double *r3 = nullptr, *p3 = nullptr, *v3 = nullptr, *x3 = nullptr, *dots3 = nullptr, *part3 = nullptr;
+    /* work vectors of mfcg_warmstart_span: span_cap vectors each */
+    double *spanU = nullptr, *spanAU = nullptr;
+    int span_cap = 0;
     /* independent right-hand sides (mfcg_solve_multi): m blocks of each */
     double *rM = nullptr, *pM = nullptr, *vM = nullptr, *xM = nullptr, *dotsM = nullptr, *partM = nullptr;
     double *histM = nullptr;
@@ -125,7 +128,7 @@ static void release(mfcg_ctx *h)
                     h->p32,        h->v32,        h->x32,     h->part32,  h->dots32, h->st32,  h->hist32,
                     h->kvec,       h->kpart,      h->ks,      h->r3,      h->p3,    h->v3,     h->x3,
                     h->dots3,      h->part3,      h->Xq,      h->rM,      h->pM,    h->vM,     h->xM,
-                    h->dotsM,      h->partM,      h->histM,   h->stM};
+                    h->dotsM,      h->partM,      h->histM,   h->stM,     h->spanU, h->spanAU};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (auto &e : h->ev_pool) {
@@ -517,6 +520,130 @@ int mfcg_warmstart(mfcg_handle h, const double *b, const double *u, double max_r
     }
     HIPCHK(h, hipStreamSynchronize(s));
     if (scale) *scale = ok ? sc : 0.0;
+    if (rel_res) *rel_res = ok ? rel : 1.0;
+    if (used) *used = ok ? 1 : 0;
+    return MFCG_OK;
+}
+
+int mfcg_interpolate(mfcg_handle from, const double *src, mfcg_handle to, double *dst, void *hip_stream)
+{
+    if (!from || !to || !src || !dst) return fail(to ? to : from, MFCG_EINVAL, "null argument");
+    for (int d = 0; d < 3; ++d)
+        if (from->mesh.cells[d] != to->mesh.cells[d])
+            return fail(to, MFCG_EINVAL, "interpolation needs the same cells on both handles");
+    if (src == dst) return fail(to, MFCG_EINVAL, "src and dst must differ");
+    InterpArgs ia{};
+    for (int d = 0; d < 3; ++d) ia.ncells[d] = to->mesh.cells[d];
+    ia.kf = from->K;
+    ia.kt = to->K;
+    interp_weights(ia.kf, ia.kt, ia.W);
+    ia.src = src;
+    ia.dst = dst;
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIPCHK(to, launch_interpolate(ia, s));
+    HIPCHK(to, hipStreamSynchronize(s));
+    return MFCG_OK;
+}
+
+int mfcg_warmstart_span(mfcg_handle h, const double *b, int32_t m, const double *const *u, double max_rel_res,
+                        double *x0, double *coef, double *rel_res, int32_t *used, void *hip_stream)
+{
+    if (!h || !b || !u || !x0) return fail(h, MFCG_EINVAL, "null argument");
+    if (m < 1 || m > MFCG_SPAN_MAX) return fail(h, MFCG_EINVAL, "m must be in 1..MFCG_SPAN_MAX");
+    for (int i = 0; i < m; ++i)
+        if (!u[i]) return fail(h, MFCG_EINVAL, "null vector u[" + std::to_string(i) + "]");
+    if (std::isnan(max_rel_res)) return fail(h, MFCG_EINVAL, "max_rel_res is NaN");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int64_t n = h->hl.n;
+    if (m > h->span_cap) {
+        HIPCHK(h, hipStreamSynchronize(s));
+        if (h->spanU) HIPCHK(h, hipFree(h->spanU));
+        if (h->spanAU) HIPCHK(h, hipFree(h->spanAU));
+        h->spanU = h->spanAU = nullptr;
+        h->span_cap = 0;
+        HIPCHK(h, dalloc(&h->spanU, (size_t)(m * n)));
+        HIPCHK(h, dalloc(&h->spanAU, (size_t)(m * n)));
+        h->span_cap = m;
+    }
+    /* internal order: U_i = u_i with the Dirichlet block zeroed, AU_i = A U_i, r = b */
+    for (int i = 0; i < m; ++i) {
+        double *Ui = h->spanU + i * n;
+        HIPCHK(h, launch_lex_to_int<double>(h->lv, u[i], Ui, s));
+        if (h->lv.nC > 0) HIPCHK(h, hipMemsetAsync(Ui + h->lv.offC, 0, sizeof(double) * h->lv.nC, s));
+        int rc = vmult_internal(h, Ui, h->spanAU + i * n, s);
+        if (rc) return rc;
+    }
+    HIPCHK(h, launch_lex_to_int<double>(h->lv, b, h->r, s));
+    /* Gram system G c = g, G_ij = U_i^T A U_j, g_i = U_i^T b (fixed-order sums) */
+    double G[MFCG_SPAN_MAX][MFCG_SPAN_MAX], g[MFCG_SPAN_MAX], bb = 0.0;
+    int rc;
+    for (int i = 0; i < m; ++i) {
+        for (int j = i; j < m; ++j) {
+            if ((rc = host_pair_sum(h, 0, h->spanU + i * n, h->spanAU + j * n, 0.0, &G[i][j], s))) return rc;
+            G[j][i] = G[i][j];
+        }
+        if ((rc = host_pair_sum(h, 0, h->spanU + i * n, h->r, 0.0, &g[i], s))) return rc;
+    }
+    if ((rc = host_pair_sum(h, 0, h->r, h->r, 0.0, &bb, s))) return rc;
+    /* Cholesky factorisation in order; a direction whose pivot is not above
+     * 1e-12 of its own A-norm square (zero, or in the span of the earlier
+     * ones) is dropped (coefficient 0) */
+    double L[MFCG_SPAN_MAX][MFCG_SPAN_MAX] = {}, c[MFCG_SPAN_MAX] = {}, y[MFCG_SPAN_MAX] = {};
+    bool keep[MFCG_SPAN_MAX] = {};
+    bool ok = std::isfinite(bb);
+    for (int i = 0; i < m && ok; ++i) {
+        double d = G[i][i];
+        for (int k = 0; k < i; ++k)
+            if (keep[k]) d -= L[i][k] * L[i][k];
+        keep[i] = std::isfinite(d) && std::isfinite(G[i][i]) && G[i][i] > 0.0 && d > 1e-12 * G[i][i];
+        if (!keep[i]) continue;
+        L[i][i] = std::sqrt(d);
+        for (int j = i + 1; j < m; ++j) {
+            double t = G[j][i];
+            for (int k = 0; k < i; ++k)
+                if (keep[k]) t -= L[j][k] * L[i][k];
+            L[j][i] = t / L[i][i];
+        }
+    }
+    int nkeep = 0;
+    for (int i = 0; i < m; ++i) nkeep += keep[i];
+    ok = ok && nkeep > 0;
+    if (ok) {
+        for (int i = 0; i < m; ++i) { /* L y = g */
+            if (!keep[i]) continue;
+            double t = g[i];
+            for (int k = 0; k < i; ++k)
+                if (keep[k]) t -= L[i][k] * y[k];
+            y[i] = t / L[i][i];
+        }
+        for (int i = m - 1; i >= 0; --i) { /* L^T c = y */
+            if (!keep[i]) continue;
+            double t = y[i];
+            for (int k = i + 1; k < m; ++k)
+                if (keep[k]) t -= L[k][i] * c[k];
+            c[i] = t / L[i][i];
+        }
+        for (int i = 0; i < m; ++i) ok = ok && std::isfinite(c[i]);
+    }
+    double rel = 1.0;
+    if (ok) {
+        LinComb lc{};
+        for (int i = 0; i < m; ++i) lc.c[i] = c[i];
+        HIPCHK(h, launch_lincomb(n, m, h->spanU, lc, h->vout, s));  /* x0 */
+        HIPCHK(h, launch_lincomb(n, m, h->spanAU, lc, h->v, s));    /* A x0 */
+        double rr = 0.0;
+        if ((rc = host_pair_sum(h, 1, h->r, h->v, 1.0, &rr, s))) return rc;
+        rel = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+        ok = std::isfinite(rr) && !(rel >= max_rel_res);
+    }
+    if (ok) {
+        HIPCHK(h, launch_int_to_lex<double>(h->lv, h->vout, x0, s));
+    } else {
+        HIPCHK(h, hipMemsetAsync(x0, 0, sizeof(double) * n, s));
+    }
+    HIPCHK(h, hipStreamSynchronize(s));
+    if (coef)
+        for (int i = 0; i < m; ++i) coef[i] = ok ? c[i] : 0.0;
     if (rel_res) *rel_res = ok ? rel : 1.0;
     if (used) *used = ok ? 1 : 0;
     return MFCG_OK;

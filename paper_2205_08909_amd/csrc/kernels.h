@@ -129,6 +129,24 @@ hipError_t launch_pair_sum(int64_t n, int mode, const double *a, const double *b
                            hipStream_t s);
 /* out = sc a */
 hipError_t launch_scale(int64_t n, const double *a, double sc, double *out, hipStream_t s);
+/* dst (Q_kt nodal values, lexicographic) = the Q_kf function src
+ * (lexicographic) at the Q_kt nodes of the same cells; W[i (kf+1) + j] =
+ * the j-th degree-kf Lagrange basis function on the GLL nodes at the i-th
+ * degree-kt GLL node */
+struct InterpArgs {
+    int32_t ncells[3];
+    int32_t kf, kt;
+    double W[MAXN * MAXN];
+    const double *src;
+    double *dst;
+};
+hipError_t launch_interpolate(const InterpArgs &a, hipStream_t s);
+/* out = sum_{i < m} c_i U_i, U_i = U + i n */
+constexpr int LINCOMB_MAX = 8;
+struct LinComb {
+    double c[LINCOMB_MAX];
+};
+hipError_t launch_lincomb(int64_t n, int m, const double *U, const LinComb &c, double *out, hipStream_t s);
 /* iterative refinement: r = b - v; x += d */
 hipError_t launch_residual(int64_t n, const double *b, const double *v, double *r, hipStream_t s);
 hipError_t launch_add_correction(int64_t n, double *x, const float *d, hipStream_t s);

@@ -618,6 +618,72 @@ hipError_t launch_scale(int64_t n, const double *a, double sc, double *out, hipS
     return hipGetLastError();
 }
 
+/* Interpolation of a continuous Q_kf function (lexicographic nodal values
+ * on the GLL nodes of every cell) at the nodes of the Q_kt space on the
+ * same cells: each destination node lies in cell e = min(g / kt, N - 1)
+ * of every axis at local index i = g - kt e, and its value is the tensor
+ * product of the 1D weights W[i][j] = L_j(xi_i) over the (kf + 1)^3 source
+ * nodes of that cell.  One thread per destination node. */
+__global__ __launch_bounds__(SETUP_WG) void interpolate_kernel(const InterpArgs a)
+{
+    const int64_t nx = (int64_t)a.ncells[0] * a.kt + 1, ny = (int64_t)a.ncells[1] * a.kt + 1;
+    const int64_t nz = (int64_t)a.ncells[2] * a.kt + 1;
+    const int64_t g = (int64_t)blockIdx.x * SETUP_WG + threadIdx.x;
+    if (g >= nx * ny * nz) return;
+    const int64_t gz = g / (nx * ny), rem = g - gz * nx * ny, gy = rem / nx, gx = rem - gy * nx;
+    const int64_t gg[3] = {gx, gy, gz};
+    int64_t base[3];
+    int li[3];
+    for (int d = 0; d < 3; ++d) {
+        const int64_t e = min(gg[d] / a.kt, (int64_t)a.ncells[d] - 1);
+        li[d] = (int)(gg[d] - e * a.kt);
+        base[d] = e * a.kf;
+    }
+    const int64_t sx = (int64_t)a.ncells[0] * a.kf + 1, sy = (int64_t)a.ncells[1] * a.kf + 1;
+    const int nf = a.kf + 1;
+    double acc = 0.0;
+    for (int jz = 0; jz < nf; ++jz) {
+        const double wz = a.W[li[2] * nf + jz];
+        if (wz == 0.0) continue;
+        for (int jy = 0; jy < nf; ++jy) {
+            const double wyz = wz * a.W[li[1] * nf + jy];
+            if (wyz == 0.0) continue;
+            const double *row = a.src + ((base[2] + jz) * sy + base[1] + jy) * sx + base[0];
+            double t = 0.0;
+            for (int jx = 0; jx < nf; ++jx) t += a.W[li[0] * nf + jx] * row[jx];
+            acc += wyz * t;
+        }
+    }
+    a.dst[g] = acc;
+}
+
+hipError_t launch_interpolate(const InterpArgs &a, hipStream_t s)
+{
+    const int64_t n = ((int64_t)a.ncells[0] * a.kt + 1) * ((int64_t)a.ncells[1] * a.kt + 1) *
+                      ((int64_t)a.ncells[2] * a.kt + 1);
+    hipLaunchKernelGGL(interpolate_kernel, dim3((unsigned)((n + SETUP_WG - 1) / SETUP_WG)), dim3(SETUP_WG), 0, s, a);
+    return hipGetLastError();
+}
+
+/* out = sum_i c_i U_i over m <= LINCOMB_MAX vectors U_i = U + i n */
+__global__ __launch_bounds__(SETUP_WG) void lincomb_kernel(int64_t n, int m, const double *__restrict__ U,
+                                                           const LinComb c, double *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * SETUP_WG + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int j = 0; j < m; ++j) acc += c.c[j] * U[j * n + i];
+    out[i] = acc;
+}
+
+hipError_t launch_lincomb(int64_t n, int m, const double *U, const LinComb &c, double *out, hipStream_t s)
+{
+    if (m < 1 || m > LINCOMB_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(lincomb_kernel, dim3((unsigned)((n + SETUP_WG - 1) / SETUP_WG)), dim3(SETUP_WG), 0, s, n, m, U,
+                       c, out);
+    return hipGetLastError();
+}
+
 /* Algorithm 5 exit: x_{k+1} = x_k + alpha_k p_k (k odd) or
  * x_{k-1} + alpha_k p_k + alpha_{k-1}/beta_{k-1} (p_k - D^{-1} r_k) (k even);
  * x_k on breakdown (xa = 0). */

@@ -93,6 +93,15 @@ static long double lagrange_value(int n, const long double *x, int i, long doubl
     return v;
 }
 
+void interp_weights(int kf, int kt, double *W)
+{
+    long double xf[MAXN], xt[MAXN];
+    lobatto_points(kf, xf);
+    lobatto_points(kt, xt);
+    for (int i = 0; i <= kt; ++i)
+        for (int j = 0; j <= kf; ++j) W[i * (kf + 1) + j] = (double)lagrange_value(kf + 1, xf, j, xt[i]);
+}
+
 int build_tables(int K, Tables<double> &tab, bool gll_quadrature, int nq)
 {
     if (nq == 0) nq = K + 1;

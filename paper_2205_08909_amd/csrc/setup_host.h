@@ -29,6 +29,9 @@ struct HostLayout {
  * (S = identity).  S and Sd are nq x (k+1), D is nq x nq, row-major. */
 int build_tables(int K, Tables<double> &tab, bool gll_quadrature = false, int nq = 0);
 void default_tile(int K, int tile[3]);
+/* W[i (kf+1) + j] = the j-th degree-kf Lagrange polynomial on the GLL nodes
+ * of [0, 1], evaluated at the i-th degree-kt GLL node (kf, kt in 1..8) */
+void interp_weights(int kf, int kt, double *W);
 /* nq: quadrature points per direction of the geometry tensor (0: k + 1) */
 int build_layout(const int ncells[3], int K, const int tile[3], int bc, HostLayout &L, int nq = 0);
 void dim_locate_host(const Dim1 &d, int64_t g, int64_t &e, int64_t &l, int64_t &len);

@@ -32,9 +32,11 @@ EXPORTED = [
     "mfcg_stream_bench", "mfcg_solve_ir", "mfcg_set_solver", "mfcg_set_coefficient", "mfcg_warmstart",
     "mfcg_autotune_tile", "mfcg_batch_setup", "mfcg_batch_info", "mfcg_batch_solve", "mfcg_batch_destroy",
     "mfcg_batch_last_error", "mfcg_set_sstep", "mfcg_set_preconditioner", "mfcg_solve_vector",
-    "mfcg_vmult_fp32", "mfcg_setup_batch", "mfcg_solve_batch", "mfcg_solve_multi",
+    "mfcg_vmult_fp32", "mfcg_setup_batch", "mfcg_solve_batch", "mfcg_solve_multi", "mfcg_warmstart_span",
+    "mfcg_interpolate",
 ]
 MULTI_MAX = 64
+SPAN_MAX = 8
 
 
 class MfcgError(RuntimeError):
@@ -93,6 +95,8 @@ def lib():
         L.mfcg_set_preconditioner.argtypes = [P, I32]
         L.mfcg_solve_vector.argtypes = [P, P, P, D, I32, ctypes.POINTER(I32), P, P, P]
         L.mfcg_solve_multi.argtypes = [P, I32, P, P, D, I32, P, P, P, P]
+        L.mfcg_warmstart_span.argtypes = [P, P, I32, P, D, P, P, P, P, P]
+        L.mfcg_interpolate.argtypes = [P, P, P, P, P]
         L.mfcg_set_coefficient.argtypes = [P, P, P]
         L.mfcg_warmstart.argtypes = [P, P, P, D, P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I32), P]
         L.mfcg_autotune_tile.argtypes = [ctypes.POINTER(Mesh), I32, I32, P, ctypes.POINTER(D), P]
@@ -352,6 +356,32 @@ class Problem:
         _check(lib().mfcg_warmstart(self.h, _ptr(b), _ptr(u), float(max_rel_res), _ptr(x0), ctypes.byref(sc),
                                     ctypes.byref(rr), ctypes.byref(used), _stream(stream)), self.h)
         return x0, sc.value, rr.value, bool(used.value)
+
+    def warmstart_span(self, b, us, max_rel_res=float("inf"), x0=None, stream=None):
+        """x0 in span(us) with the A-norm optimal coefficients (Dirichlet
+        entries zeroed first).  Returns (x0, coef, rel_res, used)."""
+        m = len(us)
+        if not 1 <= m <= SPAN_MAX:
+            raise ValueError(f"need 1..{SPAN_MAX} vectors")
+        _dev_vec(b, self.n, "b")
+        for i, u in enumerate(us):
+            _dev_vec(u, self.n, f"u[{i}]")
+        x0 = self.empty() if x0 is None else _dev_vec(x0, self.n, "x0")
+        up = (ctypes.c_void_p * m)(*[u.data_ptr() for u in us])
+        coef = (ctypes.c_double * m)()
+        rr = ctypes.c_double()
+        used = ctypes.c_int32()
+        _check(lib().mfcg_warmstart_span(self.h, _ptr(b), m, up, float(max_rel_res), _ptr(x0), coef, ctypes.byref(rr),
+                                         ctypes.byref(used), _stream(stream)), self.h)
+        return x0, list(coef), rr.value, bool(used.value)
+
+    def interpolate_from(self, other, src, dst=None, stream=None):
+        """dst = the finite-element function of handle `other` (nodal values
+        src) at this handle's nodes (same cells)."""
+        _dev_vec(src, other.n, "src")
+        dst = self.empty() if dst is None else _dev_vec(dst, self.n, "dst")
+        _check(lib().mfcg_interpolate(other.h, _ptr(src), self.h, _ptr(dst), _stream(stream)), self.h)
+        return dst
 
     def set_solver(self, solver):
         """SOLVER_FUSED (default), SOLVER_ALG5_SPLIT, SOLVER_PCG_BASIC,

@@ -273,54 +273,152 @@ def predict_x0(net, P, cells, k, b, diag, logc, ws, X1=None, u=None, max_rel_res
     return P.warmstart(b, u, max_rel_res)
 
 
-def evaluate(net, P, cells, k, seeds, tol=1e-10, maxit=50000, max_rel_res=float("inf"), log=None):
+class CoarseLevel:
+    """The same problem discretised with Q1 elements on the same cells,
+    solved to a loose tolerance and interpolated to the fine nodes
+    (mfcg_interpolate: the Q1 space is contained in the Q_k one).  It
+    carries the smooth, global part of the solution, which the network
+    cannot: its receptive field covers about a quarter of the domain width,
+    while the solution of an elliptic problem depends on the data
+    everywhere."""
+
+    def __init__(self, cells, map_kind, amplitude, tol=1e-2, maxit=20000):
+        self.P = mfcg.Problem(cells, 1, map_kind=map_kind, amplitude=amplitude)
+        self.tol, self.maxit = tol, maxit
+
+    def guess(self, Pf, smp, out=None):
+        import torch
+        self.P.set_coefficient(smp["coeff"])
+        bc = self.P.rhs(mfcg.RHS_BUMPS, smp["bumps"])
+        uc = torch.zeros_like(bc)
+        self.P.solve(bc, uc, tol=self.tol, maxit=self.maxit, want_hist=False, raise_on=False)
+        return Pf.interpolate_from(self.P, uc, out)
+
+    def close(self):
+        self.P.close()
+
+
+def evaluate(net, P, cells, k, seeds, tol=1e-10, maxit=50000, max_rel_res=float("inf"), log=None, coarse=None,
+             ir=False):
     """Plain CG from x0 = 0 against the learned x0 (features, inference and
-    scaling included in its time) on each seed."""
+    scaling included in its time) on each seed.  With a CoarseLevel also
+    the coarse-level guess alone and the A-norm optimal combination of the
+    coarse-level and learned guesses (mfcg_warmstart_span), each timed with
+    everything it computes; with ir=True also FP32-inner iterative
+    refinement (mfcg_solve_ir, residual replacement) from x0 = 0 and from the
+    best of those guesses."""
     import torch
     ws = Workspace()
     rows = []
     n = P.n
     X1 = torch.empty(3 * n, dtype=torch.bfloat16, device="cuda")
     u = torch.empty(n, dtype=torch.float64, device="cuda")
+    Uc = torch.empty(n, dtype=torch.float64, device="cuda")
+
+    def sync():
+        torch.cuda.synchronize()
+        return time.perf_counter()
+
     for seed in seeds:
-        b, diag, logc, _ = sample_problem(P, cells, k, seed, ws)
+        b, diag, logc, smp = sample_problem(P, cells, k, seed, ws)
         x = torch.zeros_like(b)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        t0 = sync()
         c0, it0, _, _ = P.solve(b, x, tol=tol, maxit=maxit, want_hist=False)
-        torch.cuda.synchronize()
-        t_zero = time.perf_counter() - t0
-        t0 = time.perf_counter()
+        t_zero = sync() - t0
+        t0 = sync()
         x0, sc, rel0, used = predict_x0(net, P, cells, k, b, diag, logc, ws, X1, u, max_rel_res)
         x0_copy = x0.clone()
         c1, it1, _, tr = P.solve(b, x0, tol=tol, maxit=maxit, want_hist=False, want_true_res=True)
-        torch.cuda.synchronize()
-        t_warm = time.perf_counter() - t0
+        t_warm = sync() - t0
         # energy-norm error of the guess relative to that of x0 = 0 (x: the converged solution)
-        e = x - x0_copy
-        ea = torch.dot(e, P.vmult(P.empty(), e)).item()
         xa = torch.dot(x, P.vmult(P.empty(), x)).item()
-        rows.append({"seed": int(seed), "iters_zero": it0, "iters_warm": it1, "s_zero": t_zero, "s_warm": t_warm,
-                     "used": bool(used), "scale": sc, "rel_res0": rel0, "status": (int(c0), int(c1)),
-                     "true_rel_res": tr, "energy_err0": float(np.sqrt(max(ea, 0.0) / xa))})
+
+        def enorm(v):
+            e = x - v
+            return float(np.sqrt(max(torch.dot(e, P.vmult(P.empty(), e)).item(), 0.0) / xa))
+
+        row = {"seed": int(seed), "iters_zero": it0, "iters_warm": it1, "s_zero": t_zero, "s_warm": t_warm,
+               "used": bool(used), "scale": sc, "rel_res0": rel0, "status": (int(c0), int(c1)),
+               "true_rel_res": tr, "energy_err0": enorm(x0_copy)}
+        best = x0_copy
+        if coarse is not None:
+            t0 = sync()
+            coarse.guess(P, smp, Uc)
+            xc, _, _, _ = P.warmstart(b, Uc, max_rel_res)
+            xc_copy = xc.clone()
+            _, itc, _, _ = P.solve(b, xc, tol=tol, maxit=maxit, want_hist=False)
+            t_c = sync() - t0
+            t0 = sync()
+            coarse.guess(P, smp, Uc)
+            nn.features((cells, cells, cells), k, logc, b, diag, ws.d, X1)
+            nn.convert(net.forward(X1, 1), u)
+            xs, coef, _, _ = P.warmstart_span(b, [Uc, u], max_rel_res)
+            xs_copy = xs.clone()
+            _, its_, _, _ = P.solve(b, xs, tol=tol, maxit=maxit, want_hist=False)
+            t_s = sync() - t0
+            row.update({"iters_coarse": itc, "s_coarse": t_c, "energy_err0_coarse": enorm(xc_copy),
+                        "iters_span": its_, "s_span": t_s, "energy_err0_span": enorm(xs_copy),
+                        "span_coef": coef})
+            best = xs_copy
+        if ir:
+            # FP32-inner refinement (residual replacement) from x0 = 0 and from the
+            # best guess, the guess recomputed inside the timed region
+            for name in ("zero", "best"):
+                t0 = sync()
+                if name == "zero":
+                    xi = torch.zeros_like(b)
+                elif coarse is not None:
+                    coarse.guess(P, smp, Uc)
+                    nn.features((cells, cells, cells), k, logc, b, diag, ws.d, X1)
+                    nn.convert(net.forward(X1, 1), u)
+                    xi, _, _, _ = P.warmstart_span(b, [Uc, u], max_rel_res)
+                else:
+                    xi, _, _, _ = predict_x0(net, P, cells, k, b, diag, logc, ws, X1, u, max_rel_res)
+                ci, outer, inner, _, tri = P.solve_ir(b, xi, tol=tol, inner_tol=1e-1, keep_direction=True,
+                                                      max_outer=100)
+                row[f"ir_{name}"] = {"s": sync() - t0, "outer": outer, "inner_iters": inner, "status": int(ci),
+                                     "true_rel_res": tri}
+        rows.append(row)
         if log:
-            log(f"seed {seed}: {it0} -> {it1} iterations, {t_zero * 1e3:.1f} -> {t_warm * 1e3:.1f} ms, "
-                f"||b - A x0|| / ||b|| = {rel0:.3f}, ||e0||_A / ||x||_A = {rows[-1]['energy_err0']:.3f}, used {used}")
+            msg = f"seed {seed}: {it0} -> {it1} iterations (learned)"
+            if coarse is not None:
+                msg += f", {row['iters_coarse']} (coarse), {row['iters_span']} (coarse + learned)"
+            log(msg)
     return rows
 
 
 def summarize(rows):
     i0 = np.array([r["iters_zero"] for r in rows], float)
-    i1 = np.array([r["iters_warm"] for r in rows], float)
     t0 = np.array([r["s_zero"] for r in rows])
-    t1 = np.array([r["s_warm"] for r in rows])
-    return {"n": len(rows),
-            "iters_zero": {"mean": float(i0.mean()), "median": float(np.median(i0)), "worst": float(i0.max())},
-            "iters_warm": {"mean": float(i1.mean()), "median": float(np.median(i1)), "worst": float(i1.max())},
-            "iter_ratio_mean": float((i1 / i0).mean()),
-            "ms_zero": {"mean": float(t0.mean() * 1e3), "median": float(np.median(t0) * 1e3)},
-            "ms_warm": {"mean": float(t1.mean() * 1e3), "median": float(np.median(t1) * 1e3)},
-            "worse_than_zero": int((i1 > i0).sum()),
-            "energy_err0_mean": float(np.mean([r["energy_err0"] for r in rows])),
-            "rel_res0_mean": float(np.mean([r["rel_res0"] for r in rows])),
-            "fallbacks": int(sum(1 for r in rows if not r["used"]))}
+
+    def stats(key_it, key_s):
+        it = np.array([r[key_it] for r in rows], float)
+        t = np.array([r[key_s] for r in rows])
+        return {"iters": {"mean": float(it.mean()), "median": float(np.median(it)), "worst": float(it.max())},
+                "ms": {"mean": float(t.mean() * 1e3), "median": float(np.median(t) * 1e3)},
+                "iter_ratio_mean": float((it / i0).mean()), "time_ratio_mean": float(t.mean() / t0.mean()),
+                "worse_than_zero": int((it > i0).sum())}
+
+    out = {"n": len(rows),
+           "zero": {"iters": {"mean": float(i0.mean()), "median": float(np.median(i0)), "worst": float(i0.max())},
+                    "ms": {"mean": float(t0.mean() * 1e3), "median": float(np.median(t0) * 1e3)}},
+           "learned": stats("iters_warm", "s_warm"),
+           "energy_err0_mean": float(np.mean([r["energy_err0"] for r in rows])),
+           "rel_res0_mean": float(np.mean([r["rel_res0"] for r in rows])),
+           "fallbacks": int(sum(1 for r in rows if not r["used"]))}
+    if "iters_coarse" in rows[0]:
+        out["coarse"] = stats("iters_coarse", "s_coarse")
+        out["coarse"]["energy_err0_mean"] = float(np.mean([r["energy_err0_coarse"] for r in rows]))
+        out["coarse_plus_learned"] = stats("iters_span", "s_span")
+        out["coarse_plus_learned"]["energy_err0_mean"] = float(np.mean([r["energy_err0_span"] for r in rows]))
+        out["coarse_plus_learned"]["learned_coef_mean"] = float(np.mean([r["span_coef"][1] for r in rows]))
+    if "ir_zero" in rows[0]:
+        tz = np.array([r["ir_zero"]["s"] for r in rows])
+        tb = np.array([r["ir_best"]["s"] for r in rows])
+        out["ir"] = {"ms_from_zero": float(tz.mean() * 1e3), "ms_from_best_guess": float(tb.mean() * 1e3),
+                     "inner_iters_from_zero": float(np.mean([r["ir_zero"]["inner_iters"] for r in rows])),
+                     "inner_iters_from_best_guess": float(np.mean([r["ir_best"]["inner_iters"] for r in rows])),
+                     "speedup_vs_plain_fp64_from_zero": float(t0.mean() / tb.mean()),
+                     "worst_true_rel_res": float(max(max(r["ir_zero"]["true_rel_res"], r["ir_best"]["true_rel_res"])
+                                                     for r in rows))}
+    return out

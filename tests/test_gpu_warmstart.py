@@ -85,12 +85,82 @@ def test_trained_network_saves_iterations():
     losses = warmstart.train(net, X, T, epochs=30, batch=8, lr=2e-3, seed=0)
     print("losses", losses[0], losses[-1])
     assert losses[-1] < 0.5 * losses[0]
-    rows = warmstart.evaluate(net, P, cells, k, list(range(10000, 10012)), tol=1e-10, log=print)
+    coarse = warmstart.CoarseLevel(cells, mfcg.MAP_SINE_SHEAR, 0.05)
+    rows = warmstart.evaluate(net, P, cells, k, list(range(10000, 10012)), tol=1e-10, log=print, coarse=coarse,
+                              ir=True)
     s = warmstart.summarize(rows)
     print(s)
     for r in rows:
         assert r["status"] == (mfcg.OK, mfcg.OK)
         assert r["true_rel_res"] <= 2e-10
         assert r["energy_err0"] <= 1.0 + 1e-9  # Galerkin scaling: never worse than x0 = 0
-    assert s["iters_warm"]["mean"] < s["iters_zero"]["mean"]
+        # the span holds both single guesses: its A-norm error is at most either one's
+        assert r["energy_err0_span"] <= min(r["energy_err0"], r["energy_err0_coarse"]) * (1 + 1e-9)
+        for name in ("ir_zero", "ir_best"):
+            assert r[name]["status"] == mfcg.OK and r[name]["true_rel_res"] <= 1e-10
+    assert s["learned"]["iters"]["mean"] < s["zero"]["iters"]["mean"]
+    assert s["coarse_plus_learned"]["iters"]["mean"] < s["zero"]["iters"]["mean"]
+    coarse.close()
+    P.close()
+
+
+@pytest.mark.parametrize("cells,kf,kt", [((5, 4, 6), 1, 3), ((3, 4, 2), 3, 2), ((4, 3, 3), 2, 4)])
+def test_interpolate_matches_oracle(oracle_mod, cells, kf, kt):
+    import torch
+    from paper_2205_08909_amd import mfcg
+    Pf = mfcg.Problem(cells, kf, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05)
+    Pt = mfcg.Problem(cells, kt, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05)
+    src = inputs.random_vector(Pf.n, 11)
+    got = Pt.interpolate_from(Pf, torch.from_numpy(src).cuda()).cpu().numpy()
+    want = oracle_mod.interpolate(cells, kf, kt, src)
+    assert np.abs(got - want).max() <= 1e-14 * np.abs(want).max()
+    with pytest.raises(mfcg.MfcgError):
+        Q = mfcg.Problem((cells[0] + 1, cells[1], cells[2]), kt)
+        Q.interpolate_from(Pf, torch.from_numpy(src).cuda())
+    Pf.close()
+    Pt.close()
+
+
+def test_warmstart_span_against_oracle(oracle_mod):
+    """Coefficients of the A-norm optimal combination against the oracle's
+    Gram system; never worse than either single Galerkin-scaled vector;
+    m = 1 is mfcg_warmstart; a dependent vector gets coefficient 0."""
+    import torch
+    from paper_2205_08909_amd import mfcg
+    cells, k = (5, 6, 4), 2
+    coeff = inputs.grf_coefficient(cells, 0.1, 1.0, seed=6)
+    m = oracle_mod.Mesh(cells, k, map_kind=1, amp=0.05, coeff=coeff)
+    A = oracle_mod.assemble(m)
+    b = oracle_mod.rhs(m, oracle_mod.F_SINE)
+    xs, _, _, _ = oracle_mod.pcg(A, A.diagonal(), b, tol=1e-13, maxit=5000)
+    mask = m.constrained_mask()
+    P = mfcg.Problem(cells, k, coeff=coeff, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05)
+    rng = np.random.default_rng(8)
+    u1 = xs * (1.0 + 0.05 * rng.standard_normal(A.n)) + 0.01 * rng.standard_normal(A.n)
+    u2 = xs - u1 + 0.02 * rng.standard_normal(A.n)
+    bt = torch.from_numpy(b).cuda()
+    ut = [torch.from_numpy(u).cuda() for u in (u1, u2)]
+    x0, coef, rel, used = P.warmstart_span(bt, ut)
+    U = np.stack([np.where(mask, 0.0, u) for u in (u1, u2)], 1)
+    AU = np.stack([A.matvec(U[:, i]) for i in range(2)], 1)
+    c_ref = np.linalg.solve(U.T @ AU, U.T @ b)
+    assert used
+    assert np.abs(np.array(coef) - c_ref).max() <= 1e-9 * np.abs(c_ref).max()
+    x0 = x0.cpu().numpy()
+    assert np.abs(x0 - U @ c_ref).max() <= 1e-9 * np.abs(x0).max()
+    enorm = lambda v: np.sqrt((xs - v) @ A.matvec(xs - v))
+    for u in (u1, u2):
+        xi, _, _, _ = P.warmstart(bt, torch.from_numpy(u).cuda())
+        assert enorm(x0) <= enorm(xi.cpu().numpy()) * (1 + 1e-12)
+    # m = 1 is the single-vector Galerkin scaling
+    x1, c1, _, _ = P.warmstart_span(bt, ut[:1])
+    xw, sc, _, _ = P.warmstart(bt, ut[0])
+    assert abs(c1[0] - sc) <= 1e-13 * abs(sc)
+    assert torch.allclose(x1, xw, rtol=1e-13, atol=0)
+    # a vector in the span of the earlier ones is dropped
+    x2, c2, _, _ = P.warmstart_span(bt, [ut[0], 2.0 * ut[0]])
+    assert c2[1] == 0.0 and abs(c2[0] - sc) <= 1e-13 * abs(sc)
+    # a zero vector alone falls back to x0 = 0
+    x3, c3, rel3, used3 = P.warmstart_span(bt, [torch.zeros_like(bt)])
+    assert not used3 and c3 == [0.0] and float(x3.abs().max()) == 0.0
     P.close()

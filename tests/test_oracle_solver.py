@@ -207,3 +207,55 @@ def test_rhs_bumps_closed_form(oracle_mod, k, N):
     wrong = params.copy()
     wrong[5::5] /= np.sqrt(2.0)
     assert abs(_bump_moments(wrong)[0] - m0) > 1e-3 * scale
+
+
+def _node_coords(cells, k, oracle_mod):
+    """Reference coordinates of the Q_k nodes along each axis."""
+    x = oracle_mod.gll(k)
+    out = []
+    for N in cells:
+        g = np.arange(N * k + 1)
+        e = np.minimum(g // k, N - 1)
+        out.append((e + x[g - k * e]) / N)
+    return out
+
+
+@pytest.mark.parametrize("cells,kf,kt", [((3, 2, 4), 1, 3), ((2, 3, 2), 2, 4), ((2, 2, 3), 1, 1), ((3, 1, 2), 3, 5)])
+def test_interpolate_reproduces_polynomials(oracle_mod, cells, kf, kt):
+    """Nested spaces: a polynomial of degree kf in each variable (the Q_kf
+    space contains it) sampled at the Q_kf nodes must come out at the Q_kt
+    nodes exactly; a dropped basis term, a wrong cell index at the right end
+    or transposed axes all fail this."""
+    cx, cy, cz = _node_coords(cells, kf, oracle_mod)
+    tx, ty, tz = _node_coords(cells, kt, oracle_mod)
+    rng = np.random.default_rng(kf * 10 + kt)
+    coef = rng.standard_normal((kf + 1, kf + 1, kf + 1))
+
+    def f(X, Y, Z):
+        out = np.zeros(np.broadcast(X, Y, Z).shape)
+        for a in range(kf + 1):
+            for b in range(kf + 1):
+                for c in range(kf + 1):
+                    out += coef[a, b, c] * X ** a * Y ** b * Z ** c
+        return out
+
+    Z, Y, X = np.meshgrid(cz, cy, cx, indexing="ij")
+    src = f(X, Y, Z).ravel()
+    Z2, Y2, X2 = np.meshgrid(tz, ty, tx, indexing="ij")
+    want = f(X2, Y2, Z2).ravel()
+    got = oracle_mod.interpolate(cells, kf, kt, src)
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+
+
+def test_interpolate_piecewise_not_global(oracle_mod):
+    """A Q1 hat function (one interior node = 1) is piecewise trilinear: at
+    the Q3 nodes it is the product of 1D hats, zero outside the 8 cells
+    around the node."""
+    cells, kf, kt = (4, 3, 3), 1, 3
+    src = np.zeros((4, 4, 5))
+    src[1, 2, 2] = 1.0  # z = 1, y = 2, x = 2
+    got = oracle_mod.interpolate(cells, kf, kt, src.ravel()).reshape(10, 10, 13)
+    tx, ty, tz = _node_coords(cells, kt, oracle_mod)
+    hat = lambda t, c, N: np.maximum(0.0, 1.0 - np.abs(t * N - c))
+    want = hat(tz, 1, 3)[:, None, None] * hat(ty, 2, 3)[None, :, None] * hat(tx, 2, 4)[None, None, :]
+    assert np.abs(got - want).max() <= 1e-14
