@@ -50,14 +50,22 @@ typedef struct {
 } mfnn_conv_desc;
 
 /* y = act(conv(x, w) + bias).  x: [n][c_in][in] (x_dtype BF16 or F32);
- * bias: c_out floats or NULL; y: [n][c_out][out] (y_dtype BF16 or F32). */
+ * bias: c_out floats or NULL; y: [n][c_out][out] (y_dtype BF16 or F32).
+ * A layer with c_in = c_out = 32, stride 1 and a cubic kernel (k <= 5,
+ * the same dilation and padding in every direction) and BF16 x runs as an
+ * implicit GEMM on the BF16 matrix cores (FP32 accumulation); the others,
+ * or those whose staging would not fit 64 KiB of LDS, as direct
+ * convolutions.  Both give the products exactly and sum them in FP32. */
 int mfnn_conv3d_fwd(const mfnn_conv_desc *desc, const void *x, int32_t x_dtype, const uint16_t *w,
                     const float *bias, int32_t act, void *y, int32_t y_dtype, void *hip_stream);
 
 /* dx = conv(., w)^T g (+ bias_in[ci]): the adjoint of the convolution in x
  * (backward data), which is also the forward map of a transposed
  * convolution with bias_in as its bias.  g: [n][c_out][out] (BF16 or F32);
- * bias_in: c_in floats or NULL; dx: [n][c_in][in] (BF16 or F32). */
+ * bias_in: c_in floats or NULL; dx: [n][c_in][in] (BF16 or F32).  With
+ * BF16 g, no bias_in and a layer of the matrix-core shape above with
+ * symmetric padding (2 p = d (k - 1)) it runs on the matrix cores as the
+ * forward convolution of g with the flipped, transposed kernel. */
 int mfnn_conv3d_bwd_data(const mfnn_conv_desc *desc, const void *g, int32_t g_dtype, const uint16_t *w,
                          const float *bias_in, void *dx, int32_t dx_dtype, void *hip_stream);
 

@@ -4,10 +4,12 @@
  * and weights, FP32 accumulation, NCDHW layout (W fastest, which is the
  * x-fastest lexicographic node order of the solver's vectors).
  *
- * The layers are direct convolutions: with 32 channels and 3^3..8^3 taps
- * on grids of 37^3..145^3 points the work per sample is a few GFLOP, and
- * the kernels keep each thread's output channels in registers and the
- * layer's weights in LDS (as FP32, read as broadcasts).
+ * The 32 -> 32 channel layers of stride 1 (forward and data gradient) run
+ * as implicit GEMMs on the BF16 matrix cores (conv_mfma_kernel).  The other
+ * shapes (3 -> 32 channels at stride 4, the 32 -> 1 transposed layer, the
+ * weight gradients) are direct convolutions that keep each thread's output
+ * channels in registers and the layer's weights in LDS (as FP32, read as
+ * broadcasts).
  *
  *   conv_fwd_kernel        y = act(conv(x, w) + b)
  *   conv_bwd_data_kernel   dx = conv(., w)^T g (+ b per input channel: the
@@ -467,6 +469,245 @@ static unsigned grid_for(int64_t n)
     return (unsigned)b;
 }
 
+/* ---------------- matrix-core path: 32 -> 32 channels, stride 1 ---------------- */
+
+/* The dense layers of the network (32 input and 32 output channels, a
+ * cubic kernel of K^3 taps with dilation d, stride 1) as an implicit GEMM
+ * on the BF16 matrix cores: per tap, out[oc][point] += W[oc][ic] x[ic][point
+ * shifted by the tap], a 32 x 32 x 8 product (v_mfma_f32_32x32x8_bf16) per
+ * block of 8 input channels, FP32 accumulation.  A workgroup of 4 waves
+ * owns 128 consecutive output points of one z-plane (a wave per 32-point
+ * block, the matrix N dimension); for each z-tap it stages the K^2 taps'
+ * weights and the input rows the block needs (all 32 channels, channel
+ * fastest, zero outside the input) in LDS, then every wave runs the K^2 x 4
+ * products of that plane.  flip = 1 reads the weights as w[ic][oc][T-1-t]:
+ * the data gradient of a stride-1 convolution with symmetric padding is
+ * this convolution of the output gradient with the flipped, transposed
+ * kernel. */
+typedef short mf_v4s __attribute__((ext_vector_type(4)));
+typedef float mf_v16f __attribute__((ext_vector_type(16)));
+constexpr int MF_C = 32, MF_WG = 256, MF_PTS = 128;
+
+struct MfGeom {
+    int32_t n;
+    int32_t in[3], out[3];
+    int32_t K, d, p;
+    int32_t flip;
+    int32_t SW, RMAX; /* slab columns, slab rows allocated */
+};
+
+template <typename TO>
+__global__ __launch_bounds__(MF_WG) void conv_mfma_kernel(const MfGeom g, const uint16_t *__restrict__ x,
+                                                          const uint16_t *__restrict__ w,
+                                                          const float *__restrict__ bias, int act,
+                                                          TO *__restrict__ y)
+{
+    extern __shared__ uint16_t mf_lds[];
+    const int K = g.K, K2 = K * K, T = K2 * K;
+    uint16_t *wl = mf_lds;                /* K^2 taps x 32 oc x 32 ic */
+    uint16_t *xs = wl + K2 * MF_C * MF_C; /* RMAX x SW points x 32 ic */
+    const int64_t plane = (int64_t)g.out[1] * g.out[2];
+    const int64_t pblocks = (plane + MF_PTS - 1) / MF_PTS;
+    const int64_t bid = blockIdx.x;
+    const int64_t pb = bid % pblocks, rest = bid / pblocks;
+    const int oz = (int)(rest % g.out[0]), n = (int)(rest / g.out[0]);
+    const int64_t q0 = pb * MF_PTS;
+    const int64_t qlast = (q0 + MF_PTS < plane ? q0 + MF_PTS : plane) - 1;
+    const int oy0 = (int)(q0 / g.out[2]), oy1 = (int)(qlast / g.out[2]);
+    const int SR = oy1 - oy0 + 1 + (K - 1) * g.d; /* <= RMAX by the launch's choice of RMAX */
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t q = q0 + wave * 32 + (lane & 31);
+    const bool qv = q < plane;
+    const int64_t qc = qv ? q : q0;
+    const int oy = (int)(qc / g.out[2]), ox = (int)(qc - (int64_t)oy * g.out[2]);
+    const int sbase = (oy - oy0) * g.SW + ox;
+    const int khalf = (lane >> 5) * 4;
+    const int64_t ivox = (int64_t)g.in[0] * g.in[1] * g.in[2];
+    mf_v16f acc;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+    for (int tz = 0; tz < K; ++tz) {
+        const int iz = oz - g.p + tz * g.d;
+        if (iz < 0 || iz >= g.in[0]) continue; /* the same for the whole workgroup */
+        __syncthreads();                       /* the previous plane's products are done */
+        for (int e = threadIdx.x; e < K2 * MF_C * MF_C; e += MF_WG) {
+            const int ic = e & 31, oc = (e >> 5) & 31, tyx = e >> 10;
+            const int t = tz * K2 + tyx;
+            wl[e] = g.flip ? w[((int64_t)ic * MF_C + oc) * T + (T - 1 - t)] : w[((int64_t)oc * MF_C + ic) * T + t];
+        }
+        const int nel = SR * g.SW * MF_C;
+        for (int e = threadIdx.x; e < nel; e += MF_WG) {
+            const int col = e % g.SW, r2 = e / g.SW;
+            const int row = r2 % SR, ic = r2 / SR;
+            const int iy = oy0 - g.p + row, ix = col - g.p;
+            uint16_t v = 0;
+            if (iy >= 0 && iy < g.in[1] && ix >= 0 && ix < g.in[2])
+                v = x[((int64_t)n * MF_C + ic) * ivox + ((int64_t)iz * g.in[1] + iy) * g.in[2] + ix];
+            xs[(row * g.SW + col) * MF_C + ic] = v;
+        }
+        __syncthreads();
+        for (int ty = 0; ty < K; ++ty)
+            for (int tx = 0; tx < K; ++tx) {
+                const uint16_t *wb = wl + ((ty * K + tx) * MF_C + (lane & 31)) * MF_C + khalf;
+                const uint16_t *xb = xs + (sbase + ty * g.d * g.SW + tx * g.d) * MF_C + khalf;
+#pragma unroll
+                for (int kb = 0; kb < 4; ++kb) {
+                    const mf_v4s a = *(const mf_v4s *)(wb + kb * 8);
+                    const mf_v4s b = *(const mf_v4s *)(xb + kb * 8);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+                }
+            }
+    }
+    if (!qv) return;
+    const int64_t ovox = (int64_t)g.out[0] * plane;
+    const int64_t ob = (int64_t)n * MF_C * ovox + (int64_t)oz * plane + q;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int oc = 8 * (v >> 2) + khalf + (v & 3);
+        float z = acc[v] + (bias ? bias[oc] : 0.f);
+        if (act == ACT_LEAKY) z = leaky(z);
+        store_f(y, ob + (int64_t)oc * ovox, z);
+    }
+}
+
+/* Weight gradient of the same layers on the matrix cores: per tap t,
+ * dw[oc][ic][t] = sum over points of g[oc][point] x[ic][point shifted by
+ * t], a 32 x 32 x 8 product per 8 points.  A workgroup of 8 waves walks a
+ * contiguous range of (sample, z-plane, 128-point block) items; wave w
+ * owns the taps t = w, w + 8, ... and keeps their 32 x 32 sums in
+ * registers for the whole range.  Per item the output gradient block is
+ * staged in LDS as [oc][point] (4 consecutive points per lane in one read)
+ * and, per z-tap, the input rows as for the forward map.  Each workgroup
+ * writes its partial sums as one chunk; the chunks are added in a fixed
+ * order afterwards. */
+constexpr int MFW_WAVES = 8, MFW_WG = 64 * MFW_WAVES, MFW_CHUNKS = 32;
+
+template <int K>
+__global__ __launch_bounds__(MFW_WG) void conv_wgrad_mfma_kernel(const MfGeom g, const uint16_t *__restrict__ x,
+                                                                 const uint16_t *__restrict__ gr,
+                                                                 float *__restrict__ part, int nchunks)
+{
+    extern __shared__ uint16_t mf_lds[];
+    constexpr int K2 = K * K, T = K2 * K;
+    uint16_t *gs = mf_lds;               /* 32 oc x MF_PTS points */
+    uint16_t *xs = gs + MF_C * MF_PTS;   /* RMAX x SW points x 32 ic */
+    int *sp0 = (int *)(xs + g.RMAX * g.SW * MF_C); /* slab offset of each point of the block */
+    const int64_t plane = (int64_t)g.out[1] * g.out[2];
+    const int64_t pblocks = (plane + MF_PTS - 1) / MF_PTS;
+    const int64_t nitems = pblocks * g.out[0] * g.n;
+    const int64_t it0 = nitems * blockIdx.x / nchunks, it1 = nitems * (blockIdx.x + 1) / nchunks;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int khalf = (lane >> 5) * 4, col = lane & 31;
+    const int64_t ivox = (int64_t)g.in[0] * g.in[1] * g.in[2];
+    const int64_t ovox = (int64_t)g.out[0] * plane;
+    constexpr int NT = (T + MFW_WAVES - 1) / MFW_WAVES; /* taps per wave */
+    mf_v16f acc[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[j][v] = 0.f;
+    for (int64_t item = it0; item < it1; ++item) {
+        const int64_t pb = item % pblocks, rest = item / pblocks;
+        const int oz = (int)(rest % g.out[0]), n = (int)(rest / g.out[0]);
+        const int64_t q0 = pb * MF_PTS;
+        const int64_t qlast = (q0 + MF_PTS < plane ? q0 + MF_PTS : plane) - 1;
+        const int oy0 = (int)(q0 / g.out[2]), oy1 = (int)(qlast / g.out[2]);
+        const int SR = oy1 - oy0 + 1 + (K - 1) * g.d;
+        __syncthreads(); /* the previous item's products are done */
+        for (int e = threadIdx.x; e < MF_C * MF_PTS; e += MFW_WG) {
+            const int oc = e / MF_PTS, i = e - oc * MF_PTS;
+            const int64_t q = q0 + i;
+            gs[e] = q < plane ? gr[((int64_t)n * MF_C + oc) * ovox + (int64_t)oz * plane + q] : (uint16_t)0;
+        }
+        for (int i = threadIdx.x; i < MF_PTS; i += MFW_WG) {
+            const int64_t q = q0 + i < plane ? q0 + i : q0; /* points past the plane: g = 0, any valid slab point */
+            const int qy = (int)(q / g.out[2]), qx = (int)(q - (int64_t)qy * g.out[2]);
+            sp0[i] = (qy - oy0) * g.SW + qx;
+        }
+        for (int tz = 0; tz < K; ++tz) {
+            const int iz = oz - g.p + tz * g.d;
+            if (iz < 0 || iz >= g.in[0]) continue; /* the same for the whole workgroup */
+            __syncthreads();                       /* the previous plane's products are done */
+            const int nel = SR * g.SW * MF_C;
+            for (int e = threadIdx.x; e < nel; e += MFW_WG) {
+                const int c2 = e % g.SW, r2 = e / g.SW;
+                const int row = r2 % SR, ic = r2 / SR;
+                const int iy = oy0 - g.p + row, ix = c2 - g.p;
+                uint16_t v = 0;
+                if (iy >= 0 && iy < g.in[1] && ix >= 0 && ix < g.in[2])
+                    v = x[((int64_t)n * MF_C + ic) * ivox + ((int64_t)iz * g.in[1] + iy) * g.in[2] + ix];
+                xs[(row * g.SW + c2) * MF_C + ic] = v;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const int t = wave + MFW_WAVES * j;
+                if (t >= T || t / K2 != tz) continue;
+                const int tyx = t - tz * K2, ty = tyx / K, tx = tyx - ty * K;
+                const int shift = ty * g.d * g.SW + tx * g.d;
+                for (int s8 = 0; s8 < MF_PTS; s8 += 8) {
+                    const mf_v4s a = *(const mf_v4s *)(gs + col * MF_PTS + s8 + khalf);
+                    mf_v4s b;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) b[u] = (short)xs[(sp0[s8 + khalf + u] + shift) * MF_C + col];
+                    acc[j] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[j], 0, 0, 0);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int t = wave + MFW_WAVES * j;
+        if (t >= T) continue;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int oc = 8 * (v >> 2) + khalf + (v & 3);
+            part[(((int64_t)blockIdx.x * MF_C + oc) * MF_C + col) * T + t] = acc[j][v];
+        }
+    }
+}
+
+/* The matrix-core geometry of a stride-1, 32 -> 32 channel layer with a
+ * cubic kernel, or false when the layer has another shape or its LDS
+ * footprint exceeds the budget.  flip: the data-gradient form (needs the
+ * symmetric padding 2p = (K-1)d; the gradient has the output's size). */
+static bool mfma_geom(const ConvGeom &g, bool flip, MfGeom &m, size_t &lds)
+{
+    if (g.ci != MF_C || g.co != MF_C) return false;
+    for (int i = 0; i < 3; ++i)
+        if (g.s[i] != 1 || g.k[i] != g.k[0] || g.d[i] != g.d[0] || g.p[i] != g.p[0]) return false;
+    const int K = g.k[0], d = g.d[0], p = g.p[0];
+    if (K < 1 || K > 5 || (flip && 2 * p != (K - 1) * d)) return false;
+    m = MfGeom{};
+    m.n = g.n;
+    for (int i = 0; i < 3; ++i) {
+        m.in[i] = flip ? g.out[i] : g.in[i];
+        m.out[i] = flip ? g.in[i] : g.out[i];
+    }
+    m.K = K;
+    m.d = d;
+    m.p = p;
+    m.flip = flip ? 1 : 0;
+    m.SW = m.out[2] + (K - 1) * d;
+    /* rows a block of MF_PTS consecutive points can touch, plus the taps' reach */
+    m.RMAX = (MF_PTS - 1) / m.out[2] + 2;
+    if (m.RMAX > m.out[1]) m.RMAX = m.out[1];
+    m.RMAX += (K - 1) * d;
+    lds = ((size_t)K * K * MF_C * MF_C + (size_t)m.RMAX * m.SW * MF_C) * sizeof(uint16_t);
+    return lds <= MAX_LDS_BYTES && m.out[0] > 0 && m.out[1] > 0 && m.out[2] > 0;
+}
+
+template <typename TO>
+static hipError_t mfma_t(const MfGeom &m, size_t lds, const void *x, const uint16_t *w, const float *bias, int act,
+                         void *y, hipStream_t s)
+{
+    const int64_t plane = (int64_t)m.out[1] * m.out[2];
+    const int64_t nb = (plane + MF_PTS - 1) / MF_PTS * m.out[0] * m.n;
+    hipLaunchKernelGGL((conv_mfma_kernel<TO>), dim3((unsigned)nb), dim3(MF_WG), lds, s, m, (const uint16_t *)x, w,
+                       bias, act, (TO *)y);
+    return hipGetLastError();
+}
+
 template <typename TI, typename TO>
 static hipError_t fwd_t(const ConvGeom &g, const void *x, const uint16_t *w, const float *bias, int act, void *y,
                         hipStream_t s)
@@ -487,6 +728,11 @@ static hipError_t fwd_t(const ConvGeom &g, const void *x, const uint16_t *w, con
 hipError_t launch_conv_fwd(const ConvGeom &g, const void *x, int tx, const uint16_t *w, const float *bias, int act,
                            void *y, int ty, hipStream_t s)
 {
+    MfGeom m;
+    size_t lds = 0;
+    if (tx == DT_BF16 && mfma_geom(g, false, m, lds))
+        return ty == DT_BF16 ? mfma_t<uint16_t>(m, lds, x, w, bias, act, y, s)
+                             : mfma_t<float>(m, lds, x, w, bias, act, y, s);
     if (tx == DT_BF16 && ty == DT_BF16) return fwd_t<uint16_t, uint16_t>(g, x, w, bias, act, y, s);
     if (tx == DT_BF16 && ty == DT_F32) return fwd_t<uint16_t, float>(g, x, w, bias, act, y, s);
     if (tx == DT_F32 && ty == DT_BF16) return fwd_t<float, uint16_t>(g, x, w, bias, act, y, s);
@@ -513,14 +759,24 @@ static hipError_t bwd_data_t(const ConvGeom &g, const void *gr, const uint16_t *
 hipError_t launch_conv_bwd_data(const ConvGeom &g, const void *gr, int tg, const uint16_t *w, const float *bias,
                                 void *dx, int tdx, hipStream_t s)
 {
+    MfGeom m;
+    size_t lds = 0;
+    if (tg == DT_BF16 && !bias && mfma_geom(g, true, m, lds))
+        return tdx == DT_BF16 ? mfma_t<uint16_t>(m, lds, gr, w, nullptr, ACT_NONE, dx, s)
+                              : mfma_t<float>(m, lds, gr, w, nullptr, ACT_NONE, dx, s);
     if (tg == DT_BF16 && tdx == DT_BF16) return bwd_data_t<uint16_t, uint16_t>(g, gr, w, bias, dx, s);
     if (tg == DT_BF16 && tdx == DT_F32) return bwd_data_t<uint16_t, float>(g, gr, w, bias, dx, s);
     if (tg == DT_F32 && tdx == DT_BF16) return bwd_data_t<float, uint16_t>(g, gr, w, bias, dx, s);
     return bwd_data_t<float, float>(g, gr, w, bias, dx, s);
 }
 
+static bool mfma_geom(const ConvGeom &g, bool flip, MfGeom &m, size_t &lds);
+
 int wgrad_chunks(const ConvGeom &g)
 {
+    MfGeom m;
+    size_t lds = 0;
+    if (mfma_geom(g, false, m, lds) && m.K == 3) return MFW_CHUNKS; /* one chunk per matrix-core workgroup */
     const int64_t T = (int64_t)g.k[0] * g.k[1] * g.k[2];
     const int64_t blocks = (int64_t)g.ci * T * (g.co % 8 == 0 ? g.co / 8 : g.co);
     int64_t c = (4096 + blocks - 1) / blocks;
@@ -551,6 +807,23 @@ static hipError_t wgrad_t(const ConvGeom &g, const void *x, const void *gr, floa
 hipError_t launch_conv_bwd_weight(const ConvGeom &g, const void *x, int tx, const void *gr, int tg, float *dw,
                                   float *db, float *work, hipStream_t s)
 {
+    MfGeom m;
+    size_t lds_fwd = 0;
+    if (tx == DT_BF16 && tg == DT_BF16 && mfma_geom(g, false, m, lds_fwd) && m.K == 3) {
+        const size_t lds = (size_t)MF_C * MF_PTS * sizeof(uint16_t) + (size_t)m.RMAX * m.SW * MF_C * sizeof(uint16_t) +
+                           MF_PTS * sizeof(int);
+        if (lds <= MAX_LDS_BYTES) {
+            const int T = 27;
+            hipLaunchKernelGGL((conv_wgrad_mfma_kernel<3>), dim3(MFW_CHUNKS), dim3(MFW_WG), lds, s, m,
+                               (const uint16_t *)x, (const uint16_t *)gr, work, MFW_CHUNKS);
+            const int64_t nw = (int64_t)MF_C * MF_C * T;
+            hipLaunchKernelGGL(conv_wsum_kernel, dim3((unsigned)((nw + NN_WG - 1) / NN_WG)), dim3(NN_WG), 0, s, nw,
+                               MFW_CHUNKS, (const float *)work, dw);
+            if (db) hipLaunchKernelGGL((conv_bsum_kernel<uint16_t>), dim3(g.co), dim3(NN_WG), 0, s, g,
+                                       (const uint16_t *)gr, db);
+            return hipGetLastError();
+        }
+    }
     if (tx == DT_BF16 && tg == DT_BF16) return wgrad_t<uint16_t, uint16_t>(g, x, gr, dw, db, work, s);
     if (tx == DT_BF16 && tg == DT_F32) return wgrad_t<uint16_t, float>(g, x, gr, dw, db, work, s);
     if (tx == DT_F32 && tg == DT_BF16) return wgrad_t<float, uint16_t>(g, x, gr, dw, db, work, s);

@@ -96,6 +96,9 @@ class Net:
                  "dY": t.empty(B * nf, dtype=t.float32, device="cuda"),
                  "dA": t.empty(B * self.c * ncs, dtype=t.float32, device="cuda"),
                  "dZ": t.empty(B * self.c * ncs, dtype=t.float32, device="cuda"),
+                 # the activation gradient in BF16 for the gradients of the
+                 # 32 -> 32 layers, which run on the matrix cores
+                 "dZb": t.empty(B * self.c * ncs, dtype=t.bfloat16, device="cuda"),
                  "g": [nn.with_batch(g, B) for g in (self.g1, self.g2, self.g3, self.g4)]}
             self._bufs[B] = d
             need = max(nn.wgrad_work(g) for g in d["g"])
@@ -126,13 +129,16 @@ class Net:
         nn.conv_bwd_weight(g4, dY, A3, self.dw(3), None, work)
         nn.channel_sum(B, 1, self.nodes, dY, self.db(3))
         # layer 3
+        dZb = d["dZb"]
         nn.act_bwd(dA, A3, dZ)
-        nn.conv_bwd_weight(g3, A2, dZ, self.dw(2), self.db(2), work)
-        nn.conv_bwd_data(g3, dZ, self.w(2), None, dA)
+        nn.convert(dZ, dZb)
+        nn.conv_bwd_weight(g3, A2, dZb, self.dw(2), self.db(2), work)
+        nn.conv_bwd_data(g3, dZb, self.w(2), None, dA)
         # layer 2
         nn.act_bwd(dA, A2, dZ)
-        nn.conv_bwd_weight(g2, A1, dZ, self.dw(1), self.db(1), work)
-        nn.conv_bwd_data(g2, dZ, self.w(1), None, dA)
+        nn.convert(dZ, dZb)
+        nn.conv_bwd_weight(g2, A1, dZb, self.dw(1), self.db(1), work)
+        nn.conv_bwd_data(g2, dZb, self.w(1), None, dA)
         # layer 1 (no gradient to the input features)
         nn.act_bwd(dA, A1, dZ)
         nn.conv_bwd_weight(g1, self._X, dZ, self.dw(0), self.db(0), work)

@@ -20,6 +20,12 @@ GEOMS = [  # (n, c_in, c_out, in spatial, k, stride, pad, dil)
     (2, 32, 32, (9, 8, 7), 3, 1, 3, 3),     # layer 3 (dilated)
     (1, 1, 32, (17, 13, 9), 8, 4, 4, 1),    # layer 4 geometry (fine -> coarse conv)
     (2, 3, 5, (6, 7, 5), 3, 2, 1, 1),       # channel counts not multiple of 8
+    # 32 -> 32 channels at stride 1 run on the matrix cores (BF16 inputs):
+    # several 128-point blocks per plane with a ragged last one, rows that
+    # a block spans partly, the dilated and the 5^3 kernels
+    (2, 32, 32, (5, 19, 37), 3, 1, 3, 3),
+    (1, 32, 32, (4, 11, 49), 5, 1, 2, 1),
+    (1, 32, 32, (3, 2, 130), 3, 1, 1, 1),
 ]
 
 
@@ -72,7 +78,7 @@ def test_conv_forward(geom, xdt, ydt, act):
 
 
 @pytest.mark.parametrize("geom", GEOMS)
-@pytest.mark.parametrize("gdt,bias", [("f32", False), ("bf16", True)])
+@pytest.mark.parametrize("gdt,bias", [("f32", False), ("bf16", True), ("bf16", False)])
 def test_conv_backward_data(geom, gdt, bias):
     import torch
     from paper_2205_08909_amd import nn
@@ -93,7 +99,7 @@ def test_conv_backward_data(geom, gdt, bias):
 
 
 @pytest.mark.parametrize("geom", GEOMS)
-@pytest.mark.parametrize("xdt,gdt", [("bf16", "f32"), ("f32", "bf16")])
+@pytest.mark.parametrize("xdt,gdt", [("bf16", "f32"), ("f32", "bf16"), ("bf16", "bf16")])
 def test_conv_backward_weight(geom, xdt, gdt):
     import torch
     from paper_2205_08909_amd import nn
