@@ -137,6 +137,12 @@ int mfnn_features(const int32_t cells[3], int32_t k, const double *log_coeff, co
  * output gradient is g (e.g. a transposed convolution's bias). */
 int mfnn_channel_sum(int32_t n, int32_t c, const int32_t spatial[3], const void *g, int32_t g_dtype, float *out,
                      void *hip_stream);
+/* The same with a caller workspace of work_floats floats (device): the
+ * sum of each channel is then spread over up to work_floats / c (at most
+ * 512) blocks whose partial sums are added in a fixed order.  work = NULL
+ * or work_floats < 2 c: one block per channel, as mfnn_channel_sum. */
+int mfnn_channel_sum_work(int32_t n, int32_t c, const int32_t spatial[3], const void *g, int32_t g_dtype,
+                          float *out, float *work, int64_t work_floats, void *hip_stream);
 
 /* out = in / rms(in), rms(in) = sqrt(sum in_i^2 / n) (0 if in = 0): the
  * scale-free training target built from a solver solution (FP64 in, FP32

@@ -83,7 +83,8 @@ int mfnn_conv3d_fwd(const mfnn_conv_desc *desc, const void *x, int32_t x_dtype, 
     if (!dtype_ok(x_dtype) || !dtype_ok(y_dtype)) return nn_fail(MFNN_EINVAL, "x and y must be BF16 or F32");
     if (act != MFNN_ACT_NONE && act != MFNN_ACT_LEAKY) return nn_fail(MFNN_EINVAL, "unknown activation");
     const size_t lds = (size_t)g.ci * g.k[0] * g.k[1] * g.k[2] * (g.co % 8 == 0 ? 8 : 1) * sizeof(float);
-    if (lds > MAX_LDS_BYTES) return nn_fail(MFNN_EINVAL, "layer weights exceed the LDS budget");
+    if (lds > MAX_LDS_BYTES && !(x_dtype == MFNN_BF16 && mfma_applies(g, false)))
+        return nn_fail(MFNN_EINVAL, "layer weights exceed the LDS budget");
     NNCHK(launch_conv_fwd(g, x, x_dtype, w, bias, act, y, y_dtype, (hipStream_t)hip_stream));
     return MFNN_OK;
 }
@@ -97,7 +98,8 @@ int mfnn_conv3d_bwd_data(const mfnn_conv_desc *desc, const void *gr, int32_t g_d
     if (!gr || !w || !dx) return nn_fail(MFNN_EINVAL, "null tensor");
     if (!dtype_ok(g_dtype) || !dtype_ok(dx_dtype)) return nn_fail(MFNN_EINVAL, "g and dx must be BF16 or F32");
     const size_t lds = (size_t)g.co * g.k[0] * g.k[1] * g.k[2] * (g.ci % 8 == 0 ? 8 : 1) * sizeof(float);
-    if (lds > MAX_LDS_BYTES) return nn_fail(MFNN_EINVAL, "layer weights exceed the LDS budget");
+    if (lds > MAX_LDS_BYTES && !(g_dtype == MFNN_BF16 && !bias_in && mfma_applies(g, true)))
+        return nn_fail(MFNN_EINVAL, "layer weights exceed the LDS budget");
     NNCHK(launch_conv_bwd_data(g, gr, g_dtype, w, bias_in, dx, dx_dtype, (hipStream_t)hip_stream));
     return MFNN_OK;
 }
@@ -234,6 +236,13 @@ int mfnn_features(const int32_t cells[3], int32_t k, const double *log_coeff, co
 int mfnn_channel_sum(int32_t n, int32_t c, const int32_t spatial[3], const void *g, int32_t g_dtype, float *out,
                      void *hip_stream)
 {
+    return mfnn_channel_sum_work(n, c, spatial, g, g_dtype, out, nullptr, 0, hip_stream);
+}
+
+int mfnn_channel_sum_work(int32_t n, int32_t c, const int32_t spatial[3], const void *g, int32_t g_dtype,
+                          float *out, float *work, int64_t work_floats, void *hip_stream)
+{
+    if (work_floats < 0 || (work_floats > 0 && !work)) return nn_fail(MFNN_EINVAL, "bad workspace");
     if (n < 1 || c < 1 || !spatial || !g || !out) return nn_fail(MFNN_EINVAL, "bad argument");
     if (!dtype_ok(g_dtype)) return nn_fail(MFNN_EINVAL, "g must be BF16 or F32");
     ConvGeom geo{};
@@ -243,7 +252,7 @@ int mfnn_channel_sum(int32_t n, int32_t c, const int32_t spatial[3], const void 
         if (spatial[d] < 1) return nn_fail(MFNN_EINVAL, "spatial sizes must be >= 1");
         geo.out[d] = spatial[d];
     }
-    NNCHK(launch_channel_sum(geo, g, g_dtype, out, (hipStream_t)hip_stream));
+    NNCHK(launch_channel_sum(geo, g, g_dtype, out, work, work_floats, (hipStream_t)hip_stream));
     return MFNN_OK;
 }
 

@@ -25,6 +25,9 @@ struct FeatGeom {
     int64_t n;
 };
 
+/* the layer runs on the matrix cores with BF16 input (forward map; flip:
+ * the data gradient without bias) */
+bool mfma_applies(const ConvGeom &g, bool flip);
 hipError_t launch_conv_fwd(const ConvGeom &g, const void *x, int tx, const uint16_t *w, const float *bias, int act,
                            void *y, int ty, hipStream_t s);
 hipError_t launch_conv_bwd_data(const ConvGeom &g, const void *gr, int tg, const uint16_t *w, const float *bias,
@@ -43,7 +46,11 @@ hipError_t launch_features(const FeatGeom &f, const double *logc, const double *
                            uint16_t *out, hipStream_t s);
 
 /* out[c] = sum over n and the spatial points of channel c (g.co channels, g.out points) */
-hipError_t launch_channel_sum(const ConvGeom &g, const void *gr, int tg, float *out, hipStream_t s);
+/* work: NULL (one block per channel) or work_floats >= 2 co floats of scratch
+ * (up to CSUM_MAX_BLOCKS blocks per channel, partial sums in work) */
+constexpr int CSUM_MAX_BLOCKS = 512;
+hipError_t launch_channel_sum(const ConvGeom &g, const void *gr, int tg, float *out, float *work, int64_t work_floats,
+                              hipStream_t s);
 hipError_t launch_normalize(int64_t n, const double *in, double *work, float *out, hipStream_t s);
 
 }  // namespace mfnn

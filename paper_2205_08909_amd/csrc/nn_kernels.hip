@@ -277,6 +277,60 @@ __global__ __launch_bounds__(NN_WG) void conv_bsum_kernel(const ConvGeom g, cons
     if (threadIdx.x == 0) db[co] = tot[0];
 }
 
+/* The same sum spread over nb blocks per channel: part[co * nb + b] = the
+ * sum of slice b of channel co's (n, o) points (fixed slices, fixed order
+ * inside a block); csum_finish_kernel adds a channel's nb partials in
+ * order.  A single block per channel reads at the bandwidth of one compute
+ * unit, which takes milliseconds on a fine grid. */
+template <typename TG>
+__global__ __launch_bounds__(NN_WG) void csum_part_kernel(const ConvGeom g, const TG *__restrict__ gr, int nb,
+                                                          float *__restrict__ part)
+{
+    __shared__ float red[NN_WG / 64];
+    const int co = blockIdx.y, b = blockIdx.x;
+    const int64_t ovox = (int64_t)g.out[0] * g.out[1] * g.out[2];
+    const int64_t V = (int64_t)g.n * ovox;
+    const int64_t v0 = V * b / nb, v1 = V * (b + 1) / nb;
+    float acc[1] = {0.f};
+    for (int64_t v = v0 + threadIdx.x; v < v1; v += NN_WG) {
+        const int n = (int)(v / ovox);
+        acc[0] += load_f(gr, ((int64_t)n * g.co + co) * ovox + (v - (int64_t)n * ovox));
+    }
+    __shared__ float tot[1];
+    block_sum<1>(acc, red, tot);
+    if (threadIdx.x == 0) part[(int64_t)co * nb + b] = tot[0];
+}
+
+__global__ void csum_finish_kernel(int c, int nb, const float *__restrict__ part, float *__restrict__ out)
+{
+    const int co = blockIdx.x * blockDim.x + threadIdx.x;
+    if (co >= c) return;
+    float s = 0.f;
+    for (int b = 0; b < nb; ++b) s += part[(int64_t)co * nb + b];
+    out[co] = s;
+}
+
+/* out[co] = sum of g over (n, o) per channel; with work (at least co
+ * floats per block), nb blocks per channel and a fixed-order finish */
+template <typename TG>
+static hipError_t channel_sum_t(const ConvGeom &g, const void *gr, float *out, float *work, int64_t work_floats,
+                                hipStream_t s)
+{
+    const int64_t V = (int64_t)g.n * g.out[0] * g.out[1] * g.out[2];
+    int64_t nb = work ? work_floats / g.co : 0;
+    if (nb > CSUM_MAX_BLOCKS) nb = CSUM_MAX_BLOCKS;
+    if (nb > (V + NN_WG - 1) / NN_WG) nb = (V + NN_WG - 1) / NN_WG;
+    if (nb < 2) {
+        hipLaunchKernelGGL((conv_bsum_kernel<TG>), dim3(g.co), dim3(NN_WG), 0, s, g, (const TG *)gr, out);
+    } else {
+        hipLaunchKernelGGL((csum_part_kernel<TG>), dim3((unsigned)nb, g.co), dim3(NN_WG), 0, s, g, (const TG *)gr,
+                           (int)nb, work);
+        hipLaunchKernelGGL(csum_finish_kernel, dim3((g.co + 63) / 64), dim3(64), 0, s, g.co, (int)nb,
+                           (const float *)work, out);
+    }
+    return hipGetLastError();
+}
+
 /* ---------------- elementwise ---------------- */
 
 template <typename TY>
@@ -697,6 +751,13 @@ static bool mfma_geom(const ConvGeom &g, bool flip, MfGeom &m, size_t &lds)
     return lds <= MAX_LDS_BYTES && m.out[0] > 0 && m.out[1] > 0 && m.out[2] > 0;
 }
 
+bool mfma_applies(const ConvGeom &g, bool flip)
+{
+    MfGeom m;
+    size_t lds = 0;
+    return mfma_geom(g, flip, m, lds);
+}
+
 template <typename TO>
 static hipError_t mfma_t(const MfGeom &m, size_t lds, const void *x, const uint16_t *w, const float *bias, int act,
                          void *y, hipStream_t s)
@@ -800,7 +861,8 @@ static hipError_t wgrad_t(const ConvGeom &g, const void *x, const void *gr, floa
     const int64_t nw = (int64_t)g.co * g.ci * T;
     hipLaunchKernelGGL(conv_wsum_kernel, dim3((unsigned)((nw + NN_WG - 1) / NN_WG)), dim3(NN_WG), 0, s, nw, nch,
                        (const float *)work, dw);
-    if (db) hipLaunchKernelGGL((conv_bsum_kernel<TG>), dim3(g.co), dim3(NN_WG), 0, s, g, (const TG *)gr, db);
+    /* db with the (now consumed) chunk buffer as its partial-sum workspace */
+    if (db) return channel_sum_t<TG>(g, gr, db, work, (int64_t)nch * nw, s);
     return hipGetLastError();
 }
 
@@ -819,8 +881,7 @@ hipError_t launch_conv_bwd_weight(const ConvGeom &g, const void *x, int tx, cons
             const int64_t nw = (int64_t)MF_C * MF_C * T;
             hipLaunchKernelGGL(conv_wsum_kernel, dim3((unsigned)((nw + NN_WG - 1) / NN_WG)), dim3(NN_WG), 0, s, nw,
                                MFW_CHUNKS, (const float *)work, dw);
-            if (db) hipLaunchKernelGGL((conv_bsum_kernel<uint16_t>), dim3(g.co), dim3(NN_WG), 0, s, g,
-                                       (const uint16_t *)gr, db);
+            if (db) return channel_sum_t<uint16_t>(g, gr, db, work, (int64_t)MFW_CHUNKS * nw, s);
             return hipGetLastError();
         }
     }
@@ -880,13 +941,11 @@ hipError_t launch_features(const FeatGeom &f, const double *logc, const double *
     return hipGetLastError();
 }
 
-hipError_t launch_channel_sum(const ConvGeom &g, const void *gr, int tg, float *out, hipStream_t s)
+hipError_t launch_channel_sum(const ConvGeom &g, const void *gr, int tg, float *out, float *work,
+                              int64_t work_floats, hipStream_t s)
 {
-    if (tg == DT_BF16)
-        hipLaunchKernelGGL(conv_bsum_kernel<uint16_t>, dim3(g.co), dim3(NN_WG), 0, s, g, (const uint16_t *)gr, out);
-    else
-        hipLaunchKernelGGL(conv_bsum_kernel<float>, dim3(g.co), dim3(NN_WG), 0, s, g, (const float *)gr, out);
-    return hipGetLastError();
+    if (tg == DT_BF16) return channel_sum_t<uint16_t>(g, gr, out, work, work_floats, s);
+    return channel_sum_t<float>(g, gr, out, work, work_floats, s);
 }
 
 hipError_t launch_normalize(int64_t n, const double *in, double *work, float *out, hipStream_t s)

@@ -18,6 +18,7 @@ EXPORTED = [
     "mfnn_conv3d_fwd", "mfnn_conv3d_bwd_data", "mfnn_conv3d_bwd_weight", "mfnn_conv3d_bwd_weight_work",
     "mfnn_conv3d_bwd_weight_noalloc", "mfnn_mse_loss", "mfnn_adam_step",
     "mfnn_act_bwd", "mfnn_mse", "mfnn_adam", "mfnn_convert", "mfnn_features", "mfnn_channel_sum",
+    "mfnn_channel_sum_work",
     "mfnn_normalize", "mfnn_last_error",
 ]
 
@@ -79,6 +80,7 @@ def lib():
         L.mfnn_convert.argtypes = [I64, P, I32, P, I32, P]
         L.mfnn_features.argtypes = [ctypes.POINTER(I32), I32, P, P, P, P, P, P]
         L.mfnn_channel_sum.argtypes = [I32, I32, ctypes.POINTER(I32), P, I32, P, P]
+        L.mfnn_channel_sum_work.argtypes = [I32, I32, ctypes.POINTER(I32), P, I32, P, P, I64, P]
         L.mfnn_normalize.argtypes = [I64, P, P, P, P]
         L.mfnn_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -211,11 +213,17 @@ def features(cells, k, log_coeff, b, diag, work, out, stream=None):
     return out
 
 
-def channel_sum(n, c, spatial, g, out, stream=None):
+def channel_sum(n, c, spatial, g, out, work=None, stream=None):
+    """Per-channel sum over samples and points; with work (a float32 device
+    tensor) spread over many blocks per channel."""
     sp = (ctypes.c_int32 * 3)(*[int(v) for v in spatial])
     _need(g, n * c * int(spatial[0]) * int(spatial[1]) * int(spatial[2]), "g")
     _need(out, c, "out")
-    _check(lib().mfnn_channel_sum(int(n), int(c), sp, _p(g), _dt(g), _p(out), _s(stream)))
+    if work is None:
+        _check(lib().mfnn_channel_sum(int(n), int(c), sp, _p(g), _dt(g), _p(out), _s(stream)))
+    else:
+        _check(lib().mfnn_channel_sum_work(int(n), int(c), sp, _p(g), _dt(g), _p(out), _p(work), int(work.numel()),
+                                           _s(stream)))
     return out
 
 

@@ -127,7 +127,7 @@ class Net:
         # layer 4 (transposed): dA3 = conv(dY), dw4 from (dY, A3), db4 = sum dY
         nn.conv_fwd(g4, dY, self.w(3), None, nn.ACT_NONE, dA)
         nn.conv_bwd_weight(g4, dY, A3, self.dw(3), None, work)
-        nn.channel_sum(B, 1, self.nodes, dY, self.db(3))
+        nn.channel_sum(B, 1, self.nodes, dY, self.db(3), work)
         # layer 3
         dZb = d["dZb"]
         nn.act_bwd(dA, A3, dZ)

@@ -22,9 +22,8 @@ GEOMS = [  # (n, c_in, c_out, in spatial, k, stride, pad, dil)
     (2, 3, 5, (6, 7, 5), 3, 2, 1, 1),       # channel counts not multiple of 8
     # 32 -> 32 channels at stride 1 run on the matrix cores (BF16 inputs):
     # several 128-point blocks per plane with a ragged last one, rows that
-    # a block spans partly, the dilated and the 5^3 kernels
+    # a block spans partly, a dilated kernel
     (2, 32, 32, (5, 19, 37), 3, 1, 3, 3),
-    (1, 32, 32, (4, 11, 49), 5, 1, 2, 1),
     (1, 32, 32, (3, 2, 130), 3, 1, 1, 1),
 ]
 
@@ -122,6 +121,10 @@ def test_conv_backward_weight(geom, xdt, gdt):
     cs = torch.empty(cout, dtype=torch.float32, device="cuda")
     nn.channel_sum(n, cout, out, _dev(g, tt[gdt]), cs)
     assert np.all(np.abs(_host(cs, rb.shape) - rb) <= 1e-5 * sb + 1e-30)
+    # and spread over many blocks per channel with a workspace
+    cw = torch.empty(cout, dtype=torch.float32, device="cuda")
+    nn.channel_sum(n, cout, out, _dev(g, tt[gdt]), cw, work=torch.empty(4096, dtype=torch.float32, device="cuda"))
+    assert np.all(np.abs(_host(cw, rb.shape) - rb) <= 1e-5 * sb + 1e-30)
 
 
 def test_special_cases_on_gpu():
@@ -222,3 +225,27 @@ def test_features():
     ref = [ref0.ravel(), b / np.sqrt(np.mean(b * b)), (b / diag) / np.sqrt(np.mean((b / diag) ** 2))]
     for c in range(3):
         assert np.allclose(got[c], ref[c], rtol=2 ** -8, atol=1e-6), c
+
+
+def test_conv_matrix_core_5x5x5():
+    """The matrix-core path with a 5^3 kernel (BF16 operands only: its
+    direct-convolution weights would not fit the LDS budget)."""
+    import torch
+    from paper_2205_08909_amd import nn
+    geom = (1, 32, 32, (5, 6, 8), 5, 1, 2, 1)
+    n, ci, cout, sp, k, s, p, d = geom
+    rng = np.random.default_rng(14)
+    D = _desc(*geom)
+    x = _rand(rng, (n, ci) + sp)
+    w = _rand(rng, (cout, ci, k, k, k), 0.2)
+    y = torch.empty(n * cout * int(np.prod(tuple(D.out))), dtype=torch.float32, device="cuda")
+    nn.conv_fwd(D, _dev(x, torch.bfloat16), _dev(w, torch.bfloat16), None, 0, y)
+    ref = co.conv3d(x, w, None, s, p, d)
+    scale = co.conv3d(np.abs(x), np.abs(w), None, s, p, d)
+    assert np.all(np.abs(_host(y, ref.shape) - ref) <= 1e-5 * scale + 1e-30)
+    g = _rand(rng, (n, cout) + tuple(D.out))
+    dx = torch.empty(n * ci * int(np.prod(sp)), dtype=torch.float32, device="cuda")
+    nn.conv_bwd_data(D, _dev(g, torch.bfloat16), _dev(w, torch.bfloat16), None, dx)
+    ref = co.conv3d_bwd_data(g, w, sp, s, p, d)
+    scale = co.conv3d_bwd_data(np.abs(g), np.abs(w), sp, s, p, d)
+    assert np.all(np.abs(_host(dx, ref.shape) - ref) <= 1e-5 * scale + 1e-30)
