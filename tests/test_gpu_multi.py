@@ -123,3 +123,23 @@ def test_multi_reuses_buffers_and_rejects_bad_m(oracle_mod, torch_cuda):
     many = [bs[0]] * (mfcg.MULTI_MAX + 1)
     with pytest.raises(ValueError):
         P.solve_multi(many, [torch.zeros_like(bs[0]) for _ in many], tol=1e-10)
+
+
+def test_multi_fullsize_equals_single_solves(torch_cuda):
+    """At the benchmark's size (Q4, 64^3 curved cells, default tiles), m = 3
+    right-hand sides for a few iterations in the launch configuration the
+    benchmark times: each equals its single solve bitwise (the operator and
+    the solve at this size are pinned against the oracle by the full-size
+    tests)."""
+    torch = torch_cuda
+    from paper_2205_08909_amd import mfcg
+    P = mfcg.Problem(64, 4, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05)
+    bs = [torch.from_numpy(inputs.random_rhs(64, 4, seed=90 + c)).cuda() for c in range(3)]
+    for maxit in (3, 4):
+        ref = _singles(torch, P, bs, [torch.zeros_like(bs[0]) for _ in bs], 1e-12, maxit)
+        xs = [torch.zeros_like(bs[0]) for _ in bs]
+        code, its, status, _ = P.solve_multi(bs, xs, tol=1e-12, maxit=maxit)
+        assert code == mfcg.ENOTCONV and its == [maxit] * 3
+        for c in range(3):
+            assert torch.equal(xs[c], ref[c][2]), f"rhs {c} maxit {maxit}"
+    P.close()
