@@ -1577,18 +1577,19 @@ int mfcg_autotune_tile(const mfcg_mesh *mesh, int32_t degree, int32_t iters, int
     int tx = 0, ty = 0;
     tile_limits(degree, &tx, &ty);
     /* candidates: the compiled maximum extent in x and y; in z 8, 16 or 32
-     * cell layers, or the mesh split into 1..8 equal tile layers (tile counts
-     * that fill the resident workgroup slots evenly); half the x/y extent
-     * with 16 layers as a check */
+     * cell layers, or the mesh split into 1..12 equal tile layers of at
+     * least 2 cells (tile counts that fill the resident workgroup slots
+     * evenly; the shallow ones for small meshes); half the x/y extent with
+     * 16 layers as a check */
     std::vector<std::array<int, 3>> cand;
     auto add = [&](int h, int z) {
         std::array<int, 3> t = {std::min(h, mesh->cells[0]), std::min(h, mesh->cells[1]), std::min(z, mesh->cells[2])};
         if (t[2] >= 1 && std::find(cand.begin(), cand.end(), t) == cand.end()) cand.push_back(t);
     };
     for (int z : {8, 16, 32}) add(tx, z);
-    for (int m = 1; m <= 8; ++m) {
+    for (int m = 1; m <= 12; ++m) {
         const int z = (mesh->cells[2] + m - 1) / m;
-        if (z >= 4 && z <= 64) add(tx, z);
+        if (z >= 2 && z <= 64) add(tx, z);
     }
     add((tx + 1) / 2, 16);
     int64_t n = 1;
