@@ -104,13 +104,16 @@ def test_autotune_returns_a_candidate():
     from paper_2205_08909_amd import mfcg
     tile, ms = mfcg.autotune_tile(12, 4, map_kind=1, amplitude=0.05, iters=3)
     assert ms > 0
-    # x/y: the compiled maximum (4) or half of it; z: 8, 12 (clipped 16/32, or 1 layer), 6, 4
-    assert tile[:2] in ((4, 4), (2, 2)) and tile[2] in (4, 6, 8, 12)
+    # x/y: the compiled maximum (4) or half of it; z: 8, 12 (clipped 16/32, or 1 layer), or the
+    # mesh split into 2..12 equal layers of at least 2 cells: 6, 4, 3, 2
+    assert tile[:2] in ((4, 4), (2, 2)) and tile[2] in (2, 3, 4, 6, 8, 12)
 
 
-def test_batch_mixed_own_and_packed_launches():
-    """One problem large enough for its own launches (>= 512 tiles) beside
-    packed small ones: still bitwise the single-problem results."""
+def test_batch_mixed_large_and_small_problems():
+    """One problem large enough to fill the device alone (>= 512 tiles)
+    beside small ones of other degrees, their fused launches running side by
+    side on the batch's per-degree streams: still bitwise the single-problem
+    results."""
     import torch
     from paper_2205_08909_amd import mfcg
     probs = [{"cells": (32, 32, 32), "degree": 6, "map_kind": 1, "amplitude": 0.05, "seed": 1},
