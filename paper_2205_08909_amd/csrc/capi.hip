@@ -1650,8 +1650,6 @@ struct mfcg_batch_ctx {
     int2 *d_items = nullptr;   /* all fused-kernel items, grouped by degree */
     int2 *d_shared = nullptr;  /* shared-node items */
     int *d_active = nullptr;
-    BatchStreams cs{};           /* side streams of the per-degree launches */
-    bool cs_ok = false;
     CGState *d_states = nullptr; /* gathered solver states of all problems */
     CGState *h_states = nullptr; /* pinned host copy */
     int64_t max_items = 0, max_shared = 0;
@@ -1669,13 +1667,6 @@ static void batch_release(mfcg_batch_ctx *hb)
     (void)hipFree(hb->d_active);
     (void)hipFree(hb->d_states);
     if (hb->h_states) (void)hipHostFree(hb->h_states);
-    if (hb->cs_ok) {
-        for (int K = 0; K <= 8; ++K) {
-            if (hb->cs.side[K]) (void)hipStreamDestroy(hb->cs.side[K]);
-            if (hb->cs.done[K]) (void)hipEventDestroy(hb->cs.done[K]);
-        }
-        if (hb->cs.start) (void)hipEventDestroy(hb->cs.start);
-    }
 }
 
 static int batch_fail(mfcg_batch_ctx *hb, int code, const std::string &msg)
@@ -1888,15 +1879,6 @@ static int batch_setup_impl(int32_t nprob, const mfcg_mesh *meshes, const int32_
     if ((e = dalloc(&hb->d_states, nprob)) != hipSuccess) return bail(e);
     if ((e = hipHostMalloc((void **)&hb->h_states, sizeof(CGState) * nprob, hipHostMallocDefault)) != hipSuccess)
         return bail(e);
-    hb->cs_ok = true;
-    if ((e = hipEventCreateWithFlags(&hb->cs.start, hipEventDisableTiming)) != hipSuccess) return bail(e);
-    for (int K = 1; K <= 8; ++K) {
-        bool used = false;
-        for (int i = 0; i < nprob; ++i) used = used || degrees[i] == K;
-        if (!used) continue;
-        if ((e = hipStreamCreateWithFlags(&hb->cs.side[K], hipStreamNonBlocking)) != hipSuccess) return bail(e);
-        if ((e = hipEventCreateWithFlags(&hb->cs.done[K], hipEventDisableTiming)) != hipSuccess) return bail(e);
-    }
     *out = hb;
     return MFCG_OK;
 }
@@ -2006,7 +1988,7 @@ int mfcg_batch_solve(mfcg_batch hb, const double *const *b, double *const *x, do
         bl.active = hb->d_active;
         bl.nactive = (int)active.size();
         const int chunk = std::min(hb->check_every, maxit - launched);
-        for (int it = 0; it < chunk; ++it) BCHK(hb, launch_batch_iteration(bl, s, &hb->cs));
+        for (int it = 0; it < chunk; ++it) BCHK(hb, launch_batch_iteration(bl, s));
         launched += chunk;
         rc = poll();
         if (rc) return rc;

@@ -58,13 +58,7 @@ struct BatchLaunch {
     const int *active;
     int nactive;
 };
-/* side streams (default priority) and events of a batch: with them the
- * per-degree fused launches of one iteration run concurrently */
-struct BatchStreams {
-    hipStream_t side[9];
-    hipEvent_t start, done[9];
-};
-hipError_t launch_batch_iteration(const BatchLaunch &b, hipStream_t s, const BatchStreams *cs = nullptr);
+hipError_t launch_batch_iteration(const BatchLaunch &b, hipStream_t s);
 /* out[i] = *probs[i].st, i < np (one launch instead of np small copies) */
 hipError_t launch_gather_states(const IterArgs<double> *probs, int np, CGState *out, hipStream_t s);
 

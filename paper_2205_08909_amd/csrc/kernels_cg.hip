@@ -325,35 +325,20 @@ hipError_t launch_finish_parts(const IterArgs<double> &a, int64_t nparts, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_batch_iteration(const BatchLaunch &b, hipStream_t s, const BatchStreams *cs)
+hipError_t launch_batch_iteration(const BatchLaunch &b, hipStream_t s)
 {
-    int nk = 0;
-    for (int K = 1; K <= 8; ++K) nk += b.nitems[K] > 0;
-    /* the degrees' fused launches touch different problems: with side
-     * streams they run side by side (forked from and joined back into s by
-     * events), so a small degree's launch fills the device next to a large
-     * one's instead of after it */
-    const bool conc = cs && nk > 1;
-    hipError_t e = hipSuccess;
-    if (conc && (e = hipEventRecord(cs->start, s)) != hipSuccess) return e;
     for (int K = 1; K <= 8; ++K) {
         const int ni = b.nitems[K];
         if (ni == 0) continue;
-        hipStream_t ks = conc ? cs->side[K] : s;
-        if (conc && (e = hipStreamWaitEvent(ks, cs->start, 0)) != hipSuccess) return e;
         switch (K) {
-        case 1: FusedDeg<1>::batch(b.probs, b.items[K], ni, ks); break;
-        case 2: FusedDeg<2>::batch(b.probs, b.items[K], ni, ks); break;
-        case 3: FusedDeg<3>::batch(b.probs, b.items[K], ni, ks); break;
-        case 4: FusedDeg<4>::batch(b.probs, b.items[K], ni, ks); break;
-        case 5: FusedDeg<5>::batch(b.probs, b.items[K], ni, ks); break;
-        case 6: FusedDeg<6>::batch(b.probs, b.items[K], ni, ks); break;
-        case 7: FusedDeg<7>::batch(b.probs, b.items[K], ni, ks); break;
-        case 8: FusedDeg<8>::batch(b.probs, b.items[K], ni, ks); break;
-        }
-        if (conc) {
-            if ((e = hipEventRecord(cs->done[K], ks)) != hipSuccess) return e;
-            if ((e = hipStreamWaitEvent(s, cs->done[K], 0)) != hipSuccess) return e;
+        case 1: FusedDeg<1>::batch(b.probs, b.items[K], ni, s); break;
+        case 2: FusedDeg<2>::batch(b.probs, b.items[K], ni, s); break;
+        case 3: FusedDeg<3>::batch(b.probs, b.items[K], ni, s); break;
+        case 4: FusedDeg<4>::batch(b.probs, b.items[K], ni, s); break;
+        case 5: FusedDeg<5>::batch(b.probs, b.items[K], ni, s); break;
+        case 6: FusedDeg<6>::batch(b.probs, b.items[K], ni, s); break;
+        case 7: FusedDeg<7>::batch(b.probs, b.items[K], ni, s); break;
+        case 8: FusedDeg<8>::batch(b.probs, b.items[K], ni, s); break;
         }
     }
     if (b.nshared_items > 0)

@@ -111,9 +111,8 @@ def test_autotune_returns_a_candidate():
 
 def test_batch_mixed_large_and_small_problems():
     """One problem large enough to fill the device alone (>= 512 tiles)
-    beside small ones of other degrees, their fused launches running side by
-    side on the batch's per-degree streams: still bitwise the single-problem
-    results."""
+    beside small ones of other degrees in the same work lists: still bitwise
+    the single-problem results."""
     import torch
     from paper_2205_08909_amd import mfcg
     probs = [{"cells": (32, 32, 32), "degree": 6, "map_kind": 1, "amplitude": 0.05, "seed": 1},
