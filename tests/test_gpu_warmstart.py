@@ -4,9 +4,12 @@ solver entry points it relies on (mfcg_set_coefficient, mfcg_warmstart).
 The network's quality has no reference (the paper has no learned part):
 it is judged by the CG residual only.  Checked here: the Galerkin-scaled
 guess never has a larger A-norm error than x0 = 0 (exactly, by
-construction), the solver still reaches 1e-10 from it, and a network
-trained for a few seconds on solver solutions saves iterations on held-out
-seeds on average.
+construction), the solver still reaches 1e-10 from it, a network trained
+for a few seconds on solver solutions saves iterations on held-out seeds
+on average, the coarse-level guess saves at least 3% of the iterations on
+every seed of the reduced replica, and the A-norm optimal combination is
+never worse than either guess; the interpolation and the span projection
+against the oracle.
 """
 import numpy as np
 import pytest
@@ -100,6 +103,9 @@ def test_trained_network_saves_iterations():
             assert r[name]["status"] == mfcg.OK and r[name]["true_rel_res"] <= 1e-10
     assert s["learned"]["iters"]["mean"] < s["zero"]["iters"]["mean"]
     assert s["coarse_plus_learned"]["iters"]["mean"] < s["zero"]["iters"]["mean"]
+    # the coarse level on this reduced replica (measured 0.936, no seed worse; 0.854 at
+    # the full 48^3 workload, where the smooth error is a larger share of the iterations)
+    assert s["coarse"]["iter_ratio_mean"] <= 0.97 and s["coarse"]["worse_than_zero"] == 0
     coarse.close()
     P.close()
 
