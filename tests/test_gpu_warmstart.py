@@ -7,7 +7,8 @@ guess never has a larger A-norm error than x0 = 0 (exactly, by
 construction), the solver still reaches 1e-10 from it, a network trained
 for a few seconds on solver solutions saves iterations on held-out seeds
 on average, the coarse-level guess saves at least 3% of the iterations on
-every seed of the reduced replica, and the A-norm optimal combination is
+average and is worse on no seed of the reduced replica, the A-norm optimal
+combination is
 never worse than either guess; the interpolation and the span projection
 against the oracle.
 """
