@@ -69,9 +69,9 @@ template <int K>
 struct Cfg;
 template <> struct Cfg<1> { static constexpr int TX = 8, TY = 8, WG = 256, GPREF = 0, OCC = 2, CARRY = 0; };
 template <> struct Cfg<2> { static constexpr int TX = 8, TY = 8, WG = 576, GPREF = 0, OCC = 2, CARRY = 0; };
-template <> struct Cfg<3> { static constexpr int TX = 5, TY = 5, WG = 448, GPREF = 0, OCC = 2, CARRY = 1; };
+template <> struct Cfg<3> { static constexpr int TX = 5, TY = 5, WG = 448, GPREF = 0, OCC = 3, CARRY = 1; };
 template <> struct Cfg<4> { static constexpr int TX = 4, TY = 4, WG = 448, GPREF = 0, OCC = 2, CARRY = 1; };
-template <> struct Cfg<5> { static constexpr int TX = 3, TY = 3, WG = 384, GPREF = 0, OCC = 3, CARRY = 1; };
+template <> struct Cfg<5> { static constexpr int TX = 3, TY = 3, WG = 384, GPREF = 0, OCC = 2, CARRY = 1; };
 template <> struct Cfg<6> { static constexpr int TX = 2, TY = 2, WG = 256, GPREF = 0, OCC = 2, CARRY = 1; };
 template <> struct Cfg<7> { static constexpr int TX = 2, TY = 2, WG = 256, GPREF = 1, OCC = 2, CARRY = 1; };
 template <> struct Cfg<8> { static constexpr int TX = 2, TY = 2, WG = 384, GPREF = 0, OCC = 1, CARRY = 0; };
@@ -129,9 +129,9 @@ constexpr int WPE_QGQ2[8] = {0, 2, 3, 2, 2, 3, 2, 2};
                                                                       : WPE_Q2[(K) < 8 ? (K) : 0])                   \
           : ((OPV) == OPV_LAPLACE_QGEOM ? WPE_QG[(K) < 9 ? (K) : 0]                                                 \
                                         : ((OPV) == OPV_MASS_QGEOM ? WPE_QGM[(K) < 9 ? (K) : 0] : MFCG_WPE_MIN(K))))
-/* the batch kernel holds more uniform values (its arguments come from
- * memory): it asks for at most two workgroups per CU to avoid spills */
-#define MFCG_WPE_MIN_BATCH(K) (((MFCG_OCC_OF(K) < 2 ? MFCG_OCC_OF(K) : 2) * Cfg<K>::WG / 64 + 3) / 4)
+/* the batch kernel reads its arguments through the global-address-space
+ * view and needs the registers of the single-problem kernel */
+#define MFCG_WPE_MIN_BATCH(K) MFCG_WPE_MIN(K)
 
 /* ------------------------------------------------------------------ */
 /* Helpers                                                             */
