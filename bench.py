@@ -254,18 +254,17 @@ def batch_experiment(args):
 
 def sweep_block(args, torch, mfcg):
     """Degree sweep of the default run: k = 1..8 at about 1e7 DoFs
-    (N = round(216 / k)), the per-degree default tiles, curved mesh, a = 1,
-    random-normal right-hand side, tol = 0: time per iteration without
-    per-launch events and the fraction of 8 TB/s by the per-DoF bytes of the
+    (N = round(216 / k)), curved mesh, a = 1, random-normal right-hand side,
+    tol = 0: time per iteration without per-launch events, with the tile the
+    library's autotuner picks for the mesh (and, beside it, the per-degree
+    default tile), and the fraction of 8 TB/s by the per-DoF bytes of the
     fused method (4.5 + 3.5 vector entries plus the stored G)."""
     from paper_2205_08909_amd import inputs
     rows = []
     S, W = args.extra_steps, 3
-    for k in range(1, 9):
-        N = round(216 / k)
-        P = mfcg.Problem(N, k, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05)
-        n = P.n
-        b = torch.from_numpy(inputs.random_rhs(N, k, seed=7)).cuda()
+
+    def time_tile(N, k, tile, b):
+        P = mfcg.Problem(N, k, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05, tile=tile)
         P.cg_begin(b, None, tol=0.0, maxit=W + S)
         P.cg_iterate(W)
         torch.cuda.synchronize()
@@ -276,18 +275,31 @@ def sweep_block(args, torch, mfcg):
         x = torch.empty_like(b)
         code, its, _ = P.cg_end(x)
         assert its == W + S, (k, code, its)
+        used = list(P.layout_info()["tile"])
+        P.close()
+        return wall, used
+
+    for k in range(1, 9):
+        N = round(216 / k)
+        b = torch.from_numpy(inputs.random_rhs(N, k, seed=7)).cuda()
+        n = b.numel()
+        t0 = time.perf_counter()
+        tile, _ = mfcg.autotune_tile(N, k, map_kind=mfcg.MAP_SINE_SHEAR, amplitude=0.05, iters=6)
+        tune_s = time.perf_counter() - t0
+        wall, used = time_tile(N, k, tile, b)
+        wall_d, used_d = time_tile(N, k, None, b)
         it_bytes = 64 * n + 8 * 6 * (k + 1) ** 3 * N ** 3
-        row = {"k": k, "cells": N, "n_dofs": n, "tile": list(P.layout_info()["tile"]),
+        row = {"k": k, "cells": N, "n_dofs": n, "tile": used, "autotune_s": round(tune_s, 2),
                "ms_per_iter": round(wall * 1e3 / S, 4), "GDoF_it_s": round(n * S / wall / 1e9, 3),
                "bytes_per_dof": round(it_bytes / n, 2),
-               "frac_8TBs": round(it_bytes * S / wall / 1e9 / HBM_PEAK_GBS, 4)}
+               "frac_8TBs": round(it_bytes * S / wall / 1e9 / HBM_PEAK_GBS, 4),
+               "default_tile": used_d, "default_tile_GDoF_it_s": round(n * S / wall_d / 1e9, 3)}
         print(f"[bench] sweep {row}", file=sys.stderr, flush=True)
         rows.append(row)
-        del b, x
-        P.close()
+        del b
         torch.cuda.empty_cache()
     return {"workload": "fused FP64 CG iteration, curved mesh (sine shear 0.05), a = 1, about 1e7 DoFs per "
-                        "degree, default tiles", "steps": S, "rows": rows}
+                        "degree, autotuned tiles (default tiles beside)", "steps": S, "rows": rows}
 
 
 def batch_block(args, torch, mfcg):
