@@ -73,7 +73,8 @@ struct mfcg_ctx {
     double *rM = nullptr, *pM = nullptr, *vM = nullptr, *xM = nullptr, *dotsM = nullptr, *partM = nullptr;
     double *histM = nullptr;
     CGState *stM = nullptr;
-    int mcap = 0, histM_cap = 0;
+    int mcap = 0;
+    int64_t histM_cap = 0;
     int nshared_blocks = 1;
     int nsum_blocks = 1;
     /* solve bookkeeping */
@@ -1125,7 +1126,7 @@ int mfcg_solve_multi(mfcg_handle h, int32_t m, const double *const *b, double *c
         if (h->histM) HIPCHK(h, hipFree(h->histM));
         h->histM = nullptr;
         HIPCHK(h, dalloc(&h->histM, (size_t)m * (maxit + 1)));
-        h->histM_cap = m * (maxit + 1);
+        h->histM_cap = (int64_t)m * (maxit + 1);
     }
     const int64_t hs = (int64_t)maxit + 1;
     std::vector<CGState> st(m);
