@@ -800,10 +800,98 @@ hipError_t launch_conv_fwd(const ConvGeom &g, const void *x, int tx, const uint1
     return fwd_t<float, float>(g, x, w, bias, act, y, s);
 }
 
+/* The data gradient of a stride-4 convolution with an 8^3 kernel and
+ * padding 4 onto one input channel: the network's last layer (a transposed
+ * convolution from the coarse grid to the nodes).  Fine index i = 4 a + r
+ * (r = 0..3) receives from coarse points a (tap r + 4) and a + 1 (tap r) in
+ * every direction, so one thread owns the 4^3 fine points of block a and
+ * reads the 8 coarse values they share once per channel; the weights of a
+ * channel (512 taps) are read from LDS as broadcasts.  The direct kernel
+ * re-reads every coarse value for each of its fine points. */
+constexpr int T4_MAXC = 32;
+
+template <typename TG, typename TO>
+__global__ __launch_bounds__(NN_WG) void tconv_s4k8_kernel(const ConvGeom g, const TG *__restrict__ gr,
+                                                           const uint16_t *__restrict__ w,
+                                                           const float *__restrict__ bias_in, TO *__restrict__ dx)
+{
+    __shared__ uint16_t wl[T4_MAXC * 512];
+    for (int e = threadIdx.x; e < g.co * 512; e += NN_WG) wl[e] = w[e]; /* w[co][0][tz][ty][tx] */
+    __syncthreads();
+    const int bx = (g.in[2] + 3) / 4, by = (g.in[1] + 3) / 4, bz = (g.in[0] + 3) / 4;
+    const int64_t nb = (int64_t)bx * by * bz;
+    const int64_t t = (int64_t)blockIdx.x * NN_WG + threadIdx.x;
+    if (t >= (int64_t)g.n * nb) return;
+    const int n = (int)(t / nb);
+    int64_t rem = t - (int64_t)n * nb;
+    const int ax = (int)(rem % bx);
+    rem /= bx;
+    const int ay = (int)(rem % by), az = (int)(rem / by);
+    const int64_t ovox = (int64_t)g.out[0] * g.out[1] * g.out[2];
+    float acc[4][4][4];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) acc[i >> 4][(i >> 2) & 3][i & 3] = 0.f;
+    for (int co = 0; co < g.co; ++co) {
+        const TG *gc = gr + ((int64_t)n * g.co + co) * ovox;
+        float gv[2][2][2];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int oz = az + (j >> 2), oy = ay + ((j >> 1) & 1), ox = ax + (j & 1);
+            gv[j >> 2][(j >> 1) & 1][j & 1] =
+                (oz < g.out[0] && oy < g.out[1] && ox < g.out[2])
+                    ? load_f(gc, ((int64_t)oz * g.out[1] + oy) * g.out[2] + ox)
+                    : 0.f;
+        }
+        const uint16_t *wc = wl + co * 512;
+#pragma unroll
+        for (int rz = 0; rz < 4; ++rz)
+#pragma unroll
+            for (int ry = 0; ry < 4; ++ry)
+#pragma unroll
+                for (int rx = 0; rx < 4; ++rx) {
+                    float a = acc[rz][ry][rx];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const int jz = j >> 2, jy = (j >> 1) & 1, jx = j & 1;
+                        /* coarse a (j = 0): tap r + 4; coarse a + 1 (j = 1): tap r */
+                        const int tz = rz + 4 * (1 - jz), ty = ry + 4 * (1 - jy), tx = rx + 4 * (1 - jx);
+                        a = fmaf(bf16_to_f32(wc[(tz * 8 + ty) * 8 + tx]), gv[jz][jy][jx], a);
+                    }
+                    acc[rz][ry][rx] = a;
+                }
+    }
+    const float b0 = bias_in ? bias_in[0] : 0.f;
+    const int64_t ivox = (int64_t)g.in[0] * g.in[1] * g.in[2];
+#pragma unroll
+    for (int rz = 0; rz < 4; ++rz)
+#pragma unroll
+        for (int ry = 0; ry < 4; ++ry)
+#pragma unroll
+            for (int rx = 0; rx < 4; ++rx) {
+                const int iz = 4 * az + rz, iy = 4 * ay + ry, ix = 4 * ax + rx;
+                if (iz < g.in[0] && iy < g.in[1] && ix < g.in[2])
+                    store_f(dx, (int64_t)n * ivox + ((int64_t)iz * g.in[1] + iy) * g.in[2] + ix, acc[rz][ry][rx] + b0);
+            }
+}
+
+static bool tconv_s4k8(const ConvGeom &g)
+{
+    if (g.ci != 1 || g.co < 1 || g.co > T4_MAXC) return false;
+    for (int i = 0; i < 3; ++i)
+        if (g.k[i] != 8 || g.s[i] != 4 || g.p[i] != 4 || g.d[i] != 1) return false;
+    return true;
+}
+
 template <typename TG, typename TO>
 static hipError_t bwd_data_t(const ConvGeom &g, const void *gr, const uint16_t *w, const float *bias, void *dx,
                              hipStream_t s)
 {
+    if (tconv_s4k8(g)) {
+        const int64_t tot = (int64_t)g.n * ((g.in[0] + 3) / 4) * ((g.in[1] + 3) / 4) * ((g.in[2] + 3) / 4);
+        hipLaunchKernelGGL((tconv_s4k8_kernel<TG, TO>), dim3((unsigned)((tot + NN_WG - 1) / NN_WG)), dim3(NN_WG), 0, s,
+                           g, (const TG *)gr, w, bias, (TO *)dx);
+        return hipGetLastError();
+    }
     const int T = g.k[0] * g.k[1] * g.k[2];
     const int64_t tot = (int64_t)g.n * g.in[0] * g.in[1] * g.in[2];
     const unsigned gx = (unsigned)((tot + NN_WG - 1) / NN_WG);
