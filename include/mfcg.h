@@ -303,8 +303,10 @@ int mfcg_solve_vector(mfcg_handle h, const double *b, double *x, double tol, int
  *   true_rel_res  host, m doubles or NULL: ||b_c - A x_c|| / ||b_c||
  * Each right-hand side follows exactly the iteration of mfcg_solve with the
  * Jacobi preconditioner on this handle's operator variant.  Allocates 4 m n
- * doubles of work vectors at the first call with this m or a larger one
- * (kept by the handle).  Ends a stepping-interface solve in progress.
+ * doubles of work vectors at the first call with this m or a larger one,
+ * and m (maxit + 1) doubles of residual history when maxit grows (both
+ * kept by the handle; ENOMEM when the device cannot hold them, after which
+ * the handle stays usable).  Ends a stepping-interface solve in progress.
  * Returns MFCG_OK when every right-hand side converged, else the first
  * non-OK status (ENOTCONV or EBREAKDOWN; the per-right-hand-side results
  * are filled in either case); EINVAL for bad arguments; ENOMEM, EHIP.

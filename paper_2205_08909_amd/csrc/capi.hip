@@ -84,10 +84,11 @@ struct mfcg_ctx {
     bool zero_rhs = false;
     /* FP32 copy of the operator and FP32 work vectors (iterative refinement) */
     float *G32 = nullptr, *dinv32 = nullptr;
+    bool fp32_ready = false; /* the FP32 buffers below are allocated and converted */
     float *r32 = nullptr, *p32 = nullptr, *v32 = nullptr, *x32 = nullptr, *part32 = nullptr, *dots32 = nullptr;
     CGState *st32 = nullptr;
     double *hist32 = nullptr;
-    int hist32_cap = 0;
+    int64_t hist32_cap = 0;
     /* timing */
     bool timing = false;
     std::vector<EventPair> ev_fused, ev_shared, ev_pool;
@@ -274,7 +275,7 @@ static int rebuild_operator(mfcg_ctx *h, hipStream_t s)
     }
     HIPCHK(h, launch_geometry(g, h->G, s));
     HIPCHK(h, launch_diagonal(g, h->G, h->diag_lex, h->dinv, s));
-    if (h->G32) {
+    if (h->fp32_ready) {
         HIPCHK(h, launch_convert(h->hl.g_elems, h->G, h->G32, s));
         HIPCHK(h, launch_convert(h->hl.n, h->dinv, h->dinv32, s));
     }
@@ -825,7 +826,12 @@ int mfcg_set_sstep(mfcg_handle h, int32_t s)
  * solvers, grown on demand. */
 static int ensure_krylov(mfcg_ctx *h, int64_t nvec, hipStream_t s)
 {
-    if (!h->kpart) {
+    if (!h->kpart || !h->ks) {
+        HIPCHK(h, hipStreamSynchronize(s));
+        if (h->kpart) HIPCHK(h, hipFree(h->kpart));
+        if (h->ks) HIPCHK(h, hipFree(h->ks));
+        h->kpart = nullptr;
+        h->ks = nullptr;
         HIPCHK(h, dalloc(&h->kpart, (size_t)MAX_VEC_BLOCKS * SSTEP_REC));
         HIPCHK(h, dalloc(&h->ks, 1));
     }
@@ -888,6 +894,7 @@ int mfcg_cg_begin(mfcg_handle h, const double *b, const double *x0, double tol, 
         HIPCHK(h, hipStreamSynchronize(s));
         HIPCHK(h, hipFree(h->hist));
         h->hist = nullptr;
+        h->hist_cap = 0; /* a failed allocation leaves no buffer behind */
         HIPCHK(h, dalloc(&h->hist, (size_t)maxit + 1));
         h->hist_cap = maxit;
     }
@@ -1121,14 +1128,17 @@ int mfcg_solve_multi(mfcg_handle h, int32_t m, const double *const *b, double *c
         HIPCHK(h, hipMemsetAsync(h->partM, 0, sizeof(double) * m * ps, s));
         h->mcap = m;
     }
-    if ((int64_t)m * (maxit + 1) > (int64_t)h->histM_cap) {
+    /* history entries per right-hand side, in 64 bits (maxit + 1 overflows
+     * 32 bits at maxit = INT32_MAX) */
+    const int64_t hs = (int64_t)maxit + 1;
+    if ((int64_t)m * hs > h->histM_cap) {
         HIPCHK(h, hipStreamSynchronize(s));
         if (h->histM) HIPCHK(h, hipFree(h->histM));
         h->histM = nullptr;
-        HIPCHK(h, dalloc(&h->histM, (size_t)m * (maxit + 1)));
-        h->histM_cap = (int64_t)m * (maxit + 1);
+        h->histM_cap = 0;
+        HIPCHK(h, dalloc(&h->histM, (size_t)((int64_t)m * hs)));
+        h->histM_cap = (int64_t)m * hs;
     }
-    const int64_t hs = (int64_t)maxit + 1;
     std::vector<CGState> st(m);
     std::vector<char> zero(m, 0);
     for (int c = 0; c < m; ++c) {
@@ -1240,7 +1250,13 @@ int mfcg_solve_vector(mfcg_handle h, const double *b, double *x, double tol, int
     /* the device CG state is reused: a scalar solve in progress ends here */
     h->maxit = 0;
     h->launched = 0;
-    if (!h->r3) {
+    if (!h->r3 || !h->p3 || !h->v3 || !h->x3 || !h->dots3 || !h->part3) {
+        /* all or nothing: after a failed allocation the next call starts over */
+        HIPCHK(h, hipStreamSynchronize(s));
+        double *bufs[] = {h->r3, h->p3, h->v3, h->x3, h->dots3, h->part3};
+        for (double *q : bufs)
+            if (q) HIPCHK(h, hipFree(q));
+        h->r3 = h->p3 = h->v3 = h->x3 = h->dots3 = h->part3 = nullptr;
         HIPCHK(h, dalloc(&h->r3, 3 * n));
         HIPCHK(h, dalloc(&h->p3, 3 * n));
         HIPCHK(h, dalloc(&h->v3, 3 * n));
@@ -1253,6 +1269,7 @@ int mfcg_solve_vector(mfcg_handle h, const double *b, double *x, double tol, int
         HIPCHK(h, hipStreamSynchronize(s));
         HIPCHK(h, hipFree(h->hist));
         h->hist = nullptr;
+        h->hist_cap = 0; /* a failed allocation leaves no buffer behind */
         HIPCHK(h, dalloc(&h->hist, (size_t)maxit + 1));
         h->hist_cap = maxit;
     }
@@ -1386,11 +1403,18 @@ int mfcg_solve(mfcg_handle h, const double *b, double *x, double tol, int32_t ma
  * vectors, built on first use. */
 static int ensure_fp32(mfcg_ctx *h, hipStream_t s)
 {
-    if (h->G32) return MFCG_OK;
+    if (h->fp32_ready) return MFCG_OK;
     if (h->gll || h->mass || h->q2 || h->qgeom)
         return fail(h, MFCG_EINVAL,
                     "the FP32 operator is built for the Gauss-point Laplacian (k+1 points, stored tensor) only");
     const HostLayout &L = h->hl;
+    /* all or nothing: what an earlier failed call left behind is freed first */
+    HIPCHK(h, hipStreamSynchronize(s));
+    void *olds[] = {h->G32, h->dinv32, h->r32, h->p32, h->v32, h->x32, h->part32, h->dots32, h->st32};
+    for (void *q : olds)
+        if (q) HIPCHK(h, hipFree(q));
+    h->G32 = h->dinv32 = h->r32 = h->p32 = h->v32 = h->x32 = h->part32 = h->dots32 = nullptr;
+    h->st32 = nullptr;
     HIPCHK(h, dalloc(&h->G32, L.g_elems));
     HIPCHK(h, dalloc(&h->dinv32, L.n));
     HIPCHK(h, dalloc(&h->r32, L.n));
@@ -1403,6 +1427,7 @@ static int ensure_fp32(mfcg_ctx *h, hipStream_t s)
     HIPCHK(h, hipMemsetAsync(h->part32, 0, sizeof(float) * std::max<int64_t>(1, L.npart), s));
     HIPCHK(h, launch_convert(L.g_elems, h->G, h->G32, s));
     HIPCHK(h, launch_convert(L.n, h->dinv, h->dinv32, s));
+    h->fp32_ready = true;
     return MFCG_OK;
 }
 
@@ -1418,11 +1443,12 @@ static int fp32_cg(mfcg_ctx *h, double rnorm, double inner_tol, int max_inner, i
                    int *its, double *beta_out, hipStream_t s)
 {
     const int64_t n = h->hl.n;
-    if (max_inner + 1 > h->hist32_cap) {
+    if (max_inner >= h->hist32_cap) {
         if (h->hist32) HIPCHK(h, hipFree(h->hist32));
         h->hist32 = nullptr;
+        h->hist32_cap = 0;
         HIPCHK(h, dalloc(&h->hist32, (size_t)max_inner + 1));
-        h->hist32_cap = max_inner + 1;
+        h->hist32_cap = (int64_t)max_inner + 1;
     }
     HIPCHK(h, hipMemsetAsync(h->x32, 0, sizeof(float) * n, s));
     if (!keep_direction) {

@@ -143,3 +143,27 @@ def test_multi_fullsize_equals_single_solves(torch_cuda):
         for c in range(3):
             assert torch.equal(xs[c], ref[c][2]), f"rhs {c} maxit {maxit}"
     P.close()
+
+
+def test_multi_failed_history_allocation_leaves_handle_usable(oracle_mod, torch_cuda):
+    """A residual history that cannot be allocated (64 right-hand sides x
+    2^31 entries, 1 TiB) is refused with MFCG_ENOMEM before any launch, and
+    the handle still solves afterwards: the iteration limit's 32-bit
+    maximum is sized in 64 bits, and a failed allocation leaves no stale
+    capacity behind."""
+    torch = torch_cuda
+    from paper_2205_08909_amd import mfcg
+    cells, k = (4, 4, 4), 2
+    _, A, P = _problem(oracle_mod, cells, k, 1, 0.05, None, None)
+    b = torch.from_numpy(inputs.random_rhs(cells, k, seed=85)).cuda()
+    m = mfcg.MULTI_MAX
+    xs = [torch.zeros_like(b) for _ in range(m)]
+    print("m", m, "maxit 2^31 - 1", flush=True)
+    code, _, _, _ = P.solve_multi([b] * m, xs, tol=1e-10, maxit=2**31 - 1, raise_on=False)
+    assert code == mfcg.ENOMEM
+    x1 = [torch.zeros_like(b)]
+    code, its, status, _ = P.solve_multi([b], x1, tol=1e-10, maxit=500)
+    ref = torch.zeros_like(b)
+    P.solve(b, ref, tol=1e-10, maxit=500)
+    assert code == mfcg.OK and status == [mfcg.OK]
+    assert torch.equal(x1[0], ref)
