@@ -106,12 +106,17 @@ static int fail(mfcg_ctx *h, int code, const std::string &msg)
     return code;
 }
 
+/* A failed HIP call is reported through the return code; the runtime's
+ * last-error state it set is cleared, so that a caller's next HIP call (a
+ * framework's allocation, say) is not taken to have failed. */
 #define HIPCHK(h, call)                                                                               \
     do {                                                                                              \
         hipError_t e_ = (call);                                                                       \
-        if (e_ != hipSuccess)                                                                         \
+        if (e_ != hipSuccess) {                                                                       \
+            (void)hipGetLastError();                                                                  \
             return fail((h), e_ == hipErrorOutOfMemory ? MFCG_ENOMEM : MFCG_EHIP,                     \
                         std::string(#call) + ": " + hipGetErrorString(e_));                            \
+        }                                                                                             \
     } while (0)
 
 template <typename T>
@@ -376,6 +381,7 @@ int mfcg_setup(const mfcg_mesh *mesh, int32_t degree, const double *cell_coeff, 
     do {                                                                                         \
         hipError_t e_ = (call);                                                                  \
         if (e_ != hipSuccess) {                                                                  \
+            (void)hipGetLastError();                                                             \
             h->err = std::string(#call) + ": " + hipGetErrorString(e_);                          \
             return bail(e_ == hipErrorOutOfMemory ? MFCG_ENOMEM : MFCG_EHIP);                    \
         }                                                                                        \
@@ -1609,16 +1615,16 @@ int mfcg_autotune_tile(const mfcg_mesh *mesh, int32_t degree, int32_t iters, int
      * evenly; the shallow ones for small meshes); half the x/y extent with
      * 16 layers as a check */
     std::vector<std::array<int, 3>> cand;
-    auto add = [&](int h, int z) {
-        std::array<int, 3> t = {std::min(h, mesh->cells[0]), std::min(h, mesh->cells[1]), std::min(z, mesh->cells[2])};
+    auto add = [&](int hx, int hy, int z) {
+        std::array<int, 3> t = {std::min(hx, mesh->cells[0]), std::min(hy, mesh->cells[1]), std::min(z, mesh->cells[2])};
         if (t[2] >= 1 && std::find(cand.begin(), cand.end(), t) == cand.end()) cand.push_back(t);
     };
-    for (int z : {8, 16, 32}) add(tx, z);
+    for (int z : {8, 16, 32}) add(tx, ty, z);
     for (int m = 1; m <= 12; ++m) {
         const int z = (mesh->cells[2] + m - 1) / m;
-        if (z >= 2 && z <= 64) add(tx, z);
+        if (z >= 2 && z <= 64) add(tx, ty, z);
     }
-    add((tx + 1) / 2, 16);
+    add((tx + 1) / 2, (ty + 1) / 2, 16);
     int64_t n = 1;
     for (int d = 0; d < 3; ++d) n *= (int64_t)mesh->cells[d] * degree + 1;
     double *b = nullptr;
@@ -1706,9 +1712,11 @@ static int batch_fail(mfcg_batch_ctx *hb, int code, const std::string &msg)
 #define BCHK(hb, call)                                                                          \
     do {                                                                                        \
         hipError_t e_ = (call);                                                                 \
-        if (e_ != hipSuccess)                                                                   \
+        if (e_ != hipSuccess) {                                                                 \
+            (void)hipGetLastError();                                                            \
             return batch_fail((hb), e_ == hipErrorOutOfMemory ? MFCG_ENOMEM : MFCG_EHIP,        \
                               std::string(#call) + ": " + hipGetErrorString(e_));                \
+        }                                                                                       \
     } while (0)
 
 static IterArgs<double> iter_args(const mfcg_ctx *h)
@@ -1893,6 +1901,7 @@ static int batch_setup_impl(int32_t nprob, const mfcg_mesh *meshes, const int32_
         hb->max_shared += hb->probs[i]->nshared_blocks;
     }
     auto bail = [&](hipError_t e) {
+        (void)hipGetLastError();
         std::string m = std::string("batch allocation: ") + hipGetErrorString(e);
         batch_release(hb);
         delete hb;

@@ -35,7 +35,10 @@ static int nn_fail(int code, const std::string &msg)
 #define NNCHK(expr)                                                                           \
     do {                                                                                      \
         hipError_t e_ = (expr);                                                               \
-        if (e_ != hipSuccess) return nn_fail(MFNN_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+        if (e_ != hipSuccess) {                                                               \
+            (void)hipGetLastError(); /* reported here; not left for the caller's next HIP call */ \
+            return nn_fail(MFNN_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));      \
+        }                                                                                     \
     } while (0)
 
 static bool dtype_ok(int32_t t) { return t == MFNN_BF16 || t == MFNN_F32; }

@@ -230,8 +230,9 @@ def test_enumeration_bijection_and_counts(cells, k, tile, bc):
 
 
 def mfcg_default_tile(k):
-    txy = {1: 8, 2: 8, 3: 5, 4: 4, 5: 3, 6: 2, 7: 2, 8: 2}[k]
-    return (txy, txy, 16)
+    tx = {1: 8, 2: 8, 3: 5, 4: 4, 5: 4, 6: 2, 7: 2, 8: 2}[k]
+    ty = {1: 8, 2: 8, 3: 5, 4: 4, 5: 3, 6: 2, 7: 2, 8: 2}[k]
+    return (tx, ty, 16)
 
 
 def test_tile_interior_blocks_are_contiguous():
