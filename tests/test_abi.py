@@ -230,8 +230,8 @@ def test_enumeration_bijection_and_counts(cells, k, tile, bc):
 
 
 def mfcg_default_tile(k):
-    tx = {1: 8, 2: 8, 3: 5, 4: 4, 5: 4, 6: 2, 7: 2, 8: 2}[k]
-    ty = {1: 8, 2: 8, 3: 5, 4: 4, 5: 3, 6: 2, 7: 2, 8: 2}[k]
+    tx = {1: 8, 2: 8, 3: 8, 4: 4, 5: 4, 6: 2, 7: 2, 8: 2}[k]
+    ty = {1: 8, 2: 8, 3: 4, 4: 4, 5: 3, 6: 2, 7: 2, 8: 2}[k]
     return (tx, ty, 16)
 
 
