@@ -115,10 +115,10 @@ inline int fused_block_size_impl(int K)
 #define MFCG_CARRY_OF(K) (Cfg<K>::CARRY)
 #endif
 /* the k+2-point variants: no more waves than their larger cell scratch
- * lets fit per CU (LDS per workgroup 32 KB at k = 1, 83 KB at k = 2,
- * 67-77 KB at k = 3..5, 49 KB at k = 6, 69 KB at k = 7), geometry loads in
- * the G pass */
-constexpr int WPE_Q2[8] = {0, 2, 3, 4, 4, 3, 2, 2};
+ * lets fit per CU (LDS per workgroup 32 KB at k = 1, 83 KB at k = 2, 86 KB
+ * at k = 3 and 94 KB at k = 5, one workgroup per CU, 77 KB at k = 4, 49 KB
+ * at k = 6, 69 KB at k = 7), geometry loads in the G pass */
+constexpr int WPE_Q2[8] = {0, 2, 3, 2, 4, 2, 2, 2};
 /* the quadratic-geometry variants hold the cell's contracted geometry (27
  * values per line) through the G pass: they ask for as many waves as their
  * register use allows without heavy spills (k = 3: 3 waves per SIMD was 4%
@@ -128,8 +128,8 @@ constexpr int WPE_QG[9] = {0, 2, 3, 3, 4, 2, 2, 2, 2};
 /* the mass operator with quadratic geometry (no derivative passes) */
 constexpr int WPE_QGM[9] = {0, 2, 3, 4, 4, 3, 2, 2, 2};
 /* both: the k+2 cell buffers plus the staged geometry fit one workgroup per
- * CU at k = 3 and 4 */
-constexpr int WPE_QGQ2[8] = {0, 2, 3, 2, 2, 3, 2, 2};
+ * CU at k = 3, 4 and 5 */
+constexpr int WPE_QGQ2[8] = {0, 2, 3, 2, 2, 2, 2, 2};
 #define MFCG_WPE_MIN_Q(K, QX, OPV)                                                                                   \
     ((QX) ? (((OPV) == OPV_LAPLACE_QGEOM || (OPV) == OPV_MASS_QGEOM) ? WPE_QGQ2[(K) < 8 ? (K) : 0]                   \
                                                                       : WPE_Q2[(K) < 8 ? (K) : 0])                   \
