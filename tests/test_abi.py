@@ -150,6 +150,20 @@ def test_setup_rejects_bad_coefficient_and_tile():
     assert L.mfcg_setup(ctypes.byref(m), 2, None, None, None, None) == mfcg.EINVAL
 
 
+@pytest.mark.parametrize("k", range(1, 9))
+def test_setup_rejects_tiles_beyond_the_compiled_extent(k):
+    """The fused kernel's LDS is sized for a compiled maximum tile extent
+    per degree and direction (x and y may differ); one cell more in either
+    direction is refused on the host, before any HIP call."""
+    L = mfcg.lib()
+    tx, ty, _ = mfcg_default_tile(k)
+    m = mfcg.make_mesh((tx + 1, ty + 1, 2))
+    h = ctypes.c_void_p()
+    for tile in ((tx + 1, 1, 1), (1, ty + 1, 1), (tx + 1, ty + 1, 1)):
+        o = mfcg.make_options(tile=tile)
+        assert L.mfcg_setup(ctypes.byref(m), k, None, ctypes.byref(o), None, ctypes.byref(h)) == mfcg.EINVAL, tile
+
+
 def test_null_handle_calls():
     L = mfcg.lib()
     n = ctypes.c_int64()
