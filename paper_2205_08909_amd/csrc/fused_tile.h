@@ -68,7 +68,8 @@ namespace mfcg {
  * 16% faster per iteration than 3x3 tiles on 384 threads, 324 lines; k = 3:
  * 8x4 tiles on 512 threads, every thread busy, 3-8% faster than 5x5 tiles
  * at three workgroups per CU, 21% with the quadratic geometry, 10% slower
- * with k+2 points). */
+ * with k+2 points; k = 8: 2x1 tiles on 192 threads, four workgroups per CU,
+ * 31% faster than 2x2 tiles on 384 threads at two per CU). */
 template <int K>
 struct Cfg;
 template <> struct Cfg<1> { static constexpr int TX = 8, TY = 8, WG = 256, GPREF = 0, OCC = 2, CARRY = 0; };
@@ -78,11 +79,11 @@ template <> struct Cfg<4> { static constexpr int TX = 4, TY = 4, WG = 448, GPREF
 template <> struct Cfg<5> { static constexpr int TX = 4, TY = 3, WG = 448, GPREF = 0, OCC = 2, CARRY = 1; };
 template <> struct Cfg<6> { static constexpr int TX = 2, TY = 2, WG = 256, GPREF = 0, OCC = 2, CARRY = 1; };
 template <> struct Cfg<7> { static constexpr int TX = 2, TY = 2, WG = 256, GPREF = 1, OCC = 2, CARRY = 1; };
-template <> struct Cfg<8> { static constexpr int TX = 2, TY = 2, WG = 384, GPREF = 0, OCC = 1, CARRY = 0; };
+template <> struct Cfg<8> { static constexpr int TX = 2, TY = 1, WG = 192, GPREF = 0, OCC = 4, CARRY = 0; };
 
 inline void tile_limits_impl(int K, int *tx, int *ty)
 {
-    static const int x[9] = {0, 8, 8, 8, 4, 4, 2, 2, 2}, y[9] = {0, 8, 8, 4, 4, 3, 2, 2, 2};
+    static const int x[9] = {0, 8, 8, 8, 4, 4, 2, 2, 2}, y[9] = {0, 8, 8, 4, 4, 3, 2, 2, 1};
     const bool ok = K >= 1 && K <= 8;
     *tx = ok ? x[K] : 0;
     *ty = ok ? y[K] : 0;
@@ -90,7 +91,7 @@ inline void tile_limits_impl(int K, int *tx, int *ty)
 
 inline int fused_block_size_impl(int K)
 {
-    static const int w[9] = {0, 256, 576, 512, 448, 448, 256, 256, 384};
+    static const int w[9] = {0, 256, 576, 512, 448, 448, 256, 256, 192};
     return (K >= 1 && K <= 8) ? w[K] : 0;
 }
 

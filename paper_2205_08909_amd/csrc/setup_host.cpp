@@ -162,7 +162,7 @@ void default_tile(int K, int tile[3])
 {
     /* xy extent of about 16 nodes per tile (the fused kernel's compiled
      * maximum), z streamed in layers */
-    static const int tx[9] = {0, 8, 8, 8, 4, 4, 2, 2, 2}, ty[9] = {0, 8, 8, 4, 4, 3, 2, 2, 2};
+    static const int tx[9] = {0, 8, 8, 8, 4, 4, 2, 2, 2}, ty[9] = {0, 8, 8, 4, 4, 3, 2, 2, 1};
     tile[0] = tx[K];
     tile[1] = ty[K];
     tile[2] = 16;

@@ -225,7 +225,7 @@ def _closed_form_counts(cells, k, tile, bc):
     ((5, 7, 9), 3, (2, 3, 4), 0),
     ((4, 4, 4), 4, (0, 0, 0), 1),
     ((3, 2, 5), 1, (2, 2, 2), 0),
-    ((6, 5, 4), 8, (2, 2, 3), 0),
+    ((6, 5, 4), 8, (2, 1, 3), 0),
     ((1, 1, 1), 4, (0, 0, 0), 0),
     ((2, 3, 1), 5, (1, 2, 1), 1),
 ])
@@ -245,7 +245,7 @@ def test_enumeration_bijection_and_counts(cells, k, tile, bc):
 
 def mfcg_default_tile(k):
     tx = {1: 8, 2: 8, 3: 8, 4: 4, 5: 4, 6: 2, 7: 2, 8: 2}[k]
-    ty = {1: 8, 2: 8, 3: 4, 4: 4, 5: 3, 6: 2, 7: 2, 8: 2}[k]
+    ty = {1: 8, 2: 8, 3: 4, 4: 4, 5: 3, 6: 2, 7: 2, 8: 1}[k]
     return (tx, ty, 16)
 
 

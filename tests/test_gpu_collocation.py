@@ -26,7 +26,7 @@ CASES = [
     ((3, 4, 5), 5, 2, (2, 3, 2), True),
     ((3, 3, 4), 6, 1, (2, 2, 3), True),
     ((3, 2, 3), 7, 1, (2, 1, 2), True),
-    ((3, 3, 2), 8, 1, (2, 2, 1), True),
+    ((3, 3, 2), 8, 1, (2, 1, 1), True),
 ]
 
 

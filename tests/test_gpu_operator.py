@@ -25,7 +25,7 @@ CASES = [
     ((3, 4, 5), 5, 1, 0.05, 0, (2, 3, 2), True),
     ((3, 3, 4), 6, 1, 0.05, 0, (2, 2, 3), True),
     ((3, 2, 3), 7, 1, 0.05, 0, (2, 1, 2), True),
-    ((3, 3, 2), 8, 1, 0.05, 0, (2, 2, 1), True),
+    ((3, 3, 2), 8, 1, 0.05, 0, (2, 1, 1), True),
     ((4, 4, 4), 3, 1, 0.05, 1, (2, 3, 3), True),       # no boundary condition (singular operator)
     ((1, 1, 1), 4, 1, 0.05, 0, None, False),           # a single cell
     ((1, 1, 1), 2, 1, 0.05, 1, None, True),

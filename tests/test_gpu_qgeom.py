@@ -31,7 +31,7 @@ CASES = [
     ((3, 4, 5), 5, 2, 1, (2, 3, 2)),
     ((3, 3, 4), 6, 1, 0, (2, 2, 3)),
     ((3, 2, 3), 7, 1, 1, (2, 1, 2)),
-    ((3, 3, 2), 8, 2, 0, (2, 2, 1)),
+    ((3, 3, 2), 8, 2, 0, (2, 1, 1)),
 ]
 
 

@@ -26,7 +26,7 @@ def _draw(i):
     if tile is not None:
         # the compiled x/y tile limits shrink with the degree
         limx = {1: 8, 2: 8, 3: 8, 4: 4, 5: 4, 6: 2, 7: 2, 8: 2}[k]
-        limy = {1: 8, 2: 8, 3: 4, 4: 4, 5: 3, 6: 2, 7: 2, 8: 2}[k]
+        limy = {1: 8, 2: 8, 3: 4, 4: 4, 5: 3, 6: 2, 7: 2, 8: 1}[k]
         tile = (min(tile[0], limx), min(tile[1], limy), tile[2])
     kind = int(rng.integers(0, 3))
     bc = int(rng.random() < 0.3)
@@ -80,7 +80,7 @@ def _draw_variant(i):
     cmax = max(2, 9 - k)
     cells = tuple(int(c) for c in rng.integers(1, cmax + 1, 3))
     limx = {1: 8, 2: 8, 3: 8, 4: 4, 5: 4, 6: 2, 7: 2, 8: 2}[k]
-    limy = {1: 8, 2: 8, 3: 4, 4: 4, 5: 3, 6: 2, 7: 2, 8: 2}[k]
+    limy = {1: 8, 2: 8, 3: 4, 4: 4, 5: 3, 6: 2, 7: 2, 8: 1}[k]
     tile = tuple(int(rng.integers(1, c + 1)) for c in cells) if rng.random() < 0.7 else None
     if tile is not None:
         tile = (min(tile[0], limx), min(tile[1], limy), tile[2])
