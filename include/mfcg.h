@@ -126,7 +126,10 @@ typedef struct {
                               * n_q = (k+2)^3 rule of the BP1-BP4 benchmarks of Sec. 6; k <= 7,
                               * Gauss only, FP64 only: not with fp32 / mfcg_solve_ir, not in a
                               * batch; the stored tensor grows to (k+2)^3 points per cell) */
-    int32_t tile[3];         /* cells per tile in x, y, z; 0: per-degree default */
+    int32_t tile[3];         /* cells per tile in x, y, z; 0: per-degree default.  x and y at most
+                              * the fused kernel's compiled extent, (x, y) = (8, 8), (8, 8),
+                              * (8, 4), (4, 4), (4, 3), (2, 2), (2, 2), (2, 1) for k = 1..8, which
+                              * is also the default; default z 16 */
     int32_t check_every;     /* iterations between host polls of the convergence flag; 0: 16 */
     int32_t fp32;            /* 1: build the FP32 operator copy of mfcg_solve_ir at set-up (else on first use) */
     int32_t quad_rule;       /* MFCG_QUAD_* */
@@ -149,7 +152,8 @@ typedef struct {
  *   cell_coeff  host, nx*ny*nz positive finite values a_e; NULL: a = 1
  *   opt         NULL: defaults
  * Errors: EINVAL (null mesh/out, cells < 1, degree out of range, bad map or
- * bc, non-positive coefficient, unsupported n_q_1d, tile < 0), ENOMEM, EHIP.
+ * bc, non-positive coefficient, unsupported n_q_1d, tile < 0 or beyond the
+ * compiled x/y extent), ENOMEM, EHIP.
  * On error *out is NULL. */
 int mfcg_setup(const mfcg_mesh *mesh, int32_t degree, const double *cell_coeff,
                const mfcg_options *opt, void *hip_stream, mfcg_handle *out);
@@ -432,8 +436,8 @@ int mfcg_stream_bench(int32_t kind, int64_t n, const double *src, double *dst, i
  * of a Poisson problem on `mesh` for each candidate tile and returns the
  * fastest in tile_out[3] and its time per iteration in *ms_out (may be
  * NULL).  Candidates: the compiled maximum extent in x and y with 8, 16 or
- * 32 cell layers in z or the mesh's z extent split into 1..8 equal tile
- * layers (4..64 cells deep), and half the x/y extent with 16 layers; all
+ * 32 cell layers in z or the mesh's z extent split into 1..12 equal tile
+ * layers (2..64 cells deep), and half the x/y extent with 16 layers; all
  * clipped to the mesh.  Builds and frees one handle per
  * candidate.  Errors: EINVAL, ENOMEM, EHIP. */
 int mfcg_autotune_tile(const mfcg_mesh *mesh, int32_t degree, int32_t iters, int32_t *tile_out, double *ms_out,
