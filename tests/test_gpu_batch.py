@@ -109,6 +109,34 @@ def test_autotune_returns_a_candidate():
     assert tile[:2] in ((4, 4), (2, 2)) and tile[2] in (2, 3, 4, 6, 8, 12)
 
 
+@pytest.mark.parametrize("k,ext", [(3, (8, 4)), (5, (4, 3)), (8, (2, 1))])
+def test_autotune_candidates_keep_the_per_axis_extents(k, ext):
+    """Degrees whose compiled tile extent differs in x and y: the autotuner
+    tries that extent and its half in each direction (never a square tile
+    beyond either), and the tile it returns solves like the default one."""
+    import torch
+    from paper_2205_08909_amd import mfcg
+    cells = 9
+    tile, ms = mfcg.autotune_tile(cells, k, map_kind=1, amplitude=0.05, iters=2)
+    print("k", k, "tile", tile, "ms", ms, flush=True)
+    half = tuple((e + 1) // 2 for e in ext)
+    assert ms > 0 and tile[:2] in (ext, half)
+    xs, iters = [], []
+    for t in (tile, None):
+        P = mfcg.Problem(cells, k, map_kind=1, amplitude=0.05, tile=t)
+        b = torch.from_numpy(inputs.random_rhs(cells, k, seed=7)).cuda()
+        x = torch.zeros_like(b)
+        code, its, _, tr = P.solve(b, x, tol=1e-10, maxit=5000, want_hist=False, want_true_res=True)
+        print("tile", t, "its", its, "true res", tr, flush=True)
+        assert code == mfcg.OK and tr <= 2e-10
+        xs.append(x)
+        iters.append(its)
+        P.close()
+    # the two tilings sum in different orders: the same iteration up to rounding
+    assert abs(iters[0] - iters[1]) <= 3
+    assert float((xs[0] - xs[1]).norm() / xs[1].norm()) <= 1e-6
+
+
 def test_batch_mixed_large_and_small_problems():
     """One problem large enough to fill the device alone (>= 512 tiles)
     beside small ones of other degrees in the same work lists: still bitwise
