@@ -1861,8 +1861,11 @@ static int batch_setup_impl(int32_t nprob, const mfcg_mesh *meshes, const int32_
             m.cells[0] = m.cells[1] = m.cells[2] = c;
             int32_t t[3];
             const TuneKey key{cache ? gpu_key() : std::string(), K, c, m.map_kind, "fp64"};
-            int ct[3];
-            if (cache && tune_cache_lookup(cache, key, ct)) {
+            int ct[3], ltx = 0, lty = 0;
+            tile_limits(K, &ltx, &lty);
+            /* a cached tile beyond this build's compiled x/y extent (a cache
+             * written by a build with other tile shapes) counts as a miss */
+            if (cache && tune_cache_lookup(cache, key, ct) && ct[0] <= ltx && ct[1] <= lty) {
                 for (int d = 0; d < 3; ++d) t[d] = ct[d];
             } else {
                 double ms = 0.0;

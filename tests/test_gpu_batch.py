@@ -199,3 +199,23 @@ def test_setup_batch_options_and_tune_cache(tmp_path):
     assert all(torch.equal(a, b) for a, b in zip(xs1, xs2))
     B1.close()
     B2.close()
+
+
+def test_tune_cache_record_beyond_the_compiled_extent_is_retuned(tmp_path):
+    """A cached tile wider than this build's compiled x/y extent (a cache
+    written by a build with other tile shapes) is not used: the degree is
+    tuned again and its record replaced."""
+    import re
+    from paper_2205_08909_amd import mfcg
+    probs = _draw(11, 4, 4, 10, kmin=2, kmax=4)
+    cache = tmp_path / "tune.json"
+    mfcg.Batch(probs, tune_cache=str(cache)).close()
+    stale = re.sub(r'"tile": \[\d+, \d+, (\d+)\]', r'"tile": [16, 16, \1]', cache.read_text())
+    assert stale.count("[16, 16,") == len({p["degree"] for p in probs})
+    cache.write_text(stale)
+    B = mfcg.Batch(probs, tune_cache=str(cache))
+    ext = {2: (8, 8), 3: (8, 4), 4: (4, 4)}
+    for p, t in zip(probs, B.tiles):
+        assert t[0] <= ext[p["degree"]][0] and t[1] <= ext[p["degree"]][1], (p["degree"], t)
+    assert "[16, 16," not in cache.read_text()
+    B.close()
