@@ -141,7 +141,9 @@ typedef struct {
                               * reproducible from run to run on the same device */
     const char *tune_cache;  /* mfcg_setup_batch: path of the autotuner cache (JSON, one record per
                               * GPU, degree, tuning cube size, map and precision; created or updated
-                              * in place); NULL: tune on every call.  Ignored by mfcg_setup */
+                              * in place; a record whose tile exceeds this build's compiled x/y
+                              * extent is tuned again and replaced); NULL: tune on every call.
+                              * Ignored by mfcg_setup */
 } mfcg_options;
 
 /* Builds the operator (Sec. 2, Eq. 3-5): tiles and DoF enumeration of the
